@@ -1,0 +1,186 @@
+"""CPU oracle -- TEST INFRASTRUCTURE ONLY.
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of
+``bench.py`` may import this package.  The product (``paper_2202_05549_amd``)
+never imports it, and the two share no code: the oracle has its own C
+routines (``oracle.c``) and its own annotation reader (``planner.py``).
+
+Numpy-level wrappers around ``liboracle.so``.  ``build()`` compiles it with
+gcc (``-O2 -fopenmp -ffp-contract=off``).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SO = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile oracle.c into liboracle.so next to it."""
+    if force or not os.path.exists(_SO):
+        src = os.path.join(_HERE, "oracle.c")
+        tmp = _SO + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-ffp-contract=off",
+                               "-fno-fast-math", "-shared", "-fPIC", "-o", tmp,
+                               src, "-lm"])
+        os.replace(tmp, _SO)
+    return _SO
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_SO):
+            build()
+        L = C.CDLL(_SO)
+        i64, p, i32 = C.c_int64, C.c_void_p, C.c_int
+        L.or_stencil1d_f32.argtypes = [i64, p, p]
+        L.or_jacobi2d_sweep_f32.argtypes = [i64, i64, p, p]
+        L.or_jacobi2d_f32.argtypes = [i64, i64, i32, p, p]
+        L.or_jacobi2d_f32.restype = i32
+        L.or_gemm_f64.argtypes = [i64, i64, i64, p, i64, p, i64, p, i64]
+        L.or_gemm_entries_f64.argtypes = [i64, p, i64, p, i64, i64, p, p, p, p]
+        L.or_matvec_f64.argtypes = [i64, i64, p, i64, p, p, i32]
+        L.or_hist256_i32.argtypes = [i64, p, p]
+        L.or_kmeans_assign_f32.argtypes = [i64, i64, i64, p, p, p]
+        L.or_kmeans_dist_f64.argtypes = [i64, p, p]
+        L.or_kmeans_dist_f64.restype = C.c_double
+        L.or_touch_i32.argtypes = [i64, i64, p]
+        _lib = L
+    return _lib
+
+
+def _ptr(a: np.ndarray):
+    assert a.flags["C_CONTIGUOUS"] or a.ndim == 0
+    return a.ctypes.data_as(C.c_void_p)
+
+
+# ------------------------------------------------------------------ kernels
+
+
+def stencil1d(x: np.ndarray) -> np.ndarray:
+    x = np.ascontiguousarray(x, dtype=np.float32)
+    y = np.empty_like(x)
+    lib().or_stencil1d_f32(x.size, _ptr(x), _ptr(y))
+    return y
+
+
+def stencil1d_iter(x: np.ndarray, iters: int) -> np.ndarray:
+    """``iters`` launches with input and output swapped after each."""
+    a = np.ascontiguousarray(x, dtype=np.float32).copy()
+    b = np.empty_like(a)
+    for _ in range(iters):
+        lib().or_stencil1d_f32(a.size, _ptr(a), _ptr(b))
+        a, b = b, a
+    return a
+
+
+def jacobi2d_sweep(x: np.ndarray) -> np.ndarray:
+    x = np.ascontiguousarray(x, dtype=np.float32)
+    y = np.empty_like(x)
+    lib().or_jacobi2d_sweep_f32(x.shape[0], x.shape[1], _ptr(x), _ptr(y))
+    return y
+
+
+def jacobi2d(x0: np.ndarray, sweeps: int, inplace: bool = False):
+    """Result of ``sweeps`` ping-pong sweeps starting from x0.
+
+    With ``inplace`` the input buffer is reused as the first ping-pong buffer
+    (saves one copy of a large field).
+    """
+    a = x0 if inplace else np.array(x0, dtype=np.float32, copy=True)
+    assert a.dtype == np.float32 and a.flags["C_CONTIGUOUS"]
+    b = np.empty_like(a)
+    w = lib().or_jacobi2d_f32(a.shape[0], a.shape[1], sweeps, _ptr(a), _ptr(b))
+    return a if w == 0 else b
+
+
+def gemm(A: np.ndarray, B: np.ndarray) -> np.ndarray:
+    """float64-accumulated A @ B for float32 A, B (any leading dimension)."""
+    assert A.dtype == np.float32 and B.dtype == np.float32
+    assert A.strides[1] == 4 and B.strides[1] == 4
+    M, K = A.shape
+    K2, N = B.shape
+    assert K == K2
+    Cm = np.empty((M, N), dtype=np.float64)
+    lib().or_gemm_f64(M, N, K, C.c_void_p(A.ctypes.data), A.strides[0] // 4,
+                      C.c_void_p(B.ctypes.data), B.strides[0] // 4, _ptr(Cm), N)
+    return Cm
+
+
+def gemm_entries(A: np.ndarray, B: np.ndarray, ii, jj):
+    """(value, |A||B| value) of selected entries of A @ B, in float64."""
+    ii = np.ascontiguousarray(ii, dtype=np.int64)
+    jj = np.ascontiguousarray(jj, dtype=np.int64)
+    val = np.empty(ii.size, dtype=np.float64)
+    av = np.empty(ii.size, dtype=np.float64)
+    K = A.shape[1]
+    lib().or_gemm_entries_f64(K, C.c_void_p(A.ctypes.data), A.strides[0] // 4,
+                              C.c_void_p(B.ctypes.data), B.strides[0] // 4,
+                              ii.size, _ptr(ii), _ptr(jj), _ptr(val), _ptr(av))
+    return val, av
+
+
+def matvec(A: np.ndarray, x: np.ndarray, absval: bool = False) -> np.ndarray:
+    assert A.dtype == np.float32 and A.strides[1] == 4
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    y = np.empty(A.shape[0], dtype=np.float64)
+    lib().or_matvec_f64(A.shape[0], A.shape[1], C.c_void_p(A.ctypes.data),
+                        A.strides[0] // 4, _ptr(x), _ptr(y), int(absval))
+    return y
+
+
+def freivalds(A, B, Cm, trials: int = 3, seed: int = 12345):
+    """Randomized check of Cm = A B in float64.
+
+    For each trial draws r in {-1, +1}^n and returns, per row i, the residual
+    |(Cm r - A (B r))_i| and the scale (|A| (|B| 1))_i; a correct float32
+    product has residual / scale of the order of the float32 unit roundoff
+    times sqrt(K).  Returns the worst ratio over rows and trials.
+    """
+    rng = np.random.default_rng(seed)
+    n = B.shape[1]
+    ones = np.ones(n, dtype=np.float64)
+    scale = matvec(A, matvec(B, ones, absval=True), absval=True)
+    worst = 0.0
+    for _ in range(trials):
+        r = rng.choice(np.array([-1.0, 1.0]), n)
+        lhs = matvec(Cm, r)
+        rhs = matvec(A, matvec(B, r))
+        ratio = np.abs(lhs - rhs) / np.maximum(scale, np.finfo(np.float64).tiny)
+        worst = max(worst, float(ratio.max()))
+    return worst
+
+
+def hist256(v: np.ndarray) -> np.ndarray:
+    v = np.ascontiguousarray(v, dtype=np.int32)
+    h = np.empty(256, dtype=np.int32)
+    lib().or_hist256_i32(v.size, _ptr(v), _ptr(h))
+    return h
+
+
+def kmeans_assign(X: np.ndarray, Cen: np.ndarray) -> np.ndarray:
+    X = np.ascontiguousarray(X, dtype=np.float32)
+    Cen = np.ascontiguousarray(Cen, dtype=np.float32)
+    lab = np.empty(X.shape[0], dtype=np.int32)
+    lib().or_kmeans_assign_f32(X.shape[0], X.shape[1], Cen.shape[0], _ptr(X),
+                               _ptr(Cen), _ptr(lab))
+    return lab
+
+
+def kmeans_dist64(x: np.ndarray, c: np.ndarray) -> float:
+    x = np.ascontiguousarray(x, dtype=np.float32)
+    c = np.ascontiguousarray(c, dtype=np.float32)
+    return float(lib().or_kmeans_dist_f64(x.size, _ptr(x), _ptr(c)))
+
+
+def touch(y: np.ndarray, grid: int) -> np.ndarray:
+    y = np.array(y, dtype=np.int32, copy=True)
+    lib().or_touch_i32(y.size, grid, _ptr(y))
+    return y

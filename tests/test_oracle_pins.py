@@ -1,0 +1,241 @@
+"""Pins of the CPU oracle against facts it does not compute itself.
+
+Each test checks one oracle routine against something fixed outside it: a
+closed form, an exact-arithmetic evaluation with the float32 rounding bound,
+a textbook special case, or a library routine on a special case (exact
+integer products, ``bincount``).  They run without a GPU.
+"""
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import oracle
+import synthetic
+
+U = 2.0 ** -24  # float32 unit roundoff
+
+
+# ------------------------------------------------------------------ stencil1d
+
+@pytest.mark.parametrize("c", [1.0, 0.75, -2.5, 3.0, 1024.0, 2.0 ** -20])
+def test_stencil1d_constant_field_is_fixed_in_interior(c):
+    n = 1000
+    y = oracle.stencil1d(np.full(n, c, np.float32))
+    assert np.all(y[1:-1] == np.float32(c))
+    # the two ends see one zero neighbour: (c + 0)/4 + c/2 = 3c/4, exact here
+    assert y[0] == np.float32(0.75 * c) and y[-1] == np.float32(0.75 * c)
+
+
+def test_stencil1d_linear_ramp_is_fixed_in_interior():
+    n = 1 << 16
+    x = np.arange(n, dtype=np.float32)
+    y = oracle.stencil1d(x)
+    assert np.array_equal(y[1:-1], x[1:-1])
+    assert y[0] == np.float32(0.25)
+    assert y[-1] == np.float32((n - 2) / 4 + (n - 1) / 2)
+
+
+@pytest.mark.parametrize("k", [1, 3, 17])
+def test_stencil1d_eigenmode(k):
+    # x_i = sin(pi k (i+1)/(n+1)) vanishes at i = -1 and i = n, so the stencil
+    # with zero outside maps it to (1/2 + cos(pi k/(n+1))/2) x exactly.
+    n = 4096
+    i = np.arange(n)
+    x64 = np.sin(np.pi * k * (i + 1) / (n + 1))
+    lam = 0.5 + 0.5 * np.cos(np.pi * k / (n + 1))
+    y = oracle.stencil1d(x64.astype(np.float32)).astype(np.float64)
+    # input rounding (<= u per entry, operator norm 1) plus two roundings
+    assert np.max(np.abs(y - lam * x64)) <= 4 * U
+
+
+def test_stencil1d_exact_arithmetic_bound():
+    rng = np.random.default_rng(7)
+    x = rng.uniform(-1, 1, 97).astype(np.float32)
+    y = oracle.stencil1d(x)
+    n = x.size
+    for i in range(n):
+        a = Fraction(float(x[i - 1])) if i > 0 else Fraction(0)
+        b = Fraction(float(x[i]))
+        c = Fraction(float(x[i + 1])) if i + 1 < n else Fraction(0)
+        exact = (a + c) / 4 + b / 2
+        bound = U * (abs(float(a + c)) / 4 + abs(float(exact))) * (1 + 4 * U)
+        assert abs(float(Fraction(float(y[i])) - exact)) <= bound, i
+
+
+# ------------------------------------------------------------------ jacobi2d
+
+def test_jacobi_constant_field_after_t_sweeps():
+    N, c, t = 40, 1.0, 7
+    y = oracle.jacobi2d(np.full((N, N), c, np.float32), t)
+    r = np.arange(N)
+    d = np.minimum.outer(np.minimum(r, N - 1 - r), np.minimum(r, N - 1 - r))
+    assert np.all(y[d >= t] == np.float32(c))
+    one = oracle.jacobi2d_sweep(np.full((N, N), c, np.float32))
+    assert one[0, 0] == 0.5 and one[0, N - 1] == 0.5 and one[N - 1, 0] == 0.5
+    assert np.all(one[0, 1:-1] == 0.75) and np.all(one[1:-1, 0] == 0.75)
+    assert np.all(one[1:-1, 1:-1] == 1.0)
+
+
+def test_jacobi_exact_arithmetic_bound_one_sweep():
+    rng = np.random.default_rng(11)
+    n, m = 9, 13
+    x = rng.uniform(-1, 1, (n, m)).astype(np.float32)
+    y = oracle.jacobi2d_sweep(x)
+
+    def g(r, c):
+        return Fraction(float(x[r, c])) if 0 <= r < n and 0 <= c < m else Fraction(0)
+
+    for r in range(n):
+        for c in range(m):
+            V = g(r - 1, c) + g(r + 1, c)
+            H = g(r, c - 1) + g(r, c + 1)
+            exact = (V + H) / 4
+            bound = U * (abs(float(V)) + abs(float(H)) + abs(float(V + H))) / 4 * (1 + 4 * U)
+            assert abs(float(Fraction(float(y[r, c])) - exact)) <= bound, (r, c)
+
+
+@pytest.mark.parametrize("N", [64, 255])
+def test_jacobi_eigenmode_decay(N):
+    # u = sin(pi (r+1)/(N+1)) sin(pi (c+1)/(N+1)) is an eigenvector of the
+    # four-neighbour mean with zero outside, eigenvalue cos(pi/(N+1)).
+    t = 100
+    r = np.arange(N)
+    s = np.sin(np.pi * (r + 1) / (N + 1))
+    u0 = np.outer(s, s)
+    lam = np.cos(np.pi / (N + 1))
+    y = oracle.jacobi2d(u0.astype(np.float32), t).astype(np.float64)
+    ref = lam ** t * u0
+    # worst case three roundings per sweep on non-negative data
+    assert np.max(np.abs(y - ref)) <= (3 * t + 2) * U * np.max(ref) * 1.01
+    assert np.max(np.abs(y - ref)) < 1e-5 * np.max(ref) * 3
+
+
+def test_jacobi_pingpong_parity_of_result_buffer():
+    x = synthetic.jacobi2d_input(32, seed=5)
+    one = oracle.jacobi2d_sweep(x)
+    two = oracle.jacobi2d_sweep(one)
+    assert np.array_equal(oracle.jacobi2d(x, 1), one)
+    assert np.array_equal(oracle.jacobi2d(x, 2), two)
+
+
+# ---------------------------------------------------------------------- GEMM
+
+def test_gemm_integer_matrices_exact():
+    rng = np.random.default_rng(3)
+    A = rng.integers(-8, 9, (37, 53))
+    B = rng.integers(-8, 9, (53, 29))
+    Cm = oracle.gemm(A.astype(np.float32), B.astype(np.float32))
+    assert np.array_equal(Cm, (A @ B).astype(np.float64))
+
+
+def test_gemm_identity_operands():
+    A = synthetic.gemm_tile(0, 0, 0, 64)
+    I = np.eye(64, dtype=np.float32)
+    assert np.array_equal(oracle.gemm(A, I), A.astype(np.float64))
+    assert np.array_equal(oracle.gemm(I, A), A.astype(np.float64))
+
+
+def test_gemm_leading_dimension_views():
+    rng = np.random.default_rng(4)
+    A = rng.integers(-3, 4, (20, 30)).astype(np.float32)
+    B = rng.integers(-3, 4, (30, 40)).astype(np.float32)
+    full = oracle.gemm(A, B)
+    sub = oracle.gemm(A[5:15, :], B[:, 10:25])
+    assert np.array_equal(sub, full[5:15, 10:25])
+
+
+def test_gemm_entries_and_freivalds_detect_error():
+    rng = np.random.default_rng(5)
+    A = rng.standard_normal((96, 80), dtype=np.float32)
+    B = rng.standard_normal((80, 72), dtype=np.float32)
+    Cf = oracle.gemm(A, B)
+    ii = rng.integers(0, 96, 50)
+    jj = rng.integers(0, 72, 50)
+    val, av = oracle.gemm_entries(A, B, ii, jj)
+    assert np.allclose(val, Cf[ii, jj], rtol=0, atol=1e-12)
+    assert np.all(av >= np.abs(val) - 1e-12)
+    C32 = Cf.astype(np.float32)
+    assert oracle.freivalds(A, B, C32) < 1e-6
+    # the row-sum scale makes Freivalds blind to errors far below 1e-5 of a
+    # whole row of |A||B|; a unit error in one entry is well above it
+    bad = C32.copy()
+    bad[17, 33] += 1.0
+    assert oracle.freivalds(A, B, bad) > 1e-5
+
+
+# ----------------------------------------------------------------- histogram
+
+def test_hist_counts_sum_and_bincount():
+    rng = np.random.default_rng(6)
+    v = synthetic.zipf_values(100_003, rng)
+    h = oracle.hist256(v)
+    assert h.sum() == v.size
+    assert np.array_equal(h, np.bincount(v, minlength=256).astype(np.int32))
+
+
+def test_hist_constant_and_out_of_range():
+    v = np.full(1000, 77, np.int32)
+    h = oracle.hist256(v)
+    assert h[77] == 1000 and h.sum() == 1000
+    w = np.array([-1, 256, 1 << 20, 5], np.int32)
+    h2 = oracle.hist256(w)
+    assert h2[5] == 1 and h2.sum() == 1
+
+
+# ------------------------------------------------------------------- k-means
+
+def test_kmeans_points_at_centres_take_own_label():
+    rng = np.random.default_rng(8)
+    Cen = rng.uniform(-10, 10, (64, 16)).astype(np.float32)
+    lab = oracle.kmeans_assign(Cen.copy(), Cen)
+    assert np.array_equal(lab, np.arange(64, dtype=np.int32))
+
+
+def test_kmeans_tie_goes_to_smallest_index():
+    Cen = np.array([[1, 0], [0, 1], [1, 0]], np.float32)
+    X = np.array([[1, 0], [0.5, 0.5], [0, 1]], np.float32)
+    # point 1 is equidistant from all; point 0 ties between centres 0 and 2
+    assert list(oracle.kmeans_assign(X, Cen)) == [0, 0, 1]
+
+
+def test_kmeans_matches_float64_argmin_on_blobs():
+    X, mu, _ = synthetic.kmeans_blobs(5000, 16, 64, seed=9)
+    lab = oracle.kmeans_assign(X, mu)
+    d = ((X.astype(np.float64)[:, None, :] - mu.astype(np.float64)[None]) ** 2).sum(-1)
+    ref = np.argmin(d, axis=1)
+    srt = np.sort(d, axis=1)
+    clear = (srt[:, 1] - srt[:, 0]) > 1e-4 * srt[:, 1]
+    assert np.array_equal(lab[clear], ref[clear])
+    p = int(np.argmax(clear))
+    assert abs(oracle.kmeans_dist64(X[p], mu[lab[p]]) - d[p, lab[p]]) < 1e-9 * d[p, lab[p]] + 1e-12
+
+
+# ------------------------------------------------------------------- touch
+
+def test_touch_exactly_once_within_n():
+    y = oracle.touch(np.zeros(100, np.int32), grid=128)
+    assert np.all(y == 1)
+    y = oracle.touch(np.zeros(100, np.int32), grid=60)
+    assert np.all(y[:60] == 1) and np.all(y[60:] == 0)
+
+
+# --------------------------------------------------------------- synthetic
+
+def test_zipf_law_normaliser():
+    cdf = synthetic.zipf_cdf()
+    w = np.arange(1, 257, dtype=np.float64) ** -1.1
+    assert abs(w.sum() - 4.8421) < 1e-3
+    assert abs(cdf[0] - 0.2065) < 1e-3
+    v = synthetic.zipf_values(200_000, np.random.default_rng(1))
+    assert v.min() >= 0 and v.max() <= 255
+    assert abs((v == 0).mean() - 0.2065) < 5e-3
+
+
+def test_batch_plan_sizes_log_uniform():
+    plan = synthetic.batch_plan(8192)
+    ns = np.array([n for _, n in plan])
+    assert ns.min() >= 1 << 10 and ns.max() < 1 << 24
+    kinds = np.array([k for k, _ in plan])
+    assert 0.45 < kinds.mean() < 0.55
+    assert abs(np.median(np.log2(ns)) - 17) < 0.3
