@@ -1,0 +1,348 @@
+/*
+ * lt.h -- C ABI of the one-GPU annotated-launch runtime (MI355X, gfx950).
+ *
+ * The runtime implements the single-GPU share of the method of
+ * "Lightning: Scaling the GPU Programming Model Beyond a Single GPU"
+ * (Heldens et al., arXiv 2202.05549):
+ *
+ *   - a kernel launch is split into superblocks: disjoint boxes of thread
+ *     blocks (Sec. 2.1 "Distributed Kernel Launches");
+ *   - arrays of up to three dimensions are split into chunks by a
+ *     distribution policy (Sec. 2.2 "Multi-Dimensional Distributed Arrays");
+ *   - a data annotation states which elements each thread reads, writes or
+ *     reduces (Sec. 2.3 "Data Annotations"); the planner turns it into one
+ *     access region per superblock and array, resolves regions to chunks and
+ *     adds dependency edges between tasks that conflict on a chunk
+ *     (Sec. 2.4 "Execution Planner");
+ *   - chunks live in device memory within a byte budget; least-recently used
+ *     chunks are spilled to pinned host memory and reloaded with asynchronous
+ *     copies that overlap kernels (Sec. 3.2, Sec. 3.4 "Memory Management").
+ *
+ * Conventions
+ *   - Every call returns lt_status: LT_OK (0) or a negative error code.  After
+ *     an error, lt_last_error(ctx) holds a message (owned by the context,
+ *     valid until the next call on it).
+ *   - Calls on one context are not thread-safe: one host thread drives a
+ *     context, as the single driver program of Sec. 3.1 does.
+ *   - Shapes and indices are int64 element counts.  Arrays are row-major: the
+ *     last axis is contiguous.  Axis 0 is the slowest.
+ *   - Boxes are half-open per axis: [lo, hi).
+ *   - Launches are asynchronous and sequentially consistent: the result equals
+ *     running the launches one after another, each over its whole grid
+ *     (Sec. 1, Sec. 2.4).  Errors that happen on the device after a call has
+ *     returned are sticky and reported by the next lt_sync / lt_wait /
+ *     lt_array_read.
+ */
+#ifndef LT_H
+#define LT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t lt_status;
+
+#define LT_OK 0
+#define LT_ERR_INVALID (-1)     /* bad argument, handle, shape, dtype, arity   */
+#define LT_ERR_PARSE (-2)       /* annotation syntax / non-affine / unknown name */
+#define LT_ERR_BUDGET (-3)      /* one task needs more device bytes than the budget */
+#define LT_ERR_OOM (-4)         /* host or device allocation failed            */
+#define LT_ERR_DEVICE (-5)      /* a HIP call failed (message carries the text) */
+#define LT_ERR_TIMEOUT (-6)     /* a bounded device wait gave up               */
+#define LT_ERR_UNSUPPORTED (-7) /* valid request this build does not implement */
+
+typedef enum lt_dtype {
+    LT_F32 = 0,
+    LT_I32 = 1,
+    LT_F64 = 2,
+    LT_I64 = 3,
+    LT_U8 = 4
+} lt_dtype;
+
+typedef struct lt_context lt_context;
+typedef struct lt_array lt_array;
+typedef struct lt_kernel lt_kernel;
+
+/* ------------------------------------------------------------------ context
+ * Execution modes for the tasks of a launch:
+ *   LT_EXEC_PLAIN   one kernel dispatch per task (superblock).
+ *   LT_EXEC_GROUPED consecutive tasks of one launch that have no edges among
+ *                   each other and run on one stream share one dispatch; each
+ *                   workgroup finds its task in a table passed by value.  The
+ *                   arithmetic per element is identical to PLAIN.
+ */
+#define LT_EXEC_PLAIN 0
+#define LT_EXEC_GROUPED 1
+
+typedef struct lt_config {
+    int32_t device;                 /* HIP device ordinal                      */
+    int32_t n_compute_streams;      /* >= 1; default 1                          */
+    int32_t exec_mode;              /* LT_EXEC_PLAIN or LT_EXEC_GROUPED         */
+    int32_t dry_run;                /* 1: plan and simulate memory only; no
+                                       device memory is touched, no kernel runs,
+                                       array contents are unavailable          */
+    uint64_t device_budget_bytes;   /* cap on device bytes held by chunks and
+                                       temporaries (Sec. 3.4); default 8 GiB    */
+    uint64_t stage_threshold_bytes; /* cap on the summed footprint of tasks
+                                       staged ahead of execution (Sec. 3.4);
+                                       default 2e9; one task is always admitted */
+    void *device_arena;             /* optional borrowed device buffer to carve
+                                       chunks from (e.g. a torch tensor); must
+                                       outlive the context; NULL = the runtime
+                                       allocates its own on first use           */
+    uint64_t arena_bytes;           /* size of device_arena                     */
+    int32_t trace;                  /* 1: record a per-operation trace          */
+    int32_t reserved[7];
+} lt_config;
+
+/* Fills *cfg with defaults. */
+void lt_config_init(lt_config *cfg);
+
+/* Creates a context on cfg->device.  cfg may be NULL (defaults).
+ * Errors: LT_ERR_INVALID (bad config), LT_ERR_DEVICE (HIP init failed). */
+lt_status lt_context_create(const lt_config *cfg, lt_context **out);
+
+/* Waits for all work, releases every array, kernel and pool of the context.
+ * Returns the first sticky error, if any. */
+lt_status lt_context_destroy(lt_context *ctx);
+
+/* Message of the last error on ctx; "" if none.  ctx may be NULL for errors
+ * of lt_context_create. */
+const char *lt_last_error(lt_context *ctx);
+
+/* ------------------------------------------------------------ distributions
+ * A distribution policy splits an array's domain into rectangular chunks
+ * that cover it (Sec. 2.2):
+ *   LT_DIST_BLOCK  chunks of chunk[a] elements along each axis a (0 = whole
+ *                  axis): row-wise = {r, 0}, column-wise = {0, c},
+ *                  tiled = {r, c}.  Edge chunks may be short.
+ *   LT_DIST_CUSTOM nboxes explicit boxes; they must be disjoint, lie inside
+ *                  the domain and cover it.
+ * Overlapping (halo) chunks are not supported by this build: a halo read is
+ * resolved from neighbouring chunks instead (a region spanning several
+ * chunks, Sec. 2.4).
+ */
+#define LT_DIST_BLOCK 0
+#define LT_DIST_CUSTOM 1
+
+typedef struct lt_box {
+    int64_t lo[3];
+    int64_t hi[3];
+} lt_box;
+
+typedef struct lt_dist {
+    int32_t kind;
+    int32_t nboxes;       /* LT_DIST_CUSTOM                          */
+    int64_t chunk[3];     /* LT_DIST_BLOCK; unused axes ignored       */
+    const lt_box *boxes;  /* LT_DIST_CUSTOM; copied at array creation */
+} lt_dist;
+
+/* ------------------------------------------------------------------- arrays
+ * lt_array_create: a device-home array.  Its chunks live in device memory and
+ *   spill to runtime-owned pinned host memory when the budget is exceeded.
+ *   Contents are undefined until written or filled.  dist NULL = one chunk.
+ * lt_array_create_host: a host-backed array whose home is the caller's
+ *   buffer host_ptr (row-major, shape[] elements).  host_ptr is BORROWED for
+ *   the array's lifetime; it should be pinned (lt_host_alloc) for
+ *   asynchronous copies.  The buffer holds the array's contents after
+ *   lt_sync; chunks are loaded on demand and written back when evicted.
+ * Errors: LT_ERR_INVALID (ndim not in 1..3, shape <= 0, dtype, dist),
+ *         LT_ERR_OOM, LT_ERR_BUDGET (creation of an array whose single chunk
+ *         exceeds the device budget is allowed; launching on it is not).
+ */
+lt_status lt_array_create(lt_context *ctx, lt_dtype dtype, int32_t ndim,
+                          const int64_t *shape, const lt_dist *dist,
+                          lt_array **out);
+lt_status lt_array_create_host(lt_context *ctx, lt_dtype dtype, int32_t ndim,
+                               const int64_t *shape, const lt_dist *dist,
+                               void *host_ptr, lt_array **out);
+
+/* Releases the array once all launches issued before this call that use it
+ * have completed (the release itself does not block). */
+lt_status lt_array_destroy(lt_context *ctx, lt_array *arr);
+
+/* Copies the whole array from host memory src (row-major).  Ordered after
+ * earlier launches; src is fully consumed when the call returns. */
+lt_status lt_array_write(lt_context *ctx, lt_array *arr, const void *src);
+
+/* Copies the whole array into host memory dst (row-major).  Blocks until all
+ * earlier launches that write the array have finished. */
+lt_status lt_array_read(lt_context *ctx, lt_array *arr, void *dst);
+
+/* Sets every element to *scalar (one element of the array's dtype). */
+lt_status lt_array_fill(lt_context *ctx, lt_array *arr, const void *scalar);
+
+/* Device-memory variants of write/read for arrays that live in device memory
+ * elsewhere (e.g. a torch tensor): src/dst are device pointers to a
+ * row-major buffer of the whole array.  Ordered like write/read; read blocks. */
+lt_status lt_array_write_device(lt_context *ctx, lt_array *arr, const void *src);
+lt_status lt_array_read_device(lt_context *ctx, lt_array *arr, void *dst);
+
+/* Pinned host memory for host-backed arrays and fast transfers. */
+lt_status lt_host_alloc(lt_context *ctx, uint64_t bytes, void **out);
+lt_status lt_host_free(lt_context *ctx, void *ptr);
+
+/* ------------------------------------------------------------------ kernels
+ * Built-in kernels, each with its parameter list and default annotation
+ * (the role of the kernel definition of Sec. 3.6).  Parameter names are what
+ * annotations refer to.  Integer parameters are int64 scalars.
+ *
+ *   touch_i32(n, y)             global i => readwrite y[i]
+ *       y[i] += 1 for i < n (exactly-once probe of the superblock split)
+ *   stencil1d_f32(n, y, x)      global i => read x[i-1:i+1], write y[i]
+ *       y[i] = 0.25*(x[i-1] + x[i+1]) + 0.5*x[i], zero outside [0, n)
+ *   jacobi2d_f32(n, m, y, x)    global [r, c] => read x[r-1:r+1, c-1:c+1], write y[r, c]
+ *       y = 0.25*((up + down) + (left + right)), zero outside the n x m field
+ *   gemm_f32(M, N, K, C, A, B)  global [i, j] => read A[i, :], read B[:, j], write C[i, j]
+ *       C = A B, FP32 inputs, FP32 matrix-core accumulation
+ *   hist256_i32(n, h, v)        global i => read v[i], reduce(+) h[:]
+ *       h[b] = #{i < n : v[i] == b}
+ *   kmeans_assign_f32(N, d, K, lab, X, Cen)
+ *                               global i => read X[i, :], read Cen[:, :], write lab[i]
+ *       lab[i] = argmin_k sum_j (X[i,j] - Cen[k,j])^2, float32 fma chain,
+ *       ties to the smallest k
+ *
+ * lt_kernel_get: the built-in with its default annotation.
+ * lt_kernel_define: the built-in body `base` under another annotation (it must
+ *   still describe every access the body makes; an under-approximating
+ *   annotation gives undefined results, as in the paper).
+ * Errors: LT_ERR_INVALID (unknown name), LT_ERR_PARSE (annotation).
+ */
+lt_status lt_kernel_get(lt_context *ctx, const char *name, lt_kernel **out);
+lt_status lt_kernel_define(lt_context *ctx, const char *base,
+                           const char *annotation, lt_kernel **out);
+
+/* ------------------------------------------------------------------- launch */
+#define LT_ARG_ARRAY 0
+#define LT_ARG_INT 1
+#define LT_ARG_FLOAT 2
+
+typedef struct lt_arg {
+    const char *name;   /* parameter name; NULL = positional          */
+    int32_t kind;       /* LT_ARG_ARRAY / LT_ARG_INT / LT_ARG_FLOAT    */
+    int32_t pad;
+    lt_array *array;
+    int64_t i;
+    double f;
+} lt_arg;
+
+/* Launches kernel k over an ndim-D grid of grid[] threads (rounded up to
+ * whole blocks of block[] threads), split into superblocks of superblock[]
+ * threads (multiples of block[]; 0 = whole axis) (Sec. 2.1).  annotation
+ * NULL = the kernel's own.  Returns immediately; *launch_id (may be NULL)
+ * names the launch for lt_wait.
+ * Errors (synchronous): LT_ERR_PARSE, LT_ERR_INVALID (grid/block/superblock,
+ * arity, dtype, rank), LT_ERR_BUDGET (a task's chunks cannot all be held in
+ * the device budget at once, Sec. 3.4). */
+lt_status lt_launch(lt_context *ctx, lt_kernel *k, int32_t ndim,
+                    const int64_t *grid, const int64_t *block,
+                    const int64_t *superblock, const char *annotation,
+                    const lt_arg *args, int32_t nargs, uint64_t *launch_id);
+
+/* Blocks until every issued launch has finished and host-backed arrays hold
+ * their contents (Sec. 3.6 "synchronize").  Returns and clears the first
+ * sticky device error. */
+lt_status lt_sync(lt_context *ctx);
+
+/* Blocks until launch `launch_id` has finished. */
+lt_status lt_wait(lt_context *ctx, uint64_t launch_id);
+
+/* ----------------------------------------------------------- introspection
+ * Planner output of a launch, for tests and tools.  Task records are kept
+ * until the next lt_sync. */
+#define LT_TASK_EXEC 0
+#define LT_TASK_COMBINE 1
+#define LT_TASK_IO 2
+
+typedef struct lt_task_info {
+    uint64_t id;          /* global task number (program order)           */
+    uint64_t launch;      /* launch id                                    */
+    int32_t kind;         /* LT_TASK_*                                     */
+    int32_t stream;       /* compute stream index it was issued on         */
+    int32_t ndeps;        /* number of predecessor tasks                   */
+    int32_t nregions;     /* number of (array, region) accesses            */
+    int64_t sb_lo[3];     /* superblock thread box (EXEC)                  */
+    int64_t sb_hi[3];
+} lt_task_info;
+
+typedef struct lt_region_info {
+    int32_t arg;          /* kernel parameter index                        */
+    int32_t mode;         /* 0 read, 1 write, 2 readwrite, 3 reduce         */
+    int32_t op;           /* reduce op: 0 +, 1 *, 2 min, 3 max             */
+    int32_t resolved;     /* 0 direct view, 1 assembled/scattered temp,
+                             2 reduction partial                            */
+    uint64_t array_id;
+    int64_t lo[3];        /* clipped access region, half-open             */
+    int64_t hi[3];
+} lt_region_info;
+
+lt_status lt_plan_tasks(lt_context *ctx, uint64_t launch_id,
+                        lt_task_info *out, int32_t cap, int32_t *n);
+lt_status lt_plan_regions(lt_context *ctx, uint64_t task_id,
+                          lt_region_info *out, int32_t cap, int32_t *n);
+lt_status lt_plan_deps(lt_context *ctx, uint64_t task_id, uint64_t *out,
+                       int32_t cap, int32_t *n);
+
+/* Unique id of an array (stable for its lifetime). */
+uint64_t lt_array_id(lt_array *arr);
+
+/* ------------------------------------------------------------------- stats */
+typedef struct lt_stats {
+    uint64_t launches, tasks, dispatches;
+    uint64_t bytes_h2d, bytes_d2h, bytes_d2d;
+    uint64_t copies_h2d, copies_d2h, copies_d2d;
+    uint64_t evictions_clean, evictions_dirty;
+    uint64_t resident_bytes, peak_resident_bytes;
+    uint64_t staged_peak_bytes;    /* high-water mark of the staged footprint */
+    uint64_t throttle_waits;
+    uint64_t assembled_regions, direct_regions;
+    double plan_seconds;           /* host time spent planning and issuing */
+} lt_stats;
+
+lt_status lt_stats_get(lt_context *ctx, lt_stats *out);
+lt_status lt_stats_reset(lt_context *ctx);
+
+/* ------------------------------------------------------------------- trace
+ * With cfg.trace = 1 every device operation is recorded in order:
+ * kind 0 kernel dispatch, 1 H2D, 2 D2H, 3 D2D, 4 fill, 5 evict (no copy),
+ * 6 alloc, 7 free.  `task` is the task id (or ~0), `a`/`b` carry
+ * kind-specific values (bytes, arena offset, chunk id), resident is the
+ * device bytes held after the operation. */
+typedef struct lt_trace_rec {
+    int32_t kind;
+    int32_t stream;
+    uint64_t task;
+    uint64_t chunk;
+    uint64_t bytes;
+    uint64_t offset;
+    uint64_t resident;
+} lt_trace_rec;
+
+lt_status lt_trace_get(lt_context *ctx, lt_trace_rec *out, uint64_t cap,
+                       uint64_t *n);
+lt_status lt_trace_clear(lt_context *ctx);
+
+/* ----------------------------------------------------------------- profile
+ * With profiling on, every kernel dispatch is bracketed by timing events on
+ * the stream it runs on; durations are summed per built-in body and collected
+ * at lt_sync.  Meant for measurement runs (the events add a little overhead).
+ */
+typedef struct lt_kernel_prof {
+    char name[32];
+    uint64_t dispatches;
+    double total_ms;      /* summed device time between the bracketing events */
+    double max_ms;
+} lt_kernel_prof;
+
+lt_status lt_profile_enable(lt_context *ctx, int32_t on);
+lt_status lt_profile_get(lt_context *ctx, lt_kernel_prof *out, int32_t cap,
+                         int32_t *n);
+lt_status lt_profile_reset(lt_context *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LT_H */

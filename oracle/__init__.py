@@ -52,6 +52,7 @@ def lib():
         L.or_kmeans_dist_f64.argtypes = [i64, p, p]
         L.or_kmeans_dist_f64.restype = C.c_double
         L.or_touch_i32.argtypes = [i64, i64, p]
+        L.or_num_threads.restype = i32
         _lib = L
     return _lib
 
@@ -178,6 +179,10 @@ def kmeans_dist64(x: np.ndarray, c: np.ndarray) -> float:
     x = np.ascontiguousarray(x, dtype=np.float32)
     c = np.ascontiguousarray(c, dtype=np.float32)
     return float(lib().or_kmeans_dist_f64(x.size, _ptr(x), _ptr(c)))
+
+
+def num_threads() -> int:
+    return int(lib().or_num_threads())
 
 
 def touch(y: np.ndarray, grid: int) -> np.ndarray:

@@ -218,3 +218,16 @@ void or_touch_i32(int64_t n, int64_t grid, int32_t *y)
     for (int64_t i = 0; i < grid && i < n; ++i)
         y[i] += 1;
 }
+
+/* Number of OpenMP threads the parallel loops above use. */
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+int or_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}

@@ -1,0 +1,395 @@
+"""Python binding of the one-GPU annotated-launch runtime (``liblt.so``).
+
+Argument marshalling only: every planning step runs in the C++ runtime and
+every kernel in hand-written HIP.  The functions keep the C-ABI names
+(``lt_context_create``, ``lt_array_create``, ``lt_launch``, ``lt_sync``...)
+and raise ``LtError`` on a non-zero status.  If the library has not been
+built, importing this package raises: there is no fallback.
+
+A small convenience layer (``Context``, ``Array``) sits on top for tests and
+the benchmark.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblt.so")
+
+LT_OK = 0
+LT_ERR_INVALID = -1
+LT_ERR_PARSE = -2
+LT_ERR_BUDGET = -3
+LT_ERR_OOM = -4
+LT_ERR_DEVICE = -5
+LT_ERR_TIMEOUT = -6
+LT_ERR_UNSUPPORTED = -7
+_ERRNAMES = {-1: "LT_ERR_INVALID", -2: "LT_ERR_PARSE", -3: "LT_ERR_BUDGET", -4: "LT_ERR_OOM",
+             -5: "LT_ERR_DEVICE", -6: "LT_ERR_TIMEOUT", -7: "LT_ERR_UNSUPPORTED"}
+
+LT_F32, LT_I32, LT_F64, LT_I64, LT_U8 = 0, 1, 2, 3, 4
+DTYPES = {LT_F32: np.float32, LT_I32: np.int32, LT_F64: np.float64, LT_I64: np.int64, LT_U8: np.uint8}
+NP2LT = {np.dtype(v): k for k, v in DTYPES.items()}
+
+LT_EXEC_PLAIN, LT_EXEC_GROUPED = 0, 1
+LT_DIST_BLOCK, LT_DIST_CUSTOM = 0, 1
+LT_ARG_ARRAY, LT_ARG_INT, LT_ARG_FLOAT = 0, 1, 2
+LT_TASK_EXEC, LT_TASK_COMBINE, LT_TASK_IO = 0, 1, 2
+
+
+class lt_config(C.Structure):
+    _fields_ = [("device", C.c_int32), ("n_compute_streams", C.c_int32), ("exec_mode", C.c_int32),
+                ("dry_run", C.c_int32), ("device_budget_bytes", C.c_uint64),
+                ("stage_threshold_bytes", C.c_uint64), ("device_arena", C.c_void_p),
+                ("arena_bytes", C.c_uint64), ("trace", C.c_int32), ("reserved", C.c_int32 * 7)]
+
+
+class lt_box(C.Structure):
+    _fields_ = [("lo", C.c_int64 * 3), ("hi", C.c_int64 * 3)]
+
+
+class lt_dist(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("nboxes", C.c_int32), ("chunk", C.c_int64 * 3),
+                ("boxes", C.POINTER(lt_box))]
+
+
+class lt_arg(C.Structure):
+    _fields_ = [("name", C.c_char_p), ("kind", C.c_int32), ("pad", C.c_int32), ("array", C.c_void_p),
+                ("i", C.c_int64), ("f", C.c_double)]
+
+
+class lt_task_info(C.Structure):
+    _fields_ = [("id", C.c_uint64), ("launch", C.c_uint64), ("kind", C.c_int32), ("stream", C.c_int32),
+                ("ndeps", C.c_int32), ("nregions", C.c_int32), ("sb_lo", C.c_int64 * 3),
+                ("sb_hi", C.c_int64 * 3)]
+
+
+class lt_region_info(C.Structure):
+    _fields_ = [("arg", C.c_int32), ("mode", C.c_int32), ("op", C.c_int32), ("resolved", C.c_int32),
+                ("array_id", C.c_uint64), ("lo", C.c_int64 * 3), ("hi", C.c_int64 * 3)]
+
+
+class lt_stats(C.Structure):
+    _fields_ = [(n, C.c_uint64) for n in (
+        "launches", "tasks", "dispatches", "bytes_h2d", "bytes_d2h", "bytes_d2d", "copies_h2d",
+        "copies_d2h", "copies_d2d", "evictions_clean", "evictions_dirty", "resident_bytes",
+        "peak_resident_bytes", "staged_peak_bytes", "throttle_waits", "assembled_regions",
+        "direct_regions")] + [("plan_seconds", C.c_double)]
+
+
+class lt_trace_rec(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("stream", C.c_int32), ("task", C.c_uint64), ("chunk", C.c_uint64),
+                ("bytes", C.c_uint64), ("offset", C.c_uint64), ("resident", C.c_uint64)]
+
+
+class lt_kernel_prof(C.Structure):
+    _fields_ = [("name", C.c_char * 32), ("dispatches", C.c_uint64), ("total_ms", C.c_double),
+                ("max_ms", C.c_double)]
+
+
+class LtError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("%s: %s" % (_ERRNAMES.get(status, str(status)), msg))
+        self.status = status
+
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError("liblt.so is not built (run __graft_entry__.build() or "
+                      "python paper_2202_05549_amd/build.py); there is no fallback path")
+
+_lib = C.CDLL(LIB_PATH)
+
+# (name, restype, argtypes)
+_P = C.c_void_p
+_SIGS = [
+    ("lt_config_init", None, [C.POINTER(lt_config)]),
+    ("lt_context_create", C.c_int32, [C.POINTER(lt_config), C.POINTER(_P)]),
+    ("lt_context_destroy", C.c_int32, [_P]),
+    ("lt_last_error", C.c_char_p, [_P]),
+    ("lt_array_create", C.c_int32, [_P, C.c_int32, C.c_int32, C.POINTER(C.c_int64), C.POINTER(lt_dist),
+                                    C.POINTER(_P)]),
+    ("lt_array_create_host", C.c_int32, [_P, C.c_int32, C.c_int32, C.POINTER(C.c_int64),
+                                         C.POINTER(lt_dist), _P, C.POINTER(_P)]),
+    ("lt_array_destroy", C.c_int32, [_P, _P]),
+    ("lt_array_write", C.c_int32, [_P, _P, _P]),
+    ("lt_array_read", C.c_int32, [_P, _P, _P]),
+    ("lt_array_fill", C.c_int32, [_P, _P, _P]),
+    ("lt_array_write_device", C.c_int32, [_P, _P, _P]),
+    ("lt_array_read_device", C.c_int32, [_P, _P, _P]),
+    ("lt_array_id", C.c_uint64, [_P]),
+    ("lt_host_alloc", C.c_int32, [_P, C.c_uint64, C.POINTER(_P)]),
+    ("lt_host_free", C.c_int32, [_P, _P]),
+    ("lt_kernel_get", C.c_int32, [_P, C.c_char_p, C.POINTER(_P)]),
+    ("lt_kernel_define", C.c_int32, [_P, C.c_char_p, C.c_char_p, C.POINTER(_P)]),
+    ("lt_launch", C.c_int32, [_P, _P, C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_int64),
+                              C.POINTER(C.c_int64), C.c_char_p, C.POINTER(lt_arg), C.c_int32,
+                              C.POINTER(C.c_uint64)]),
+    ("lt_sync", C.c_int32, [_P]),
+    ("lt_wait", C.c_int32, [_P, C.c_uint64]),
+    ("lt_plan_tasks", C.c_int32, [_P, C.c_uint64, C.POINTER(lt_task_info), C.c_int32, C.POINTER(C.c_int32)]),
+    ("lt_plan_regions", C.c_int32, [_P, C.c_uint64, C.POINTER(lt_region_info), C.c_int32,
+                                    C.POINTER(C.c_int32)]),
+    ("lt_plan_deps", C.c_int32, [_P, C.c_uint64, C.POINTER(C.c_uint64), C.c_int32, C.POINTER(C.c_int32)]),
+    ("lt_stats_get", C.c_int32, [_P, C.POINTER(lt_stats)]),
+    ("lt_stats_reset", C.c_int32, [_P]),
+    ("lt_trace_get", C.c_int32, [_P, C.POINTER(lt_trace_rec), C.c_uint64, C.POINTER(C.c_uint64)]),
+    ("lt_trace_clear", C.c_int32, [_P]),
+    ("lt_profile_enable", C.c_int32, [_P, C.c_int32]),
+    ("lt_profile_get", C.c_int32, [_P, C.POINTER(lt_kernel_prof), C.c_int32, C.POINTER(C.c_int32)]),
+    ("lt_profile_reset", C.c_int32, [_P]),
+]
+
+for _name, _res, _args in _SIGS:
+    _fn = getattr(_lib, _name)
+    _fn.restype = _res
+    _fn.argtypes = _args
+    globals()[_name] = _fn
+
+
+def exported_symbols():
+    """Names the binding resolves in liblt.so."""
+    return [s[0] for s in _SIGS]
+
+
+def check(ctx, st):
+    if st != LT_OK:
+        msg = lt_last_error(ctx)
+        raise LtError(st, msg.decode() if msg else "")
+    return st
+
+
+def _i64(vals, n=3, fill=0):
+    arr = (C.c_int64 * n)()
+    for i in range(n):
+        arr[i] = int(vals[i]) if i < len(vals) else fill
+    return arr
+
+
+def make_dist(chunk=None, boxes=None):
+    """BLOCK distribution with per-axis chunk extents (0 = whole axis), or a
+    CUSTOM distribution from half-open boxes [(lo, hi), ...]."""
+    d = lt_dist()
+    if boxes is not None:
+        arr = (lt_box * len(boxes))()
+        for i, (lo, hi) in enumerate(boxes):
+            for a in range(3):
+                arr[i].lo[a] = lo[a] if a < len(lo) else 0
+                arr[i].hi[a] = hi[a] if a < len(hi) else 1
+        d.kind = LT_DIST_CUSTOM
+        d.nboxes = len(boxes)
+        d.boxes = arr
+        d._keep = arr
+    else:
+        d.kind = LT_DIST_BLOCK
+        for a in range(3):
+            d.chunk[a] = (chunk[a] if chunk is not None and a < len(chunk) else 0)
+    return d
+
+
+class Array:
+    """An lt_array handle with its numpy dtype and shape."""
+
+    def __init__(self, ctx: "Context", handle, dtype, shape, host=None):
+        self.ctx = ctx
+        self.h = handle
+        self.dtype = np.dtype(dtype)
+        self.shape = tuple(int(s) for s in shape)
+        self.host = host  # keeps a host-backed buffer alive
+
+    @property
+    def id(self):
+        return int(lt_array_id(self.h))
+
+    @property
+    def nbytes(self):
+        return int(np.prod(self.shape)) * self.dtype.itemsize
+
+    def write(self, a: np.ndarray):
+        a = np.ascontiguousarray(a, dtype=self.dtype)
+        assert a.shape == self.shape
+        check(self.ctx.h, lt_array_write(self.ctx.h, self.h, a.ctypes.data))
+
+    def read(self) -> np.ndarray:
+        out = np.empty(self.shape, self.dtype)
+        check(self.ctx.h, lt_array_read(self.ctx.h, self.h, out.ctypes.data))
+        return out
+
+    def fill(self, value):
+        v = np.array(value, dtype=self.dtype)
+        check(self.ctx.h, lt_array_fill(self.ctx.h, self.h, v.ctypes.data))
+
+    def write_device(self, ptr: int):
+        check(self.ctx.h, lt_array_write_device(self.ctx.h, self.h, C.c_void_p(ptr)))
+
+    def read_device(self, ptr: int):
+        check(self.ctx.h, lt_array_read_device(self.ctx.h, self.h, C.c_void_p(ptr)))
+
+    def destroy(self):
+        if self.h:
+            check(self.ctx.h, lt_array_destroy(self.ctx.h, self.h))
+            self.h = None
+
+
+class Context:
+    """An lt_context with keyword configuration (see lt_config in lt.h)."""
+
+    def __init__(self, **cfg):
+        c = lt_config()
+        lt_config_init(C.byref(c))
+        for k, v in cfg.items():
+            if k == "device_arena":
+                v = C.c_void_p(v)
+            setattr(c, k, v)
+        h = _P()
+        st = lt_context_create(C.byref(c), C.byref(h))
+        if st != LT_OK:
+            raise LtError(st, lt_last_error(None).decode())
+        self.h = h
+        self.cfg = c
+        self._kernels = {}
+
+    def close(self):
+        if self.h:
+            st = lt_context_destroy(self.h)
+            self.h = None
+            if st != LT_OK:
+                raise LtError(st, "context destroy")
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            if getattr(self, "h", None):
+                lt_context_destroy(self.h)
+                self.h = None
+        except Exception:
+            pass
+
+    def array(self, shape, dtype=np.float32, chunk=None, boxes=None) -> Array:
+        shape = tuple(shape)
+        dt = NP2LT[np.dtype(dtype)]
+        d = make_dist(chunk, boxes)
+        h = _P()
+        check(self.h, lt_array_create(self.h, dt, len(shape), _i64(shape, len(shape)), C.byref(d), C.byref(h)))
+        return Array(self, h, dtype, shape)
+
+    def array_host(self, buf: np.ndarray, chunk=None, boxes=None) -> Array:
+        """Host-backed array over ``buf`` (kept alive by the handle)."""
+        assert buf.flags["C_CONTIGUOUS"]
+        dt = NP2LT[buf.dtype]
+        d = make_dist(chunk, boxes)
+        h = _P()
+        check(self.h, lt_array_create_host(self.h, dt, buf.ndim, _i64(buf.shape, buf.ndim), C.byref(d),
+                                           C.c_void_p(buf.ctypes.data), C.byref(h)))
+        return Array(self, h, buf.dtype, buf.shape, host=buf)
+
+    def pinned(self, shape, dtype=np.float32) -> np.ndarray:
+        """A numpy view of pinned host memory owned by the context."""
+        nbytes = int(np.prod(shape)) * np.dtype(dtype).itemsize
+        p = _P()
+        check(self.h, lt_host_alloc(self.h, nbytes, C.byref(p)))
+        buf = (C.c_char * nbytes).from_address(p.value)
+        return np.frombuffer(buf, dtype=dtype).reshape(shape)
+
+    def kernel(self, name, annotation=None):
+        key = (name, annotation)
+        if key not in self._kernels:
+            k = _P()
+            if annotation is None:
+                check(self.h, lt_kernel_get(self.h, name.encode(), C.byref(k)))
+            else:
+                check(self.h, lt_kernel_define(self.h, name.encode(), annotation.encode(), C.byref(k)))
+            self._kernels[key] = k
+        return self._kernels[key]
+
+    def launch(self, name, grid, block, superblock=None, args=(), annotation=None, kernel_annotation=None):
+        """Launch built-in ``name``.  ``args`` is a sequence of Array, int or
+        float (positional), or (name, value) pairs."""
+        k = self.kernel(name, kernel_annotation)
+        nd = len(grid)
+        A = (lt_arg * max(1, len(args)))()
+        for i, a in enumerate(args):
+            nm = None
+            if isinstance(a, tuple):
+                nm, a = a
+            A[i].name = nm.encode() if nm else None
+            if isinstance(a, Array):
+                A[i].kind = LT_ARG_ARRAY
+                A[i].array = a.h
+            elif isinstance(a, (int, np.integer)):
+                A[i].kind = LT_ARG_INT
+                A[i].i = int(a)
+            else:
+                A[i].kind = LT_ARG_FLOAT
+                A[i].f = float(a)
+        lid = C.c_uint64()
+        sb = superblock if superblock is not None else [0] * nd
+        check(self.h, lt_launch(self.h, k, nd, _i64(grid, nd), _i64(block, nd), _i64(sb, nd),
+                                annotation.encode() if annotation else None, A, len(args), C.byref(lid)))
+        return lid.value
+
+    def sync(self):
+        check(self.h, lt_sync(self.h))
+
+    def wait(self, launch_id):
+        check(self.h, lt_wait(self.h, launch_id))
+
+    def stats(self) -> dict:
+        s = lt_stats()
+        check(self.h, lt_stats_get(self.h, C.byref(s)))
+        return {f: getattr(s, f) for f, _ in s._fields_}
+
+    def reset_stats(self):
+        check(self.h, lt_stats_reset(self.h))
+
+    def tasks(self, launch_id):
+        n = C.c_int32()
+        check(self.h, lt_plan_tasks(self.h, launch_id, None, 0, C.byref(n)))
+        buf = (lt_task_info * max(1, n.value))()
+        check(self.h, lt_plan_tasks(self.h, launch_id, buf, n.value, C.byref(n)))
+        return [buf[i] for i in range(n.value)]
+
+    def regions(self, task_id):
+        n = C.c_int32()
+        check(self.h, lt_plan_regions(self.h, task_id, None, 0, C.byref(n)))
+        buf = (lt_region_info * max(1, n.value))()
+        check(self.h, lt_plan_regions(self.h, task_id, buf, n.value, C.byref(n)))
+        return [buf[i] for i in range(n.value)]
+
+    def deps(self, task_id):
+        n = C.c_int32()
+        check(self.h, lt_plan_deps(self.h, task_id, None, 0, C.byref(n)))
+        buf = (C.c_uint64 * max(1, n.value))()
+        check(self.h, lt_plan_deps(self.h, task_id, buf, n.value, C.byref(n)))
+        return [int(buf[i]) for i in range(n.value)]
+
+    def trace(self):
+        n = C.c_uint64()
+        check(self.h, lt_trace_get(self.h, None, 0, C.byref(n)))
+        buf = (lt_trace_rec * max(1, n.value))()
+        check(self.h, lt_trace_get(self.h, buf, n.value, C.byref(n)))
+        return [buf[i] for i in range(n.value)]
+
+    def profile(self, on=True):
+        check(self.h, lt_profile_enable(self.h, 1 if on else 0))
+
+    def profile_reset(self):
+        check(self.h, lt_profile_reset(self.h))
+
+    def profile_get(self) -> dict:
+        n = C.c_int32()
+        check(self.h, lt_profile_get(self.h, None, 0, C.byref(n)))
+        buf = (lt_kernel_prof * max(1, n.value))()
+        check(self.h, lt_profile_get(self.h, buf, n.value, C.byref(n)))
+        return {buf[i].name.decode(): {"dispatches": int(buf[i].dispatches), "total_ms": buf[i].total_ms,
+                                       "max_ms": buf[i].max_ms} for i in range(n.value)}
+
+    def clear_trace(self):
+        check(self.h, lt_trace_clear(self.h))

@@ -1,0 +1,955 @@
+// Launch planning and task issue.
+//
+// lt_launch (Sec. 2.4 "Execution Planner"): the grid is split into
+// superblocks; for each superblock and array argument the annotation gives
+// an access region, which is resolved against the array's chunks:
+//   - a region inside one chunk, or inside a run of chunks that sit next to
+//     each other in device memory with the array's own layout, is handed to
+//     the kernel as a direct view (no copy);
+//   - otherwise a temporary is assembled from the chunks before the kernel
+//     and, for writes, scattered back after it (Sec. 2.4: distributions change
+//     performance, never results).  Temporaries are loaded before a write too
+//     (write-allocate), so elements of the bounding box that the kernel does
+//     not write keep their values;
+//   - a reduce(f) argument gets a private partial per superblock, initialised
+//     to f's identity; one combine task per launch folds the partials into
+//     the target, which is overwritten.
+// Conflict analysis: each chunk remembers its last writer and the readers
+// and reducers since; a new access adds edges for read-after-write,
+// write-after-read/write and reduce/other conflicts (Sec. 2.4), so the
+// incremental DAG is sequentially consistent.  Edges become device-side
+// event waits; the host never blocks while issuing (Sec. 3.3: scheduling
+// overlaps planning; here the GPU's queues run the DAG).
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <climits>
+#include <cstdio>
+
+#include "lt_internal.h"
+
+namespace lt {
+
+namespace {
+
+struct ArgPlan {
+    bool used = false;
+    Mode mode = M_READ;
+    ROp op = R_ADD;
+    Box region;
+    std::vector<Chunk *> chunks;
+};
+
+struct TaskPlan {
+    uint64_t id = 0;
+    Box sb;
+    ArgPlan arg[MAXPARAM];
+    int64_t footprint = 0;
+};
+
+
+struct Partials {       // one reduce argument of one launch
+    int param = -1;
+    ROp op = R_ADD;
+    int64_t off = -1;   // arena offset of the partial block
+    int64_t bytes = 0;
+    int64_t total_elems = 0;
+    Fence ready;        // identity fill done
+    int64_t cursor = 0; // next free element of the block
+    std::vector<CombinePart> parts;
+    std::vector<uint64_t> producers;
+};
+
+double now_s() {
+    return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+// view of `region` backed by memory with element strides `st` whose element
+// `org` sits at byte address `addr`
+KView make_view(char *addr, const int64_t *org, const int64_t *st, int nd, int esz) {
+    KView v;
+    int64_t off = 0;
+    for (int a = 0; a < nd; ++a) off += org[a] * st[a];
+    v.base = (int64_t)(intptr_t)addr - off * esz;
+    for (int a = 0; a < KMAXD; ++a) v.s[a] = a < nd ? st[a] : 0;
+    return v;
+}
+
+// direct view over the chunks of a region, when possible
+bool direct_view(Ctx *ctx, const Array *arr, const std::vector<Chunk *> &ch, KView *v) {
+    for (Chunk *c : ch)
+        if (c->dev_off < 0 || !c->dev_valid) return false;
+    if (ch.size() == 1) {
+        *v = make_view(dev_ptr(ctx, ch[0]), ch[0]->box.lo, ch[0]->dev_stride, arr->ndim, arr->esz);
+        return true;
+    }
+    if (!arr->row_slab) return false;
+    for (size_t i = 0; i + 1 < ch.size(); ++i)
+        if (ch[i + 1]->dev_off != ch[i]->dev_off + ch[i]->bytes || ch[i + 1]->box.lo[0] != ch[i]->box.hi[0])
+            return false;
+    *v = make_view(dev_ptr(ctx, ch[0]), ch[0]->box.lo, ch[0]->dev_stride, arr->ndim, arr->esz);
+    return true;
+}
+
+void add_dep(std::vector<uint64_t> *deps, uint64_t id) {
+    if (id && std::find(deps->begin(), deps->end(), id) == deps->end()) deps->push_back(id);
+}
+
+// dependency edges for one access of `c` (Sec. 2.4 conflicts)
+void conflict_edges(const Chunk *c, Mode m, ROp op, std::vector<uint64_t> *deps) {
+    add_dep(deps, c->last_writer);
+    if (m == M_READ) {
+        for (uint64_t r : c->reducers) add_dep(deps, r);
+        return;
+    }
+    if (m == M_REDUCE) {
+        for (uint64_t r : c->readers) add_dep(deps, r);
+        if (c->reduce_op != (int)op)
+            for (uint64_t r : c->reducers) add_dep(deps, r);
+        return;
+    }
+    for (uint64_t r : c->readers) add_dep(deps, r);
+    for (uint64_t r : c->reducers) add_dep(deps, r);
+}
+
+void record_access(Chunk *c, Mode m, ROp op, uint64_t id) {
+    if (m == M_READ) {
+        c->readers.push_back(id);
+    } else if (m == M_REDUCE) {
+        if (c->reduce_op != (int)op) c->reducers.clear();
+        c->reduce_op = (int)op;
+        c->reducers.push_back(id);
+    } else {
+        c->last_writer = id;
+        c->readers.clear();
+        c->reducers.clear();
+        c->reduce_op = -1;
+    }
+}
+
+Fence task_fence(Ctx *ctx, const std::vector<uint64_t> &deps) {
+    Fence f;
+    for (uint64_t d : deps) {
+        auto it = ctx->tasks.find(d);
+        if (it != ctx->tasks.end() && it->second.seq) f.add(it->second.stream, it->second.seq);
+    }
+    return f;
+}
+
+}  // namespace
+
+static Group &group_of(Ctx *ctx) { return ctx->group; }
+
+static void apply_uses(Ctx *ctx, const std::vector<ChunkUse> &uses, int s, uint64_t p) {
+    for (const ChunkUse &u : uses) {
+        Chunk *c = u.c;
+        c->last_access.add(s, p);
+        if (u.write) {
+            c->data_ready = Fence();
+            c->data_ready.add(s, p);
+            c->host_valid = false;
+            c->defined = true;
+        }
+    }
+    (void)ctx;
+}
+
+static hipEvent_t prof_event(Ctx *ctx) {
+    if (!ctx->prof_pool.empty()) {
+        hipEvent_t e = ctx->prof_pool.back();
+        ctx->prof_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    (void)hipEventCreate(&e);
+    return e;
+}
+
+lt_status prof_begin(Ctx *ctx, int s, const char *name, hipEvent_t *a) {
+    (void)name;
+    *a = nullptr;
+    if (!ctx->prof || ctx->dry) return LT_OK;
+    *a = prof_event(ctx);
+    hipError_t r = hipEventRecord(*a, ctx->streams[s].h);
+    if (r != hipSuccess) return hip_fail(ctx, r, "hipEventRecord(profile)");
+    return LT_OK;
+}
+
+lt_status prof_end(Ctx *ctx, int s, const char *name, hipEvent_t a) {
+    if (!a) return LT_OK;
+    hipEvent_t b = prof_event(ctx);
+    hipError_t r = hipEventRecord(b, ctx->streams[s].h);
+    if (r != hipSuccess) return hip_fail(ctx, r, "hipEventRecord(profile)");
+    ctx->prof_pending.push_back({name, a, b});
+    return LT_OK;
+}
+
+void prof_collect(Ctx *ctx) {
+    for (auto &p : ctx->prof_pending) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+            lt_kernel_prof &k = ctx->prof_acc[p.name];
+            snprintf(k.name, sizeof k.name, "%s", p.name);
+            k.dispatches++;
+            k.total_ms += ms;
+            if (ms > k.max_ms) k.max_ms = ms;
+        }
+        ctx->prof_pool.push_back(p.a);
+        ctx->prof_pool.push_back(p.b);
+    }
+    ctx->prof_pending.clear();
+}
+
+static lt_status dispatch(Ctx *ctx, const KernelDef *def, KLaunch &kl, int s) {
+    ctx->stats.dispatches++;
+    trace_op(ctx, 0, s, kl.ntask ? 0 : ~0ull, 0, (uint64_t)kl.ntask, 0);
+    if (ctx->dry) return LT_OK;
+    kl.stream = ctx->streams[s].h;
+    hipEvent_t pa;
+    lt_status st = prof_begin(ctx, s, def->name, &pa);
+    if (st) return st;
+    hipError_t r = def->fn(kl);
+    if (r != hipSuccess) return hip_fail(ctx, r, def->name);
+    return prof_end(ctx, s, def->name, pa);
+}
+
+lt_status flush_group(Ctx *ctx) {
+    Group &g = group_of(ctx);
+    if (!g.open) return LT_OK;
+    g.open = false;
+    lt_status st = stream_wait(ctx, g.stream, g.wait);
+    if (st) return st;
+    // tasks beyond the kernel's group size go in further dispatches
+    int mg = std::max(1, std::min(g.def->max_group, KMAXG));
+    for (size_t i = 0; i < g.tasks.size(); i += mg) {
+        KLaunch kl = g.proto;
+        kl.ntask = (int)std::min<size_t>(mg, g.tasks.size() - i);
+        kl.tasks = g.tasks.data() + i;
+        st = dispatch(ctx, g.def, kl, g.stream);
+        if (st) return st;
+        bump(ctx, g.stream);
+    }
+    uint64_t p = ctx->streams[g.stream].seq;
+    for (uint64_t id : g.ids) {
+        TaskRec &r = ctx->tasks[id];
+        r.stream = g.stream;
+        r.seq = p;
+    }
+    apply_uses(ctx, g.uses, g.stream, p);
+    g.tasks.clear();
+    g.ids.clear();
+    g.uses.clear();
+    return LT_OK;
+}
+
+static int pick_stream(Ctx *ctx, const Fence &deps) {
+    if (ctx->ncompute == 1) return 0;
+    int only = -1, cnt = 0;
+    for (int s = 0; s < ctx->ncompute; ++s)
+        if (deps.s[s] > ctx->streams[s].done) {
+            only = s;
+            ++cnt;
+        }
+    if (cnt == 1) return only;
+    int s = ctx->rr;
+    ctx->rr = (ctx->rr + 1) % ctx->ncompute;
+    return s;
+}
+
+// Staging throttle (Sec. 3.4): the summed footprint of tasks that have
+// loaded data ahead of their execution stays under the threshold; the copy
+// stream waits for the oldest staged tasks to finish.  One task is always
+// admitted.
+static lt_status throttle(Ctx *ctx, int64_t footprint) {
+    int64_t thr = (int64_t)ctx->cfg.stage_threshold_bytes;
+    while (!ctx->staged.empty() && ctx->staged_bytes + footprint > thr) {
+        auto f = ctx->staged.front();
+        ctx->staged.pop_front();
+        ctx->staged_bytes -= f.second;
+        lt_status st = stream_wait(ctx, ctx->h2d, f.first);
+        if (st) return st;
+        ctx->stats.throttle_waits++;
+    }
+    return LT_OK;
+}
+
+// Makes chunk c resident and valid on the device for an access of mode m
+// that covers `region`.  Device-side prerequisites go into *wait.
+static lt_status stage_chunk(Ctx *ctx, Chunk *c, Mode m, const Box &region,
+                             Fence *wait, bool *staged_copy, int64_t footprint,
+                             const Fence &placed) {
+    const int nd = c->arr->ndim;
+    Fence mem = placed;
+    if (c->dev_off < 0) {
+        Fence f;
+        lt_status st = alloc_chunk(ctx, c, &f);
+        if (st) return st;
+        mem.merge(f);
+        c->dev_valid = false;
+    }
+    if (!c->dev_valid) {
+        lt_status st;
+        bool overwrite = (m == M_WRITE) && region.contains(c->box, nd);
+        if (c->host_valid && c->defined && !overwrite) {
+            if (!*staged_copy) {
+                st = throttle(ctx, footprint);
+                if (st) return st;
+                *staged_copy = true;
+            }
+            Fence f = mem;
+            f.merge(c->host_ready);
+            st = stream_wait(ctx, ctx->h2d, f);
+            if (st) return st;
+            int64_t ext[MAXD];
+            for (int a = 0; a < MAXD; ++a) ext[a] = c->box.hi[a] - c->box.lo[a];
+            st = copy_box(ctx, ctx->h2d, dev_ptr(ctx, c), c->dev_stride, c->host_ptr, c->host_stride, ext,
+                          nd, c->arr->esz, hipMemcpyHostToDevice);
+            if (st) return st;
+            uint64_t p = bump(ctx, ctx->h2d);
+            trace_op(ctx, 1, ctx->h2d, ~0ull, c->id, c->bytes, c->dev_off);
+            c->data_ready = Fence();
+            c->data_ready.add(ctx->h2d, p);
+            c->last_access = mem;
+            c->last_access.add(ctx->h2d, p);
+        } else {
+            c->data_ready = mem;
+            c->last_access = mem;
+        }
+        c->dev_valid = true;
+    }
+    wait->merge(c->data_ready);
+    // a write must also follow every earlier use of the memory
+    if (m != M_READ) wait->merge(c->last_access);
+    c->lru = ++ctx->lru_clock;
+    return LT_OK;
+}
+
+struct Temp {
+    int param;
+    int64_t off;
+    Box region;
+    int64_t stride[MAXD];
+    std::vector<Chunk *> chunks;
+    bool scatter;
+};
+
+static lt_status copy_region(Ctx *ctx, int s, Chunk *c, const Temp &t, int esz, int nd, bool to_temp) {
+    Box o = intersect(c->box, t.region, nd);
+    if (o.empty(nd)) return LT_OK;
+    int64_t coff = 0, toff = 0, ext[MAXD];
+    for (int a = 0; a < MAXD; ++a) {
+        int64_t lo = a < nd ? o.lo[a] : 0;
+        coff += (lo - (a < nd ? c->box.lo[a] : 0)) * c->dev_stride[a];
+        toff += (lo - (a < nd ? t.region.lo[a] : 0)) * t.stride[a];
+        ext[a] = a < nd ? o.hi[a] - o.lo[a] : 1;
+    }
+    char *cp = dev_ptr(ctx, c) + coff * esz;
+    char *tp = ctx->arena_base + t.off + toff * esz;
+    if (to_temp)
+        return copy_box(ctx, s, tp, t.stride, cp, c->dev_stride, ext, nd, esz, hipMemcpyDeviceToDevice);
+    return copy_box(ctx, s, cp, c->dev_stride, tp, t.stride, ext, nd, esz, hipMemcpyDeviceToDevice);
+}
+
+static void identity_bytes(lt_dtype dt, ROp op, unsigned char *out, int *esz) {
+    if (dt == LT_F32) {
+        float v = op == R_ADD ? 0.f : op == R_MUL ? 1.f : op == R_MIN ? INFINITY : -INFINITY;
+        memcpy(out, &v, 4);
+        *esz = 4;
+    } else if (dt == LT_I32) {
+        int32_t v = op == R_ADD ? 0 : op == R_MUL ? 1 : op == R_MIN ? INT32_MAX : INT32_MIN;
+        memcpy(out, &v, 4);
+        *esz = 4;
+    } else if (dt == LT_F64) {
+        double v = op == R_ADD ? 0. : op == R_MUL ? 1. : op == R_MIN ? INFINITY : -INFINITY;
+        memcpy(out, &v, 8);
+        *esz = 8;
+    } else {
+        int64_t v = op == R_ADD ? 0 : op == R_MUL ? 1 : op == R_MIN ? INT64_MAX : INT64_MIN;
+        memcpy(out, &v, 8);
+        *esz = 8;
+    }
+}
+
+static lt_status issue_exec(Ctx *ctx, lt_kernel *k, TaskPlan &tp, uint64_t L,
+                            const KLaunch &proto, Array **arrs, std::vector<Partials> &parts,
+                            int nd) {
+    const KernelDef *def = k->def;
+    Group &g = group_of(ctx);
+    TaskRec rec;
+    rec.id = tp.id;
+    rec.launch = L;
+    rec.kind = LT_TASK_EXEC;
+    rec.sb = tp.sb;
+
+    // conflict analysis
+    bool has_reduce = false;
+    for (int p = 0; p < def->nparam; ++p) {
+        ArgPlan &a = tp.arg[p];
+        if (!a.used) continue;
+        if (a.mode == M_REDUCE) {
+            has_reduce = true;
+            continue;  // the combine task accesses the target
+        }
+        for (Chunk *c : a.chunks) conflict_edges(c, a.mode, a.op, &rec.deps);
+    }
+
+    // can this task join the open group without staging or copies?
+    bool simple = !has_reduce;
+    KTask kt;
+    memset(&kt, 0, sizeof kt);
+    for (int a = 0; a < MAXD; ++a) {
+        kt.lo[a] = tp.sb.lo[a];
+        kt.hi[a] = tp.sb.hi[a];
+    }
+    if (simple)
+        for (int p = 0; p < def->nparam && simple; ++p) {
+            ArgPlan &a = tp.arg[p];
+            if (!a.used) continue;
+            if (!direct_view(ctx, arrs[p], a.chunks, &kt.v[p])) simple = false;
+        }
+    bool in_group = false;
+    if (simple && ctx->cfg.exec_mode == LT_EXEC_GROUPED && g.open && g.launch == L && g.def == def) {
+        in_group = true;
+        for (uint64_t d : rec.deps)
+            if (std::find(g.ids.begin(), g.ids.end(), d) != g.ids.end()) in_group = false;
+    }
+    lt_status st;
+    if (!in_group) {
+        st = flush_group(ctx);
+        if (st) return st;
+    }
+
+    if (simple) {
+        Fence wait = task_fence(ctx, rec.deps);
+        std::vector<ChunkUse> uses;
+        for (int p = 0; p < def->nparam; ++p) {
+            ArgPlan &a = tp.arg[p];
+            if (!a.used) continue;
+            for (Chunk *c : a.chunks) {
+                wait.merge(c->data_ready);
+                if (a.mode != M_READ) wait.merge(c->last_access);
+                c->lru = ++ctx->lru_clock;
+                uses.push_back({c, a.mode != M_READ});
+            }
+            rec.regions.push_back(lt_region_info{p, (int)a.mode, (int)a.op, 0, arrs[p]->id,
+                                                 {a.region.lo[0], a.region.lo[1], a.region.lo[2]},
+                                                 {a.region.hi[0], a.region.hi[1], a.region.hi[2]}});
+            ctx->stats.direct_regions++;
+            for (Chunk *c : a.chunks) record_access(c, a.mode, a.op, tp.id);
+        }
+        if (!g.open) {
+            g.open = true;
+            g.launch = L;
+            g.def = def;
+            g.stream = pick_stream(ctx, wait);
+            g.proto = proto;
+            g.wait = Fence();
+        }
+        g.wait.merge(wait);
+        g.tasks.push_back(kt);
+        g.ids.push_back(tp.id);
+        g.uses.insert(g.uses.end(), uses.begin(), uses.end());
+        ctx->tasks[tp.id] = rec;
+        if (ctx->cfg.exec_mode != LT_EXEC_GROUPED || (int)g.tasks.size() >= std::min(def->max_group, KMAXG))
+            return flush_group(ctx);
+        return LT_OK;
+    }
+
+    // ---- general path: staging, temporaries, partials
+    Fence wait = task_fence(ctx, rec.deps);
+    std::vector<Chunk *> pinned;
+    for (int p = 0; p < def->nparam; ++p)
+        for (Chunk *c : tp.arg[p].chunks) {
+            c->pin++;
+            pinned.push_back(c);
+        }
+    auto unpin = [&]() {
+        for (Chunk *c : pinned) c->pin--;
+    };
+    bool staged_copy = false;
+    std::vector<ChunkUse> uses;
+    for (int p = 0; p < def->nparam; ++p) {
+        ArgPlan &a = tp.arg[p];
+        if (!a.used || a.mode == M_REDUCE) continue;
+        Fence placed;
+        if (a.chunks.size() > 1 && arrs[p]->row_slab) {
+            st = place_run(ctx, a.chunks, &placed);
+            if (st) {
+                unpin();
+                return st;
+            }
+        }
+        for (Chunk *c : a.chunks) {
+            st = stage_chunk(ctx, c, a.mode, a.region, &wait, &staged_copy, tp.footprint, placed);
+            if (st) {
+                unpin();
+                return st;
+            }
+            uses.push_back({c, a.mode != M_READ});
+        }
+    }
+    // views: direct, assembled temporaries, partials
+    std::vector<Temp> temps;
+    for (int p = 0; p < def->nparam; ++p) {
+        ArgPlan &a = tp.arg[p];
+        if (!a.used) continue;
+        Array *arr = arrs[p];
+        int resolved = 0;
+        if (a.mode == M_REDUCE) {
+            Partials *P = nullptr;
+            for (auto &x : parts)
+                if (x.param == p) P = &x;
+            // this superblock's partial
+            CombinePart cp;
+            cp.off = P->cursor;
+            P->cursor += a.region.volume(arr->ndim);
+            for (int d = 0; d < KMAXD; ++d) {
+                cp.lo[d] = a.region.lo[d];
+                cp.hi[d] = a.region.hi[d];
+            }
+            int64_t st_[MAXD];
+            int64_t s = 1;
+            for (int d = MAXD - 1; d >= 0; --d) {
+                st_[d] = s;
+                s *= d < arr->ndim ? a.region.hi[d] - a.region.lo[d] : 1;
+            }
+            kt.v[p] = make_view(ctx->arena_base + P->off + cp.off * arr->esz, a.region.lo, st_, arr->ndim, arr->esz);
+            P->parts.push_back(cp);
+            P->producers.push_back(tp.id);
+            wait.merge(P->ready);
+            resolved = 2;
+        } else if (direct_view(ctx, arr, a.chunks, &kt.v[p])) {
+            resolved = 0;
+            ctx->stats.direct_regions++;
+        } else {
+            Temp t;
+            t.param = p;
+            t.region = a.region;
+            t.chunks = a.chunks;
+            t.scatter = a.mode != M_READ;
+            int64_t s = 1;
+            for (int d = MAXD - 1; d >= 0; --d) {
+                t.stride[d] = s;
+                s *= d < arr->ndim ? a.region.hi[d] - a.region.lo[d] : 1;
+            }
+            Fence mem;
+            st = alloc_range(ctx, (a.region.volume(arr->ndim) * arr->esz + 255) / 256 * 256, 2, nullptr,
+                             &t.off, &mem);
+            if (st) {
+                unpin();
+                return st;
+            }
+            wait.merge(mem);
+            kt.v[p] = make_view(ctx->arena_base + t.off, a.region.lo, t.stride, arr->ndim, arr->esz);
+            temps.push_back(t);
+            resolved = 1;
+            ctx->stats.assembled_regions++;
+        }
+        rec.regions.push_back(lt_region_info{p, (int)a.mode, (int)a.op, resolved, arr->id,
+                                             {a.region.lo[0], a.region.lo[1], a.region.lo[2]},
+                                             {a.region.hi[0], a.region.hi[1], a.region.hi[2]}});
+    }
+    int s = pick_stream(ctx, wait);
+    st = stream_wait(ctx, s, wait);
+    if (st) {
+        unpin();
+        return st;
+    }
+    // assemble (also for writes: write-allocate)
+    for (Temp &t : temps) {
+        Array *arr = arrs[t.param];
+        for (Chunk *c : t.chunks) {
+            st = copy_region(ctx, s, c, t, arr->esz, arr->ndim, true);
+            if (st) {
+                unpin();
+                return st;
+            }
+        }
+        if (!t.chunks.empty()) bump(ctx, s);
+    }
+    KLaunch kl = proto;
+    kl.ntask = 1;
+    kl.tasks = &kt;
+    st = dispatch(ctx, def, kl, s);
+    if (st) {
+        unpin();
+        return st;
+    }
+    bump(ctx, s);
+    for (Temp &t : temps) {
+        if (!t.scatter) continue;
+        Array *arr = arrs[t.param];
+        for (Chunk *c : t.chunks) {
+            st = copy_region(ctx, s, c, t, arr->esz, arr->ndim, false);
+            if (st) {
+                unpin();
+                return st;
+            }
+        }
+        bump(ctx, s);
+    }
+    uint64_t pt = ctx->streams[s].seq;
+    rec.stream = s;
+    rec.seq = pt;
+    for (int p = 0; p < def->nparam; ++p) {
+        ArgPlan &a = tp.arg[p];
+        if (!a.used || a.mode == M_REDUCE) continue;
+        for (Chunk *c : a.chunks) record_access(c, a.mode, a.op, tp.id);
+    }
+    apply_uses(ctx, uses, s, pt);
+    Fence done;
+    done.add(s, pt);
+    for (Temp &t : temps) ctx->arena.release(t.off, done);
+    if (staged_copy) {
+        ctx->staged.push_back({done, tp.footprint});
+        ctx->staged_bytes += tp.footprint;
+        ctx->stats.staged_peak_bytes = std::max<uint64_t>(ctx->stats.staged_peak_bytes, ctx->staged_bytes);
+    }
+    unpin();
+    ctx->tasks[tp.id] = rec;
+    return LT_OK;
+}
+
+// One combine task per reduce argument of a launch: the target region (the
+// union of the partial boxes) is overwritten by the fold of the partials.
+static lt_status issue_combine(Ctx *ctx, Partials &P, Array *arr, uint64_t L) {
+    const int nd = arr->ndim;
+    if (P.parts.empty()) return LT_OK;
+    Box U;
+    for (int a = 0; a < MAXD; ++a) {
+        U.lo[a] = P.parts[0].lo[a];
+        U.hi[a] = P.parts[0].hi[a];
+    }
+    for (auto &q : P.parts) {
+        Box b;
+        for (int a = 0; a < MAXD; ++a) {
+            b.lo[a] = q.lo[a];
+            b.hi[a] = q.hi[a];
+        }
+        U = bbox_union(U, b, nd);
+    }
+    TaskRec rec;
+    rec.id = ctx->next_task_id++;
+    rec.launch = L;
+    rec.kind = LT_TASK_COMBINE;
+    rec.sb = U;
+    std::vector<Chunk *> ch;
+    chunks_overlapping(arr, U, &ch);
+    for (uint64_t pid : P.producers) add_dep(&rec.deps, pid);
+    for (Chunk *c : ch) conflict_edges(c, M_WRITE, R_ADD, &rec.deps);
+    lt_status st = flush_group(ctx);
+    if (st) return st;
+    Fence wait = task_fence(ctx, rec.deps);
+    for (Chunk *c : ch) c->pin++;
+    bool staged_copy = false;
+    std::vector<ChunkUse> uses;
+    Fence placed;
+    if (ch.size() > 1 && arr->row_slab) {
+        st = place_run(ctx, ch, &placed);
+        if (st) {
+            for (Chunk *x : ch) x->pin--;
+            return st;
+        }
+    }
+    for (Chunk *c : ch) {
+        st = stage_chunk(ctx, c, M_WRITE, U, &wait, &staged_copy, 0, placed);
+        if (st) {
+            for (Chunk *x : ch) x->pin--;
+            return st;
+        }
+        uses.push_back({c, true});
+    }
+    KView tv;
+    Temp t;
+    bool tmp = false;
+    if (!direct_view(ctx, arr, ch, &tv)) {
+        tmp = true;
+        t.param = 0;
+        t.region = U;
+        t.chunks = ch;
+        t.scatter = true;
+        int64_t s = 1;
+        for (int d = MAXD - 1; d >= 0; --d) {
+            t.stride[d] = s;
+            s *= d < nd ? U.hi[d] - U.lo[d] : 1;
+        }
+        Fence mem;
+        st = alloc_range(ctx, (U.volume(nd) * arr->esz + 255) / 256 * 256, 2, nullptr, &t.off, &mem);
+        if (st) {
+            for (Chunk *x : ch) x->pin--;
+            return st;
+        }
+        wait.merge(mem);
+        tv = make_view(ctx->arena_base + t.off, U.lo, t.stride, nd, arr->esz);
+        ctx->stats.assembled_regions++;
+    }
+    int s = pick_stream(ctx, wait);
+    st = stream_wait(ctx, s, wait);
+    if (!st && tmp) {
+        for (Chunk *c : ch)
+            if (!st) st = copy_region(ctx, s, c, t, arr->esz, nd, true);
+        bump(ctx, s);
+    }
+    for (size_t i = 0; i < P.parts.size() && !st; i += KMAXPART) {
+        CombineArgs ca;
+        memset(&ca, 0, sizeof ca);
+        ca.ndim = nd;
+        ca.dtype = arr->dtype;
+        ca.op = P.op;
+        ca.accumulate = i > 0;
+        for (int a = 0; a < KMAXD; ++a) {
+            ca.lo[a] = a < nd ? U.lo[a] : 0;
+            ca.hi[a] = a < nd ? U.hi[a] : 1;
+        }
+        ca.target = tv;
+        ca.part_base = (int64_t)(intptr_t)(ctx->arena_base + P.off);
+        ca.nparts = (int)std::min<size_t>(KMAXPART, P.parts.size() - i);
+        for (int j = 0; j < ca.nparts; ++j) ca.parts[j] = P.parts[i + j];
+        ctx->stats.dispatches++;
+        trace_op(ctx, 0, s, rec.id, 0, ca.nparts, 0);
+        if (!ctx->dry) {
+            hipError_t r = launch_combine(ctx->streams[s].h, ca);
+            if (r != hipSuccess) st = hip_fail(ctx, r, "combine");
+        }
+        bump(ctx, s);
+    }
+    if (!st && tmp) {
+        for (Chunk *c : ch)
+            if (!st) st = copy_region(ctx, s, c, t, arr->esz, nd, false);
+        bump(ctx, s);
+    }
+    for (Chunk *x : ch) x->pin--;
+    if (st) return st;
+    uint64_t pt = ctx->streams[s].seq;
+    rec.stream = s;
+    rec.seq = pt;
+    for (Chunk *c : ch) record_access(c, M_WRITE, R_ADD, rec.id);
+    apply_uses(ctx, uses, s, pt);
+    Fence done;
+    done.add(s, pt);
+    if (tmp) ctx->arena.release(t.off, done);
+    ctx->arena.release(P.off, done);
+    rec.regions.push_back(lt_region_info{P.param, (int)M_REDUCE, (int)P.op, tmp ? 1 : 0, arr->id,
+                                         {U.lo[0], U.lo[1], U.lo[2]}, {U.hi[0], U.hi[1], U.hi[2]}});
+    ctx->tasks[rec.id] = rec;
+    ctx->launch_tasks[L].push_back(rec.id);
+    return LT_OK;
+}
+
+lt_status launch(Ctx *ctx, lt_kernel *k, int nd, const int64_t *grid,
+                 const int64_t *block, const int64_t *sb, const char *annotation,
+                 const lt_arg *args, int nargs, uint64_t *launch_id) {
+    double t0 = now_s();
+    if (!k || !k->def) return set_err(ctx, LT_ERR_INVALID, "NULL kernel");
+    const KernelDef *def = k->def;
+    if (ctx->sticky != LT_OK)
+        return set_err(ctx, ctx->sticky, "earlier asynchronous error: %s", ctx->sticky_msg.c_str());
+    std::shared_ptr<Annotation> an = k->annot;
+    if (annotation) {
+        lt_status st = compile_annotation(ctx, def, annotation, &an);
+        if (st) return st;
+    }
+    // bind arguments
+    if (nargs != def->nparam)
+        return set_err(ctx, LT_ERR_INVALID, "%s takes %d arguments, got %d", def->name, def->nparam, nargs);
+    Array *arrs[MAXPARAM] = {nullptr};
+    int64_t iparams[MAXPARAM] = {0};
+    double fparams[MAXPARAM] = {0};
+    bool bound[MAXPARAM] = {false};
+    for (int i = 0; i < nargs; ++i) {
+        int p = i;
+        if (args[i].name) {
+            p = -1;
+            for (int q = 0; q < def->nparam; ++q)
+                if (!strcmp(args[i].name, def->params[q].name)) p = q;
+            if (p < 0) return set_err(ctx, LT_ERR_INVALID, "%s has no parameter '%s'", def->name, args[i].name);
+        }
+        if (bound[p]) return set_err(ctx, LT_ERR_INVALID, "parameter '%s' given twice", def->params[p].name);
+        bound[p] = true;
+        const ParamDef &pd = def->params[p];
+        if (pd.kind == P_ARRAY) {
+            if (args[i].kind != LT_ARG_ARRAY || !args[i].array)
+                return set_err(ctx, LT_ERR_INVALID, "parameter '%s' must be an array", pd.name);
+            Array *a = args[i].array;
+            if (a->dead) return set_err(ctx, LT_ERR_INVALID, "array for '%s' was destroyed", pd.name);
+            if (a->dtype != pd.dtype || a->ndim != pd.ndim)
+                return set_err(ctx, LT_ERR_INVALID, "array for '%s' has the wrong dtype or rank", pd.name);
+            arrs[p] = a;
+        } else if (pd.kind == P_INT) {
+            if (args[i].kind != LT_ARG_INT)
+                return set_err(ctx, LT_ERR_INVALID, "parameter '%s' must be an integer", pd.name);
+            iparams[p] = args[i].i;
+        } else {
+            if (args[i].kind == LT_ARG_FLOAT) fparams[p] = args[i].f;
+            else if (args[i].kind == LT_ARG_INT) fparams[p] = (double)args[i].i;
+            else return set_err(ctx, LT_ERR_INVALID, "parameter '%s' must be a number", pd.name);
+        }
+    }
+    if (nd != def->grid_ndim)
+        return set_err(ctx, LT_ERR_INVALID, "%s needs a %d-D grid, got %d-D", def->name, def->grid_ndim, nd);
+    for (int kd = 0; kd < 3; ++kd)
+        if (an->nbound[kd] >= 0 && an->nbound[kd] != nd)
+            return set_err(ctx, LT_ERR_PARSE, "annotation binds %d axes but the grid has %d", an->nbound[kd], nd);
+    int64_t G[MAXD] = {1, 1, 1}, S[MAXD] = {1, 1, 1}, B[MAXD] = {1, 1, 1}, nsb[MAXD] = {1, 1, 1};
+    int64_t total = 1;
+    for (int a = 0; a < nd; ++a) {
+        if (!grid || !block) return set_err(ctx, LT_ERR_INVALID, "grid and block are required");
+        if (grid[a] < 0 || block[a] < 1)
+            return set_err(ctx, LT_ERR_INVALID, "axis %d: grid must be >= 0 and block >= 1", a);
+        B[a] = block[a];
+        G[a] = (grid[a] + B[a] - 1) / B[a] * B[a];
+        int64_t s = sb ? sb[a] : 0;
+        if (s < 0 || (s > 0 && s % B[a] != 0))
+            return set_err(ctx, LT_ERR_INVALID, "axis %d: superblock %lld is not a multiple of block %lld", a,
+                           (long long)s, (long long)B[a]);
+        S[a] = (s == 0 || s > G[a]) ? G[a] : s;
+        nsb[a] = S[a] > 0 ? (G[a] + S[a] - 1) / S[a] : 0;
+        total *= nsb[a];
+    }
+    if (total > ((int64_t)1 << 22)) return set_err(ctx, LT_ERR_INVALID, "too many superblocks (%lld)", (long long)total);
+    // combined access per array parameter
+    Mode pmode[MAXPARAM];
+    ROp pop[MAXPARAM];
+    bool pany[MAXPARAM] = {false};
+    for (auto &ac : an->acc) {
+        int p = ac.param;
+        if (!pany[p]) {
+            pmode[p] = ac.mode;
+            pop[p] = ac.op;
+            pany[p] = true;
+        } else if (pmode[p] == M_REDUCE || ac.mode == M_REDUCE) {
+            if (pmode[p] != ac.mode || pop[p] != ac.op)
+                return set_err(ctx, LT_ERR_PARSE, "array '%s' mixes reductions", def->params[p].name);
+        } else if (pmode[p] != ac.mode) {
+            pmode[p] = M_RW;
+        }
+    }
+    // plan every superblock
+    std::vector<TaskPlan> plans;
+    plans.reserve((size_t)total);
+    int64_t idx[MAXD] = {0, 0, 0};
+    std::unordered_map<Chunk *, int> seen;
+    for (int64_t t = 0; t < total; ++t) {
+        int64_t r = t;
+        for (int a = nd - 1; a >= 0; --a) {
+            idx[a] = r % nsb[a];
+            r /= nsb[a];
+        }
+        TaskPlan tp;
+        int64_t blo[MAXD], bhi[MAXD];
+        for (int a = 0; a < nd; ++a) {
+            tp.sb.lo[a] = idx[a] * S[a];
+            tp.sb.hi[a] = std::min(G[a], tp.sb.lo[a] + S[a]);
+            blo[a] = tp.sb.lo[a] / B[a];
+            bhi[a] = tp.sb.hi[a] / B[a];
+        }
+        VarRange vr;
+        var_ranges(nd, blo, bhi, B, &vr);
+        for (auto &ac : an->acc) {
+            int p = ac.param;
+            Box rg;
+            if (!access_region(ac, nd, B, vr, iparams, arrs[p], &rg)) continue;
+            ArgPlan &a = tp.arg[p];
+            a.region = a.used ? bbox_union(a.region, rg, arrs[p]->ndim) : rg;
+            a.used = true;
+            a.mode = pmode[p];
+            a.op = pop[p];
+        }
+        seen.clear();
+        for (int p = 0; p < def->nparam; ++p) {
+            ArgPlan &a = tp.arg[p];
+            if (!a.used) continue;
+            Array *arr = arrs[p];
+            if (a.mode == M_REDUCE) {
+                tp.footprint += a.region.volume(arr->ndim) * arr->esz;
+                continue;
+            }
+            chunks_overlapping(arr, a.region, &a.chunks);
+            bool multi = a.chunks.size() > 1;
+            for (Chunk *c : a.chunks)
+                if (!seen.count(c)) {
+                    seen[c] = 1;
+                    tp.footprint += (c->bytes + 255) / 256 * 256;
+                }
+            if (multi && !arr->row_slab) tp.footprint += a.region.volume(arr->ndim) * arr->esz + 256;
+        }
+        plans.push_back(std::move(tp));
+    }
+    lt_status st = ensure_arena(ctx);
+    if (st) return st;
+    // partial blocks for reduce arguments
+    std::vector<Partials> parts;
+    int64_t part_bytes = 0;
+    for (int p = 0; p < def->nparam; ++p) {
+        if (def->params[p].kind != P_ARRAY || !pany[p] || pmode[p] != M_REDUCE) continue;
+        Partials P;
+        P.param = p;
+        P.op = pop[p];
+        for (auto &tp : plans)
+            if (tp.arg[p].used) P.total_elems += tp.arg[p].region.volume(arrs[p]->ndim);
+        P.bytes = (P.total_elems * arrs[p]->esz + 255) / 256 * 256;
+        part_bytes += P.bytes;
+        parts.push_back(P);
+    }
+    for (auto &tp : plans)
+        if (tp.footprint + part_bytes > ctx->arena.capacity)
+            return set_err(ctx, LT_ERR_BUDGET,
+                           "a task of %s needs %lld device bytes; the budget is %lld", def->name,
+                           (long long)(tp.footprint + part_bytes), (long long)ctx->arena.capacity);
+    uint64_t L = ctx->next_launch_id++;
+    if (launch_id) *launch_id = L;
+    ctx->stats.launches++;
+    KLaunch proto;
+    memset(&proto, 0, sizeof proto);
+    proto.ndim = nd;
+    for (int p = 0; p < MAXPARAM && p < KMAXP; ++p) {
+        proto.iarg[p] = iparams[p];
+        proto.farg[p] = fparams[p];
+    }
+    for (int a = 0; a < MAXD; ++a) proto.block[a] = B[a];
+    proto.variant = 0;
+    for (auto &P : parts) {
+        if (P.total_elems == 0) continue;
+        st = flush_group(ctx);
+        if (st) return st;
+        Fence mem;
+        st = alloc_range(ctx, P.bytes, 2, nullptr, &P.off, &mem);
+        if (st) return st;
+        int s = 0;
+        st = stream_wait(ctx, s, mem);
+        if (st) return st;
+        unsigned char idv[8];
+        int esz;
+        identity_bytes(arrs[P.param]->dtype, P.op, idv, &esz);
+        trace_op(ctx, 4, s, ~0ull, 0, (uint64_t)P.bytes, (uint64_t)P.off);
+        if (!ctx->dry) {
+            hipError_t r = launch_fill(ctx->streams[s].h, ctx->arena_base + P.off, P.total_elems, esz, idv);
+            if (r != hipSuccess) return hip_fail(ctx, r, "fill");
+        }
+        P.ready.add(s, bump(ctx, s));
+    }
+    std::vector<uint64_t> &lt_ids = ctx->launch_tasks[L];
+    for (auto &tp : plans) {
+        tp.id = ctx->next_task_id++;
+        lt_ids.push_back(tp.id);
+        st = issue_exec(ctx, k, tp, L, proto, arrs, parts, nd);
+        if (st) return st;
+        ctx->stats.tasks++;
+    }
+    st = flush_group(ctx);
+    if (st) return st;
+    for (auto &P : parts) {
+        st = issue_combine(ctx, P, arrs[P.param], L);
+        if (st) return st;
+    }
+    Fence done;
+    for (uint64_t id : ctx->launch_tasks[L]) {
+        auto &r = ctx->tasks[id];
+        done.add(r.stream, r.seq);
+    }
+    ctx->launch_done[L] = done;
+    ctx->stats.plan_seconds += now_s() - t0;
+    return LT_OK;
+}
+
+}  // namespace lt

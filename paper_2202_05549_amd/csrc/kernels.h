@@ -1,0 +1,82 @@
+// Interface between the executor and the hand-written HIP kernels.
+//
+// Every task (superblock) reaches its kernel as a KTask: the superblock's box
+// of global thread indices plus one KView per array parameter.  A view's base
+// address is pre-offset by the origin of the memory that backs the region
+// (a chunk, a run of contiguous chunks, or a temporary), so that the kernel
+// addresses elements with their GLOBAL array indices:
+//     addr(i0, i1, i2) = base + (i0*s0 + i1*s1 + i2*s2) * sizeof(T).
+// This is the paper's wrapper mechanism (Sec. 3.5: the block index is
+// offset once, and array handles subtract the chunk offset once at
+// construction, so element access costs nothing extra).  Kernels only touch
+// elements inside the annotated region of each view.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace lt {
+
+constexpr int KMAXD = 3;
+constexpr int KMAXARR = 6;   // array parameters per kernel
+constexpr int KMAXG = 32;    // tasks per grouped dispatch
+constexpr int KMAXP = 8;     // parameters per kernel
+
+struct KView {
+    int64_t base;            // byte address of element (0, 0, 0); may lie outside the allocation
+    int64_t s[KMAXD];        // element strides
+};
+
+struct KTask {
+    int64_t lo[KMAXD];       // superblock thread box, global indices, half-open
+    int64_t hi[KMAXD];
+    KView v[KMAXP];          // indexed by parameter number (scalars unused)
+};
+
+struct KLaunch {
+    hipStream_t stream;
+    int ndim;
+    int ntask;
+    const KTask *tasks;
+    int64_t iarg[KMAXP];     // int scalar parameters by parameter number
+    double farg[KMAXP];
+    int64_t block[KMAXD];    // logical block shape of the launch
+    int variant;             // tuning variant (0 = default)
+};
+
+typedef hipError_t (*KernelFn)(const KLaunch &);
+
+// Built-in bodies (kernels.hip).
+hipError_t launch_touch_i32(const KLaunch &);
+hipError_t launch_stencil1d_f32(const KLaunch &);
+hipError_t launch_jacobi2d_f32(const KLaunch &);
+hipError_t launch_gemm_f32(const KLaunch &);
+hipError_t launch_hist256_i32(const KLaunch &);
+hipError_t launch_kmeans_assign_f32(const KLaunch &);
+
+// Runtime helpers.
+// Sets `count` elements of size esz (1, 4 or 8 bytes) at dst to *value.
+hipError_t launch_fill(hipStream_t s, void *dst, int64_t count, int esz,
+                       const void *value);
+
+// Reduction combine: target[e] = identity (+ or * or min or max) of every
+// partial p whose box contains e, for e in box `u`.  Partials are dense boxes
+// stored at part_base + part_off[p] elements.  `accumulate` = 1 starts from
+// the target's current value instead of the identity.
+struct CombinePart {
+    int64_t off;             // element offset of the partial
+    int64_t lo[KMAXD], hi[KMAXD];
+};
+constexpr int KMAXPART = 24;
+struct CombineArgs {
+    int ndim, dtype, op, accumulate;
+    int64_t lo[KMAXD], hi[KMAXD];     // union box u
+    KView target;
+    int64_t part_base;               // byte address of the partial block
+    int nparts;
+    CombinePart parts[KMAXPART];
+};
+hipError_t launch_combine(hipStream_t s, const CombineArgs &a);
+
+}  // namespace lt

@@ -1,0 +1,547 @@
+// Hand-written CDNA4 (gfx950) kernels for the built-in task bodies.
+//
+// Every body receives a table of tasks (superblocks).  A dispatch covers one
+// or more tasks; each workgroup locates its task by a search over the
+// per-task block offsets, then works on global indices through pre-offset
+// views (the wrapper scheme of Sec. 3.5).  All float arithmetic is IEEE
+// float32 with round-to-nearest; this file is built with -ffp-contract=off
+// so no multiply-add is fused unless written as fmaf.
+#include <hip/hip_runtime.h>
+
+#include <climits>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+
+#include "kernels.h"
+
+namespace lt {
+
+namespace {
+
+constexpr int WAVE = 64;
+
+template <class T>
+__device__ __forceinline__ T *at(int64_t base, int64_t idx) {
+    return reinterpret_cast<T *>(base) + idx;
+}
+
+// Task lookup: blk_begin[t] <= b < blk_begin[t+1].
+__device__ __forceinline__ int find_task(const int *begin, int ntask, int b) {
+    int lo = 0, hi = ntask - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (begin[mid] <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// Physical workgroups are dealt round-robin to the 8 XCDs.  Remap so each
+// XCD receives a contiguous range of logical tiles (neighbouring tiles share
+// halo rows in that XCD's L2).  Identity on the tail that is not a multiple
+// of 8.
+__device__ __forceinline__ int xcd_remap(int b, int nb) {
+    int per = nb >> 3;
+    if (b >= (per << 3)) return b;
+    return (b & 7) * per + (b >> 3);
+}
+
+inline unsigned grid_of(int64_t blocks) { return (unsigned)blocks; }
+
+}  // namespace
+
+// ==================================================================== touch
+struct TouchTask {
+    int64_t lo, hi;
+    int64_t y;
+};
+struct TouchArgs {
+    int64_t n;
+    int ntask;
+    int begin[KMAXG + 1];
+    TouchTask t[KMAXG];
+};
+
+__global__ __launch_bounds__(256) void k_touch(TouchArgs a) {
+    int ti = find_task(a.begin, a.ntask, blockIdx.x);
+    const TouchTask &t = a.t[ti];
+    int64_t i = t.lo + (int64_t)(blockIdx.x - a.begin[ti]) * 256 + threadIdx.x;
+    if (i < t.hi && i < a.n && i >= 0) *at<int32_t>(t.y, i) += 1;
+}
+
+hipError_t launch_touch_i32(const KLaunch &L) {
+    TouchArgs a;
+    a.n = L.iarg[0];
+    a.ntask = L.ntask;
+    int64_t nb = 0;
+    for (int i = 0; i < L.ntask; ++i) {
+        a.begin[i] = (int)nb;
+        a.t[i].lo = L.tasks[i].lo[0];
+        a.t[i].hi = L.tasks[i].hi[0];
+        a.t[i].y = L.tasks[i].v[1].base;
+        nb += (a.t[i].hi - a.t[i].lo + 255) / 256;
+    }
+    a.begin[L.ntask] = (int)nb;
+    if (nb == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_touch, dim3(grid_of(nb)), dim3(256), 0, L.stream, a);
+    return hipGetLastError();
+}
+
+// ================================================================ stencil1d
+// y[i] = 0.25*(x[i-1] + x[i+1]) + 0.5*x[i], zero outside [0, n).
+// Each thread produces 4 consecutive outputs; neighbours across lanes come
+// from the adjacent lane's registers, the two wave-edge lanes load theirs.
+struct StTask {
+    int64_t lo, hi;
+    int64_t y, x;
+};
+struct StArgs {
+    int64_t n;
+    int ntask;
+    int begin[KMAXG + 1];
+    StTask t[KMAXG];
+};
+
+__device__ __forceinline__ float st_point(float l, float m, float r) {
+    float s = l + r;
+    float t = 0.25f * s;
+    float u = 0.5f * m;
+    return t + u;
+}
+
+__global__ __launch_bounds__(256) void k_stencil1d(StArgs a) {
+    int ti = find_task(a.begin, a.ntask, blockIdx.x);
+    const StTask &t = a.t[ti];
+    const int64_t n = a.n;
+    const int64_t end = t.hi < n ? t.hi : n;          // outputs [lo, end)
+    const int64_t rend = end + 1 < n ? end + 1 : n;    // inputs read: [lo-1, rend)
+    const int64_t i0 = t.lo + ((int64_t)(blockIdx.x - a.begin[ti]) * 256 + threadIdx.x) * 4;
+    const float *X = reinterpret_cast<const float *>(t.x);
+    float *Y = reinterpret_cast<float *>(t.y);
+    const bool aligned = ((t.x + t.lo * 4) & 15) == 0 && ((t.y + t.lo * 4) & 15) == 0;
+    float v[4];
+    if (aligned && i0 + 3 < end) {
+        float4 q = *reinterpret_cast<const float4 *>(X + i0);
+        v[0] = q.x;
+        v[1] = q.y;
+        v[2] = q.z;
+        v[3] = q.w;
+    } else {
+        for (int j = 0; j < 4; ++j) v[j] = (i0 + j < rend) ? X[i0 + j] : 0.f;
+    }
+    const int lane = threadIdx.x & (WAVE - 1);
+    float left = __shfl_up(v[3], 1);
+    float right = __shfl_down(v[0], 1);
+    if (i0 >= end) return;
+    if (lane == 0) left = (i0 - 1 >= 0) ? X[i0 - 1] : 0.f;
+    if (lane == WAVE - 1 && i0 + 3 < end) right = (i0 + 4 < n) ? X[i0 + 4] : 0.f;
+    float o[4];
+    o[0] = st_point(left, v[0], v[1]);
+    o[1] = st_point(v[0], v[1], v[2]);
+    o[2] = st_point(v[1], v[2], v[3]);
+    o[3] = st_point(v[2], v[3], right);
+    if (aligned && i0 + 3 < end) {
+        *reinterpret_cast<float4 *>(Y + i0) = make_float4(o[0], o[1], o[2], o[3]);
+    } else {
+        for (int j = 0; j < 4; ++j)
+            if (i0 + j < end) Y[i0 + j] = o[j];
+    }
+}
+
+hipError_t launch_stencil1d_f32(const KLaunch &L) {
+    StArgs a;
+    a.n = L.iarg[0];
+    a.ntask = L.ntask;
+    int64_t nb = 0;
+    for (int i = 0; i < L.ntask; ++i) {
+        a.begin[i] = (int)nb;
+        a.t[i].lo = L.tasks[i].lo[0];
+        a.t[i].hi = L.tasks[i].hi[0];
+        a.t[i].y = L.tasks[i].v[1].base;
+        a.t[i].x = L.tasks[i].v[2].base;
+        int64_t e = std::min(a.t[i].hi, a.n) - a.t[i].lo;
+        nb += e > 0 ? (e + 1023) / 1024 : 0;
+    }
+    a.begin[L.ntask] = (int)nb;
+    if (nb == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_stencil1d, dim3(grid_of(nb)), dim3(256), 0, L.stream, a);
+    return hipGetLastError();
+}
+
+// ================================================================= jacobi2d
+// y[r][c] = 0.25*((x[r-1][c] + x[r+1][c]) + (x[r][c-1] + x[r][c+1])), zero
+// outside the n x m field.  A workgroup owns 1024 columns (4 per thread) of
+// JROWS consecutive rows and slides a three-row window down them, so every
+// input row is loaded once per tile; horizontal neighbours come from the
+// adjacent lanes.
+struct JTask {
+    int64_t r0, r1, c0, c1;
+    int64_t y, x;
+    int64_t ys, xs;   // row strides (elements)
+    int tx;           // column tiles
+    int vec;          // float4 path usable
+};
+struct JArgs {
+    int64_t n, m;
+    int ntask, rows, nblocks;
+    int begin[KMAXG + 1];
+    JTask t[KMAXG];
+};
+
+__device__ __forceinline__ float jpoint(float u, float d, float l, float r) {
+    float v = u + d;
+    float h = l + r;
+    float s = v + h;
+    return 0.25f * s;
+}
+
+__global__ __launch_bounds__(256) void k_jacobi2d(JArgs a) {
+    const int b = xcd_remap(blockIdx.x, a.nblocks);
+    const int ti = find_task(a.begin, a.ntask, b);
+    const JTask &t = a.t[ti];
+    const int local = b - a.begin[ti];
+    const int tyi = local / t.tx, txi = local - tyi * t.tx;
+    const int64_t n = a.n, m = a.m;
+    const int64_t r0 = t.r0 + (int64_t)tyi * a.rows;
+    const int64_t r1e = r0 + a.rows < t.r1 ? r0 + a.rows : t.r1;
+    const int64_t r1 = r1e < n ? r1e : n;
+    const int64_t cend = t.c1 < m ? t.c1 : m;            // outputs [c0, cend)
+    const int64_t rcend = cend + 1 < m ? cend + 1 : m;     // inputs read up to rcend
+    const int64_t col = t.c0 + ((int64_t)txi * 256 + threadIdx.x) * 4;
+    const bool active = col < cend;
+    const float *X = reinterpret_cast<const float *>(t.x);
+    float *Y = reinterpret_cast<float *>(t.y);
+    const int lane = threadIdx.x & (WAVE - 1);
+
+    auto load4 = [&](int64_t r, float *v) {
+        if (r < 0 || r >= n || !active) {
+            v[0] = v[1] = v[2] = v[3] = 0.f;
+            return;
+        }
+        const float *p = X + r * t.xs + col;
+        if (t.vec) {
+            float4 q = *reinterpret_cast<const float4 *>(p);
+            v[0] = q.x;
+            v[1] = q.y;
+            v[2] = q.z;
+            v[3] = q.w;
+        } else {
+            for (int j = 0; j < 4; ++j) v[j] = (col + j < rcend) ? p[j] : 0.f;
+        }
+    };
+    float up[4], mid[4], dn[4];
+    load4(r0 - 1, up);
+    load4(r0, mid);
+    for (int64_t r = r0; r < r1; ++r) {
+        load4(r + 1, dn);
+        float left = __shfl_up(mid[3], 1);
+        float right = __shfl_down(mid[0], 1);
+        const float *row = X + r * t.xs;
+        if (active && lane == 0) left = (col - 1 >= 0) ? row[col - 1] : 0.f;
+        if (active && lane == WAVE - 1 && col + 3 < cend) right = (col + 4 < m) ? row[col + 4] : 0.f;
+        if (active) {
+            // columns at or past m were loaded as zero
+            float o0 = jpoint(up[0], dn[0], left, mid[1]);
+            float o1 = jpoint(up[1], dn[1], mid[0], mid[2]);
+            float o2 = jpoint(up[2], dn[2], mid[1], mid[3]);
+            float o3 = jpoint(up[3], dn[3], mid[2], right);
+            float *q = Y + r * t.ys + col;
+            if (t.vec) {
+                *reinterpret_cast<float4 *>(q) = make_float4(o0, o1, o2, o3);
+            } else {
+                float o[4] = {o0, o1, o2, o3};
+                for (int j = 0; j < 4; ++j)
+                    if (col + j < cend) q[j] = o[j];
+            }
+        }
+        for (int j = 0; j < 4; ++j) {
+            up[j] = mid[j];
+            mid[j] = dn[j];
+        }
+    }
+}
+
+hipError_t launch_jacobi2d_f32(const KLaunch &L) {
+    JArgs a;
+    a.n = L.iarg[0];
+    a.m = L.iarg[1];
+    a.ntask = L.ntask;
+    a.rows = L.variant > 0 ? L.variant : 16;
+    int64_t nb = 0;
+    for (int i = 0; i < L.ntask; ++i) {
+        const KTask &k = L.tasks[i];
+        JTask &t = a.t[i];
+        t.r0 = k.lo[0];
+        t.r1 = std::min(k.hi[0], a.n);
+        t.c0 = k.lo[1];
+        t.c1 = std::min(k.hi[1], a.m);
+        t.y = k.v[2].base;
+        t.x = k.v[3].base;
+        t.ys = k.v[2].s[0];
+        t.xs = k.v[3].s[0];
+        t.vec = ((t.x + t.c0 * 4) & 15) == 0 && ((t.y + t.c0 * 4) & 15) == 0 && (t.xs & 3) == 0 &&
+                (t.ys & 3) == 0 && ((t.c1 - t.c0) & 3) == 0;
+        int64_t cols = t.c1 - t.c0, rows = t.r1 - t.r0;
+        t.tx = cols > 0 ? (int)((cols + 1023) / 1024) : 0;
+        int64_t ty = rows > 0 ? (rows + a.rows - 1) / a.rows : 0;
+        a.begin[i] = (int)nb;
+        nb += (int64_t)t.tx * ty;
+    }
+    a.begin[L.ntask] = (int)nb;
+    a.nblocks = (int)nb;
+    if (nb == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_jacobi2d, dim3(grid_of(nb)), dim3(256), 0, L.stream, a);
+    return hipGetLastError();
+}
+
+// ================================================================ hist256
+// h[b] += #{i in task : v[i] == b}; h is the superblock's private partial.
+// Each wave keeps its own 256-bin LDS histogram (skewed data hammers few
+// bins), the workgroup sums them and adds to the partial with integer
+// atomics, which are exact and order-free.
+struct HTask {
+    int64_t lo, hi;
+    int64_t h, v;
+};
+struct HArgs {
+    int64_t n;
+    int ntask;
+    int per_task;
+    int begin[KMAXG + 1];
+    HTask t[KMAXG];
+};
+
+__global__ __launch_bounds__(256) void k_hist256(HArgs a) {
+    __shared__ int sh[4][256];
+    int ti = find_task(a.begin, a.ntask, blockIdx.x);
+    const HTask &t = a.t[ti];
+    const int w = threadIdx.x >> 6;
+    for (int i = threadIdx.x; i < 4 * 256; i += 256) (&sh[0][0])[i] = 0;
+    __syncthreads();
+    const int64_t end = t.hi < a.n ? t.hi : a.n;
+    const int nblk = a.begin[ti + 1] - a.begin[ti];
+    const int32_t *V = reinterpret_cast<const int32_t *>(t.v);
+    for (int64_t i = t.lo + (int64_t)(blockIdx.x - a.begin[ti]) * 256 + threadIdx.x; i < end;
+         i += (int64_t)nblk * 256) {
+        int32_t b = V[i];
+        if ((uint32_t)b < 256u) atomicAdd(&sh[w][b], 1);
+    }
+    __syncthreads();
+    int32_t *H = reinterpret_cast<int32_t *>(t.h);
+    int s = sh[0][threadIdx.x] + sh[1][threadIdx.x] + sh[2][threadIdx.x] + sh[3][threadIdx.x];
+    if (s) atomicAdd(H + threadIdx.x, s);
+}
+
+hipError_t launch_hist256_i32(const KLaunch &L) {
+    HArgs a;
+    a.n = L.iarg[0];
+    a.ntask = L.ntask;
+    int64_t nb = 0;
+    for (int i = 0; i < L.ntask; ++i) {
+        a.t[i].lo = L.tasks[i].lo[0];
+        a.t[i].hi = L.tasks[i].hi[0];
+        a.t[i].h = L.tasks[i].v[1].base;
+        a.t[i].v = L.tasks[i].v[2].base;
+        int64_t e = std::min(a.t[i].hi, a.n) - a.t[i].lo;
+        int64_t blocks = e > 0 ? std::min<int64_t>((e + 4095) / 4096, 2048) : 0;
+        a.begin[i] = (int)nb;
+        nb += blocks;
+    }
+    a.begin[L.ntask] = (int)nb;
+    if (nb == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_hist256, dim3(grid_of(nb)), dim3(256), 0, L.stream, a);
+    return hipGetLastError();
+}
+
+// ========================================================== kmeans assign
+// lab[p] = argmin_k sum_j (X[p][j] - C[k][j])^2 with the float32 chain
+// acc = fmaf(d, d, acc) over j in order from 0, strict < (ties keep the
+// smaller k).  Centres are staged in LDS once per workgroup.
+struct KTaskK {
+    int64_t lo, hi;
+    int64_t lab, x, c;
+    int64_t xs, cs;   // row strides
+};
+struct KArgs {
+    int64_t N, d, K;
+    int ntask;
+    int begin[KMAXG + 1];
+    KTaskK t[KMAXG];
+};
+
+constexpr int KM_MAXD = 32;
+constexpr int KM_MAXK = 256;
+
+template <int D>
+__global__ __launch_bounds__(256) void k_kmeans(KArgs a) {
+    __shared__ float cen[KM_MAXK * KM_MAXD];
+    int ti = find_task(a.begin, a.ntask, blockIdx.x);
+    const KTaskK &t = a.t[ti];
+    const int d = D > 0 ? D : (int)a.d;
+    const int K = (int)a.K;
+    const float *C = reinterpret_cast<const float *>(t.c);
+    for (int i = threadIdx.x; i < K * d; i += 256) cen[i] = C[(i / d) * t.cs + (i % d)];
+    __syncthreads();
+    const int64_t end = t.hi < a.N ? t.hi : a.N;
+    int64_t p = t.lo + (int64_t)(blockIdx.x - a.begin[ti]) * 256 + threadIdx.x;
+    if (p >= end) return;
+    const float *X = reinterpret_cast<const float *>(t.x) + p * t.xs;
+    float x[KM_MAXD];
+#pragma unroll
+    for (int j = 0; j < (D > 0 ? D : KM_MAXD); ++j)
+        if (D > 0 || j < d) x[j] = X[j];
+    float best = INFINITY;
+    int arg = 0;
+    for (int k = 0; k < K; ++k) {
+        const float *ck = cen + k * d;
+        float acc = 0.f;
+#pragma unroll
+        for (int j = 0; j < (D > 0 ? D : KM_MAXD); ++j) {
+            if (D > 0 || j < d) {
+                float df = x[j] - ck[j];
+                acc = fmaf(df, df, acc);
+            }
+        }
+        if (acc < best) {
+            best = acc;
+            arg = k;
+        }
+    }
+    *at<int32_t>(t.lab, p) = arg;
+}
+
+hipError_t launch_kmeans_assign_f32(const KLaunch &L) {
+    KArgs a;
+    a.N = L.iarg[0];
+    a.d = L.iarg[1];
+    a.K = L.iarg[2];
+    if (a.d < 1 || a.d > KM_MAXD || a.K < 1 || a.K > KM_MAXK) return hipErrorInvalidValue;
+    a.ntask = L.ntask;
+    int64_t nb = 0;
+    for (int i = 0; i < L.ntask; ++i) {
+        const KTask &k = L.tasks[i];
+        a.t[i].lo = k.lo[0];
+        a.t[i].hi = k.hi[0];
+        a.t[i].lab = k.v[3].base;
+        a.t[i].x = k.v[4].base;
+        a.t[i].xs = k.v[4].s[0];
+        a.t[i].c = k.v[5].base;
+        a.t[i].cs = k.v[5].s[0];
+        int64_t e = std::min(a.t[i].hi, a.N) - a.t[i].lo;
+        a.begin[i] = (int)nb;
+        nb += e > 0 ? (e + 255) / 256 : 0;
+    }
+    a.begin[L.ntask] = (int)nb;
+    if (nb == 0) return hipSuccess;
+    if (a.d == 16)
+        hipLaunchKernelGGL(k_kmeans<16>, dim3(grid_of(nb)), dim3(256), 0, L.stream, a);
+    else
+        hipLaunchKernelGGL(k_kmeans<0>, dim3(grid_of(nb)), dim3(256), 0, L.stream, a);
+    return hipGetLastError();
+}
+
+// =================================================================== fill
+template <class T>
+__global__ __launch_bounds__(256) void k_fill(T *p, int64_t count, T v) {
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < count; i += (int64_t)gridDim.x * 256) p[i] = v;
+}
+
+hipError_t launch_fill(hipStream_t s, void *dst, int64_t count, int esz, const void *value) {
+    if (count <= 0) return hipSuccess;
+    int64_t blocks = std::min<int64_t>((count + 255) / 256, 65536);
+    if (esz == 4) {
+        uint32_t v;
+        std::memcpy(&v, value, 4);
+        hipLaunchKernelGGL(k_fill<uint32_t>, dim3((unsigned)blocks), dim3(256), 0, s, (uint32_t *)dst, count, v);
+    } else if (esz == 8) {
+        uint64_t v;
+        std::memcpy(&v, value, 8);
+        hipLaunchKernelGGL(k_fill<uint64_t>, dim3((unsigned)blocks), dim3(256), 0, s, (uint64_t *)dst, count, v);
+    } else if (esz == 1) {
+        uint8_t v;
+        std::memcpy(&v, value, 1);
+        hipLaunchKernelGGL(k_fill<uint8_t>, dim3((unsigned)blocks), dim3(256), 0, s, (uint8_t *)dst, count, v);
+    } else {
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+// ================================================================ combine
+template <class T>
+__device__ __forceinline__ T rop(int op, T a, T b) {
+    switch (op) {
+        case 0: return a + b;
+        case 1: return a * b;
+        case 2: return b < a ? b : a;
+        default: return b > a ? b : a;
+    }
+}
+
+template <class T>
+__device__ __forceinline__ T identity(int op);
+template <>
+__device__ __forceinline__ float identity<float>(int op) {
+    return op == 0 ? 0.f : op == 1 ? 1.f : op == 2 ? INFINITY : -INFINITY;
+}
+template <>
+__device__ __forceinline__ double identity<double>(int op) {
+    return op == 0 ? 0. : op == 1 ? 1. : op == 2 ? INFINITY : -INFINITY;
+}
+template <>
+__device__ __forceinline__ int32_t identity<int32_t>(int op) {
+    return op == 0 ? 0 : op == 1 ? 1 : op == 2 ? INT_MAX : INT_MIN;
+}
+template <>
+__device__ __forceinline__ int64_t identity<int64_t>(int op) {
+    return op == 0 ? 0 : op == 1 ? 1 : op == 2 ? LLONG_MAX : LLONG_MIN;
+}
+
+template <class T>
+__global__ __launch_bounds__(256) void k_combine(CombineArgs a) {
+    int64_t e1 = a.hi[1] - a.lo[1], e2 = a.hi[2] - a.lo[2];
+    int64_t total = (a.hi[0] - a.lo[0]) * e1 * e2;
+    for (int64_t f = (int64_t)blockIdx.x * 256 + threadIdx.x; f < total; f += (int64_t)gridDim.x * 256) {
+        int64_t i2 = f % e2, r = f / e2;
+        int64_t i1 = r % e1, i0 = r / e1;
+        int64_t g[3] = {a.lo[0] + i0, a.lo[1] + i1, a.lo[2] + i2};
+        T *tp = reinterpret_cast<T *>(a.target.base) + g[0] * a.target.s[0] + g[1] * a.target.s[1] +
+                g[2] * a.target.s[2];
+        T acc = a.accumulate ? *tp : identity<T>(a.op);
+        for (int p = 0; p < a.nparts; ++p) {
+            const CombinePart &q = a.parts[p];
+            bool in = true;
+            for (int x = 0; x < a.ndim; ++x)
+                if (g[x] < q.lo[x] || g[x] >= q.hi[x]) in = false;
+            if (!in) continue;
+            int64_t s1 = a.ndim > 2 ? q.hi[2] - q.lo[2] : 1;
+            int64_t s0 = a.ndim > 1 ? (q.hi[1] - q.lo[1]) * s1 : 1;
+            int64_t off = (g[0] - q.lo[0]) * s0;
+            if (a.ndim > 1) off += (g[1] - q.lo[1]) * s1;
+            if (a.ndim > 2) off += g[2] - q.lo[2];
+            acc = rop<T>(a.op, acc, reinterpret_cast<const T *>(a.part_base)[q.off + off]);
+        }
+        *tp = acc;
+    }
+}
+
+hipError_t launch_combine(hipStream_t s, const CombineArgs &a) {
+    int64_t total = 1;
+    for (int x = 0; x < KMAXD; ++x) total *= (a.hi[x] - a.lo[x]);
+    if (total <= 0) return hipSuccess;
+    unsigned blocks = (unsigned)std::min<int64_t>((total + 255) / 256, 4096);
+    switch (a.dtype) {
+        case 0: hipLaunchKernelGGL(k_combine<float>, dim3(blocks), dim3(256), 0, s, a); break;
+        case 1: hipLaunchKernelGGL(k_combine<int32_t>, dim3(blocks), dim3(256), 0, s, a); break;
+        case 2: hipLaunchKernelGGL(k_combine<double>, dim3(blocks), dim3(256), 0, s, a); break;
+        case 3: hipLaunchKernelGGL(k_combine<int64_t>, dim3(blocks), dim3(256), 0, s, a); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+// ================================================================== gemm
+hipError_t launch_gemm_f32(const KLaunch &) { return hipErrorNotSupported; }
+
+}  // namespace lt

@@ -1,0 +1,397 @@
+// Internal data structures of the annotated-launch runtime.
+//
+// Planner side (no HIP dependency): boxes, affine index forms, compiled
+// annotations, distributions and chunks, task records with their dependency
+// edges.  Executor side: streams with sequence numbers, vector-clock fences,
+// the device arena and the memory manager.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "lt.h"
+#include "kernels.h"
+
+namespace lt {
+
+constexpr int MAXD = 3;
+constexpr int MAXPARAM = 8;
+constexpr int MAXSTREAM = 8;
+
+// ------------------------------------------------------------------- boxes
+// Half-open [lo, hi) per axis; unused axes are [0, 1).
+struct Box {
+    int64_t lo[MAXD] = {0, 0, 0};
+    int64_t hi[MAXD] = {1, 1, 1};
+    bool empty(int nd) const {
+        for (int a = 0; a < nd; ++a)
+            if (hi[a] <= lo[a]) return true;
+        return false;
+    }
+    int64_t volume(int nd) const {
+        int64_t v = 1;
+        for (int a = 0; a < nd; ++a) v *= (hi[a] > lo[a] ? hi[a] - lo[a] : 0);
+        return v;
+    }
+    bool contains(const Box &o, int nd) const {
+        for (int a = 0; a < nd; ++a)
+            if (o.lo[a] < lo[a] || o.hi[a] > hi[a]) return false;
+        return true;
+    }
+    bool equals(const Box &o, int nd) const {
+        for (int a = 0; a < nd; ++a)
+            if (o.lo[a] != lo[a] || o.hi[a] != hi[a]) return false;
+        return true;
+    }
+};
+
+inline Box intersect(const Box &a, const Box &b, int nd) {
+    Box r;
+    for (int x = 0; x < nd; ++x) {
+        r.lo[x] = a.lo[x] > b.lo[x] ? a.lo[x] : b.lo[x];
+        r.hi[x] = a.hi[x] < b.hi[x] ? a.hi[x] : b.hi[x];
+    }
+    return r;
+}
+
+inline Box bbox_union(const Box &a, const Box &b, int nd) {
+    Box r;
+    for (int x = 0; x < nd; ++x) {
+        r.lo[x] = a.lo[x] < b.lo[x] ? a.lo[x] : b.lo[x];
+        r.hi[x] = a.hi[x] > b.hi[x] ? a.hi[x] : b.hi[x];
+    }
+    return r;
+}
+
+// ------------------------------------------------------------- annotations
+enum Mode { M_READ = 0, M_WRITE = 1, M_RW = 2, M_REDUCE = 3 };
+enum ROp { R_ADD = 0, R_MUL = 1, R_MIN = 2, R_MAX = 3 };
+
+// Variable slots: kind * 3 + position, kind 0 = global, 1 = block, 2 = local.
+constexpr int NVAR = 9;
+
+// c0 + sum v[k] * var_k + sum p[q] * scalar_param_q
+struct Affine {
+    int64_t c0 = 0;
+    int64_t v[NVAR] = {0};
+    int64_t p[MAXPARAM] = {0};
+    bool is_const() const {
+        for (int k = 0; k < NVAR; ++k)
+            if (v[k]) return false;
+        for (int k = 0; k < MAXPARAM; ++k)
+            if (p[k]) return false;
+        return true;
+    }
+};
+
+struct IndexSpec {
+    bool has_lo = true, has_hi = true;  // slice bounds present (point: both)
+    Affine lo, hi;                      // point: lo == hi
+};
+
+struct Access {
+    Mode mode = M_READ;
+    ROp op = R_ADD;
+    int param = -1;                     // kernel parameter index (an array)
+    std::vector<IndexSpec> idx;
+};
+
+struct Annotation {
+    std::string text;
+    int nbound[3] = {-1, -1, -1};       // names bound per kind (-1 = unbound)
+    std::vector<Access> acc;
+};
+
+// ------------------------------------------------------------- kernel defs
+enum ParamKind { P_ARRAY = 0, P_INT = 1, P_FLOAT = 2 };
+
+struct ParamDef {
+    const char *name;
+    ParamKind kind;
+    lt_dtype dtype;  // arrays
+    int ndim;        // arrays: required rank
+};
+
+struct KernelDef {
+    const char *name;
+    const char *annotation;
+    int nparam;
+    ParamDef params[MAXPARAM];
+    int grid_ndim;          // rank of the launch grid the body expects
+    KernelFn fn;            // host launcher
+    int max_group;          // tasks per grouped dispatch
+};
+
+const KernelDef *find_builtin(const char *name);
+
+}  // namespace lt
+
+struct lt_kernel {
+    const lt::KernelDef *def;
+    std::shared_ptr<lt::Annotation> annot;
+};
+
+namespace lt {
+
+// ------------------------------------------------------------ fences/points
+// A fence is a vector clock: for each stream the sequence number of the
+// last operation that must have completed.
+struct Fence {
+    uint64_t s[MAXSTREAM] = {0};
+    void merge(const Fence &o) {
+        for (int i = 0; i < MAXSTREAM; ++i)
+            if (o.s[i] > s[i]) s[i] = o.s[i];
+    }
+    void add(int stream, uint64_t seq) {
+        if (seq > s[stream]) s[stream] = seq;
+    }
+};
+
+using Array = ::lt_array;  // declared in lt.h, defined below
+
+// ------------------------------------------------------------------ chunks
+struct Chunk {
+    uint64_t id = 0;
+    Array *arr = nullptr;
+    int index = 0;
+    Box box;
+    int64_t elems = 0, bytes = 0;
+
+    // device copy
+    int64_t dev_off = -1;      // arena offset; -1 = not allocated
+    int64_t dev_stride[MAXD];  // element strides of the device copy
+    bool dev_valid = false;
+    // host copy (home for host-backed arrays; spill copy otherwise)
+    char *host_ptr = nullptr;  // address of element box.lo
+    int64_t host_stride[MAXD] = {0, 0, 0};
+    bool host_owned = false;   // runtime-allocated pinned spill buffer
+    bool host_valid = false;
+    bool defined = false;      // holds data written by someone (else undefined)
+
+    // access history for conflict analysis (task ids; program order)
+    uint64_t last_writer = 0;  // 0 = none
+    std::vector<uint64_t> readers;
+    std::vector<uint64_t> reducers;
+    int reduce_op = -1;
+
+    Fence data_ready;   // the device copy holds valid data after this
+    Fence last_access;  // every device-side use so far
+    Fence host_ready;   // host copy complete (after a write-back)
+    uint64_t lru = 0;
+    int pin = 0;
+};
+
+// ------------------------------------------------------------------ arrays
+}  // namespace lt
+
+struct lt_array {
+    uint64_t id = 0;
+    lt_dtype dtype = LT_F32;
+    int esz = 4;
+    int ndim = 1;
+    int64_t shape[lt::MAXD] = {1, 1, 1};
+    int64_t strides[lt::MAXD] = {1, 1, 1};
+    bool host_backed = false;
+    char *host_base = nullptr;
+    bool row_slab = false;   // every chunk spans full trailing axes
+    int dist_kind = LT_DIST_BLOCK;
+    int64_t dist_chunk[lt::MAXD] = {0, 0, 0};  // BLOCK
+    int64_t nch[lt::MAXD] = {1, 1, 1};         // BLOCK: chunks per axis
+    std::vector<lt::Chunk *> chunks;
+    bool dead = false;
+};
+
+namespace lt {
+
+// ------------------------------------------------------------------- tasks
+struct RegionRec {
+    lt_region_info info;
+};
+
+struct TaskRec {
+    uint64_t id = 0, launch = 0;
+    int kind = LT_TASK_EXEC;
+    int stream = 0;
+    uint64_t seq = 0;                  // completion point on `stream`
+    Box sb;
+    std::vector<uint64_t> deps;
+    std::vector<lt_region_info> regions;
+};
+
+// --------------------------------------------------------------- streams
+struct Mark {
+    uint64_t seq;
+    hipEvent_t ev;
+};
+
+struct Stream {
+    hipStream_t h = nullptr;
+    uint64_t seq = 0;                  // operations issued
+    uint64_t done = 0;                 // operations known to have completed
+    std::deque<Mark> marks;            // events recorded at given seqs
+    uint64_t waited[MAXSTREAM] = {0};  // highest seq of other streams waited on
+};
+
+// ------------------------------------------------------------- the arena
+struct Seg {
+    int64_t off = 0, size = 0;
+    int kind = 0;                      // 0 free, 1 chunk, 2 temporary
+    Chunk *chunk = nullptr;
+    Fence fence;                       // free: memory reusable after this
+};
+
+struct TraceSink;
+
+struct Arena {
+    int64_t capacity = 0;
+    std::map<int64_t, Seg> segs;       // covers [0, capacity)
+    int64_t used = 0, peak = 0;
+    void init(int64_t cap);
+    // best fit among free segments; returns offset or -1
+    int64_t take_free(int64_t size, Fence *fence_out, int kind, Chunk *owner);
+    // takes [off, off+size) if a free segment covers it; returns off or -1
+    int64_t take_at(int64_t off, int64_t size, Fence *fence_out, int kind, Chunk *owner);
+    void release(int64_t off, const Fence &fence);
+    Seg *find(int64_t off);
+    int64_t largest_free() const;
+};
+
+// ------------------------------------------------------------ open group
+// Tasks of one launch collected for a single grouped dispatch.
+struct ChunkUse {
+    Chunk *c;
+    bool write;
+};
+
+struct Group {
+    bool open = false;
+    uint64_t launch = 0;
+    const KernelDef *def = nullptr;
+    int stream = 0;
+    KLaunch proto;
+    std::vector<KTask> tasks;
+    std::vector<uint64_t> ids;
+    std::vector<ChunkUse> uses;
+    Fence wait;
+};
+
+}  // namespace lt
+
+struct lt_context {
+    lt_config cfg;
+    std::string err;
+    int ncompute = 1;
+    int h2d = 1, d2h = 2;              // stream indices
+    int nstreams = 3;
+    lt::Stream streams[lt::MAXSTREAM];
+    std::vector<hipEvent_t> event_pool;
+    bool dry = false;
+
+    // memory
+    lt::Arena arena;
+    char *arena_base = nullptr;
+    bool arena_owned = false;
+    uint64_t lru_clock = 0;
+
+    // objects
+    uint64_t next_array_id = 1, next_chunk_id = 1, next_task_id = 1;
+    uint64_t next_launch_id = 1;
+    std::vector<lt::Array *> arrays;
+    std::vector<std::unique_ptr<lt_kernel>> kernels;
+    std::unordered_map<std::string, std::shared_ptr<lt::Annotation>> annot_cache;
+
+    // planner records (kept until lt_sync)
+    std::unordered_map<uint64_t, lt::TaskRec> tasks;
+    std::unordered_map<uint64_t, std::vector<uint64_t>> launch_tasks;
+    std::unordered_map<uint64_t, lt::Fence> launch_done;
+
+    // throttle: staged tasks (completion point, footprint)
+    std::deque<std::pair<lt::Fence, int64_t>> staged;
+    int64_t staged_bytes = 0;
+
+    // sticky asynchronous error
+    lt_status sticky = LT_OK;
+    std::string sticky_msg;
+
+    lt_stats stats;
+    std::vector<lt_trace_rec> trace;
+    int rr = 0;                        // round-robin compute stream
+    lt::Group group;                   // tasks awaiting one grouped dispatch
+
+    // profiling: (kernel name, start, end) awaiting resolution
+    bool prof = false;
+    struct ProfPending {
+        const char *name;
+        hipEvent_t a, b;
+    };
+    std::vector<ProfPending> prof_pending;
+    std::map<std::string, lt_kernel_prof> prof_acc;
+    std::vector<hipEvent_t> prof_pool;
+    std::vector<void *> host_allocs;
+};
+
+namespace lt {
+using Ctx = lt_context;
+
+// annotation compiler (annot.cpp)
+lt_status compile_annotation(Ctx *ctx, const KernelDef *def, const char *text,
+                             std::shared_ptr<Annotation> *out);
+
+// planner helpers (plan.cpp)
+struct VarRange {
+    int64_t lo[NVAR], hi[NVAR];
+};
+void var_ranges(int nd, const int64_t *blk_lo, const int64_t *blk_hi,
+                const int64_t *block, VarRange *r);
+bool access_region(const Access &a, int nd_grid, const int64_t *block,
+                   const VarRange &vr, const int64_t *params, const Array *arr,
+                   Box *out);
+lt_status make_chunks(Ctx *ctx, Array *arr, const lt_dist *dist);
+void chunks_overlapping(const Array *arr, const Box &r, std::vector<Chunk *> *out);
+
+// executor (exec.cpp)
+lt_status launch(Ctx *ctx, lt_kernel *k, int nd, const int64_t *grid,
+                 const int64_t *block, const int64_t *sb, const char *annotation,
+                 const lt_arg *args, int nargs, uint64_t *launch_id);
+lt_status sync_all(Ctx *ctx);
+lt_status flush_group(Ctx *ctx);
+lt_status prof_begin(Ctx *ctx, int s, const char *name, hipEvent_t *a);
+lt_status prof_end(Ctx *ctx, int s, const char *name, hipEvent_t a);
+void prof_collect(Ctx *ctx);
+lt_status wait_fence(Ctx *ctx, const Fence &f);
+lt_status array_write(Ctx *ctx, Array *arr, const void *src, bool device_src);
+lt_status array_read(Ctx *ctx, Array *arr, void *dst, bool device_dst);
+lt_status array_fill(Ctx *ctx, Array *arr, const void *scalar);
+lt_status array_destroy(Ctx *ctx, Array *arr);
+lt_status ensure_arena(Ctx *ctx);
+void ctx_release_all(Ctx *ctx);
+
+// memory manager and streams (memory.cpp)
+uint64_t bump(Ctx *ctx, int stream);
+lt_status stream_wait(Ctx *ctx, int stream, const Fence &f);
+lt_status copy_box(Ctx *ctx, int stream, char *dst, const int64_t *ds,
+                   const char *src, const int64_t *ss, const int64_t *ext,
+                   int nd, int esz, hipMemcpyKind kind);
+lt_status alloc_range(Ctx *ctx, int64_t size, int kind, Chunk *owner,
+                      int64_t *off, Fence *fence);
+lt_status alloc_chunk(Ctx *ctx, Chunk *c, Fence *fence);
+bool alloc_slab(Ctx *ctx, Array *arr);
+lt_status place_run(Ctx *ctx, const std::vector<Chunk *> &run, Fence *mem);
+lt_status evict_chunk(Ctx *ctx, Chunk *c);
+lt_status ensure_host_copy(Ctx *ctx, Chunk *c);
+char *dev_ptr(Ctx *ctx, const Chunk *c);
+void trace_op(Ctx *ctx, int kind, int stream, uint64_t task, uint64_t chunk,
+              uint64_t bytes, uint64_t offset);
+
+lt_status set_err(Ctx *ctx, lt_status st, const char *fmt, ...);
+lt_status hip_fail(Ctx *ctx, hipError_t e, const char *what);
+
+}  // namespace lt

@@ -1,0 +1,574 @@
+// Device arena, streams/fences and the memory manager.
+//
+// Memory manager (Sec. 3.4 "Memory Management"): chunks live in one
+// pre-allocated device arena whose size is the device budget (the paper uses
+// pre-allocated pools because device and page-locked allocations are slow).
+// When a task's chunks do not fit, least-recently-used chunks that the task
+// does not need are evicted: a chunk whose device copy is newer than its
+// host copy is first copied back (device -> pinned host), a clean one is
+// dropped.  Evicted data is reloaded asynchronously when a later task needs
+// it.  All copies are asynchronous on dedicated copy streams.
+//
+// Ordering without host blocking: every stream operation gets a sequence
+// number; a Fence is a vector clock over streams.  Freed memory carries the
+// fence of its last users, and whoever reuses it first waits for that fence
+// on the device (an event wait), so the host issues the whole schedule ahead
+// and never waits for the GPU except in lt_sync / lt_wait / lt_array_read.
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+
+#include "lt_internal.h"
+
+namespace lt {
+
+static int64_t round_up(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
+
+lt_status set_err(Ctx *ctx, lt_status st, const char *fmt, ...) {
+    char buf[1024];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    if (ctx) ctx->err = buf;
+    return st;
+}
+
+lt_status hip_fail(Ctx *ctx, hipError_t e, const char *what) {
+    char buf[512];
+    snprintf(buf, sizeof buf, "%s: %s (%d)", what, hipGetErrorString(e), (int)e);
+    if (ctx) {
+        ctx->err = buf;
+        if (ctx->sticky == LT_OK) {
+            ctx->sticky = LT_ERR_DEVICE;
+            ctx->sticky_msg = buf;
+        }
+    }
+    return LT_ERR_DEVICE;
+}
+
+// ------------------------------------------------------------------ arena
+void Arena::init(int64_t cap) {
+    capacity = cap;
+    segs.clear();
+    Seg s;
+    s.off = 0;
+    s.size = cap;
+    segs[0] = s;
+    used = peak = 0;
+}
+
+Seg *Arena::find(int64_t off) {
+    auto it = segs.find(off);
+    return it == segs.end() ? nullptr : &it->second;
+}
+
+int64_t Arena::largest_free() const {
+    int64_t m = 0;
+    for (auto &kv : segs)
+        if (kv.second.kind == 0) m = std::max(m, kv.second.size);
+    return m;
+}
+
+int64_t Arena::take_free(int64_t size, Fence *fence_out, int kind, Chunk *owner) {
+    auto best = segs.end();
+    for (auto it = segs.begin(); it != segs.end(); ++it) {
+        const Seg &s = it->second;
+        if (s.kind != 0 || s.size < size) continue;
+        if (best == segs.end() || s.size < best->second.size) best = it;
+    }
+    if (best == segs.end()) return -1;
+    return take_at(best->first, size, fence_out, kind, owner);
+}
+
+int64_t Arena::take_at(int64_t off, int64_t size, Fence *fence_out, int kind, Chunk *owner) {
+    // the free segment containing `off`
+    auto it = segs.upper_bound(off);
+    if (it == segs.begin()) return -1;
+    --it;
+    Seg s = it->second;
+    if (s.kind != 0 || off + size > s.off + s.size) return -1;
+    segs.erase(it);
+    if (off > s.off) {
+        Seg head = s;
+        head.size = off - s.off;
+        segs[head.off] = head;
+    }
+    Seg mid = s;
+    mid.off = off;
+    mid.size = size;
+    mid.kind = kind;
+    mid.chunk = owner;
+    segs[off] = mid;
+    if (off + size < s.off + s.size) {
+        Seg tail = s;
+        tail.off = off + size;
+        tail.size = s.off + s.size - tail.off;
+        segs[tail.off] = tail;
+    }
+    if (fence_out) *fence_out = s.fence;
+    used += size;
+    peak = std::max(peak, used);
+    return off;
+}
+
+void Arena::release(int64_t off, const Fence &fence) {
+    auto it = segs.find(off);
+    if (it == segs.end() || it->second.kind == 0) return;
+    used -= it->second.size;
+    it->second.kind = 0;
+    it->second.chunk = nullptr;
+    it->second.fence.merge(fence);
+    // coalesce with the next and previous free segments
+    auto nx = std::next(it);
+    if (nx != segs.end() && nx->second.kind == 0) {
+        it->second.size += nx->second.size;
+        it->second.fence.merge(nx->second.fence);
+        segs.erase(nx);
+    }
+    if (it != segs.begin()) {
+        auto pv = std::prev(it);
+        if (pv->second.kind == 0) {
+            pv->second.size += it->second.size;
+            pv->second.fence.merge(it->second.fence);
+            segs.erase(it);
+        }
+    }
+}
+
+// ---------------------------------------------------------------- tracing
+void trace_op(Ctx *ctx, int kind, int stream, uint64_t task, uint64_t chunk,
+              uint64_t bytes, uint64_t offset) {
+    if (!ctx->cfg.trace) return;
+    lt_trace_rec r;
+    r.kind = kind;
+    r.stream = stream;
+    r.task = task;
+    r.chunk = chunk;
+    r.bytes = bytes;
+    r.offset = offset;
+    r.resident = (uint64_t)ctx->arena.used;
+    ctx->trace.push_back(r);
+}
+
+// ---------------------------------------------------------------- streams
+static hipEvent_t get_event(Ctx *ctx) {
+    if (!ctx->event_pool.empty()) {
+        hipEvent_t e = ctx->event_pool.back();
+        ctx->event_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return nullptr;
+    return e;
+}
+
+uint64_t bump(Ctx *ctx, int s) { return ++ctx->streams[s].seq; }
+
+// Event whose completion implies stream t has executed through `seq`.
+static lt_status mark_at(Ctx *ctx, int t, uint64_t seq, hipEvent_t *ev, uint64_t *mseq) {
+    Stream &S = ctx->streams[t];
+    for (auto &m : S.marks)
+        if (m.seq >= seq) {
+            *ev = m.ev;
+            *mseq = m.seq;
+            return LT_OK;
+        }
+    hipEvent_t e = get_event(ctx);
+    if (!e) return set_err(ctx, LT_ERR_DEVICE, "hipEventCreate failed");
+    hipError_t r = hipEventRecord(e, S.h);
+    if (r != hipSuccess) return hip_fail(ctx, r, "hipEventRecord");
+    S.marks.push_back({S.seq, e});
+    *ev = e;
+    *mseq = S.seq;
+    return LT_OK;
+}
+
+lt_status stream_wait(Ctx *ctx, int s, const Fence &f) {
+    Stream &S = ctx->streams[s];
+    for (int t = 0; t < ctx->nstreams; ++t) {
+        if (t == s) continue;
+        uint64_t need = f.s[t];
+        if (need <= ctx->streams[t].done || need <= S.waited[t]) continue;
+        if (ctx->dry) {
+            S.waited[t] = need;
+            continue;
+        }
+        hipEvent_t ev;
+        uint64_t mseq;
+        lt_status st = mark_at(ctx, t, need, &ev, &mseq);
+        if (st) return st;
+        hipError_t r = hipStreamWaitEvent(S.h, ev, 0);
+        if (r != hipSuccess) return hip_fail(ctx, r, "hipStreamWaitEvent");
+        S.waited[t] = mseq;
+    }
+    return LT_OK;
+}
+
+lt_status wait_fence(Ctx *ctx, const Fence &f) {
+    if (ctx->dry) return LT_OK;
+    for (int t = 0; t < ctx->nstreams; ++t) {
+        if (f.s[t] <= ctx->streams[t].done) continue;
+        hipEvent_t ev;
+        uint64_t mseq;
+        lt_status st = mark_at(ctx, t, f.s[t], &ev, &mseq);
+        if (st) return st;
+        hipError_t r = hipEventSynchronize(ev);
+        if (r != hipSuccess) return hip_fail(ctx, r, "hipEventSynchronize");
+    }
+    return LT_OK;
+}
+
+// ------------------------------------------------------------------ copies
+// Copies a box of `ext` elements between two strided layouts (element
+// strides; the last axis is contiguous on both sides).  Axes that are
+// contiguous on both sides are merged first.
+lt_status copy_box(Ctx *ctx, int stream, char *dst, const int64_t *ds,
+                   const char *src, const int64_t *ss, const int64_t *ext,
+                   int nd, int esz, hipMemcpyKind kind) {
+    // axes from the innermost outwards; an outer axis is merged into the
+    // current innermost group when both layouts are contiguous across them
+    int64_t e[MAXD], d[MAXD], s[MAXD];
+    int n = 0;
+    for (int a = nd - 1; a >= 0; --a) {
+        if (ext[a] <= 0) return LT_OK;
+        if (n > 0 && ds[a] == e[n - 1] * d[n - 1] && ss[a] == e[n - 1] * s[n - 1]) {
+            e[n - 1] *= ext[a];
+            continue;
+        }
+        e[n] = ext[a];
+        d[n] = ds[a];
+        s[n] = ss[a];
+        ++n;
+    }
+    // reorder outermost first
+    for (int i = 0; i < n / 2; ++i) {
+        std::swap(e[i], e[n - 1 - i]);
+        std::swap(d[i], d[n - 1 - i]);
+        std::swap(s[i], s[n - 1 - i]);
+    }
+    int64_t bytes = esz;
+    for (int a = 0; a < n; ++a) bytes *= e[a];
+    int tk = kind == hipMemcpyHostToDevice ? 1 : kind == hipMemcpyDeviceToHost ? 2 : 3;
+    if (tk == 1) {
+        ctx->stats.bytes_h2d += bytes;
+        ctx->stats.copies_h2d++;
+    } else if (tk == 2) {
+        ctx->stats.bytes_d2h += bytes;
+        ctx->stats.copies_d2h++;
+    } else {
+        ctx->stats.bytes_d2d += bytes;
+        ctx->stats.copies_d2d++;
+    }
+    if (ctx->dry) return LT_OK;
+    if (kind == hipMemcpyHostToHost) {
+        // plain CPU copy; the caller has synchronized pending device copies
+        for (int64_t i = 0; i < (n == 3 ? e[0] : 1); ++i) {
+            int64_t rows = n >= 2 ? e[n - 2] : 1;
+            for (int64_t r = 0; r < rows; ++r) {
+                int64_t doff = (n == 3 ? i * d[0] : 0) + (n >= 2 ? r * d[n - 2] : 0);
+                int64_t soff = (n == 3 ? i * s[0] : 0) + (n >= 2 ? r * s[n - 2] : 0);
+                memcpy(dst + doff * esz, src + soff * esz, (size_t)(e[n - 1] * esz));
+            }
+        }
+        return LT_OK;
+    }
+    hipStream_t h = ctx->streams[stream].h;
+    hipError_t r = hipSuccess;
+    if (n == 1) {
+        r = hipMemcpyAsync(dst, src, e[0] * esz, kind, h);
+    } else if (n == 2) {
+        r = hipMemcpy2DAsync(dst, d[0] * esz, src, s[0] * esz, e[1] * esz, e[0], kind, h);
+    } else {
+        for (int64_t i = 0; i < e[0] && r == hipSuccess; ++i)
+            r = hipMemcpy2DAsync(dst + i * d[0] * esz, d[1] * esz, src + i * s[0] * esz,
+                                 s[1] * esz, e[2] * esz, e[1], kind, h);
+    }
+    if (r != hipSuccess) return hip_fail(ctx, r, "hipMemcpyAsync");
+    return LT_OK;
+}
+
+// ------------------------------------------------------------------- arena
+lt_status ensure_arena(Ctx *ctx) {
+    if (ctx->arena.capacity > 0) return LT_OK;
+    int64_t cap = (int64_t)ctx->cfg.device_budget_bytes;
+    if (ctx->cfg.device_arena) {
+        if (cap <= 0 || cap > (int64_t)ctx->cfg.arena_bytes) cap = (int64_t)ctx->cfg.arena_bytes;
+        ctx->arena_base = (char *)ctx->cfg.device_arena;
+        ctx->arena_owned = false;
+    } else if (!ctx->dry) {
+        void *p = nullptr;
+        hipError_t r = hipMalloc(&p, (size_t)cap);
+        if (r != hipSuccess) return hip_fail(ctx, r, "hipMalloc(device arena)");
+        ctx->arena_base = (char *)p;
+        ctx->arena_owned = true;
+    }
+    ctx->arena.init(cap);
+    return LT_OK;
+}
+
+static void note_resident(Ctx *ctx) {
+    ctx->stats.resident_bytes = (uint64_t)ctx->arena.used;
+    if (ctx->stats.resident_bytes > ctx->stats.peak_resident_bytes)
+        ctx->stats.peak_resident_bytes = ctx->stats.resident_bytes;
+}
+
+lt_status ensure_host_copy(Ctx *ctx, Chunk *c) {
+    if (c->host_ptr) return LT_OK;
+    Array *arr = c->arr;
+    if (arr->host_backed) {
+        int64_t off = 0;
+        for (int a = 0; a < arr->ndim; ++a) off += c->box.lo[a] * arr->strides[a];
+        c->host_ptr = arr->host_base + off * arr->esz;
+        for (int a = 0; a < MAXD; ++a) c->host_stride[a] = arr->strides[a];
+        return LT_OK;
+    }
+    void *p = nullptr;
+    if (ctx->dry) {
+        p = malloc(1);
+    } else {
+        hipError_t r = hipHostMalloc(&p, (size_t)c->bytes, hipHostMallocDefault);
+        if (r != hipSuccess) return set_err(ctx, LT_ERR_OOM, "pinned spill buffer of %lld bytes: %s",
+                                            (long long)c->bytes, hipGetErrorString(r));
+    }
+    c->host_ptr = (char *)p;
+    c->host_owned = true;
+    for (int a = 0; a < MAXD; ++a) c->host_stride[a] = c->dev_stride[a];
+    return LT_OK;
+}
+
+static void chunk_ext(const Chunk *c, int64_t *ext) {
+    for (int a = 0; a < MAXD; ++a) ext[a] = c->box.hi[a] - c->box.lo[a];
+}
+
+char *dev_ptr(Ctx *ctx, const Chunk *c) { return ctx->arena_base + c->dev_off; }
+
+// Evicts one unpinned chunk: write back if its device copy is newer.
+lt_status evict_chunk(Ctx *ctx, Chunk *c) {
+    Fence f = c->last_access;
+    if (c->dev_valid && !c->host_valid && c->defined) {
+        lt_status st = ensure_host_copy(ctx, c);
+        if (st) return st;
+        st = stream_wait(ctx, ctx->d2h, c->data_ready);
+        if (st) return st;
+        int64_t ext[MAXD];
+        chunk_ext(c, ext);
+        st = copy_box(ctx, ctx->d2h, c->host_ptr, c->host_stride, dev_ptr(ctx, c), c->dev_stride,
+                      ext, c->arr->ndim, c->arr->esz, hipMemcpyDeviceToHost);
+        if (st) return st;
+        uint64_t p = bump(ctx, ctx->d2h);
+        c->host_ready = Fence();
+        c->host_ready.add(ctx->d2h, p);
+        c->host_valid = true;
+        f.add(ctx->d2h, p);
+        ctx->stats.evictions_dirty++;
+        trace_op(ctx, 2, ctx->d2h, ~0ull, c->id, c->bytes, c->dev_off);
+    } else {
+        ctx->stats.evictions_clean++;
+    }
+    ctx->arena.release(c->dev_off, f);
+    trace_op(ctx, 5, -1, ~0ull, c->id, c->bytes, c->dev_off);
+    c->dev_off = -1;
+    c->dev_valid = false;
+    note_resident(ctx);
+    return LT_OK;
+}
+
+// Allocates `size` bytes of the arena, evicting least-recently-used unpinned
+// chunks when no free range is large enough.  `fence` receives the point
+// after which the memory may be overwritten.
+lt_status alloc_range(Ctx *ctx, int64_t size, int kind, Chunk *owner,
+                      int64_t *off, Fence *fence) {
+    lt_status st = ensure_arena(ctx);
+    if (st) return st;
+    Arena &A = ctx->arena;
+    int64_t o = A.take_free(size, fence, kind, owner);
+    if (o < 0) {
+        // choose the contiguous window of free or evictable segments whose
+        // most recently used chunk is the oldest (exact LRU when chunks have
+        // equal sizes); pinned chunks and temporaries block a window
+        std::vector<Seg *> order;
+        order.reserve(A.segs.size());
+        for (auto &kv : A.segs) order.push_back(&kv.second);
+        int64_t best_start = -1;
+        uint64_t best_cost = ~0ull;
+        size_t n = order.size();
+        for (size_t i = 0; i < n; ++i) {
+            int64_t sum = 0;
+            uint64_t cost = 0;
+            size_t j = i;
+            bool ok = false;
+            for (; j < n; ++j) {
+                Seg *s = order[j];
+                if (s->kind == 2 || (s->kind == 1 && s->chunk->pin > 0)) break;
+                if (s->kind == 1) cost = std::max<uint64_t>(cost, s->chunk->lru + 1);
+                sum += s->size;
+                if (sum >= size) {
+                    ok = true;
+                    break;
+                }
+            }
+            if (ok && cost < best_cost) {
+                best_cost = cost;
+                best_start = order[i]->off;
+            }
+        }
+        if (best_start < 0)
+            return set_err(ctx, LT_ERR_BUDGET,
+                           "cannot place %lld bytes in the device budget of %lld bytes "
+                           "(%lld in use, largest free range %lld)",
+                           (long long)size, (long long)A.capacity, (long long)A.used,
+                           (long long)A.largest_free());
+        // evict every chunk in the window
+        std::vector<Chunk *> victims;
+        int64_t sum = 0;
+        for (auto it = A.segs.find(best_start); it != A.segs.end() && sum < size; ++it) {
+            if (it->second.kind == 1) victims.push_back(it->second.chunk);
+            sum += it->second.size;
+        }
+        for (Chunk *v : victims) {
+            st = evict_chunk(ctx, v);
+            if (st) return st;
+        }
+        o = A.take_at(best_start, size, fence, kind, owner);
+        if (o < 0) return set_err(ctx, LT_ERR_BUDGET, "internal: eviction window did not free %lld bytes",
+                                  (long long)size);
+    }
+    *off = o;
+    trace_op(ctx, 6, -1, ~0ull, owner ? owner->id : 0, size, o);
+    note_resident(ctx);
+    return LT_OK;
+}
+
+// Places a chunk in the arena.  A chunk of a row-slab array goes right after
+// its resident predecessor when that space is free, so runs of neighbouring
+// chunks stay contiguous and regions spanning them resolve to direct views.
+lt_status alloc_chunk(Ctx *ctx, Chunk *c, Fence *fence) {
+    lt_status st = ensure_arena(ctx);
+    if (st) return st;
+    Array *arr = c->arr;
+    if (arr->row_slab && c->index > 0) {
+        Chunk *p = arr->chunks[c->index - 1];
+        if (p->dev_off >= 0) {
+            int64_t o = ctx->arena.take_at(p->dev_off + p->bytes, c->bytes, fence, 1, c);
+            if (o >= 0) {
+                c->dev_off = o;
+                trace_op(ctx, 6, -1, ~0ull, c->id, c->bytes, o);
+                note_resident(ctx);
+                return LT_OK;
+            }
+        }
+    }
+    int64_t off;
+    st = alloc_range(ctx, round_up(c->bytes, 256), 1, c, &off, fence);
+    if (st) return st;
+    c->dev_off = off;
+    return LT_OK;
+}
+
+// Splits the arena range [off, off + total) into one segment per chunk, in
+// order, each chunk directly after the previous one.
+static void carve(Ctx *ctx, int64_t off, int64_t total, const std::vector<Chunk *> &run, const Fence &f) {
+    Arena &A = ctx->arena;
+    Seg whole = A.segs[off];
+    A.segs.erase(off);
+    int64_t cur = off;
+    for (size_t i = 0; i < run.size(); ++i) {
+        Chunk *c = run[i];
+        Seg s;
+        s.off = cur;
+        s.size = (i + 1 == run.size()) ? (off + total - cur) : c->bytes;
+        s.kind = 1;
+        s.chunk = c;
+        s.fence = f;
+        A.segs[cur] = s;
+        c->dev_off = cur;
+        cur += c->bytes;
+    }
+    (void)whole;
+}
+
+// Makes a run of neighbouring chunks of a row-slab array resident in one
+// contiguous range, in order, so that a region spanning them is a direct
+// view.  Resident members that are scattered are evicted first (their data
+// goes back to the host copy) and everything is reloaded into the window.
+// Returns the fence after which the window's memory may be written.
+lt_status place_run(Ctx *ctx, const std::vector<Chunk *> &run, Fence *mem) {
+    bool contiguous = true;
+    for (size_t i = 0; i < run.size(); ++i) {
+        if (run[i]->dev_off < 0) contiguous = false;
+        else if (i > 0 && run[i - 1]->dev_off >= 0 && run[i]->dev_off != run[i - 1]->dev_off + run[i - 1]->bytes)
+            contiguous = false;
+    }
+    if (contiguous) return LT_OK;
+    // try to extend in place: every missing member right after its predecessor
+    bool ok = true;
+    for (size_t i = 1; i < run.size() && ok; ++i) {
+        if (run[i]->dev_off >= 0) continue;
+        if (run[i - 1]->dev_off < 0) {
+            ok = false;
+            break;
+        }
+        Fence f;
+        int64_t o = ctx->arena.take_at(run[i - 1]->dev_off + run[i - 1]->bytes, run[i]->bytes, &f, 1, run[i]);
+        if (o < 0) {
+            ok = false;
+            break;
+        }
+        run[i]->dev_off = o;
+        run[i]->dev_valid = false;
+        mem->merge(f);
+    }
+    if (ok) {
+        bool cont = true;
+        for (size_t i = 1; i < run.size(); ++i)
+            if (run[i]->dev_off != run[i - 1]->dev_off + run[i - 1]->bytes) cont = false;
+        if (cont) return LT_OK;
+    }
+    // evict every resident member and reload the run into one window
+    for (Chunk *c : run)
+        if (c->dev_off >= 0) {
+            if (!c->dev_valid) {  // placed above but not loaded yet
+                ctx->arena.release(c->dev_off, Fence());
+                c->dev_off = -1;
+                continue;
+            }
+            lt_status st = evict_chunk(ctx, c);
+            if (st) return st;
+        }
+    int64_t total = 0;
+    for (Chunk *c : run) total += c->bytes;
+    int64_t rounded = round_up(total, 256);
+    for (Chunk *c : run) c->pin--;
+    int64_t off;
+    Fence f;
+    lt_status st = alloc_range(ctx, rounded, 1, nullptr, &off, &f);
+    for (Chunk *c : run) c->pin++;
+    if (st) return st;
+    carve(ctx, off, rounded, run, f);
+    for (Chunk *c : run) c->dev_valid = false;
+    mem->merge(f);
+    return LT_OK;
+}
+
+// Allocates every chunk of a device-home array as one contiguous range if it
+// fits in free memory right now (no eviction).  Returns true on success.
+bool alloc_slab(Ctx *ctx, Array *arr) {
+    if (ensure_arena(ctx)) return false;
+    int64_t total = 0;
+    for (Chunk *c : arr->chunks) total += c->bytes;
+    int64_t rounded = round_up(total, 256);
+    Fence f;
+    int64_t o = ctx->arena.take_free(rounded, &f, 1, nullptr);
+    if (o < 0) return false;
+    carve(ctx, o, rounded, arr->chunks, f);
+    for (Chunk *c : arr->chunks) {
+        c->dev_valid = true;
+        c->data_ready = f;
+        c->last_access = f;
+    }
+    note_resident(ctx);
+    return true;
+}
+
+}  // namespace lt

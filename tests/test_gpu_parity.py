@@ -1,0 +1,229 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle.
+
+Float kernels are compared bit for bit: each body fixes its float32
+operation order and the oracle follows the same order, so the only admissible
+difference is none (the workload tolerance, max-rel 1e-5, is the fallback
+and is never needed).  Integer results are bit-exact by definition.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synthetic
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def L():
+    import paper_2202_05549_amd as L
+    return L
+
+
+def ctx_of(L, **kw):
+    kw.setdefault("device_budget_bytes", 4 << 30)
+    return L.Context(**kw)
+
+
+# ------------------------------------------------------------------- touch
+
+@pytest.mark.parametrize("mode", [0, 1])
+@pytest.mark.parametrize("n,block,sb,chunk", [(1000, 16, 64, 100), (4096, 1, 1000, 512), (70001, 64, 4096, 0)])
+def test_touch_every_index_exactly_once(L, mode, n, block, sb, chunk):
+    say("touch", mode, n, block, sb, chunk)
+    with ctx_of(L, exec_mode=mode) as ctx:
+        y = ctx.array([n], np.int32, chunk=[chunk])
+        y.fill(0)
+        ctx.launch("touch_i32", [n], [block], [sb], args=[n, y])
+        ctx.launch("touch_i32", [n], [block], [sb], args=[n, y])
+        ctx.sync()
+        got = y.read()
+    exp = oracle.touch(oracle.touch(np.zeros(n, np.int32), n), n)
+    assert np.array_equal(got, exp)
+
+
+# --------------------------------------------------------------- stencil1d
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_stencil1d_config1_bit_exact(L, mode):
+    # 1-D 3-point stencil, 2^20 float32 ~U(-1,1) seed 0, 8 chunks of 2^17
+    n = 1 << 20
+    say("stencil1d config", mode)
+    x0 = synthetic.stencil1d_input(n, 0)
+    with ctx_of(L, exec_mode=mode) as ctx:
+        x = ctx.array([n], chunk=[1 << 17])
+        y = ctx.array([n], chunk=[1 << 17])
+        x.write(x0)
+        lid = ctx.launch("stencil1d_f32", [n], [256], [1 << 17], args=[n, y, x])
+        assert len(ctx.tasks(lid)) == 8
+        ctx.sync()
+        got = y.read()
+    assert np.array_equal(got, oracle.stencil1d(x0))
+
+
+@pytest.mark.parametrize("n,chunk,block,sb", [(1000003, 99991, 1, 77777), (5, 2, 1, 1), (4099, 4096, 4, 8),
+                                              (123457, 1 << 14, 32, 96)])
+def test_stencil1d_ragged_bit_exact(L, n, chunk, block, sb):
+    say("stencil1d ragged", n, chunk, block, sb)
+    x0 = synthetic.stencil1d_input(n, 17)
+    for mode in (0, 1):
+        with ctx_of(L, exec_mode=mode) as ctx:
+            x = ctx.array([n], chunk=[chunk])
+            y = ctx.array([n], chunk=[chunk])
+            x.write(x0)
+            ctx.launch("stencil1d_f32", [n], [block], [sb], args=[n, y, x])
+            ctx.sync()
+            assert np.array_equal(y.read(), oracle.stencil1d(x0)), mode
+
+
+def test_paper_host_sample_ten_iterations(L):
+    # Sec. 3.6 host sample: n = 1e6, chunks of 64000, superblocks of 64000
+    # threads, blocks of 16, ten launches with input and output swapped
+    n = 1_000_000
+    say("host sample")
+    x0 = synthetic.stencil1d_input(n, 3)
+    with ctx_of(L) as ctx:
+        a = ctx.array([n], chunk=[64000])
+        b = ctx.array([n], chunk=[64000])
+        a.write(x0)
+        inp, out = a, b
+        for _ in range(10):
+            ctx.launch("stencil1d_f32", [n], [16], [64000], args=[n, out, inp])
+            inp, out = out, inp
+        ctx.sync()
+        got = inp.read()
+    assert np.array_equal(got, oracle.stencil1d_iter(x0, 10))
+
+
+@pytest.mark.parametrize("budget_chunks", [4, 7])
+def test_stencil1d_out_of_core_matches(L, budget_chunks):
+    # device budget of a few chunks: chunks spill to pinned host memory and
+    # come back; the result must not change (distribution/budget invariance)
+    chunk = 1 << 16
+    n = 24 * chunk + 123
+    say("stencil1d spill", budget_chunks)
+    x0 = synthetic.stencil1d_input(n, 5)
+    with ctx_of(L, device_budget_bytes=budget_chunks * chunk * 4 + 4096) as ctx:
+        a = ctx.array([n], chunk=[chunk])
+        b = ctx.array([n], chunk=[chunk])
+        a.write(x0)
+        inp, out = a, b
+        for _ in range(5):
+            ctx.launch("stencil1d_f32", [n], [256], [chunk], args=[n, out, inp])
+            inp, out = out, inp
+        ctx.sync()
+        got = inp.read()
+        st = ctx.stats()
+    assert st["evictions_dirty"] > 0 and st["bytes_h2d"] > 0
+    assert st["peak_resident_bytes"] <= budget_chunks * chunk * 4 + 4096
+    assert np.array_equal(got, oracle.stencil1d_iter(x0, 5))
+
+
+# ----------------------------------------------------------------- jacobi
+
+@pytest.mark.parametrize("shape,chunk,sb,mode", [
+    ((300, 517), (37, 0), (37, 0), 0),
+    ((300, 517), (37, 0), (37, 0), 1),
+    ((256, 1024), (64, 0), (32, 0), 1),
+    ((129, 300), (0, 64), (16, 0), 0),      # column chunks: regions assembled
+    ((129, 300), (40, 100), (40, 100), 0),  # tiles: halo regions span tiles
+    ((1, 1), (0, 0), (0, 0), 0),
+    ((3, 1027), (1, 0), (1, 0), 1),
+])
+def test_jacobi_small_bit_exact(L, shape, chunk, sb, mode):
+    say("jacobi", shape, chunk, sb, mode)
+    n, m = shape
+    x0 = synthetic.jacobi2d_input(n, m, seed=9)
+    with ctx_of(L, exec_mode=mode) as ctx:
+        a = ctx.array([n, m], chunk=list(chunk))
+        b = ctx.array([n, m], chunk=list(chunk))
+        a.write(x0)
+        inp, out = a, b
+        for _ in range(5):
+            ctx.launch("jacobi2d_f32", [n, m], [1, 1], list(sb), args=[n, m, out, inp])
+            inp, out = out, inp
+        ctx.sync()
+        got = inp.read()
+    assert np.array_equal(got, oracle.jacobi2d(x0, 5))
+
+
+def test_jacobi_out_of_core_matches(L):
+    n, m = 1024, 1024
+    say("jacobi spill")
+    x0 = synthetic.jacobi2d_input(n, m, seed=10)
+    with ctx_of(L, device_budget_bytes=10 * 64 * m * 4) as ctx:
+        a = ctx.array([n, m], chunk=[64, 0])
+        b = ctx.array([n, m], chunk=[64, 0])
+        a.write(x0)
+        inp, out = a, b
+        for _ in range(4):
+            ctx.launch("jacobi2d_f32", [n, m], [1, 256], [64, 0], args=[n, m, out, inp])
+            inp, out = out, inp
+        ctx.sync()
+        got = inp.read()
+        assert ctx.stats()["evictions_dirty"] > 0
+    assert np.array_equal(got, oracle.jacobi2d(x0, 4))
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_jacobi_config2_full_size_bit_exact(L, mode):
+    # 2-D Jacobi 16384^2 ~U(0,1) seed 1, 100 ping-pong sweeps, 512-row
+    # chunks and superblocks (the benchmark configuration)
+    n = 16384
+    sweeps = 100
+    say("jacobi config2", mode)
+    x0 = synthetic.jacobi2d_input(n, seed=1)
+    with ctx_of(L, exec_mode=mode) as ctx:
+        a = ctx.array([n, n], chunk=[512, 0])
+        b = ctx.array([n, n], chunk=[512, 0])
+        a.write(x0)
+        inp, out = a, b
+        for _ in range(sweeps):
+            ctx.launch("jacobi2d_f32", [n, n], [1, 256], [512, 0], args=[n, n, out, inp])
+            inp, out = out, inp
+        ctx.sync()
+        got = inp.read()
+    ref = oracle.jacobi2d(x0, sweeps, inplace=True)
+    assert np.array_equal(got, ref)
+
+
+# ---------------------------------------------------------------- hist256
+
+@pytest.mark.parametrize("n,chunk,sb", [(1_000_003, 1 << 16, 1 << 16), (777, 100, 64), (1 << 22, 1 << 20, 1 << 19)])
+def test_hist256_bit_exact_and_overwrites_target(L, n, chunk, sb):
+    say("hist", n, chunk, sb)
+    v = synthetic.zipf_values(n, np.random.default_rng(12))
+    with ctx_of(L) as ctx:
+        va = ctx.array([n], np.int32, chunk=[chunk])
+        h = ctx.array([256], np.int32)
+        va.write(v)
+        h.fill(12345)  # reduce(+) overwrites the target
+        ctx.launch("hist256_i32", [n], [1], [sb], args=[n, h, va])
+        ctx.sync()
+        got = h.read()
+    assert np.array_equal(got, oracle.hist256(v))
+
+
+# ----------------------------------------------------------------- k-means
+
+@pytest.mark.parametrize("N,d,K,chunk", [(100_003, 16, 64, 1 << 14), (5000, 3, 7, 999), (4096, 32, 256, 0)])
+def test_kmeans_assign_labels_bit_exact(L, N, d, K, chunk):
+    say("kmeans", N, d, K)
+    X, mu, _ = synthetic.kmeans_blobs(N, d, K, seed=13)
+    with ctx_of(L) as ctx:
+        xa = ctx.array([N, d], chunk=[chunk, 0])
+        ca = ctx.array([K, d])
+        lab = ctx.array([N], np.int32, chunk=[chunk])
+        xa.write(X)
+        ca.write(mu)
+        ctx.launch("kmeans_assign_f32", [N], [1], [chunk if chunk else 0], args=[N, d, K, lab, xa, ca])
+        ctx.sync()
+        got = lab.read()
+    assert np.array_equal(got, oracle.kmeans_assign(X, mu))
