@@ -214,13 +214,15 @@ __global__ __launch_bounds__(256) void k_jacobi2d(JArgs a) {
     float *Y = reinterpret_cast<float *>(t.y);
     const int lane = threadIdx.x & (WAVE - 1);
 
+    // lanes past the last output column still load the halo column cend
+    // (read by their left neighbour lane) when it lies inside the field
     auto load4 = [&](int64_t r, float *v) {
-        if (r < 0 || r >= n || !active) {
+        if (r < 0 || r >= n || col >= rcend) {
             v[0] = v[1] = v[2] = v[3] = 0.f;
             return;
         }
         const float *p = X + r * t.xs + col;
-        if (t.vec) {
+        if (t.vec && active) {
             float4 q = *reinterpret_cast<const float4 *>(p);
             v[0] = q.x;
             v[1] = q.y;

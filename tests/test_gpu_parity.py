@@ -190,8 +190,12 @@ def test_jacobi_config2_full_size_bit_exact(L, mode):
             inp, out = out, inp
         ctx.sync()
         got = inp.read()
-    ref = oracle.jacobi2d(x0, sweeps, inplace=True)
-    assert np.array_equal(got, ref)
+    if "ref" not in _C2:
+        _C2["ref"] = oracle.jacobi2d(x0, sweeps, inplace=True)
+    assert np.array_equal(got, _C2["ref"])
+
+
+_C2 = {}
 
 
 # ---------------------------------------------------------------- hist256
