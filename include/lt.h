@@ -95,8 +95,16 @@ typedef struct lt_config {
                                        allocates its own on first use           */
     uint64_t arena_bytes;           /* size of device_arena                     */
     int32_t trace;                  /* 1: record a per-operation trace          */
-    int32_t reserved[7];
+    int32_t sb_order;               /* superblock issue order of 2-D/3-D grids:
+                                       LT_ORDER_ROWMAJOR or LT_ORDER_SERPENTINE
+                                       (odd rows of superblocks reversed, so
+                                       consecutive rows reuse the chunks the
+                                       previous row touched last)            */
+    int32_t reserved[6];
 } lt_config;
+
+#define LT_ORDER_ROWMAJOR 0
+#define LT_ORDER_SERPENTINE 1
 
 /* Fills *cfg with defaults. */
 void lt_config_init(lt_config *cfg);
@@ -214,6 +222,12 @@ lt_status lt_host_free(lt_context *ctx, void *ptr);
 lt_status lt_kernel_get(lt_context *ctx, const char *name, lt_kernel **out);
 lt_status lt_kernel_define(lt_context *ctx, const char *base,
                            const char *annotation, lt_kernel **out);
+
+/* Selects a tuning variant of a built-in body for later launches through
+ * this handle (0 = default).  Variants change only the work mapping, never
+ * the per-element arithmetic: jacobi2d_f32 takes 8, 16 or 32 rows per
+ * workgroup tile.  Unknown variants fall back to the default. */
+lt_status lt_kernel_tune(lt_context *ctx, lt_kernel *k, int32_t variant);
 
 /* ------------------------------------------------------------------- launch */
 #define LT_ARG_ARRAY 0

@@ -35,6 +35,7 @@ DTYPES = {LT_F32: np.float32, LT_I32: np.int32, LT_F64: np.float64, LT_I64: np.i
 NP2LT = {np.dtype(v): k for k, v in DTYPES.items()}
 
 LT_EXEC_PLAIN, LT_EXEC_GROUPED = 0, 1
+LT_ORDER_ROWMAJOR, LT_ORDER_SERPENTINE = 0, 1
 LT_DIST_BLOCK, LT_DIST_CUSTOM = 0, 1
 LT_ARG_ARRAY, LT_ARG_INT, LT_ARG_FLOAT = 0, 1, 2
 LT_TASK_EXEC, LT_TASK_COMBINE, LT_TASK_IO = 0, 1, 2
@@ -44,7 +45,8 @@ class lt_config(C.Structure):
     _fields_ = [("device", C.c_int32), ("n_compute_streams", C.c_int32), ("exec_mode", C.c_int32),
                 ("dry_run", C.c_int32), ("device_budget_bytes", C.c_uint64),
                 ("stage_threshold_bytes", C.c_uint64), ("device_arena", C.c_void_p),
-                ("arena_bytes", C.c_uint64), ("trace", C.c_int32), ("reserved", C.c_int32 * 7)]
+                ("arena_bytes", C.c_uint64), ("trace", C.c_int32), ("sb_order", C.c_int32),
+                ("reserved", C.c_int32 * 6)]
 
 
 class lt_box(C.Structure):
@@ -124,6 +126,7 @@ _SIGS = [
     ("lt_host_free", C.c_int32, [_P, _P]),
     ("lt_kernel_get", C.c_int32, [_P, C.c_char_p, C.POINTER(_P)]),
     ("lt_kernel_define", C.c_int32, [_P, C.c_char_p, C.c_char_p, C.POINTER(_P)]),
+    ("lt_kernel_tune", C.c_int32, [_P, _P, C.c_int32]),
     ("lt_launch", C.c_int32, [_P, _P, C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_int64),
                               C.POINTER(C.c_int64), C.c_char_p, C.POINTER(lt_arg), C.c_int32,
                               C.POINTER(C.c_uint64)]),
@@ -308,6 +311,9 @@ class Context:
                 check(self.h, lt_kernel_define(self.h, name.encode(), annotation.encode(), C.byref(k)))
             self._kernels[key] = k
         return self._kernels[key]
+
+    def tune(self, name, variant, kernel_annotation=None):
+        check(self.h, lt_kernel_tune(self.h, self.kernel(name, kernel_annotation), int(variant)))
 
     def launch(self, name, grid, block, superblock=None, args=(), annotation=None, kernel_annotation=None):
         """Launch built-in ``name``.  ``args`` is a sequence of Array, int or

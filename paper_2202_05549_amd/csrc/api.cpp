@@ -571,6 +571,12 @@ lt_status lt_kernel_define(lt_context *ctx, const char *base, const char *annota
     return LT_OK;
 }
 
+lt_status lt_kernel_tune(lt_context *ctx, lt_kernel *k, int32_t variant) {
+    if (!ctx || !k) return LT_ERR_INVALID;
+    k->variant = variant;
+    return LT_OK;
+}
+
 lt_status lt_launch(lt_context *ctx, lt_kernel *k, int32_t ndim, const int64_t *grid, const int64_t *block,
                     const int64_t *superblock, const char *annotation, const lt_arg *args, int32_t nargs,
                     uint64_t *launch_id) {

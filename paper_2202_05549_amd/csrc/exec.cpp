@@ -835,6 +835,11 @@ lt_status launch(Ctx *ctx, lt_kernel *k, int nd, const int64_t *grid,
             idx[a] = r % nsb[a];
             r /= nsb[a];
         }
+        if (ctx->cfg.sb_order == LT_ORDER_SERPENTINE && nd >= 2) {
+            // reverse the fastest axis on every other row of superblocks
+            int64_t outer = t / nsb[nd - 1];
+            if (outer & 1) idx[nd - 1] = nsb[nd - 1] - 1 - idx[nd - 1];
+        }
         TaskPlan tp;
         int64_t blo[MAXD], bhi[MAXD];
         for (int a = 0; a < nd; ++a) {
@@ -907,7 +912,7 @@ lt_status launch(Ctx *ctx, lt_kernel *k, int nd, const int64_t *grid,
         proto.farg[p] = fparams[p];
     }
     for (int a = 0; a < MAXD; ++a) proto.block[a] = B[a];
-    proto.variant = 0;
+    proto.variant = k->variant;
     for (auto &P : parts) {
         if (P.total_elems == 0) continue;
         st = flush_group(ctx);

@@ -1,0 +1,217 @@
+// C = A * B in float32 on the CDNA4 matrix cores (v_mfma_f32_32x32x2f32).
+//
+// One task is one superblock of C (thread (i, j) owns C[i][j]; annotation
+// read A[i, :], read B[:, j], write C[i, j]).  A workgroup of 256 threads
+// computes a 256 x 256 block of C: its four waves each own 128 x 128 as
+// 4 x 4 MFMA blocks of 32 x 32 (256 accumulators per lane).  K advances in
+// tiles of 32 staged in LDS: A transposed to [k][m] (odd row stride, so the
+// transposing stores do not collide on banks), B as [k][n].  The LDS tile is
+// double-buffered and the next tile's global loads are in flight while the
+// current one feeds the matrix cores.  Rows/columns/K beyond the operands are
+// read as zero and C is written only inside the task and the matrix.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "kernels.h"
+
+namespace lt {
+
+namespace {
+
+constexpr int BM = 256, BN = 256, BK = 32;
+constexpr int LDA = BM + 1;   // As[k][m]
+constexpr int LDB = BN + 4;   // Bs[k][n]
+constexpr int GMAX = 8;       // tasks per dispatch
+
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+struct GTask {
+    int64_t i0, i1, j0, j1;   // C rows / columns of the task, clipped to M, N
+    int64_t a, b, c;          // pre-offset bases
+    int64_t as, bs, cs;       // row strides
+    int tn;                   // column tiles
+    int vec;                  // 16-byte loads usable for A and B
+};
+
+struct GArgs {
+    int64_t K;
+    int ntask, nblocks;
+    int begin[GMAX + 1];
+    GTask t[GMAX];
+};
+
+__device__ __forceinline__ int find_task_g(const int *begin, int ntask, int b) {
+    int lo = 0, hi = ntask - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (begin[mid] <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ int xcd_remap_g(int b, int nb) {
+    int per = nb >> 3;
+    if (b >= (per << 3)) return b;
+    return (b & 7) * per + (b >> 3);
+}
+
+}  // namespace
+
+__global__ __launch_bounds__(256, 1) void k_gemm(GArgs g) {
+    __shared__ float As[2][BK][LDA];
+    __shared__ float Bs[2][BK][LDB];
+
+    const int b = xcd_remap_g(blockIdx.x, g.nblocks);
+    const int ti = find_task_g(g.begin, g.ntask, b);
+    const GTask &t = g.t[ti];
+    const int local = b - g.begin[ti];
+    const int tmi = local / t.tn, tni = local - tmi * t.tn;
+    const int64_t m0 = t.i0 + (int64_t)tmi * BM;
+    const int64_t n0 = t.j0 + (int64_t)tni * BN;
+    const int64_t K = g.K;
+    const float *A = reinterpret_cast<const float *>(t.a);
+    const float *B = reinterpret_cast<const float *>(t.b);
+    float *C = reinterpret_cast<float *>(t.c);
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int wm = (wave >> 1) * 128, wn = (wave & 1) * 128;
+
+    // global -> register staging of one K tile
+    // A: thread covers rows tid/8 + 32*j, k4 = tid%8 (8 float4)
+    // B: thread covers k = tid/64 + 4*j, n4 = tid%64 (8 float4)
+    float4 ra[8], rb[8];
+    const int a_row = tid >> 3, a_k4 = tid & 7;
+    const int b_k = tid >> 6, b_n4 = tid & 63;
+
+    auto load_tile = [&](int64_t k0) {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int64_t r = m0 + a_row + 32 * j;
+            const int64_t k = k0 + a_k4 * 4;
+            if (t.vec && r < t.i1 && k + 3 < K) {
+                ra[j] = *reinterpret_cast<const float4 *>(A + r * t.as + k);
+            } else {
+                float v[4];
+                for (int q = 0; q < 4; ++q) v[q] = (r < t.i1 && k + q < K) ? A[r * t.as + k + q] : 0.f;
+                ra[j] = make_float4(v[0], v[1], v[2], v[3]);
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int64_t k = k0 + b_k + 4 * j;
+            const int64_t c = n0 + b_n4 * 4;
+            if (t.vec && k < K && c + 3 < t.j1) {
+                rb[j] = *reinterpret_cast<const float4 *>(B + k * t.bs + c);
+            } else {
+                float v[4];
+                for (int q = 0; q < 4; ++q) v[q] = (k < K && c + q < t.j1) ? B[k * t.bs + c + q] : 0.f;
+                rb[j] = make_float4(v[0], v[1], v[2], v[3]);
+            }
+        }
+    };
+    auto store_tile = [&](int buf) {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int m = a_row + 32 * j;
+            As[buf][a_k4 * 4 + 0][m] = ra[j].x;
+            As[buf][a_k4 * 4 + 1][m] = ra[j].y;
+            As[buf][a_k4 * 4 + 2][m] = ra[j].z;
+            As[buf][a_k4 * 4 + 3][m] = ra[j].w;
+        }
+#pragma unroll
+        for (int j = 0; j < 8; ++j) *reinterpret_cast<float4 *>(&Bs[buf][b_k + 4 * j][b_n4 * 4]) = rb[j];
+    };
+
+    f32x16 acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+            for (int v = 0; v < 16; ++v) acc[i][j][v] = 0.f;
+
+    const int nk = (int)((K + BK - 1) / BK);
+    load_tile(0);
+    store_tile(0);
+    __syncthreads();
+    const int half = lane >> 5, l32 = lane & 31;
+    for (int kt = 0; kt < nk; ++kt) {
+        const int buf = kt & 1;
+        const bool more = kt + 1 < nk;
+        if (more) load_tile((int64_t)(kt + 1) * BK);
+        // the next tile goes into the other LDS buffer half-way through this
+        // one, so its stores overlap the matrix-core work
+#pragma unroll
+        for (int s = 0; s < BK / 2; ++s) {
+            if (s == BK / 4 && more) store_tile(buf ^ 1);
+            const int k = 2 * s + half;
+            float av[4], bv[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) av[i] = As[buf][k][wm + 32 * i + l32];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) bv[j] = Bs[buf][k][wn + 32 * j + l32];
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[i], bv[j], acc[i][j], 0, 0, 0);
+        }
+        __syncthreads();
+    }
+
+    // accumulator v of a 32 x 32 block holds row 8*(v/4) + 4*(lane/32) + v%4,
+    // column lane%32
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int64_t col = n0 + wn + 32 * j + l32;
+#pragma unroll
+            for (int v = 0; v < 16; ++v) {
+                const int64_t row = m0 + wm + 32 * i + 8 * (v >> 2) + 4 * half + (v & 3);
+                if (row < t.i1 && col < t.j1) C[row * t.cs + col] = acc[i][j][v];
+            }
+        }
+}
+
+hipError_t launch_gemm_f32(const KLaunch &L) {
+    GArgs g;
+    const int64_t M = L.iarg[0], N = L.iarg[1];
+    g.K = L.iarg[2];
+    if (L.ntask > GMAX) return hipErrorInvalidValue;
+    g.ntask = L.ntask;
+    int64_t nb = 0;
+    for (int i = 0; i < L.ntask; ++i) {
+        const KTask &k = L.tasks[i];
+        GTask &t = g.t[i];
+        t.i0 = k.lo[0];
+        t.i1 = k.hi[0] < M ? k.hi[0] : M;
+        t.j0 = k.lo[1];
+        t.j1 = k.hi[1] < N ? k.hi[1] : N;
+        t.c = k.v[3].base;
+        t.cs = k.v[3].s[0];
+        t.a = k.v[4].base;
+        t.as = k.v[4].s[0];
+        t.b = k.v[5].base;
+        t.bs = k.v[5].s[0];
+        // 16-byte loads need every row start of A (from column 0) and of B
+        // (from the task's first column) on a 16-byte boundary
+        t.vec = (t.as % 4 == 0) && (t.bs % 4 == 0) && (t.a % 16 == 0) && ((t.b + t.j0 * 4) % 16 == 0) &&
+                (t.j0 % 4 == 0);
+        int64_t rows = t.i1 - t.i0, cols = t.j1 - t.j0;
+        int64_t tm = rows > 0 ? (rows + BM - 1) / BM : 0;
+        t.tn = cols > 0 ? (int)((cols + BN - 1) / BN) : 0;
+        g.begin[i] = (int)nb;
+        nb += tm * t.tn;
+    }
+    g.begin[L.ntask] = (int)nb;
+    g.nblocks = (int)nb;
+    if (nb == 0) return hipSuccess;  // K = 0 still runs: C becomes the empty sum, 0
+    hipLaunchKernelGGL(k_gemm, dim3((unsigned)nb), dim3(256), 0, L.stream, g);
+    return hipGetLastError();
+}
+
+}  // namespace lt

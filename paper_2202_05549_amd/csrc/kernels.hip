@@ -49,6 +49,14 @@ __device__ __forceinline__ int xcd_remap(int b, int nb) {
 
 inline unsigned grid_of(int64_t blocks) { return (unsigned)blocks; }
 
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// 16-byte store that bypasses cache retention (streaming output)
+__device__ __forceinline__ void nt_store4(float *p, float4 v) {
+    f32x4 w = {v.x, v.y, v.z, v.w};
+    __builtin_nontemporal_store(w, reinterpret_cast<f32x4 *>(p));
+}
+
 }  // namespace
 
 // ==================================================================== touch
@@ -172,7 +180,7 @@ hipError_t launch_stencil1d_f32(const KLaunch &L) {
 // ================================================================= jacobi2d
 // y[r][c] = 0.25*((x[r-1][c] + x[r+1][c]) + (x[r][c-1] + x[r][c+1])), zero
 // outside the n x m field.  A workgroup owns 1024 columns (4 per thread) of
-// JROWS consecutive rows and slides a three-row window down them, so every
+// RB consecutive rows and slides a three-row window down them, so every
 // input row is loaded once per tile; horizontal neighbours come from the
 // adjacent lanes.
 struct JTask {
@@ -196,6 +204,12 @@ __device__ __forceinline__ float jpoint(float u, float d, float l, float r) {
     return 0.25f * s;
 }
 
+// Full tiles (RB rows inside the field, float4 layout) take the unrolled
+// path: all RB + 2 input rows of the thread's four columns are loaded before
+// any arithmetic, which keeps RB + 2 independent 16-byte loads per lane in
+// flight; the output rows are written with non-temporal stores (they are
+// not read again by this sweep).  Ragged tiles use the sliding window.
+template <int RB>
 __global__ __launch_bounds__(256) void k_jacobi2d(JArgs a) {
     const int b = xcd_remap(blockIdx.x, a.nblocks);
     const int ti = find_task(a.begin, a.ntask, b);
@@ -203,8 +217,8 @@ __global__ __launch_bounds__(256) void k_jacobi2d(JArgs a) {
     const int local = b - a.begin[ti];
     const int tyi = local / t.tx, txi = local - tyi * t.tx;
     const int64_t n = a.n, m = a.m;
-    const int64_t r0 = t.r0 + (int64_t)tyi * a.rows;
-    const int64_t r1e = r0 + a.rows < t.r1 ? r0 + a.rows : t.r1;
+    const int64_t r0 = t.r0 + (int64_t)tyi * RB;
+    const int64_t r1e = r0 + RB < t.r1 ? r0 + RB : t.r1;
     const int64_t r1 = r1e < n ? r1e : n;
     const int64_t cend = t.c1 < m ? t.c1 : m;            // outputs [c0, cend)
     const int64_t rcend = cend + 1 < m ? cend + 1 : m;     // inputs read up to rcend
@@ -213,6 +227,37 @@ __global__ __launch_bounds__(256) void k_jacobi2d(JArgs a) {
     const float *X = reinterpret_cast<const float *>(t.x);
     float *Y = reinterpret_cast<float *>(t.y);
     const int lane = threadIdx.x & (WAVE - 1);
+
+    if (t.vec && r1 - r0 == RB) {
+        float4 v[RB + 2];
+#pragma unroll
+        for (int i = 0; i < RB + 2; ++i) {
+            const int64_t r = r0 - 1 + i;
+            if (active && r >= 0 && r < n)
+                v[i] = *reinterpret_cast<const float4 *>(X + r * t.xs + col);
+            else
+                v[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+#pragma unroll
+        for (int i = 1; i <= RB; ++i) {
+            const int64_t r = r0 - 1 + i;
+            const float4 up = v[i - 1], mid = v[i], dn = v[i + 1];
+            float left = __shfl_up(mid.w, 1);
+            float right = __shfl_down(mid.x, 1);
+            const float *row = X + r * t.xs;
+            if (active && lane == 0) left = (col - 1 >= 0) ? row[col - 1] : 0.f;
+            if (active && (lane == WAVE - 1 || col + 4 >= cend)) right = (col + 4 < m) ? row[col + 4] : 0.f;
+            if (active) {
+                float4 o;
+                o.x = jpoint(up.x, dn.x, left, mid.y);
+                o.y = jpoint(up.y, dn.y, mid.x, mid.z);
+                o.z = jpoint(up.z, dn.z, mid.y, mid.w);
+                o.w = jpoint(up.w, dn.w, mid.z, right);
+                nt_store4(Y + r * t.ys + col, o);
+            }
+        }
+        return;
+    }
 
     // lanes past the last output column still load the halo column cend
     // (read by their left neighbour lane) when it lies inside the field
@@ -269,7 +314,8 @@ hipError_t launch_jacobi2d_f32(const KLaunch &L) {
     a.n = L.iarg[0];
     a.m = L.iarg[1];
     a.ntask = L.ntask;
-    a.rows = L.variant > 0 ? L.variant : 16;
+    // rows per tile: 8, 16 (default) or 32
+    a.rows = (L.variant == 8 || L.variant == 32) ? L.variant : 16;
     int64_t nb = 0;
     for (int i = 0; i < L.ntask; ++i) {
         const KTask &k = L.tasks[i];
@@ -293,7 +339,12 @@ hipError_t launch_jacobi2d_f32(const KLaunch &L) {
     a.begin[L.ntask] = (int)nb;
     a.nblocks = (int)nb;
     if (nb == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_jacobi2d, dim3(grid_of(nb)), dim3(256), 0, L.stream, a);
+    if (a.rows == 8)
+        hipLaunchKernelGGL(k_jacobi2d<8>, dim3(grid_of(nb)), dim3(256), 0, L.stream, a);
+    else if (a.rows == 32)
+        hipLaunchKernelGGL(k_jacobi2d<32>, dim3(grid_of(nb)), dim3(256), 0, L.stream, a);
+    else
+        hipLaunchKernelGGL(k_jacobi2d<16>, dim3(grid_of(nb)), dim3(256), 0, L.stream, a);
     return hipGetLastError();
 }
 
@@ -542,8 +593,5 @@ hipError_t launch_combine(hipStream_t s, const CombineArgs &a) {
     }
     return hipGetLastError();
 }
-
-// ================================================================== gemm
-hipError_t launch_gemm_f32(const KLaunch &) { return hipErrorNotSupported; }
 
 }  // namespace lt

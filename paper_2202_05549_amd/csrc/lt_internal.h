@@ -137,6 +137,7 @@ const KernelDef *find_builtin(const char *name);
 struct lt_kernel {
     const lt::KernelDef *def;
     std::shared_ptr<lt::Annotation> annot;
+    int variant = 0;
 };
 
 namespace lt {

@@ -231,3 +231,93 @@ def test_kmeans_assign_labels_bit_exact(L, N, d, K, chunk):
         ctx.sync()
         got = lab.read()
     assert np.array_equal(got, oracle.kmeans_assign(X, mu))
+
+
+# -------------------------------------------------------------------- GEMM
+# Tolerance (componentwise, from the float32 error of a length-K dot product
+# and the workload's 1e-5): |C - C_ref| <= 1e-5 * (|A| |B|) elementwise, with
+# C_ref and |A||B| in float64.
+
+def _gemm_case(L, M, N, K, chunkA, chunkB, chunkC, sb, seed=21, ident=False):
+    rng = np.random.default_rng(seed)
+    A = rng.standard_normal((M, K), dtype=np.float32)
+    B = np.eye(K, N, dtype=np.float32) if ident else rng.standard_normal((K, N), dtype=np.float32)
+    with ctx_of(L) as ctx:
+        a = ctx.array([M, K], chunk=list(chunkA))
+        b = ctx.array([K, N], chunk=list(chunkB))
+        c = ctx.array([M, N], chunk=list(chunkC))
+        a.write(A)
+        b.write(B)
+        c.fill(np.nan)
+        ctx.launch("gemm_f32", [M, N], [1, 1], list(sb), args=[M, N, K, c, a, b])
+        ctx.sync()
+        got = c.read()
+    return A, B, got
+
+
+@pytest.mark.parametrize("M,N,K,chunkA,chunkB,chunkC,sb", [
+    (300, 260, 77, (128, 0), (0, 100), (128, 100), (128, 100)),
+    (256, 256, 64, (0, 0), (0, 0), (0, 0), (0, 0)),
+    (513, 257, 129, (200, 0), (0, 0), (0, 0), (256, 0)),   # odd strides: scalar loads
+    (64, 1000, 1, (0, 0), (0, 500), (64, 500), (64, 500)),
+])
+def test_gemm_small_componentwise(L, M, N, K, chunkA, chunkB, chunkC, sb):
+    say("gemm", M, N, K, sb)
+    A, B, got = _gemm_case(L, M, N, K, chunkA, chunkB, chunkC, sb)
+    ref = oracle.gemm(A, B)
+    scale = oracle.gemm(np.abs(A), np.abs(B))
+    assert not np.isnan(got).any()
+    assert np.all(np.abs(got - ref) <= 1e-5 * scale + 1e-30)
+
+
+def test_gemm_identity_is_exact(L):
+    say("gemm identity")
+    A, B, got = _gemm_case(L, 512, 384, 384, (256, 0), (0, 128), (256, 128), (256, 128), ident=True)
+    assert np.array_equal(got, A[:, :384])
+
+
+def test_gemm_one_4096_tile_sampled(L):
+    M = N = 4096
+    K = 8192
+    say("gemm 4096 tile")
+    A, B, got = _gemm_case(L, M, N, K, (4096, 0), (0, 4096), (4096, 4096), (4096, 4096), seed=2)
+    rng = np.random.default_rng(5)
+    ii = rng.integers(0, M, 2048)
+    jj = rng.integers(0, N, 2048)
+    val, av = oracle.gemm_entries(A, B, ii, jj)
+    assert np.all(np.abs(got[ii, jj] - val) <= 1e-5 * av)
+    assert oracle.freivalds(A, B, got) < 1e-5
+
+
+def test_gemm_config3_out_of_core(L):
+    # C = A B, FP32, 65536^2 operands (16 GiB each) in pinned host memory,
+    # device budget 16 GiB, 4096^2 superblocks in serpentine order: A is split
+    # in 4096-row panels, B in 4096-column panels, C in 4096^2 tiles.  Checked
+    # by Freivalds at full size and 4096 sampled entries against float64.
+    n, T = 65536, 4096
+    say("gemm config3: allocating 48 GiB pinned host memory")
+    with ctx_of(L, device_budget_bytes=16 << 30, stage_threshold_bytes=8 << 30,
+                sb_order=L.LT_ORDER_SERPENTINE) as ctx:
+        A = ctx.pinned((n, n))
+        B = ctx.pinned((n, n))
+        Cm = ctx.pinned((n, n))
+        say("gemm config3: generating operands")
+        synthetic.gemm_operand(0, n, T, out=A, workers=16)
+        synthetic.gemm_operand(1, n, T, out=B, workers=16)
+        a = ctx.array_host(A, chunk=[T, 0])
+        b = ctx.array_host(B, chunk=[0, T])
+        c = ctx.array_host(Cm, chunk=[T, T])
+        say("gemm config3: launching")
+        ctx.launch("gemm_f32", [n, n], [1, 1], [T, T], args=[n, n, n, c, a, b])
+        ctx.sync()
+        st = ctx.stats()
+        say("gemm config3: H2D GiB %.1f D2H GiB %.1f" % (st["bytes_h2d"] / 2**30, st["bytes_d2h"] / 2**30))
+        assert st["peak_resident_bytes"] <= 16 << 30
+        assert st["evictions_dirty"] > 0
+        rng = np.random.default_rng(7)
+        ii = rng.integers(0, n, 4096)
+        jj = rng.integers(0, n, 4096)
+        val, av = oracle.gemm_entries(A, B, ii, jj)
+        assert np.all(np.abs(Cm[ii, jj] - val) <= 1e-5 * av)
+        say("gemm config3: Freivalds")
+        assert oracle.freivalds(A, B, Cm, trials=2) < 1e-5
