@@ -100,7 +100,9 @@ typedef struct lt_config {
                                        (odd rows of superblocks reversed, so
                                        consecutive rows reuse the chunks the
                                        previous row touched last)            */
-    int32_t reserved[6];
+    int32_t drain_workgroups;       /* workgroups of the batch drain kernel;
+                                       0 = 1024                               */
+    int32_t reserved[5];
 } lt_config;
 
 #define LT_ORDER_ROWMAJOR 0
@@ -256,6 +258,17 @@ lt_status lt_launch(lt_context *ctx, lt_kernel *k, int32_t ndim,
                     const int64_t *superblock, const char *annotation,
                     const lt_arg *args, int32_t nargs, uint64_t *launch_id);
 
+/* count launches in one call, exactly as count successive lt_launch calls:
+ * launch i runs kernels[i] over grids[i*ndim ...] with blocks[i*ndim ...],
+ * superblocks[i*ndim ...] (NULL = whole grid) and args[i*nargs ...]; all
+ * launches share ndim, nargs and the annotation (NULL = each kernel's own).
+ * launch_ids (may be NULL) receives count ids.  Stops at the first failing
+ * launch and returns its error; the launches before it stay issued. */
+lt_status lt_launch_many(lt_context *ctx, lt_kernel *const *kernels, int32_t count,
+                         int32_t ndim, const int64_t *grids, const int64_t *blocks,
+                         const int64_t *superblocks, const char *annotation,
+                         const lt_arg *args, int32_t nargs, uint64_t *launch_ids);
+
 /* Blocks until every issued launch has finished and host-backed arrays hold
  * their contents (Sec. 3.6 "synchronize").  Returns and clears the first
  * sticky device error. */
@@ -263,6 +276,23 @@ lt_status lt_sync(lt_context *ctx);
 
 /* Blocks until launch `launch_id` has finished. */
 lt_status lt_wait(lt_context *ctx, uint64_t launch_id);
+
+/* ------------------------------------------------------------------ batching
+ * lt_batch_begin opens a batch: later launches are planned as usual, but
+ * their tasks become entries of a device task table instead of dispatches.
+ * lt_batch_end (or any call that needs the results: lt_sync, lt_wait,
+ * lt_array_read/write/fill/destroy) issues the table with one upload, one
+ * clear of its counters and ONE persistent drain dispatch; the batch stays
+ * open for further launches until lt_batch_end.  Edges between tasks of the
+ * batch become counter waits inside the drain; edges to earlier work become
+ * stream waits before it.  Results are identical to the unbatched path.
+ * Supported bodies: touch_i32, stencil1d_f32, jacobi2d_f32, hist256_i32
+ * (int32 reduce(+) with equal partial boxes).  Every chunk a batched task
+ * touches must be resident: LT_ERR_UNSUPPORTED otherwise (and for other
+ * bodies).  A dependency wait inside the drain that exceeds its poll limit
+ * reports LT_ERR_TIMEOUT at the next lt_sync. */
+lt_status lt_batch_begin(lt_context *ctx);
+lt_status lt_batch_end(lt_context *ctx);
 
 /* ----------------------------------------------------------- introspection
  * Planner output of a launch, for tests and tools.  Task records are kept

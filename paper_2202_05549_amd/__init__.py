@@ -46,7 +46,7 @@ class lt_config(C.Structure):
                 ("dry_run", C.c_int32), ("device_budget_bytes", C.c_uint64),
                 ("stage_threshold_bytes", C.c_uint64), ("device_arena", C.c_void_p),
                 ("arena_bytes", C.c_uint64), ("trace", C.c_int32), ("sb_order", C.c_int32),
-                ("reserved", C.c_int32 * 6)]
+                ("drain_workgroups", C.c_int32), ("reserved", C.c_int32 * 5)]
 
 
 class lt_box(C.Structure):
@@ -92,6 +92,11 @@ class lt_kernel_prof(C.Structure):
                 ("max_ms", C.c_double)]
 
 
+# numpy mirror of lt_arg, for building argument tables without Python loops
+ARG_DTYPE = np.dtype([("name", np.uint64), ("kind", np.int32), ("pad", np.int32), ("array", np.uint64),
+                      ("i", np.int64), ("f", np.float64)])
+
+
 class LtError(RuntimeError):
     def __init__(self, status, msg):
         super().__init__("%s: %s" % (_ERRNAMES.get(status, str(status)), msg))
@@ -130,7 +135,11 @@ _SIGS = [
     ("lt_launch", C.c_int32, [_P, _P, C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_int64),
                               C.POINTER(C.c_int64), C.c_char_p, C.POINTER(lt_arg), C.c_int32,
                               C.POINTER(C.c_uint64)]),
+    ("lt_launch_many", C.c_int32, [_P, C.POINTER(_P), C.c_int32, C.c_int32, C.c_void_p, C.c_void_p,
+                                   C.c_void_p, C.c_char_p, C.c_void_p, C.c_int32, C.c_void_p]),
     ("lt_sync", C.c_int32, [_P]),
+    ("lt_batch_begin", C.c_int32, [_P]),
+    ("lt_batch_end", C.c_int32, [_P]),
     ("lt_wait", C.c_int32, [_P, C.c_uint64]),
     ("lt_plan_tasks", C.c_int32, [_P, C.c_uint64, C.POINTER(lt_task_info), C.c_int32, C.POINTER(C.c_int32)]),
     ("lt_plan_regions", C.c_int32, [_P, C.c_uint64, C.POINTER(lt_region_info), C.c_int32,
@@ -340,6 +349,52 @@ class Context:
         check(self.h, lt_launch(self.h, k, nd, _i64(grid, nd), _i64(block, nd), _i64(sb, nd),
                                 annotation.encode() if annotation else None, A, len(args), C.byref(lid)))
         return lid.value
+
+    def batch_begin(self):
+        check(self.h, lt_batch_begin(self.h))
+
+    def batch_end(self):
+        check(self.h, lt_batch_end(self.h))
+
+    def launch_many(self, names, grids, blocks, superblocks, args, annotation=None):
+        """Many launches in one call.  ``names``: kernel name per launch (or
+        one name); ``grids``/``blocks``/``superblocks``: int arrays (count, ndim);
+        ``args``: ARG_DTYPE array (count, nargs) - see ``arg_table``."""
+        grids = np.ascontiguousarray(grids, dtype=np.int64)
+        count, nd = grids.shape
+        blocks = np.ascontiguousarray(np.broadcast_to(blocks, grids.shape), dtype=np.int64)
+        sbs = None if superblocks is None else np.ascontiguousarray(np.broadcast_to(superblocks, grids.shape),
+                                                                     dtype=np.int64)
+        if isinstance(names, str):
+            names = [names] * count
+        ks = (_P * max(1, count))()
+        cache = {}
+        for i, nm in enumerate(names):
+            if nm not in cache:
+                cache[nm] = self.kernel(nm).value
+            ks[i] = cache[nm]
+        args = np.ascontiguousarray(args)
+        assert args.dtype == ARG_DTYPE and args.shape[0] == count
+        ids = np.zeros(count, dtype=np.uint64)
+        check(self.h, lt_launch_many(self.h, ks, count, nd, grids.ctypes.data, blocks.ctypes.data,
+                                     None if sbs is None else sbs.ctypes.data,
+                                     annotation.encode() if annotation else None, args.ctypes.data,
+                                     args.shape[1], ids.ctypes.data))
+        return ids
+
+    @staticmethod
+    def arg_table(count, columns):
+        """ARG_DTYPE table (count, len(columns)); each column is a list/array of
+        Array handles (LT_ARG_ARRAY) or an int array (LT_ARG_INT)."""
+        t = np.zeros((count, len(columns)), dtype=ARG_DTYPE)
+        for j, col in enumerate(columns):
+            if len(col) and isinstance(col[0], Array):
+                t["kind"][:, j] = LT_ARG_ARRAY
+                t["array"][:, j] = np.array([a.h.value for a in col], dtype=np.uint64)
+            else:
+                t["kind"][:, j] = LT_ARG_INT
+                t["i"][:, j] = np.asarray(col, dtype=np.int64)
+        return t
 
     def sync(self):
         check(self.h, lt_sync(self.h))

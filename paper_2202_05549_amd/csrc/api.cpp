@@ -10,13 +10,13 @@ namespace lt {
 // ----------------------------------------------------------- built-in table
 static const KernelDef kBuiltins[] = {
     {"touch_i32", "global i => readwrite y[i]", 2,
-     {{"n", P_INT, LT_I32, 0}, {"y", P_ARRAY, LT_I32, 1}}, 1, launch_touch_i32, KMAXG},
+     {{"n", P_INT, LT_I32, 0}, {"y", P_ARRAY, LT_I32, 1}}, 1, launch_touch_i32, KMAXG, DK_TOUCH},
     {"stencil1d_f32", "global i => read x[i-1:i+1], write y[i]", 3,
      {{"n", P_INT, LT_F32, 0}, {"y", P_ARRAY, LT_F32, 1}, {"x", P_ARRAY, LT_F32, 1}}, 1,
-     launch_stencil1d_f32, KMAXG},
+     launch_stencil1d_f32, KMAXG, DK_STENCIL1D},
     {"jacobi2d_f32", "global [r, c] => read x[r-1:r+1, c-1:c+1], write y[r, c]", 4,
      {{"n", P_INT, LT_F32, 0}, {"m", P_INT, LT_F32, 0}, {"y", P_ARRAY, LT_F32, 2}, {"x", P_ARRAY, LT_F32, 2}},
-     2, launch_jacobi2d_f32, KMAXG},
+     2, launch_jacobi2d_f32, KMAXG, DK_JACOBI2D},
     {"gemm_f32", "global [i, j] => read A[i, :], read B[:, j], write C[i, j]", 6,
      {{"M", P_INT, LT_F32, 0},
       {"N", P_INT, LT_F32, 0},
@@ -24,10 +24,10 @@ static const KernelDef kBuiltins[] = {
       {"C", P_ARRAY, LT_F32, 2},
       {"A", P_ARRAY, LT_F32, 2},
       {"B", P_ARRAY, LT_F32, 2}},
-     2, launch_gemm_f32, 8},
+     2, launch_gemm_f32, 8, -1},
     {"hist256_i32", "global i => read v[i], reduce(+) h[:]", 3,
      {{"n", P_INT, LT_I32, 0}, {"h", P_ARRAY, LT_I32, 1}, {"v", P_ARRAY, LT_I32, 1}}, 1,
-     launch_hist256_i32, 1},
+     launch_hist256_i32, 1, DK_HIST256},
     {"kmeans_assign_f32", "global i => read X[i, :], read Cen[:, :], write lab[i]", 6,
      {{"N", P_INT, LT_F32, 0},
       {"d", P_INT, LT_F32, 0},
@@ -35,7 +35,7 @@ static const KernelDef kBuiltins[] = {
       {"lab", P_ARRAY, LT_I32, 1},
       {"X", P_ARRAY, LT_F32, 2},
       {"Cen", P_ARRAY, LT_F32, 2}},
-     1, launch_kmeans_assign_f32, KMAXG},
+     1, launch_kmeans_assign_f32, KMAXG, -1},
 };
 
 const KernelDef *find_builtin(const char *name) {
@@ -56,14 +56,15 @@ static int dtype_size(lt_dtype d) {
     return 0;
 }
 
+// A handle is live while it belongs to this context and was not destroyed.
+// (Handles of destroyed arrays stay valid memory until the next lt_sync.)
 static bool live(Ctx *ctx, Array *arr) {
-    if (!arr || arr->dead) return false;
-    return std::find(ctx->arrays.begin(), ctx->arrays.end(), arr) != ctx->arrays.end();
+    return arr && arr->magic == LT_ARRAY_MAGIC && arr->owner == ctx && !arr->dead;
 }
 
 // ------------------------------------------------------------------- sync
 lt_status sync_all(Ctx *ctx) {
-    lt_status st = flush_group(ctx);
+    lt_status st = flush_all(ctx);
     // write dirty chunks of host-backed arrays back to their home buffers
     for (Array *arr : ctx->arrays) {
         if (arr->dead || !arr->host_backed) continue;
@@ -93,7 +94,19 @@ lt_status sync_all(Ctx *ctx) {
             if (r != hipSuccess && !st) st = hip_fail(ctx, r, "hipStreamSynchronize");
         }
         prof_collect(ctx);
+        for (int i = 0; i < ctx->status_next; ++i)
+            if (ctx->status_host[i] && ctx->sticky == LT_OK) {
+                ctx->sticky = LT_ERR_TIMEOUT;
+                ctx->sticky_msg = "a dependency wait inside the batch drain exceeded its poll limit";
+            }
+        ctx->status_next = 0;
     }
+    for (size_t i = 0; i < ctx->staging_used.size(); ++i) {
+        ctx->staging_free.push_back(ctx->staging_used[i]);
+        ctx->staging_size_free.push_back(ctx->staging_size_used[i]);
+    }
+    ctx->staging_used.clear();
+    ctx->staging_size_used.clear();
     for (int s = 0; s < ctx->nstreams; ++s) {
         Stream &S = ctx->streams[s];
         S.done = S.seq;
@@ -101,9 +114,8 @@ lt_status sync_all(Ctx *ctx) {
         S.marks.clear();
     }
     // every task has completed: forget the DAG
-    ctx->tasks.clear();
-    ctx->launch_tasks.clear();
-    ctx->launch_done.clear();
+    ctx->tasks.reset(ctx->next_task_id);
+    ctx->launches.reset(ctx->next_launch_id);
     ctx->staged.clear();
     ctx->staged_bytes = 0;
     for (Array *arr : ctx->arrays)
@@ -127,6 +139,7 @@ lt_status sync_all(Ctx *ctx) {
             }
             delete c;
         }
+        arr->magic = 0;
         delete arr;
     }
     ctx->arrays.swap(keep);
@@ -151,7 +164,13 @@ void ctx_release_all(Ctx *ctx) {
         for (hipEvent_t e : ctx->prof_pool) (void)hipEventDestroy(e);
         if (ctx->arena_owned && ctx->arena_base) (void)hipFree(ctx->arena_base);
         for (void *p : ctx->host_allocs) (void)hipHostFree(p);
+        for (void *p : ctx->staging_free) (void)hipHostFree(p);
+        if (ctx->status_host) (void)hipHostFree(ctx->status_host);
+    } else {
+        for (void *p : ctx->staging_free) free(p);
     }
+    ctx->staging_free.clear();
+    ctx->status_host = nullptr;
     ctx->event_pool.clear();
     ctx->host_allocs.clear();
 }
@@ -161,7 +180,7 @@ void ctx_release_all(Ctx *ctx) {
 // are overwritten after all earlier uses; chunks of a host-backed array that
 // are not on the device are written in their home buffer.
 lt_status array_write(Ctx *ctx, Array *arr, const void *src, bool device_src) {
-    lt_status st = flush_group(ctx);
+    lt_status st = flush_all(ctx);
     if (st) return st;
     TaskRec rec;
     rec.id = ctx->next_task_id++;
@@ -225,7 +244,7 @@ lt_status array_write(Ctx *ctx, Array *arr, const void *src, bool device_src) {
         c->reduce_op = -1;
     }
     rec.seq = ctx->streams[ctx->h2d].seq;
-    ctx->tasks[rec.id] = rec;
+    ctx->tasks.at(rec.id) = std::move(rec);
     if (!ctx->dry) {
         hipError_t r = hipStreamSynchronize(ctx->streams[ctx->h2d].h);
         if (r != hipSuccess) return hip_fail(ctx, r, "hipStreamSynchronize");
@@ -235,7 +254,7 @@ lt_status array_write(Ctx *ctx, Array *arr, const void *src, bool device_src) {
 
 lt_status array_read(Ctx *ctx, Array *arr, void *dst, bool device_dst) {
     if (ctx->dry) return set_err(ctx, LT_ERR_INVALID, "array contents are unavailable in a dry run");
-    lt_status st = flush_group(ctx);
+    lt_status st = flush_all(ctx);
     if (st) return st;
     const int nd = arr->ndim;
     bool need_host = false;
@@ -288,7 +307,7 @@ lt_status array_read(Ctx *ctx, Array *arr, void *dst, bool device_dst) {
 }
 
 lt_status array_fill(Ctx *ctx, Array *arr, const void *scalar) {
-    lt_status st = flush_group(ctx);
+    lt_status st = flush_all(ctx);
     if (st) return st;
     TaskRec rec;
     rec.id = ctx->next_task_id++;
@@ -348,12 +367,12 @@ lt_status array_fill(Ctx *ctx, Array *arr, const void *scalar) {
         c->reducers.clear();
     }
     rec.seq = ctx->streams[0].seq;
-    ctx->tasks[rec.id] = rec;
+    ctx->tasks.at(rec.id) = std::move(rec);
     return LT_OK;
 }
 
 lt_status array_destroy(Ctx *ctx, Array *arr) {
-    lt_status st = flush_group(ctx);
+    lt_status st = flush_all(ctx);
     if (st) return st;
     arr->dead = true;
     for (Chunk *c : arr->chunks) {
@@ -457,6 +476,7 @@ static lt_status create_common(lt_context *ctx, lt_dtype dtype, int32_t ndim, co
     for (int a = 0; a < ndim; ++a)
         if (shape[a] <= 0) return set_err(ctx, LT_ERR_INVALID, "shape[%d] must be > 0", a);
     Array *arr = new Array();
+    arr->owner = ctx;
     arr->id = ctx->next_array_id++;
     arr->dtype = dtype;
     arr->esz = esz;
@@ -588,6 +608,41 @@ lt_status lt_launch(lt_context *ctx, lt_kernel *k, int32_t ndim, const int64_t *
     return launch(ctx, k, ndim, grid, block, superblock, annotation, args, nargs, launch_id);
 }
 
+lt_status lt_launch_many(lt_context *ctx, lt_kernel *const *kernels, int32_t count, int32_t ndim,
+                         const int64_t *grids, const int64_t *blocks, const int64_t *superblocks,
+                         const char *annotation, const lt_arg *args, int32_t nargs, uint64_t *launch_ids) {
+    if (!ctx) return LT_ERR_INVALID;
+    if (count < 0 || !kernels || !grids || !blocks || ndim < 1 || ndim > 3 || (nargs > 0 && !args))
+        return set_err(ctx, LT_ERR_INVALID, "invalid lt_launch_many arguments");
+    for (int32_t i = 0; i < count; ++i) {
+        const lt_arg *a = args + (size_t)i * nargs;
+        for (int j = 0; j < nargs; ++j)
+            if (a[j].kind == LT_ARG_ARRAY && !live(ctx, a[j].array))
+                return set_err(ctx, LT_ERR_INVALID, "launch %d argument %d is not a live array", i, j);
+        uint64_t id = 0;
+        lt_status st = launch(ctx, kernels[i], ndim, grids + (size_t)i * ndim, blocks + (size_t)i * ndim,
+                              superblocks ? superblocks + (size_t)i * ndim : nullptr, annotation, a, nargs, &id);
+        if (launch_ids) launch_ids[i] = id;
+        if (st) return st;
+    }
+    return LT_OK;
+}
+
+lt_status lt_batch_begin(lt_context *ctx) {
+    if (!ctx) return LT_ERR_INVALID;
+    lt_status st = flush_group(ctx);
+    if (st) return st;
+    ctx->batch.open = true;
+    return LT_OK;
+}
+
+lt_status lt_batch_end(lt_context *ctx) {
+    if (!ctx) return LT_ERR_INVALID;
+    lt_status st = batch_flush(ctx);
+    ctx->batch.open = false;
+    return st;
+}
+
 lt_status lt_sync(lt_context *ctx) {
     if (!ctx) return LT_ERR_INVALID;
     return sync_all(ctx);
@@ -595,15 +650,13 @@ lt_status lt_sync(lt_context *ctx) {
 
 lt_status lt_wait(lt_context *ctx, uint64_t launch_id) {
     if (!ctx) return LT_ERR_INVALID;
-    lt_status st = flush_group(ctx);
+    lt_status st = flush_all(ctx);
     if (st) return st;
-    auto it = ctx->launch_done.find(launch_id);
-    if (it == ctx->launch_done.end()) {
-        if (launch_id == 0 || launch_id >= ctx->next_launch_id)
-            return set_err(ctx, LT_ERR_INVALID, "unknown launch id %llu", (unsigned long long)launch_id);
-        return LT_OK;  // completed before the last lt_sync
-    }
-    st = wait_fence(ctx, it->second);
+    if (launch_id == 0 || launch_id >= ctx->next_launch_id)
+        return set_err(ctx, LT_ERR_INVALID, "unknown launch id %llu", (unsigned long long)launch_id);
+    LaunchRec *lr = ctx->launches.get(launch_id);
+    if (!lr) return LT_OK;  // completed before the last lt_sync
+    st = wait_fence(ctx, lr->done);
     if (st) return st;
     if (ctx->sticky != LT_OK) {
         lt_status s = ctx->sticky;
@@ -616,12 +669,12 @@ lt_status lt_wait(lt_context *ctx, uint64_t launch_id) {
 
 lt_status lt_plan_tasks(lt_context *ctx, uint64_t launch_id, lt_task_info *out, int32_t cap, int32_t *n) {
     if (!ctx || !n) return LT_ERR_INVALID;
-    flush_group(ctx);
-    auto it = ctx->launch_tasks.find(launch_id);
-    if (it == ctx->launch_tasks.end()) return set_err(ctx, LT_ERR_INVALID, "no task records for launch");
-    *n = (int32_t)it->second.size();
+    flush_all(ctx);
+    LaunchRec *lr = ctx->launches.get(launch_id);
+    if (!lr) return set_err(ctx, LT_ERR_INVALID, "no task records for launch");
+    *n = (int32_t)lr->tasks.size();
     for (int i = 0; i < *n && i < cap; ++i) {
-        const TaskRec &r = ctx->tasks[it->second[i]];
+        const TaskRec &r = ctx->tasks.at(lr->tasks[i]);
         lt_task_info &t = out[i];
         memset(&t, 0, sizeof t);
         t.id = r.id;
@@ -641,20 +694,20 @@ lt_status lt_plan_tasks(lt_context *ctx, uint64_t launch_id, lt_task_info *out, 
 lt_status lt_plan_regions(lt_context *ctx, uint64_t task_id, lt_region_info *out, int32_t cap, int32_t *n) {
     if (!ctx || !n) return LT_ERR_INVALID;
     flush_group(ctx);
-    auto it = ctx->tasks.find(task_id);
-    if (it == ctx->tasks.end()) return set_err(ctx, LT_ERR_INVALID, "unknown task id");
-    *n = (int32_t)it->second.regions.size();
-    for (int i = 0; i < *n && i < cap; ++i) out[i] = it->second.regions[i];
+    TaskRec *tr = ctx->tasks.get(task_id);
+    if (!tr || !tr->id) return set_err(ctx, LT_ERR_INVALID, "unknown task id");
+    *n = (int32_t)tr->regions.size();
+    for (int i = 0; i < *n && i < cap; ++i) out[i] = tr->regions[i];
     return LT_OK;
 }
 
 lt_status lt_plan_deps(lt_context *ctx, uint64_t task_id, uint64_t *out, int32_t cap, int32_t *n) {
     if (!ctx || !n) return LT_ERR_INVALID;
     flush_group(ctx);
-    auto it = ctx->tasks.find(task_id);
-    if (it == ctx->tasks.end()) return set_err(ctx, LT_ERR_INVALID, "unknown task id");
-    *n = (int32_t)it->second.deps.size();
-    for (int i = 0; i < *n && i < cap; ++i) out[i] = it->second.deps[i];
+    TaskRec *tr = ctx->tasks.get(task_id);
+    if (!tr || !tr->id) return set_err(ctx, LT_ERR_INVALID, "unknown task id");
+    *n = (int32_t)tr->deps.size();
+    for (int i = 0; i < *n && i < cap; ++i) out[i] = tr->deps[i];
     return LT_OK;
 }
 

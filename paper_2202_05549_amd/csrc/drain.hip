@@ -1,0 +1,134 @@
+// Persistent drain kernel: executes a queue of tasks from many launches in
+// one dispatch.  Each workgroup takes the next (task, tile) ticket, waits
+// until the task's dependency counters are reached (a bounded poll: after
+// spin_limit polls it gives up, flags the error and skips the tile, so every
+// wave exits), runs the tile with the same device body as the per-task
+// kernels, and publishes completion with a release fence and a counter
+// increment.  Tickets are handed out in program order and dependencies point
+// to earlier tasks only, so a waiting workgroup always waits on tiles that
+// running workgroups already hold: the drain makes progress.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "bodies.h"
+#include "kernels.h"
+
+namespace lt {
+
+using namespace body;
+
+__device__ __forceinline__ void run_tile(const DTask &t, int64_t local, int *sh) {
+    switch (t.kind) {
+        case DK_TOUCH: {
+            const int64_t s0 = t.lo0 + local * DSPAN;
+            for (int64_t sp = 0; sp < DSPAN; sp += THREADS) touch_span(t.y, t.n, t.lo0, t.hi0, s0 + sp);
+            break;
+        }
+        case DK_STENCIL1D: {
+            const int64_t end = t.hi0 < t.n ? t.hi0 : t.n;
+            const int64_t s0 = t.lo0 + local * DSPAN;
+            for (int64_t sp = 0; sp < DSPAN; sp += 1024) {
+                if (s0 + sp >= end) break;
+                stencil_span(t.x, t.y, t.n, t.lo0, t.hi0, s0 + sp);
+            }
+            break;
+        }
+        case DK_JACOBI2D: {
+            JView v;
+            v.r0 = t.lo0;
+            v.r1 = t.hi0;
+            v.c0 = t.lo1;
+            v.c1 = t.hi1;
+            v.y = t.y;
+            v.x = t.x;
+            v.ys = t.ys;
+            v.xs = t.xs;
+            v.vec = t.vec;
+            const int tyi = (int)(local / t.tx), txi = (int)(local - (int64_t)tyi * t.tx);
+            const int64_t rend = t.hi0 < t.n ? t.hi0 : t.n;
+            for (int sub = 0; sub < DJROWS / 8; ++sub) {
+                const int64_t tr0 = t.lo0 + (int64_t)tyi * DJROWS + sub * 8;
+                if (tr0 >= rend) break;
+                jacobi_tile<8>(v, t.n, t.m, tr0, txi);
+            }
+            break;
+        }
+        case DK_HIST256: {
+            const int64_t end = t.hi0 < t.n ? t.hi0 : t.n;
+            const int64_t s0 = t.lo0 + local * DSPAN;
+            const int64_t s1 = s0 + DSPAN < end ? s0 + DSPAN : end;
+            hist_span(t.x, s0, s1, THREADS, sh);
+            hist_flush(t.y, sh);
+            break;
+        }
+        case DK_SUM_PARTIALS: {
+            // y[e] = sum over p of partial p at element e, e in [lo0, hi0);
+            // partials are dense blocks of m elements starting at x
+            const int32_t *P = reinterpret_cast<const int32_t *>(t.x);
+            for (int64_t e = t.lo0 + threadIdx.x; e < t.hi0; e += THREADS) {
+                int32_t acc = 0;
+                for (int64_t p = 0; p < t.aux; ++p) acc += P[p * t.m + (e - t.lo0)];
+                *at<int32_t>(t.y, e) = acc;
+            }
+            break;
+        }
+        default:
+            break;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_drain(const DTask *q, int ntasks, int32_t *ctr, int ticket_idx,
+                                               int64_t total, int64_t spin_limit) {
+    __shared__ int sh[4 * 256];
+    __shared__ int s_tile, s_task, s_ok;
+    for (int i = threadIdx.x; i < 4 * 256; i += THREADS) sh[i] = 0;
+    int cur = 0;
+    for (;;) {
+        if (threadIdx.x == 0) s_tile = atomicAdd(&ctr[ticket_idx], 1);
+        __syncthreads();
+        const int64_t tile = s_tile;
+        if (tile >= total) break;
+        if (threadIdx.x == 0) {
+            while (cur + 1 < ntasks && q[cur + 1].tile_begin <= tile) ++cur;
+            const DTask &t = q[cur];
+            int ok = 1;
+            for (int d = 0; d < t.ndeps && ok; ++d) {
+                int64_t spins = 0;
+                while (__hip_atomic_load(&ctr[t.dep_ctr[d]], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) <
+                       t.dep_val[d]) {
+                    __builtin_amdgcn_s_sleep(2);
+                    if (++spins > spin_limit) {
+                        ok = 0;
+                        atomicOr(&ctr[ticket_idx + 1], 1);
+                        break;
+                    }
+                }
+            }
+            __threadfence();  // acquire: see the predecessors' writes
+            s_task = cur;
+            s_ok = ok;
+        }
+        __syncthreads();
+        const DTask &t = q[s_task];
+        if (s_ok) run_tile(t, tile - t.tile_begin, sh);
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            __threadfence();  // release: this tile's writes before the count
+            int prev = atomicAdd(&ctr[s_task], 1);
+            if (prev == t.ntiles - 1 && t.signal >= 0) atomicAdd(&ctr[t.signal], 1);
+        }
+    }
+}
+
+hipError_t launch_drain(hipStream_t s, const DTask *q, int ntasks, int32_t *counters, int ticket_idx,
+                        int64_t total_tiles, int nwg, int64_t spin_limit) {
+    if (total_tiles <= 0 || ntasks <= 0) return hipSuccess;
+    if (nwg < 1) nwg = 1;
+    if ((int64_t)nwg > total_tiles) nwg = (int)total_tiles;
+    hipLaunchKernelGGL(k_drain, dim3((unsigned)nwg), dim3(256), 0, s, q, ntasks, counters, ticket_idx,
+                       total_tiles, spin_limit);
+    return hipGetLastError();
+}
+
+}  // namespace lt

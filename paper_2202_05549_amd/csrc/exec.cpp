@@ -58,6 +58,9 @@ struct Partials {       // one reduce argument of one launch
     int64_t cursor = 0; // next free element of the block
     std::vector<CombinePart> parts;
     std::vector<uint64_t> producers;
+    bool batched = false;   // block lives in the batch's partial area
+    int64_t rel = 0;        // its byte offset there
+    int signal = -1;        // batch signal bumped by each producer
 };
 
 double now_s() {
@@ -130,8 +133,8 @@ void record_access(Chunk *c, Mode m, ROp op, uint64_t id) {
 Fence task_fence(Ctx *ctx, const std::vector<uint64_t> &deps) {
     Fence f;
     for (uint64_t d : deps) {
-        auto it = ctx->tasks.find(d);
-        if (it != ctx->tasks.end() && it->second.seq) f.add(it->second.stream, it->second.seq);
+        TaskRec *r = ctx->tasks.get(d);
+        if (r && r->seq) f.add(r->stream, r->seq);
     }
     return f;
 }
@@ -231,7 +234,7 @@ lt_status flush_group(Ctx *ctx) {
     }
     uint64_t p = ctx->streams[g.stream].seq;
     for (uint64_t id : g.ids) {
-        TaskRec &r = ctx->tasks[id];
+        TaskRec &r = ctx->tasks.at(id);
         r.stream = g.stream;
         r.seq = p;
     }
@@ -370,6 +373,330 @@ static void identity_bytes(lt_dtype dt, ROp op, unsigned char *out, int *esz) {
     }
 }
 
+// ------------------------------------------------------------ batched path
+// Between lt_batch_begin and lt_batch_end, tasks become entries of a device
+// queue drained by one persistent kernel.  Edges to tasks of the same batch
+// become counter waits inside the kernel; edges to earlier work become one
+// stream wait before the drain.  Every chunk a batched task touches must
+// already be resident (no staging inside the drain).
+
+// signal and counter indices are only known at the end: encode them as
+// negative markers until then
+static int32_t sig_marker(int s) { return -2 - s; }
+
+static lt_status batch_dep(Ctx *ctx, DTask &d, uint64_t dep) {
+    Batch &B = ctx->batch;
+    int qi = B.find(dep);
+    if (qi < 0) {
+        TaskRec *tr = ctx->tasks.get(dep);
+        if (tr && tr->seq) B.wait.add(tr->stream, tr->seq);
+        return LT_OK;
+    }
+    for (int i = 0; i < d.ndeps; ++i)
+        if (d.dep_ctr[i] == qi) return LT_OK;
+    if (d.ndeps >= DMAXDEP)
+        return set_err(ctx, LT_ERR_UNSUPPORTED, "a batched task has more than %d predecessors in its batch", DMAXDEP);
+    d.dep_ctr[d.ndeps] = qi;
+    d.dep_val[d.ndeps] = B.q[qi].ntiles;
+    d.ndeps++;
+    return LT_OK;
+}
+
+static void batch_push(Ctx *ctx, DTask &d, uint64_t id) {
+    Batch &B = ctx->batch;
+    if (d.ntiles < 1) d.ntiles = 1;  // an empty task still completes (and signals)
+    d.tile_begin = B.tiles;
+    B.tiles += d.ntiles;
+    if (B.index.empty()) B.index_base = id;
+    if (id - B.index_base >= B.index.size()) B.index.resize(id - B.index_base + 1, -1);
+    B.index[id - B.index_base] = (int)B.q.size();
+    B.q.push_back(d);
+    B.ids.push_back(id);
+}
+
+static lt_status batch_add_exec(Ctx *ctx, const KernelDef *def, TaskPlan &tp, TaskRec &rec, const KLaunch &proto,
+                                Array **arrs, std::vector<Partials> &parts) {
+    Batch &B = ctx->batch;
+    DTask d;
+    memset(&d, 0, sizeof d);
+    d.signal = -1;
+    KTask kt;
+    memset(&kt, 0, sizeof kt);
+    std::vector<ChunkUse> uses;
+    for (int p = 0; p < def->nparam; ++p) {
+        ArgPlan &a = tp.arg[p];
+        if (!a.used) continue;
+        Array *arr = arrs[p];
+        if (a.mode == M_REDUCE) {
+            Partials *P = nullptr;
+            for (auto &x : parts)
+                if (x.param == p) P = &x;
+            CombinePart cp;
+            cp.off = P->cursor;
+            P->cursor += a.region.volume(arr->ndim);
+            int64_t org = 0, s = 1;
+            for (int q = MAXD - 1; q >= 0; --q) {
+                org += (q < arr->ndim ? a.region.lo[q] : 0) * s;
+                s *= q < arr->ndim ? a.region.hi[q] - a.region.lo[q] : 1;
+            }
+            for (int q = 0; q < KMAXD; ++q) {
+                cp.lo[q] = a.region.lo[q];
+                cp.hi[q] = a.region.hi[q];
+            }
+            P->parts.push_back(cp);
+            P->producers.push_back(tp.id);
+            // relative byte address of element 0 of the partial's view
+            kt.v[p].base = P->rel + (cp.off - org) * arr->esz;
+            kt.v[p].s[0] = 1;
+            d.signal = sig_marker(P->signal);
+            rec.regions.push_back(lt_region_info{p, (int)a.mode, (int)a.op, 2, arr->id,
+                                                 {a.region.lo[0], a.region.lo[1], a.region.lo[2]},
+                                                 {a.region.hi[0], a.region.hi[1], a.region.hi[2]}});
+            continue;
+        }
+        if (!direct_view(ctx, arr, a.chunks, &kt.v[p]))
+            return set_err(ctx, LT_ERR_UNSUPPORTED,
+                           "inside a batch every chunk a task touches must be resident and contiguous (%s)",
+                           def->params[p].name);
+        for (Chunk *c : a.chunks) {
+            c->lru = ++ctx->lru_clock;
+            uses.push_back({c, a.mode != M_READ});
+        }
+        rec.regions.push_back(lt_region_info{p, (int)a.mode, (int)a.op, 0, arr->id,
+                                             {a.region.lo[0], a.region.lo[1], a.region.lo[2]},
+                                             {a.region.hi[0], a.region.hi[1], a.region.hi[2]}});
+        ctx->stats.direct_regions++;
+    }
+    d.lo0 = tp.sb.lo[0];
+    d.hi0 = tp.sb.hi[0];
+    d.lo1 = tp.sb.lo[1];
+    d.hi1 = tp.sb.hi[1];
+    bool partial_y = false;
+    if (def->dkind == DK_TOUCH) {
+        d.kind = DK_TOUCH;
+        d.n = proto.iarg[0];
+        d.y = kt.v[1].base;
+    } else if (def->dkind == DK_STENCIL1D) {
+        d.kind = DK_STENCIL1D;
+        d.n = proto.iarg[0];
+        d.y = kt.v[1].base;
+        d.x = kt.v[2].base;
+    } else if (def->dkind == DK_HIST256) {
+        d.kind = DK_HIST256;
+        d.n = proto.iarg[0];
+        d.y = kt.v[1].base;
+        d.x = kt.v[2].base;
+        partial_y = true;
+    } else if (def->dkind == DK_JACOBI2D) {
+        d.kind = DK_JACOBI2D;
+        d.n = proto.iarg[0];
+        d.m = proto.iarg[1];
+        d.y = kt.v[2].base;
+        d.x = kt.v[3].base;
+        d.ys = kt.v[2].s[0];
+        d.xs = kt.v[3].s[0];
+        d.hi0 = std::min(d.hi0, d.n);
+        d.hi1 = std::min(d.hi1, d.m);
+        d.vec = ((d.x + d.lo1 * 4) & 15) == 0 && ((d.y + d.lo1 * 4) & 15) == 0 && (d.xs & 3) == 0 &&
+                (d.ys & 3) == 0 && ((d.hi1 - d.lo1) & 3) == 0;
+        int64_t cols = d.hi1 - d.lo1, rows = d.hi0 - d.lo0;
+        d.tx = cols > 0 ? (int)((cols + 1023) / 1024) : 1;
+        d.ntiles = rows > 0 && cols > 0 ? (int)(((rows + DJROWS - 1) / DJROWS) * d.tx) : 0;
+    } else {
+        return set_err(ctx, LT_ERR_UNSUPPORTED, "%s cannot run inside a batch", def->name);
+    }
+    if (d.kind != DK_JACOBI2D) {
+        int64_t e = std::min(d.hi0, d.n) - d.lo0;
+        d.ntiles = e > 0 ? (int)((e + DSPAN - 1) / DSPAN) : 0;
+    }
+    for (uint64_t dep : rec.deps) {
+        lt_status st = batch_dep(ctx, d, dep);
+        if (st) return st;
+    }
+    for (int p = 0; p < def->nparam; ++p) {
+        ArgPlan &a = tp.arg[p];
+        if (!a.used || a.mode == M_REDUCE) continue;
+        for (Chunk *c : a.chunks) record_access(c, a.mode, a.op, tp.id);
+    }
+    if (partial_y) B.patch_y.push_back({(int)B.q.size(), 0});
+    batch_push(ctx, d, tp.id);
+    B.uses.insert(B.uses.end(), uses.begin(), uses.end());
+    if (B.launches.empty() || B.launches.back() != rec.launch) B.launches.push_back(rec.launch);
+    ctx->tasks.at(tp.id) = std::move(rec);
+    return LT_OK;
+}
+
+static lt_status batch_add_combine(Ctx *ctx, Partials &P, Array *arr, uint64_t L) {
+    Batch &B = ctx->batch;
+    const int nd = arr->ndim;
+    if (P.parts.empty()) return LT_OK;
+    if (nd != 1 || P.op != R_ADD || arr->dtype != LT_I32)
+        return set_err(ctx, LT_ERR_UNSUPPORTED, "batched reductions support int32 reduce(+) on 1-D targets");
+    for (auto &q : P.parts)
+        if (q.lo[0] != P.parts[0].lo[0] || q.hi[0] != P.parts[0].hi[0])
+            return set_err(ctx, LT_ERR_UNSUPPORTED, "batched reductions need equal partial boxes");
+    Box U;
+    U.lo[0] = P.parts[0].lo[0];
+    U.hi[0] = P.parts[0].hi[0];
+    TaskRec rec;
+    rec.id = ctx->next_task_id++;
+    rec.launch = L;
+    rec.kind = LT_TASK_COMBINE;
+    rec.sb = U;
+    std::vector<Chunk *> ch;
+    chunks_overlapping(arr, U, &ch);
+    for (Chunk *c : ch) conflict_edges(c, M_WRITE, R_ADD, &rec.deps);
+    DTask d;
+    memset(&d, 0, sizeof d);
+    d.signal = -1;
+    d.kind = DK_SUM_PARTIALS;
+    KView tv;
+    if (!direct_view(ctx, arr, ch, &tv))
+        return set_err(ctx, LT_ERR_UNSUPPORTED, "inside a batch the reduction target must be resident");
+    d.y = tv.base;
+    d.lo0 = U.lo[0];
+    d.hi0 = U.hi[0];
+    d.m = U.hi[0] - U.lo[0];
+    d.aux = (int64_t)P.parts.size();
+    d.x = P.rel;
+    d.ndeps = 1;
+    d.dep_ctr[0] = sig_marker(P.signal);
+    d.dep_val[0] = (int32_t)P.producers.size();
+    for (uint64_t dep : rec.deps) {
+        lt_status st = batch_dep(ctx, d, dep);
+        if (st) return st;
+    }
+    B.patch_x.push_back({(int)B.q.size(), 0});
+    d.ntiles = 1;
+    batch_push(ctx, d, rec.id);
+    for (Chunk *c : ch) {
+        record_access(c, M_WRITE, R_ADD, rec.id);
+        c->lru = ++ctx->lru_clock;
+        B.uses.push_back({c, true});
+    }
+    rec.regions.push_back(lt_region_info{P.param, (int)M_REDUCE, (int)P.op, 0, arr->id,
+                                         {U.lo[0], U.lo[1], U.lo[2]}, {U.hi[0], U.hi[1], U.hi[2]}});
+    ctx->launches.at(L).tasks.push_back(rec.id);
+    if (B.launches.empty() || B.launches.back() != L) B.launches.push_back(L);
+    ctx->tasks.at(rec.id) = std::move(rec);
+    return LT_OK;
+}
+
+static void *staging_get(Ctx *ctx, uint64_t bytes, lt_status *st) {
+    for (size_t i = 0; i < ctx->staging_free.size(); ++i)
+        if (ctx->staging_size_free[i] >= bytes) {
+            void *p = ctx->staging_free[i];
+            ctx->staging_used.push_back(p);
+            ctx->staging_size_used.push_back(ctx->staging_size_free[i]);
+            ctx->staging_free.erase(ctx->staging_free.begin() + i);
+            ctx->staging_size_free.erase(ctx->staging_size_free.begin() + i);
+            return p;
+        }
+    uint64_t sz = std::max<uint64_t>(bytes, 1 << 20);
+    void *p = nullptr;
+    if (ctx->dry) {
+        p = malloc(sz);
+    } else {
+        hipError_t r = hipHostMalloc(&p, sz, hipHostMallocDefault);
+        if (r != hipSuccess) {
+            *st = set_err(ctx, LT_ERR_OOM, "pinned staging buffer: %s", hipGetErrorString(r));
+            return nullptr;
+        }
+    }
+    ctx->staging_used.push_back(p);
+    ctx->staging_size_used.push_back(sz);
+    return p;
+}
+
+lt_status batch_flush(Ctx *ctx) {
+    Batch &B = ctx->batch;
+    if (B.q.empty()) return LT_OK;
+    lt_status st = flush_group(ctx);
+    if (st) return st;
+    const int ntasks = (int)B.q.size();
+    const int nctr = ntasks + B.nsignals + 2;
+    const int64_t qbytes = (int64_t)ntasks * (int64_t)sizeof(DTask);
+    const int64_t qalloc = (qbytes + 255) / 256 * 256;
+    const int64_t calloc_ = ((int64_t)nctr * 4 + 255) / 256 * 256;
+    const int64_t total = qalloc + calloc_ + B.part_bytes;
+    int64_t off;
+    Fence mem;
+    st = alloc_range(ctx, total, 2, nullptr, &off, &mem);
+    if (st) return st;
+    char *base = ctx->arena_base + off;
+    int64_t part_base = (int64_t)(intptr_t)(base + qalloc + calloc_);
+    for (auto &pr : B.patch_y) B.q[pr.first].y += part_base;
+    for (auto &pr : B.patch_x) B.q[pr.first].x += part_base;
+    for (DTask &d : B.q) {
+        if (d.signal <= -2) d.signal = ntasks + (-2 - d.signal);
+        for (int i = 0; i < d.ndeps; ++i)
+            if (d.dep_ctr[i] <= -2) d.dep_ctr[i] = ntasks + (-2 - d.dep_ctr[i]);
+    }
+    void *stage = staging_get(ctx, (uint64_t)qbytes, &st);
+    if (!stage) return st;
+    memcpy(stage, B.q.data(), (size_t)qbytes);
+    const int s = 0;
+    B.wait.merge(mem);
+    st = stream_wait(ctx, s, B.wait);
+    if (st) return st;
+    int nwg = ctx->cfg.drain_workgroups > 0 ? ctx->cfg.drain_workgroups : 1024;
+    if (!ctx->dry) {
+        hipStream_t h = ctx->streams[s].h;
+        hipError_t r = hipMemcpyAsync(base, stage, (size_t)qbytes, hipMemcpyHostToDevice, h);
+        if (r != hipSuccess) return hip_fail(ctx, r, "batch queue upload");
+        uint32_t zero = 0;
+        r = launch_fill(h, base + qalloc, (calloc_ + B.part_bytes) / 4, 4, &zero);
+        if (r != hipSuccess) return hip_fail(ctx, r, "batch clear");
+        r = launch_drain(h, reinterpret_cast<const DTask *>(base), ntasks,
+                         reinterpret_cast<int32_t *>(base + qalloc), ntasks + B.nsignals, B.tiles, nwg,
+                         (int64_t)1 << 24);
+        if (r != hipSuccess) return hip_fail(ctx, r, "drain");
+        // error flag back to pinned host memory, checked at lt_sync
+        if (ctx->status_next >= ctx->status_slots) {
+            int ns = std::max(64, ctx->status_slots * 2);
+            int32_t *p = nullptr;
+            r = hipHostMalloc((void **)&p, (size_t)ns * 4, hipHostMallocDefault);
+            if (r != hipSuccess) return hip_fail(ctx, r, "status buffer");
+            if (ctx->status_host) {
+                // earlier slots are still pending; keep the old buffer alive
+                r = hipStreamSynchronize(h);
+                if (r != hipSuccess) return hip_fail(ctx, r, "hipStreamSynchronize");
+                memcpy(p, ctx->status_host, (size_t)ctx->status_slots * 4);
+                (void)hipHostFree(ctx->status_host);
+            }
+            ctx->status_host = p;
+            ctx->status_slots = ns;
+        }
+        int slot = ctx->status_next++;
+        r = hipMemcpyAsync(ctx->status_host + slot, base + qalloc + (int64_t)(ntasks + B.nsignals + 1) * 4, 4,
+                           hipMemcpyDeviceToHost, h);
+        if (r != hipSuccess) return hip_fail(ctx, r, "drain status copy");
+    }
+    ctx->stats.dispatches += 2;
+    trace_op(ctx, 0, s, ~0ull, 0, (uint64_t)ntasks, 0);
+    uint64_t p = bump(ctx, s);
+    for (uint64_t id : B.ids) {
+        TaskRec &r = ctx->tasks.at(id);
+        r.stream = s;
+        r.seq = p;
+    }
+    apply_uses(ctx, B.uses, s, p);
+    Fence done;
+    done.add(s, p);
+    ctx->arena.release(off, done);
+    for (uint64_t L : B.launches) ctx->launches.at(L).done.add(s, p);  // they complete with the drain
+    bool open = B.open;
+    B = Batch();
+    B.open = open;
+    return LT_OK;
+}
+
+lt_status flush_all(Ctx *ctx) {
+    lt_status st = flush_group(ctx);
+    if (st) return st;
+    return batch_flush(ctx);
+}
+
 static lt_status issue_exec(Ctx *ctx, lt_kernel *k, TaskPlan &tp, uint64_t L,
                             const KLaunch &proto, Array **arrs, std::vector<Partials> &parts,
                             int nd) {
@@ -392,6 +719,8 @@ static lt_status issue_exec(Ctx *ctx, lt_kernel *k, TaskPlan &tp, uint64_t L,
         }
         for (Chunk *c : a.chunks) conflict_edges(c, a.mode, a.op, &rec.deps);
     }
+
+    if (ctx->batch.open) return batch_add_exec(ctx, def, tp, rec, proto, arrs, parts);
 
     // can this task join the open group without staging or copies?
     bool simple = !has_reduce;
@@ -449,7 +778,7 @@ static lt_status issue_exec(Ctx *ctx, lt_kernel *k, TaskPlan &tp, uint64_t L,
         g.tasks.push_back(kt);
         g.ids.push_back(tp.id);
         g.uses.insert(g.uses.end(), uses.begin(), uses.end());
-        ctx->tasks[tp.id] = rec;
+        ctx->tasks.at(tp.id) = std::move(rec);
         if (ctx->cfg.exec_mode != LT_EXEC_GROUPED || (int)g.tasks.size() >= std::min(def->max_group, KMAXG))
             return flush_group(ctx);
         return LT_OK;
@@ -606,7 +935,7 @@ static lt_status issue_exec(Ctx *ctx, lt_kernel *k, TaskPlan &tp, uint64_t L,
         ctx->stats.staged_peak_bytes = std::max<uint64_t>(ctx->stats.staged_peak_bytes, ctx->staged_bytes);
     }
     unpin();
-    ctx->tasks[tp.id] = rec;
+    ctx->tasks.at(tp.id) = std::move(rec);
     return LT_OK;
 }
 
@@ -615,6 +944,7 @@ static lt_status issue_exec(Ctx *ctx, lt_kernel *k, TaskPlan &tp, uint64_t L,
 static lt_status issue_combine(Ctx *ctx, Partials &P, Array *arr, uint64_t L) {
     const int nd = arr->ndim;
     if (P.parts.empty()) return LT_OK;
+    if (P.batched) return batch_add_combine(ctx, P, arr, L);
     Box U;
     for (int a = 0; a < MAXD; ++a) {
         U.lo[a] = P.parts[0].lo[a];
@@ -731,8 +1061,8 @@ static lt_status issue_combine(Ctx *ctx, Partials &P, Array *arr, uint64_t L) {
     ctx->arena.release(P.off, done);
     rec.regions.push_back(lt_region_info{P.param, (int)M_REDUCE, (int)P.op, tmp ? 1 : 0, arr->id,
                                          {U.lo[0], U.lo[1], U.lo[2]}, {U.hi[0], U.hi[1], U.hi[2]}});
-    ctx->tasks[rec.id] = rec;
-    ctx->launch_tasks[L].push_back(rec.id);
+    ctx->launches.at(L).tasks.push_back(rec.id);
+    ctx->tasks.at(rec.id) = std::move(rec);
     return LT_OK;
 }
 
@@ -828,7 +1158,7 @@ lt_status launch(Ctx *ctx, lt_kernel *k, int nd, const int64_t *grid,
     std::vector<TaskPlan> plans;
     plans.reserve((size_t)total);
     int64_t idx[MAXD] = {0, 0, 0};
-    std::unordered_map<Chunk *, int> seen;
+    std::vector<Chunk *> seen;
     for (int64_t t = 0; t < total; ++t) {
         int64_t r = t;
         for (int a = nd - 1; a >= 0; --a) {
@@ -872,8 +1202,8 @@ lt_status launch(Ctx *ctx, lt_kernel *k, int nd, const int64_t *grid,
             chunks_overlapping(arr, a.region, &a.chunks);
             bool multi = a.chunks.size() > 1;
             for (Chunk *c : a.chunks)
-                if (!seen.count(c)) {
-                    seen[c] = 1;
+                if (std::find(seen.begin(), seen.end(), c) == seen.end()) {
+                    seen.push_back(c);
                     tp.footprint += (c->bytes + 255) / 256 * 256;
                 }
             if (multi && !arr->row_slab) tp.footprint += a.region.volume(arr->ndim) * arr->esz + 256;
@@ -915,6 +1245,16 @@ lt_status launch(Ctx *ctx, lt_kernel *k, int nd, const int64_t *grid,
     proto.variant = k->variant;
     for (auto &P : parts) {
         if (P.total_elems == 0) continue;
+        if (ctx->batch.open) {
+            // partials live in the batch's area, cleared once before the drain
+            if (P.op != R_ADD)
+                return set_err(ctx, LT_ERR_UNSUPPORTED, "batched reductions support reduce(+) only");
+            P.batched = true;
+            P.rel = ctx->batch.part_bytes;
+            ctx->batch.part_bytes += P.bytes;
+            P.signal = ctx->batch.nsignals++;
+            continue;
+        }
         st = flush_group(ctx);
         if (st) return st;
         Fence mem;
@@ -933,10 +1273,9 @@ lt_status launch(Ctx *ctx, lt_kernel *k, int nd, const int64_t *grid,
         }
         P.ready.add(s, bump(ctx, s));
     }
-    std::vector<uint64_t> &lt_ids = ctx->launch_tasks[L];
     for (auto &tp : plans) {
         tp.id = ctx->next_task_id++;
-        lt_ids.push_back(tp.id);
+        ctx->launches.at(L).tasks.push_back(tp.id);
         st = issue_exec(ctx, k, tp, L, proto, arrs, parts, nd);
         if (st) return st;
         ctx->stats.tasks++;
@@ -947,12 +1286,11 @@ lt_status launch(Ctx *ctx, lt_kernel *k, int nd, const int64_t *grid,
         st = issue_combine(ctx, P, arrs[P.param], L);
         if (st) return st;
     }
-    Fence done;
-    for (uint64_t id : ctx->launch_tasks[L]) {
-        auto &r = ctx->tasks[id];
-        done.add(r.stream, r.seq);
+    LaunchRec &lr = ctx->launches.at(L);
+    for (uint64_t id : lr.tasks) {
+        TaskRec *r = ctx->tasks.get(id);
+        if (r && r->seq) lr.done.add(r->stream, r->seq);
     }
-    ctx->launch_done[L] = done;
     ctx->stats.plan_seconds += now_s() - t0;
     return LT_OK;
 }

@@ -80,3 +80,40 @@ struct CombineArgs {
 hipError_t launch_combine(hipStream_t s, const CombineArgs &a);
 
 }  // namespace lt
+
+namespace lt {
+
+// ------------------------------------------------------------ batched path
+// A batch of tasks from many launches, drained by one persistent kernel.
+// Work items are (task, tile) pairs handed out in program order by an atomic
+// ticket; a task's tiles start once every dependency counter has reached its
+// value.  counters[i] counts the finished tiles of task i; a task whose last
+// tile finishes also bumps counters[signal] once.
+enum DKind { DK_TOUCH = 0, DK_STENCIL1D = 1, DK_JACOBI2D = 2, DK_HIST256 = 3, DK_SUM_PARTIALS = 4 };
+constexpr int DMAXDEP = 8;
+constexpr int64_t DSPAN = 16384;  // elements per tile of the 1-D bodies
+constexpr int DJROWS = 32;        // rows per Jacobi tile (four 8-row passes)
+
+struct DTask {
+    int32_t kind;
+    int32_t ntiles;
+    int64_t tile_begin;
+    int32_t ndeps;
+    int32_t signal;                // -1 = none
+    int32_t dep_ctr[DMAXDEP];
+    int32_t dep_val[DMAXDEP];
+    int64_t lo0, hi0, lo1, hi1;    // thread box (rows, columns) or range
+    int64_t n, m;                  // scalar parameters
+    int64_t y, x;                  // pre-offset views (output, input)
+    int64_t ys, xs;                // row strides
+    int32_t tx;                    // Jacobi column tiles
+    int32_t vec;                   // Jacobi float4 layout
+    int64_t aux;                   // DK_SUM_PARTIALS: number of partials
+};
+
+// counters: ntasks + nsignals task/signal counters, then the ticket, then an
+// error flag (bit 0: a dependency wait gave up after spin_limit polls).
+hipError_t launch_drain(hipStream_t s, const DTask *q, int ntasks, int32_t *counters, int ticket_idx,
+                        int64_t total_tiles, int nwg, int64_t spin_limit);
+
+}  // namespace lt

@@ -13,20 +13,16 @@
 #include <cstdint>
 #include <cstring>
 
+#include "bodies.h"
 #include "kernels.h"
 
 namespace lt {
 
+using namespace body;
+
 namespace {
 
-constexpr int WAVE = 64;
-
-template <class T>
-__device__ __forceinline__ T *at(int64_t base, int64_t idx) {
-    return reinterpret_cast<T *>(base) + idx;
-}
-
-// Task lookup: blk_begin[t] <= b < blk_begin[t+1].
+// Task lookup: begin[t] <= b < begin[t+1].
 __device__ __forceinline__ int find_task(const int *begin, int ntask, int b) {
     int lo = 0, hi = ntask - 1;
     while (lo < hi) {
@@ -37,25 +33,7 @@ __device__ __forceinline__ int find_task(const int *begin, int ntask, int b) {
     return lo;
 }
 
-// Physical workgroups are dealt round-robin to the 8 XCDs.  Remap so each
-// XCD receives a contiguous range of logical tiles (neighbouring tiles share
-// halo rows in that XCD's L2).  Identity on the tail that is not a multiple
-// of 8.
-__device__ __forceinline__ int xcd_remap(int b, int nb) {
-    int per = nb >> 3;
-    if (b >= (per << 3)) return b;
-    return (b & 7) * per + (b >> 3);
-}
-
 inline unsigned grid_of(int64_t blocks) { return (unsigned)blocks; }
-
-typedef float f32x4 __attribute__((ext_vector_type(4)));
-
-// 16-byte store that bypasses cache retention (streaming output)
-__device__ __forceinline__ void nt_store4(float *p, float4 v) {
-    f32x4 w = {v.x, v.y, v.z, v.w};
-    __builtin_nontemporal_store(w, reinterpret_cast<f32x4 *>(p));
-}
 
 }  // namespace
 
@@ -74,8 +52,7 @@ struct TouchArgs {
 __global__ __launch_bounds__(256) void k_touch(TouchArgs a) {
     int ti = find_task(a.begin, a.ntask, blockIdx.x);
     const TouchTask &t = a.t[ti];
-    int64_t i = t.lo + (int64_t)(blockIdx.x - a.begin[ti]) * 256 + threadIdx.x;
-    if (i < t.hi && i < a.n && i >= 0) *at<int32_t>(t.y, i) += 1;
+    touch_span(t.y, a.n, t.lo, t.hi, t.lo + (int64_t)(blockIdx.x - a.begin[ti]) * 256);
 }
 
 hipError_t launch_touch_i32(const KLaunch &L) {
@@ -111,50 +88,10 @@ struct StArgs {
     StTask t[KMAXG];
 };
 
-__device__ __forceinline__ float st_point(float l, float m, float r) {
-    float s = l + r;
-    float t = 0.25f * s;
-    float u = 0.5f * m;
-    return t + u;
-}
-
 __global__ __launch_bounds__(256) void k_stencil1d(StArgs a) {
     int ti = find_task(a.begin, a.ntask, blockIdx.x);
     const StTask &t = a.t[ti];
-    const int64_t n = a.n;
-    const int64_t end = t.hi < n ? t.hi : n;          // outputs [lo, end)
-    const int64_t rend = end + 1 < n ? end + 1 : n;    // inputs read: [lo-1, rend)
-    const int64_t i0 = t.lo + ((int64_t)(blockIdx.x - a.begin[ti]) * 256 + threadIdx.x) * 4;
-    const float *X = reinterpret_cast<const float *>(t.x);
-    float *Y = reinterpret_cast<float *>(t.y);
-    const bool aligned = ((t.x + t.lo * 4) & 15) == 0 && ((t.y + t.lo * 4) & 15) == 0;
-    float v[4];
-    if (aligned && i0 + 3 < end) {
-        float4 q = *reinterpret_cast<const float4 *>(X + i0);
-        v[0] = q.x;
-        v[1] = q.y;
-        v[2] = q.z;
-        v[3] = q.w;
-    } else {
-        for (int j = 0; j < 4; ++j) v[j] = (i0 + j < rend) ? X[i0 + j] : 0.f;
-    }
-    const int lane = threadIdx.x & (WAVE - 1);
-    float left = __shfl_up(v[3], 1);
-    float right = __shfl_down(v[0], 1);
-    if (i0 >= end) return;
-    if (lane == 0) left = (i0 - 1 >= 0) ? X[i0 - 1] : 0.f;
-    if (lane == WAVE - 1 && i0 + 3 < end) right = (i0 + 4 < n) ? X[i0 + 4] : 0.f;
-    float o[4];
-    o[0] = st_point(left, v[0], v[1]);
-    o[1] = st_point(v[0], v[1], v[2]);
-    o[2] = st_point(v[1], v[2], v[3]);
-    o[3] = st_point(v[2], v[3], right);
-    if (aligned && i0 + 3 < end) {
-        *reinterpret_cast<float4 *>(Y + i0) = make_float4(o[0], o[1], o[2], o[3]);
-    } else {
-        for (int j = 0; j < 4; ++j)
-            if (i0 + j < end) Y[i0 + j] = o[j];
-    }
+    stencil_span(t.x, t.y, a.n, t.lo, t.hi, t.lo + (int64_t)(blockIdx.x - a.begin[ti]) * 1024);
 }
 
 hipError_t launch_stencil1d_f32(const KLaunch &L) {
@@ -184,11 +121,8 @@ hipError_t launch_stencil1d_f32(const KLaunch &L) {
 // input row is loaded once per tile; horizontal neighbours come from the
 // adjacent lanes.
 struct JTask {
-    int64_t r0, r1, c0, c1;
-    int64_t y, x;
-    int64_t ys, xs;   // row strides (elements)
+    JView v;
     int tx;           // column tiles
-    int vec;          // float4 path usable
 };
 struct JArgs {
     int64_t n, m;
@@ -197,18 +131,6 @@ struct JArgs {
     JTask t[KMAXG];
 };
 
-__device__ __forceinline__ float jpoint(float u, float d, float l, float r) {
-    float v = u + d;
-    float h = l + r;
-    float s = v + h;
-    return 0.25f * s;
-}
-
-// Full tiles (RB rows inside the field, float4 layout) take the unrolled
-// path: all RB + 2 input rows of the thread's four columns are loaded before
-// any arithmetic, which keeps RB + 2 independent 16-byte loads per lane in
-// flight; the output rows are written with non-temporal stores (they are
-// not read again by this sweep).  Ragged tiles use the sliding window.
 template <int RB>
 __global__ __launch_bounds__(256) void k_jacobi2d(JArgs a) {
     const int b = xcd_remap(blockIdx.x, a.nblocks);
@@ -216,97 +138,7 @@ __global__ __launch_bounds__(256) void k_jacobi2d(JArgs a) {
     const JTask &t = a.t[ti];
     const int local = b - a.begin[ti];
     const int tyi = local / t.tx, txi = local - tyi * t.tx;
-    const int64_t n = a.n, m = a.m;
-    const int64_t r0 = t.r0 + (int64_t)tyi * RB;
-    const int64_t r1e = r0 + RB < t.r1 ? r0 + RB : t.r1;
-    const int64_t r1 = r1e < n ? r1e : n;
-    const int64_t cend = t.c1 < m ? t.c1 : m;            // outputs [c0, cend)
-    const int64_t rcend = cend + 1 < m ? cend + 1 : m;     // inputs read up to rcend
-    const int64_t col = t.c0 + ((int64_t)txi * 256 + threadIdx.x) * 4;
-    const bool active = col < cend;
-    const float *X = reinterpret_cast<const float *>(t.x);
-    float *Y = reinterpret_cast<float *>(t.y);
-    const int lane = threadIdx.x & (WAVE - 1);
-
-    if (t.vec && r1 - r0 == RB) {
-        float4 v[RB + 2];
-#pragma unroll
-        for (int i = 0; i < RB + 2; ++i) {
-            const int64_t r = r0 - 1 + i;
-            if (active && r >= 0 && r < n)
-                v[i] = *reinterpret_cast<const float4 *>(X + r * t.xs + col);
-            else
-                v[i] = make_float4(0.f, 0.f, 0.f, 0.f);
-        }
-#pragma unroll
-        for (int i = 1; i <= RB; ++i) {
-            const int64_t r = r0 - 1 + i;
-            const float4 up = v[i - 1], mid = v[i], dn = v[i + 1];
-            float left = __shfl_up(mid.w, 1);
-            float right = __shfl_down(mid.x, 1);
-            const float *row = X + r * t.xs;
-            if (active && lane == 0) left = (col - 1 >= 0) ? row[col - 1] : 0.f;
-            if (active && (lane == WAVE - 1 || col + 4 >= cend)) right = (col + 4 < m) ? row[col + 4] : 0.f;
-            if (active) {
-                float4 o;
-                o.x = jpoint(up.x, dn.x, left, mid.y);
-                o.y = jpoint(up.y, dn.y, mid.x, mid.z);
-                o.z = jpoint(up.z, dn.z, mid.y, mid.w);
-                o.w = jpoint(up.w, dn.w, mid.z, right);
-                nt_store4(Y + r * t.ys + col, o);
-            }
-        }
-        return;
-    }
-
-    // lanes past the last output column still load the halo column cend
-    // (read by their left neighbour lane) when it lies inside the field
-    auto load4 = [&](int64_t r, float *v) {
-        if (r < 0 || r >= n || col >= rcend) {
-            v[0] = v[1] = v[2] = v[3] = 0.f;
-            return;
-        }
-        const float *p = X + r * t.xs + col;
-        if (t.vec && active) {
-            float4 q = *reinterpret_cast<const float4 *>(p);
-            v[0] = q.x;
-            v[1] = q.y;
-            v[2] = q.z;
-            v[3] = q.w;
-        } else {
-            for (int j = 0; j < 4; ++j) v[j] = (col + j < rcend) ? p[j] : 0.f;
-        }
-    };
-    float up[4], mid[4], dn[4];
-    load4(r0 - 1, up);
-    load4(r0, mid);
-    for (int64_t r = r0; r < r1; ++r) {
-        load4(r + 1, dn);
-        float left = __shfl_up(mid[3], 1);
-        float right = __shfl_down(mid[0], 1);
-        const float *row = X + r * t.xs;
-        if (active && lane == 0) left = (col - 1 >= 0) ? row[col - 1] : 0.f;
-        if (active && lane == WAVE - 1 && col + 3 < cend) right = (col + 4 < m) ? row[col + 4] : 0.f;
-        if (active) {
-            // columns at or past m were loaded as zero
-            float o0 = jpoint(up[0], dn[0], left, mid[1]);
-            float o1 = jpoint(up[1], dn[1], mid[0], mid[2]);
-            float o2 = jpoint(up[2], dn[2], mid[1], mid[3]);
-            float o3 = jpoint(up[3], dn[3], mid[2], right);
-            float *q = Y + r * t.ys + col;
-            if (t.vec) {
-                *reinterpret_cast<float4 *>(q) = make_float4(o0, o1, o2, o3);
-            } else {
-                float o[4] = {o0, o1, o2, o3};
-                for (int j = 0; j < 4; ++j)
-                    if (col + j < cend) q[j] = o[j];
-            }
-        }
-        for (int j = 0; j < 4; ++j) {
-            up[j] = mid[j];
-            mid[j] = dn[j];
-        }
-    }
+    jacobi_tile<RB>(t.v, a.n, a.m, t.v.r0 + (int64_t)tyi * RB, txi);
 }
 
 hipError_t launch_jacobi2d_f32(const KLaunch &L) {
@@ -319,7 +151,8 @@ hipError_t launch_jacobi2d_f32(const KLaunch &L) {
     int64_t nb = 0;
     for (int i = 0; i < L.ntask; ++i) {
         const KTask &k = L.tasks[i];
-        JTask &t = a.t[i];
+        JTask &jt = a.t[i];
+        JView &t = jt.v;
         t.r0 = k.lo[0];
         t.r1 = std::min(k.hi[0], a.n);
         t.c0 = k.lo[1];
@@ -331,10 +164,10 @@ hipError_t launch_jacobi2d_f32(const KLaunch &L) {
         t.vec = ((t.x + t.c0 * 4) & 15) == 0 && ((t.y + t.c0 * 4) & 15) == 0 && (t.xs & 3) == 0 &&
                 (t.ys & 3) == 0 && ((t.c1 - t.c0) & 3) == 0;
         int64_t cols = t.c1 - t.c0, rows = t.r1 - t.r0;
-        t.tx = cols > 0 ? (int)((cols + 1023) / 1024) : 0;
+        jt.tx = cols > 0 ? (int)((cols + 1023) / 1024) : 0;
         int64_t ty = rows > 0 ? (rows + a.rows - 1) / a.rows : 0;
         a.begin[i] = (int)nb;
-        nb += (int64_t)t.tx * ty;
+        nb += (int64_t)jt.tx * ty;
     }
     a.begin[L.ntask] = (int)nb;
     a.nblocks = (int)nb;
@@ -366,24 +199,15 @@ struct HArgs {
 };
 
 __global__ __launch_bounds__(256) void k_hist256(HArgs a) {
-    __shared__ int sh[4][256];
+    __shared__ int sh[4 * 256];
     int ti = find_task(a.begin, a.ntask, blockIdx.x);
     const HTask &t = a.t[ti];
-    const int w = threadIdx.x >> 6;
-    for (int i = threadIdx.x; i < 4 * 256; i += 256) (&sh[0][0])[i] = 0;
+    for (int i = threadIdx.x; i < 4 * 256; i += 256) sh[i] = 0;
     __syncthreads();
     const int64_t end = t.hi < a.n ? t.hi : a.n;
     const int nblk = a.begin[ti + 1] - a.begin[ti];
-    const int32_t *V = reinterpret_cast<const int32_t *>(t.v);
-    for (int64_t i = t.lo + (int64_t)(blockIdx.x - a.begin[ti]) * 256 + threadIdx.x; i < end;
-         i += (int64_t)nblk * 256) {
-        int32_t b = V[i];
-        if ((uint32_t)b < 256u) atomicAdd(&sh[w][b], 1);
-    }
-    __syncthreads();
-    int32_t *H = reinterpret_cast<int32_t *>(t.h);
-    int s = sh[0][threadIdx.x] + sh[1][threadIdx.x] + sh[2][threadIdx.x] + sh[3][threadIdx.x];
-    if (s) atomicAdd(H + threadIdx.x, s);
+    hist_span(t.v, t.lo + (int64_t)(blockIdx.x - a.begin[ti]) * 256, end, (int64_t)nblk * 256, sh);
+    hist_flush(t.h, sh);
 }
 
 hipError_t launch_hist256_i32(const KLaunch &L) {

@@ -128,6 +128,7 @@ struct KernelDef {
     int grid_ndim;          // rank of the launch grid the body expects
     KernelFn fn;            // host launcher
     int max_group;          // tasks per grouped dispatch
+    int dkind;              // body id in the batch drain (DK_*), -1 = not batchable
 };
 
 const KernelDef *find_builtin(const char *name);
@@ -193,7 +194,11 @@ struct Chunk {
 // ------------------------------------------------------------------ arrays
 }  // namespace lt
 
+constexpr uint32_t LT_ARRAY_MAGIC = 0x4c544152u;
+
 struct lt_array {
+    uint32_t magic = LT_ARRAY_MAGIC;
+    void *owner = nullptr;   // the context
     uint64_t id = 0;
     lt_dtype dtype = LT_F32;
     int esz = 4;
@@ -227,6 +232,27 @@ struct TaskRec {
     std::vector<lt_region_info> regions;
 };
 
+// Records keyed by sequential ids (tasks, launches), dropped at lt_sync.
+template <class T>
+struct IdTable {
+    uint64_t base = 1;
+    std::deque<T> v;
+    T *get(uint64_t id) { return (id >= base && id < base + v.size()) ? &v[id - base] : nullptr; }
+    T &at(uint64_t id) {
+        while (base + v.size() <= id) v.emplace_back();
+        return v[id - base];
+    }
+    void reset(uint64_t next) {
+        v.clear();
+        base = next;
+    }
+};
+
+struct LaunchRec {
+    std::vector<uint64_t> tasks;
+    Fence done;
+};
+
 // --------------------------------------------------------------- streams
 struct Mark {
     uint64_t seq;
@@ -254,7 +280,17 @@ struct TraceSink;
 struct Arena {
     int64_t capacity = 0;
     std::map<int64_t, Seg> segs;       // covers [0, capacity)
+    std::multimap<int64_t, int64_t> free_by_size;  // free segments: size -> offset
     int64_t used = 0, peak = 0;
+    void index_add(const Seg &s) { free_by_size.insert({s.size, s.off}); }
+    void index_del(const Seg &s) {
+        auto r = free_by_size.equal_range(s.size);
+        for (auto it = r.first; it != r.second; ++it)
+            if (it->second == s.off) {
+                free_by_size.erase(it);
+                return;
+            }
+    }
     void init(int64_t cap);
     // best fit among free segments; returns offset or -1
     int64_t take_free(int64_t size, Fence *fence_out, int kind, Chunk *owner);
@@ -270,6 +306,25 @@ struct Arena {
 struct ChunkUse {
     Chunk *c;
     bool write;
+};
+
+struct Batch {
+    bool open = false;                 // between lt_batch_begin and lt_batch_end
+    std::vector<DTask> q;
+    std::vector<uint64_t> ids;         // task id of each queue entry
+    uint64_t index_base = 0;           // queue index of task id: index[id - index_base]
+    std::vector<int> index;
+    std::vector<uint64_t> launches;    // launches with tasks in this batch
+    int find(uint64_t id) const {
+        if (index.empty() || id < index_base || id - index_base >= index.size()) return -1;
+        return index[id - index_base];
+    }
+    std::vector<std::pair<int, int64_t>> patch_y, patch_x;  // partial-relative views
+    int64_t part_bytes = 0;
+    int nsignals = 0;
+    int64_t tiles = 0;
+    std::vector<ChunkUse> uses;
+    Fence wait;                        // dependencies issued before the batch
 };
 
 struct Group {
@@ -310,9 +365,8 @@ struct lt_context {
     std::unordered_map<std::string, std::shared_ptr<lt::Annotation>> annot_cache;
 
     // planner records (kept until lt_sync)
-    std::unordered_map<uint64_t, lt::TaskRec> tasks;
-    std::unordered_map<uint64_t, std::vector<uint64_t>> launch_tasks;
-    std::unordered_map<uint64_t, lt::Fence> launch_done;
+    lt::IdTable<lt::TaskRec> tasks;
+    lt::IdTable<lt::LaunchRec> launches;
 
     // throttle: staged tasks (completion point, footprint)
     std::deque<std::pair<lt::Fence, int64_t>> staged;
@@ -326,6 +380,11 @@ struct lt_context {
     std::vector<lt_trace_rec> trace;
     int rr = 0;                        // round-robin compute stream
     lt::Group group;                   // tasks awaiting one grouped dispatch
+    lt::Batch batch;                   // tasks awaiting the drain kernel
+    std::vector<void *> staging_free, staging_used;   // pinned upload buffers
+    std::vector<uint64_t> staging_size_free, staging_size_used;
+    int32_t *status_host = nullptr;    // drain error flags copied back
+    int status_slots = 0, status_next = 0;
 
     // profiling: (kernel name, start, end) awaiting resolution
     bool prof = false;
@@ -364,6 +423,8 @@ lt_status launch(Ctx *ctx, lt_kernel *k, int nd, const int64_t *grid,
                  const lt_arg *args, int nargs, uint64_t *launch_id);
 lt_status sync_all(Ctx *ctx);
 lt_status flush_group(Ctx *ctx);
+lt_status batch_flush(Ctx *ctx);
+lt_status flush_all(Ctx *ctx);
 lt_status prof_begin(Ctx *ctx, int s, const char *name, hipEvent_t *a);
 lt_status prof_end(Ctx *ctx, int s, const char *name, hipEvent_t a);
 void prof_collect(Ctx *ctx);

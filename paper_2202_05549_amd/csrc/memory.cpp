@@ -51,10 +51,12 @@ lt_status hip_fail(Ctx *ctx, hipError_t e, const char *what) {
 void Arena::init(int64_t cap) {
     capacity = cap;
     segs.clear();
+    free_by_size.clear();
     Seg s;
     s.off = 0;
     s.size = cap;
     segs[0] = s;
+    index_add(s);
     used = peak = 0;
 }
 
@@ -64,21 +66,13 @@ Seg *Arena::find(int64_t off) {
 }
 
 int64_t Arena::largest_free() const {
-    int64_t m = 0;
-    for (auto &kv : segs)
-        if (kv.second.kind == 0) m = std::max(m, kv.second.size);
-    return m;
+    return free_by_size.empty() ? 0 : free_by_size.rbegin()->first;
 }
 
 int64_t Arena::take_free(int64_t size, Fence *fence_out, int kind, Chunk *owner) {
-    auto best = segs.end();
-    for (auto it = segs.begin(); it != segs.end(); ++it) {
-        const Seg &s = it->second;
-        if (s.kind != 0 || s.size < size) continue;
-        if (best == segs.end() || s.size < best->second.size) best = it;
-    }
-    if (best == segs.end()) return -1;
-    return take_at(best->first, size, fence_out, kind, owner);
+    auto it = free_by_size.lower_bound(size);  // best fit
+    if (it == free_by_size.end()) return -1;
+    return take_at(it->second, size, fence_out, kind, owner);
 }
 
 int64_t Arena::take_at(int64_t off, int64_t size, Fence *fence_out, int kind, Chunk *owner) {
@@ -88,11 +82,13 @@ int64_t Arena::take_at(int64_t off, int64_t size, Fence *fence_out, int kind, Ch
     --it;
     Seg s = it->second;
     if (s.kind != 0 || off + size > s.off + s.size) return -1;
+    index_del(s);
     segs.erase(it);
     if (off > s.off) {
         Seg head = s;
         head.size = off - s.off;
         segs[head.off] = head;
+        index_add(head);
     }
     Seg mid = s;
     mid.off = off;
@@ -105,6 +101,7 @@ int64_t Arena::take_at(int64_t off, int64_t size, Fence *fence_out, int kind, Ch
         tail.off = off + size;
         tail.size = s.off + s.size - tail.off;
         segs[tail.off] = tail;
+        index_add(tail);
     }
     if (fence_out) *fence_out = s.fence;
     used += size;
@@ -122,6 +119,7 @@ void Arena::release(int64_t off, const Fence &fence) {
     // coalesce with the next and previous free segments
     auto nx = std::next(it);
     if (nx != segs.end() && nx->second.kind == 0) {
+        index_del(nx->second);
         it->second.size += nx->second.size;
         it->second.fence.merge(nx->second.fence);
         segs.erase(nx);
@@ -129,11 +127,14 @@ void Arena::release(int64_t off, const Fence &fence) {
     if (it != segs.begin()) {
         auto pv = std::prev(it);
         if (pv->second.kind == 0) {
+            index_del(pv->second);
             pv->second.size += it->second.size;
             pv->second.fence.merge(it->second.fence);
             segs.erase(it);
+            it = pv;
         }
     }
+    index_add(it->second);
 }
 
 // ---------------------------------------------------------------- tracing
