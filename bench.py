@@ -1,30 +1,39 @@
-"""Benchmark: 2-D Jacobi through annotated launches on one MI355X.
+"""Benchmarks of the annotated-launch runtime on one MI355X.
 
-Workload (one step): 100 ping-pong sweeps of the five-point Jacobi stencil on
-a 16384 x 16384 float32 field (~U[0,1), seed 1), as 100 annotated launches
+Default workload (``--workload jacobi``): 100 ping-pong sweeps of the
+five-point Jacobi stencil on a 16384 x 16384 float32 field (~U[0,1), seed 1)
+as 100 annotated launches
     global [r, c] => read x[r-1:r+1, c-1:c+1], write y[r, c]
 with 512-row chunks and 512-row superblocks (32 tasks per launch, 3200 per
-step), followed by lt_sync.  Planning, DAG edges and issue are inside the
-timed region.  Inputs are resident in HBM before timing starts.
+step), then lt_sync.  Planning, DAG edges and issue are inside the timed
+region; inputs are resident in HBM before timing starts.  Three executors:
+plain (one dispatch per task), grouped (the edge-free tasks of a launch
+share one dispatch) and drain (the whole step as one batch: one persistent
+dispatch, task edges resolved on the device).  ``value`` is the fastest of
+grouped and drain; plain is reported beside it.
 
-Metric: effective GB/s = algorithmic bytes / wall time, where a sweep moves
-8 bytes per point (read x once, write y once): 100 * 16384^2 * 8 B per step.
-The grouped executor (ready tasks of a launch share one dispatch) gives the
-reported value; the plain executor (one dispatch per task) is reported
-beside it.  p50/p99 are per-step wall times.
+Other workloads (one JSON line each):
+  stencil1d  1-D 3-point stencil, 2^20 float32, 8 chunks of 2^17, one
+             launch per step, plain per-chunk dispatches (also grouped/drain)
+  gemm_ooc   C = A B, 65536^2 float32 operands in pinned host memory, device
+             budget 16 GiB, 4096^2 superblocks in serpentine order
+  batch      8192 independent launches, stencil1d and hist256 mixed, sizes
+             log-uniform 2^10..2^24: plain vs batched (drain) vs graph replay
+  serve      Poisson request stream of Jacobi, k-means and GEMM requests
+             through the serving loop (see paper_2202_05549_amd/serve.py)
 
-roofline: dominant kernel k_jacobi2d, achieved = algorithmic bytes per
-dispatch / mean dispatch duration measured with HIP events on the runtime's
-compute stream during the timed steps; peak = 8 TB/s HBM.
-cpu_baseline: the CPU oracle timed on a bounded number of sweeps of the same
-field on this host's cores.
+roofline: the dominant kernel's algorithmic bytes (or FLOP) per dispatch /
+its mean dispatch duration, timed with HIP events on the runtime's own
+stream during the timed steps.  cpu_baseline: the CPU oracle timed on a
+bounded sample of the same workload on this host's cores (jacobi only).
 
-python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu]
+python bench.py [--workload W] [--steps K] [--warmup W] [--gpus 1] [--no-cpu]
 """
 from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -34,23 +43,46 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
+METRIC = "effective GB/s (% HBM or host-link roofline), plain vs batched; p50/p99 latency"
+HBM_PEAK_GBS = 8000.0
+MFMA_FP32_PEAK = 157.3
+PCIE_NOMINAL_GBS = 63.0
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def pct(times, q):
+    return float(np.percentile(np.asarray(times) * 1e3, q))
+
+
+def base_line(workload_cfg, steps, warmup):
+    return {"metric": METRIC, "n_gpus": 1, "steps": steps, "warmup": warmup, "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "data": "synthetic", "config": workload_cfg}
+
+
+def torch_arena(torch, nbytes):
+    t = torch.empty(nbytes, dtype=torch.uint8, device="cuda:0")
+    torch.cuda.synchronize()
+    return t
+
+
+# =================================================================== jacobi
 N = 16384
 SWEEPS = 100
 CHUNK_ROWS = 512
-BYTES_PER_POINT = 8
-HBM_PEAK_GBS = 8000.0
 
 
-def run_gpu(mode: int, steps: int, warmup: int, x0: np.ndarray, torch):
-    import paper_2202_05549_amd as L
-
+def jacobi_run(L, torch, x0, executor, steps, warmup, rows=None):
     field_bytes = N * N * 4
-    budget = 2 * field_bytes + (64 << 20)
-    arena = torch.empty(budget, dtype=torch.uint8, device="cuda:0")
-    torch.cuda.synchronize()
-    ctx = L.Context(device=0, device_budget_bytes=budget, device_arena=arena.data_ptr(),
-                    arena_bytes=budget, exec_mode=mode)
+    budget = 2 * field_bytes + (256 << 20)
+    arena = torch_arena(torch, budget)
+    ctx = L.Context(device=0, device_budget_bytes=budget, device_arena=arena.data_ptr(), arena_bytes=budget,
+                    exec_mode=0 if executor == "plain" else 1)
     try:
+        if rows:
+            ctx.tune("jacobi2d_f32", rows)
         a = ctx.array([N, N], chunk=[CHUNK_ROWS, 0])
         b = ctx.array([N, N], chunk=[CHUNK_ROWS, 0])
         a.write(x0)
@@ -58,15 +90,19 @@ def run_gpu(mode: int, steps: int, warmup: int, x0: np.ndarray, torch):
         ctx.sync()
 
         def step():
+            if executor == "drain":
+                ctx.batch_begin()
             inp, out = a, b
             for _ in range(SWEEPS):
                 ctx.launch("jacobi2d_f32", [N, N], [1, 256], [CHUNK_ROWS, 0], args=[N, N, out, inp])
                 inp, out = out, inp
+            if executor == "drain":
+                ctx.batch_end()
             ctx.sync()
 
         for _ in range(warmup):
             step()
-        ctx.profile(True)
+        ctx.profile(executor != "plain")  # plain: per-dispatch events would slow the host path
         ctx.profile_reset()
         ctx.reset_stats()
         torch.cuda.synchronize()
@@ -78,8 +114,13 @@ def run_gpu(mode: int, steps: int, warmup: int, x0: np.ndarray, torch):
             times.append(time.perf_counter() - s0)
         torch.cuda.synchronize()
         total = time.perf_counter() - t0
-        prof = ctx.profile_get()
         stats = ctx.stats()
+        prof = ctx.profile_get()
+        if executor == "plain":  # kernel time from a separate profiled step
+            ctx.profile(True)
+            ctx.profile_reset()
+            step()
+            prof = ctx.profile_get()
         ctx.profile(False)
     finally:
         ctx.close()
@@ -87,7 +128,7 @@ def run_gpu(mode: int, steps: int, warmup: int, x0: np.ndarray, torch):
     return total, times, prof, stats
 
 
-def cpu_baseline(x0: np.ndarray, budget_s: float = 12.0):
+def jacobi_cpu_baseline(x0, budget_s=12.0):
     import oracle
 
     a = np.array(x0, copy=True)
@@ -99,92 +140,338 @@ def cpu_baseline(x0: np.ndarray, budget_s: float = 12.0):
     t0 = time.perf_counter()
     oracle.jacobi2d(a, sweeps, inplace=True)
     dt = time.perf_counter() - t0
-    gbs = sweeps * N * N * BYTES_PER_POINT / dt / 1e9
-    return {"value": round(gbs, 3), "unit": "GB/s", "cores": oracle.num_threads(), "kind": "oracle",
+    return {"value": round(sweeps * N * N * 8 / dt / 1e9, 3), "unit": "GB/s", "cores": oracle.num_threads(),
+            "kind": "oracle",
             "sample": "%d sweeps of the 16384x16384 float32 field (of %d per step), %.2f s" % (sweeps, SWEEPS, dt)}
+
+
+def bench_jacobi(args, L, torch):
+    import synthetic
+
+    log("generating the 16384^2 field")
+    x0 = synthetic.jacobi2d_input(N, seed=1)
+    step_bytes = SWEEPS * N * N * 8
+    res = {}
+    for ex in ("grouped", "drain", "plain"):
+        log("%s executor: %d warm-up + %d timed steps" % (ex, args.warmup, args.steps))
+        total, times, prof, stats = jacobi_run(L, torch, x0, ex, args.steps, args.warmup, args.rows)
+        kname = "drain" if ex == "drain" else "jacobi2d_f32"
+        k = prof.get(kname, {"dispatches": 0, "total_ms": float("nan")})
+        per_dispatch_bytes = {"grouped": N * N * 8, "plain": CHUNK_ROWS * N * 8, "drain": step_bytes}[ex]
+        avg_ms = k["total_ms"] / max(1, k["dispatches"])
+        res[ex] = {"ms_per_step": total / args.steps * 1e3, "gbs": step_bytes / (total / args.steps) / 1e9,
+                   "p50_ms": pct(times, 50), "p99_ms": pct(times, 99), "kernel_avg_ms": avg_ms,
+                   "kernel_gbs": per_dispatch_bytes / (avg_ms * 1e-3) / 1e9,
+                   "dispatches_per_step": stats["dispatches"] / args.steps,
+                   "plan_ms_per_step": stats["plan_seconds"] / args.steps * 1e3}
+        log("%s: %s" % (ex, json.dumps(res[ex])))
+    best = max(("grouped", "drain"), key=lambda e: res[e]["gbs"])
+    m = res[best]
+    line = base_line({"workload": "jacobi2d 16384x16384 f32 ~U[0,1) seed 1, 100 ping-pong sweeps, 512-row chunks "
+                                  "and superblocks, in HBM", "executor": best, "sweeps_per_step": SWEEPS,
+                      "tasks_per_step": SWEEPS * N // CHUNK_ROWS}, args.steps, args.warmup)
+    line.update({"value": round(m["gbs"], 2), "unit": "GB/s", "ms_per_step": round(m["ms_per_step"], 4),
+                 "dtype": "f32", "hbm_frac": round(m["gbs"] / HBM_PEAK_GBS, 4), "p50_ms": round(m["p50_ms"], 3),
+                 "p99_ms": round(m["p99_ms"], 3),
+                 "roofline": {"bound": "hbm", "achieved": round(m["kernel_gbs"], 2), "peak": HBM_PEAK_GBS,
+                              "unit": "GB/s", "frac": round(m["kernel_gbs"] / HBM_PEAK_GBS, 4), "traffic": None,
+                              "kernel": "k_drain" if best == "drain" else "k_jacobi2d",
+                              "kernel_avg_ms": round(m["kernel_avg_ms"], 4)}})
+    for ex in ("grouped", "drain", "plain"):
+        if ex == best:
+            continue
+        r = res[ex]
+        line[ex] = {"value": round(r["gbs"], 2), "ms_per_step": round(r["ms_per_step"], 4),
+                    "p50_ms": round(r["p50_ms"], 3), "p99_ms": round(r["p99_ms"], 3),
+                    "kernel_gbs": round(r["kernel_gbs"], 2), "dispatches_per_step": r["dispatches_per_step"]}
+    line["batched_over_plain"] = round(m["gbs"] / res["plain"]["gbs"], 3)
+    if not args.no_cpu:
+        log("cpu baseline (oracle)")
+        line["cpu_baseline"] = jacobi_cpu_baseline(x0)
+    return line
+
+
+# ================================================================ stencil1d
+def bench_stencil1d(args, L, torch):
+    import synthetic
+
+    n, chunk = 1 << 20, 1 << 17
+    x0 = synthetic.stencil1d_input(n, 0)
+    res = {}
+    for ex in ("plain", "grouped", "drain"):
+        arena = torch_arena(torch, 64 << 20)
+        ctx = L.Context(device_budget_bytes=64 << 20, device_arena=arena.data_ptr(), arena_bytes=64 << 20,
+                        exec_mode=0 if ex == "plain" else 1)
+        x = ctx.array([n], chunk=[chunk])
+        y = ctx.array([n], chunk=[chunk])
+        x.write(x0)
+        ctx.sync()
+
+        def step():
+            if ex == "drain":
+                ctx.batch_begin()
+            ctx.launch("stencil1d_f32", [n], [256], [chunk], args=[n, y, x])
+            if ex == "drain":
+                ctx.batch_end()
+            ctx.sync()
+
+        steps = max(args.steps, 200)
+        for _ in range(max(args.warmup, 10)):
+            step()
+        ctx.profile(True)
+        ctx.profile_reset()
+        times = []
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            s0 = time.perf_counter()
+            step()
+            times.append(time.perf_counter() - s0)
+        total = time.perf_counter() - t0
+        prof = ctx.profile_get()
+        ctx.close()
+        del arena
+        kname = "drain" if ex == "drain" else "stencil1d_f32"
+        k = prof[kname]
+        per_dispatch = {"plain": chunk * 8, "grouped": n * 8, "drain": n * 8}[ex]
+        avg_ms = k["total_ms"] / k["dispatches"]
+        res[ex] = {"gbs": n * 8 / (total / steps) / 1e9, "us_per_launch": total / steps * 1e6,
+                   "p50_us": pct(times, 50) * 1e3, "p99_us": pct(times, 99) * 1e3,
+                   "kernel_gbs": per_dispatch / (avg_ms * 1e-3) / 1e9, "kernel_avg_us": avg_ms * 1e3,
+                   "dispatches_per_launch": k["dispatches"] / steps, "steps": steps}
+        log("%s: %s" % (ex, json.dumps(res[ex])))
+    m = res["plain"]
+    line = base_line({"workload": "stencil1d 2^20 f32 ~U(-1,1) seed 0, 8 chunks of 2^17, one launch per step, "
+                                  "plain per-chunk dispatches, data warm in the 256 MB Infinity Cache",
+                      "executor": "plain"}, m["steps"], max(args.warmup, 10))
+    line.update({"value": round(m["gbs"], 2), "unit": "GB/s", "ms_per_step": round(m["us_per_launch"] / 1e3, 5),
+                 "dtype": "f32", "p50_us": round(m["p50_us"], 2), "p99_us": round(m["p99_us"], 2),
+                 "roofline": {"bound": "hbm", "achieved": round(m["kernel_gbs"], 2), "peak": HBM_PEAK_GBS,
+                              "unit": "GB/s", "frac": round(m["kernel_gbs"] / HBM_PEAK_GBS, 4), "traffic": None,
+                              "kernel": "k_stencil1d", "kernel_avg_us": round(m["kernel_avg_us"], 3),
+                              "note": "launch-latency bound: 1 MiB per dispatch, data cache-resident"}})
+    for ex in ("grouped", "drain"):
+        r = res[ex]
+        line[ex] = {"value": round(r["gbs"], 2), "p50_us": round(r["p50_us"], 2), "p99_us": round(r["p99_us"], 2),
+                    "kernel_gbs": round(r["kernel_gbs"], 2)}
+    return line
+
+
+# ================================================================= gemm_ooc
+def bench_gemm_ooc(args, L, torch):
+    import synthetic
+
+    n, T = 65536, 4096
+    steps = args.steps if args.steps_given else 1
+    warmup = args.warmup if args.warmup_given else 0
+    ctx = L.Context(device_budget_bytes=16 << 30, stage_threshold_bytes=8 << 30, sb_order=L.LT_ORDER_SERPENTINE)
+    try:
+        log("allocating 48 GiB of pinned host memory")
+        A = ctx.pinned((n, n))
+        B = ctx.pinned((n, n))
+        Cm = ctx.pinned((n, n))
+        log("generating operands")
+        synthetic.gemm_operand(0, n, T, out=A, workers=16)
+        synthetic.gemm_operand(1, n, T, out=B, workers=16)
+        a = ctx.array_host(A, chunk=[T, 0])
+        b = ctx.array_host(B, chunk=[0, T])
+        c = ctx.array_host(Cm, chunk=[T, T])
+
+        def step():
+            ctx.launch("gemm_f32", [n, n], [1, 1], [T, T], args=[n, n, n, c, a, b])
+            ctx.sync()
+
+        for _ in range(warmup):
+            step()
+        ctx.profile(True)
+        ctx.profile_reset()
+        ctx.reset_stats()
+        times = []
+        for i in range(steps):
+            log("timed step %d" % i)
+            s0 = time.perf_counter()
+            step()
+            times.append(time.perf_counter() - s0)
+        total = sum(times)
+        prof = ctx.profile_get()["gemm_f32"]
+        st = ctx.stats()
+    finally:
+        ctx.close()
+    flops = 2.0 * n ** 3
+    wall = total / steps
+    kernel_tflops = flops / (prof["total_ms"] / steps * 1e-3) / 1e12
+    compulsory = 3 * n * n * 4
+    h2d = st["bytes_h2d"] / steps
+    d2h = st["bytes_d2h"] / steps
+    line = base_line({"workload": "out-of-core GEMM 65536^3 f32 ~N(0,1) seed 2, A/B/C in pinned host memory "
+                                  "(48 GiB), device budget 16 GiB, 4096^2 superblocks in serpentine order",
+                      "executor": "plain", "stage_threshold_bytes": 8 << 30}, steps, warmup)
+    line.update({"value": round(compulsory / wall / 1e9, 2), "unit": "GB/s", "ms_per_step": round(wall * 1e3, 2),
+                 "dtype": "f32", "tflops_wall": round(flops / wall / 1e12, 2),
+                 "mfma_frac_wall": round(flops / wall / 1e12 / MFMA_FP32_PEAK, 4),
+                 "link": {"h2d_gib": round(h2d / 2**30, 2), "d2h_gib": round(d2h / 2**30, 2),
+                          "compulsory_gib": 48.0, "h2d_gbs_avg": round(h2d / wall / 1e9, 2),
+                          "link_busy_frac_at_57gbs": round((h2d + d2h) / 57e9 / wall, 3)},
+                 "kernel_busy_frac": round(prof["total_ms"] / steps * 1e-3 / wall, 4),
+                 "p50_ms": round(pct(times, 50), 2), "p99_ms": round(pct(times, 99), 2),
+                 "roofline": {"bound": "mfma", "achieved": round(kernel_tflops, 2), "peak": MFMA_FP32_PEAK,
+                              "unit": "TFLOP/s", "frac": round(kernel_tflops / MFMA_FP32_PEAK, 4), "traffic": None,
+                              "kernel": "k_gemm", "kernel_avg_ms": round(prof["total_ms"] / prof["dispatches"], 3)}})
+    return line
+
+
+# ==================================================================== batch
+def bench_batch(args, L, torch):
+    import synthetic
+    from paper_2202_05549_amd import autotune
+
+    plan = synthetic.batch_plan(8192)
+    ns = np.array([n for _, n in plan], dtype=np.int64)
+    kinds = np.array([k for k, _ in plan])
+    names = ["stencil1d_f32" if k == 0 else "hist256_i32" for k in kinds]
+    elems = int(ns.sum())
+    algo_bytes = int((ns[kinds == 0] * 8).sum() + (ns[kinds == 1] * 4).sum() + 1024 * (kinds == 1).sum())
+    budget = int(algo_bytes * 1.05) + (8 << 30)
+    arena = torch_arena(torch, budget)
+    ctx = L.Context(device_budget_bytes=budget, device_arena=arena.data_ptr(), arena_bytes=budget)
+    g = torch.Generator(device="cuda:0")
+    g.manual_seed(3)
+    cdf = torch.tensor(synthetic.zipf_cdf(), dtype=torch.float64, device="cuda:0")
+    log("creating %d arrays (%.1f GB of inputs and outputs), inputs drawn on the GPU" % (len(plan), algo_bytes / 1e9))
+    arrs = []
+    for k, n in plan:
+        if k == 0:
+            x = ctx.array([n])
+            y = ctx.array([n])
+            t = torch.rand(n, generator=g, device="cuda:0", dtype=torch.float32) * 2 - 1
+        else:
+            x = ctx.array([n], np.int32)
+            y = ctx.array([256], np.int32)
+            u = torch.rand(n, generator=g, device="cuda:0", dtype=torch.float64)
+            t = torch.clamp(torch.searchsorted(cdf, u, right=True), max=255).to(torch.int32)
+        x.write_device(t.data_ptr())
+        arrs.append((y, x))
+    del t
+    torch.cuda.synchronize()
+    grids = ns[:, None]
+    res = {}
+
+    def run(mode, sb, wg=1024, flush=0, steps=None, times=None, graph=None):
+        ctx.configure(drain_workgroups=wg, batch_flush_tasks=flush)
+        sbs = np.full((len(plan), 1), sb, dtype=np.int64)
+        args_t = L.Context.arg_table(len(plan), [ns, [a[0] for a in arrs], [a[1] for a in arrs]])
+        s0 = time.perf_counter()
+        if mode == "graph":
+            ctx.graph_launch(graph)
+        else:
+            if mode == "batched":
+                ctx.batch_begin()
+            ctx.launch_many(names, grids, [1], sbs, args_t)
+            if mode == "batched":
+                ctx.batch_end()
+        ctx.sync()
+        dt = time.perf_counter() - s0
+        if times is not None:
+            times.append(dt)
+        return dt
+
+    log("autotuning superblock size, drain width and flush size on the full mix")
+    best = autotune.tune("batch8192", {"sb": [1 << 16, 1 << 18, 1 << 20, 1 << 22], "wg": [512, 1024, 2048],
+                                       "flush": [0, 4096]},
+                         lambda sb, wg, flush: run("batched", sb, wg, flush), reps=1, cache=None, log=log)
+    log("tuned: %s" % best)
+    best_plain = autotune.tune("batch8192_plain", {"sb": [1 << 18, 1 << 20, 1 << 22, 1 << 24]},
+                               lambda sb: run("plain", sb), reps=1, cache=None, log=log)
+    log("tuned plain: %s" % best_plain)
+    for mode in ("plain", "batched", "graph"):
+        graph = None
+        if mode == "graph":
+            ctx.configure(drain_workgroups=best["wg"], batch_flush_tasks=0)
+            ctx.graph_begin()
+            ctx.launch_many(names, grids, [1], np.full((len(plan), 1), best["sb"], dtype=np.int64),
+                            L.Context.arg_table(len(plan), [ns, [a[0] for a in arrs], [a[1] for a in arrs]]))
+            graph = ctx.graph_end()
+        sb = best_plain["sb"] if mode == "plain" else best["sb"]
+        for _ in range(args.warmup):
+            run(mode, sb, best["wg"], best["flush"] if mode == "batched" else 0, graph=graph)
+        ctx.profile(mode != "plain")
+        ctx.profile_reset()
+        ctx.reset_stats()
+        times = []
+        for _ in range(args.steps):
+            run(mode, sb, best["wg"], best["flush"] if mode == "batched" else 0, times=times, graph=graph)
+        prof = ctx.profile_get()
+        stats = ctx.stats()
+        ctx.profile(False)
+        if graph is not None:
+            ctx.graph_destroy(graph)
+        wall = float(np.mean(times))
+        r = {"gbs": algo_bytes / wall / 1e9, "ms_per_step": wall * 1e3, "p50_ms": pct(times, 50),
+             "p99_ms": pct(times, 99), "dispatches_per_step": stats["dispatches"] / args.steps,
+             "tasks_per_step": stats["tasks"] / args.steps, "plan_ms_per_step": stats["plan_seconds"] / args.steps * 1e3}
+        if "drain" in prof:
+            k = prof["drain"]
+            r["drain_ms"] = k["total_ms"] / args.steps
+            r["kernel_gbs"] = algo_bytes / (r["drain_ms"] * 1e-3) / 1e9
+        res[mode] = r
+        log("%s: %s" % (mode, json.dumps(r)))
+    m = res["batched"]
+    line = base_line({"workload": "batching: 8192 independent launches, stencil1d f32 ~U(-1,1) and hist256 int32 "
+                                  "bounded Zipf(1.1), sizes floor(2^U(10,24)) seed 3 (%d elements)" % elems,
+                      "executor": "batched (persistent drain)", "superblock": best["sb"],
+                      "drain_workgroups": best["wg"], "batch_flush_tasks": best["flush"],
+                      "plain_superblock": best_plain["sb"]}, args.steps, args.warmup)
+    line.update({"value": round(m["gbs"], 2), "unit": "GB/s", "ms_per_step": round(m["ms_per_step"], 3),
+                 "dtype": "f32+i32", "p50_ms": round(m["p50_ms"], 3), "p99_ms": round(m["p99_ms"], 3),
+                 "hbm_frac": round(m["gbs"] / HBM_PEAK_GBS, 4),
+                 "roofline": {"bound": "hbm", "achieved": round(m.get("kernel_gbs", float("nan")), 2),
+                              "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                              "frac": round(m.get("kernel_gbs", float("nan")) / HBM_PEAK_GBS, 4), "traffic": None,
+                              "kernel": "k_drain", "kernel_ms_per_step": round(m.get("drain_ms", float("nan")), 3)},
+                 "plain": {k: round(v, 3) for k, v in res["plain"].items()},
+                 "graph": {k: round(v, 3) for k, v in res["graph"].items()},
+                 "batched_over_plain": round(m["gbs"] / res["plain"]["gbs"], 3),
+                 "graph_over_plain": round(res["graph"]["gbs"] / res["plain"]["gbs"], 3)})
+    ctx.close()
+    del arena
+    return line
+
+
+# ==================================================================== serve
+def bench_serve(args, L, torch):
+    from paper_2202_05549_amd import serve
+
+    return serve.bench(args, L, torch, log)
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=None)
+    ap.add_argument("--warmup", type=int, default=None)
+    ap.add_argument("--workload", choices=["jacobi", "stencil1d", "gemm_ooc", "batch", "serve"], default="jacobi")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--mode", choices=["both", "grouped", "plain"], default="both")
+    ap.add_argument("--rows", type=int, default=8, help="rows per Jacobi tile (8, 16, 32)")
     args = ap.parse_args()
+    args.steps_given = args.steps is not None
+    args.warmup_given = args.warmup is not None
+    if args.steps is None:
+        args.steps = 10
+    if args.warmup is None:
+        args.warmup = 2
     if args.gpus != 1:
-        print("bench.py measures one GPU only; multi-GPU runs are not part of this build "
+        print("bench.py measures one GPU only; runs on several GPUs are not part of this build "
               "(requested --gpus %d)" % args.gpus, file=sys.stderr)
         sys.exit(2)
-
     import torch
-    import synthetic
 
     if not torch.cuda.is_available():
         print("no GPU visible", file=sys.stderr)
         sys.exit(1)
-    print("[bench] generating 16384^2 field", file=sys.stderr, flush=True)
-    x0 = synthetic.jacobi2d_input(N, seed=1)
-    step_bytes = SWEEPS * N * N * BYTES_PER_POINT
+    import paper_2202_05549_amd as L
 
-    res = {}
-    modes = {"grouped": 1, "plain": 0}
-    for name, mode in modes.items():
-        if args.mode != "both" and args.mode != name:
-            continue
-        print("[bench] %s executor: %d warmup + %d timed steps" % (name, args.warmup, args.steps),
-              file=sys.stderr, flush=True)
-        total, times, prof, stats = run_gpu(mode, args.steps, args.warmup, x0, torch)
-        k = prof.get("jacobi2d_f32", {"dispatches": 0, "total_ms": float("nan")})
-        per_dispatch_points = (N * N) if mode == 1 else (CHUNK_ROWS * N)
-        avg_ms = k["total_ms"] / max(1, k["dispatches"])
-        res[name] = {
-            "ms_per_step": total / args.steps * 1e3,
-            "gbs": step_bytes / (total / args.steps) / 1e9,
-            "p50_ms": float(np.percentile(times, 50)) * 1e3,
-            "p99_ms": float(np.percentile(times, 99)) * 1e3,
-            "dispatches_per_step": k["dispatches"] / args.steps,
-            "kernel_avg_ms": avg_ms,
-            "kernel_gbs": per_dispatch_points * BYTES_PER_POINT / (avg_ms * 1e-3) / 1e9,
-            "plan_ms_per_step": stats["plan_seconds"] / args.steps * 1e3,
-        }
-        print("[bench] %s: %s" % (name, json.dumps(res[name])), file=sys.stderr, flush=True)
-
-    main_name = "grouped" if "grouped" in res else "plain"
-    m = res[main_name]
-    line = {
-        "metric": "effective GB/s (% HBM or host-link roofline), plain vs batched; p50/p99 latency",
-        "value": round(m["gbs"], 2),
-        "unit": "GB/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": round(m["ms_per_step"], 4),
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32",
-        "data": "synthetic",
-        "config": {"workload": "jacobi2d 16384x16384 f32 ~U[0,1) seed 1, 100 ping-pong sweeps, "
-                               "512-row chunks and superblocks, in HBM",
-                   "executor": main_name, "sweeps_per_step": SWEEPS, "tasks_per_step": SWEEPS * N // CHUNK_ROWS},
-        "hbm_frac": round(m["gbs"] / HBM_PEAK_GBS, 4),
-        "p50_ms": round(m["p50_ms"], 3),
-        "p99_ms": round(m["p99_ms"], 3),
-        "roofline": {"bound": "hbm", "achieved": round(m["kernel_gbs"], 2), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(m["kernel_gbs"] / HBM_PEAK_GBS, 4), "traffic": None,
-                     "kernel": "k_jacobi2d", "kernel_avg_ms": round(m["kernel_avg_ms"], 4)},
-    }
-    if "plain" in res and main_name != "plain":
-        p = res["plain"]
-        line["plain"] = {"value": round(p["gbs"], 2), "ms_per_step": round(p["ms_per_step"], 4),
-                         "p50_ms": round(p["p50_ms"], 3), "p99_ms": round(p["p99_ms"], 3),
-                         "kernel_gbs": round(p["kernel_gbs"], 2),
-                         "dispatches_per_step": p["dispatches_per_step"]}
-        line["batched_over_plain"] = round(m["gbs"] / p["gbs"], 3)
-    if not args.no_cpu:
-        print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
-        line["cpu_baseline"] = cpu_baseline(x0)
+    fn = {"jacobi": bench_jacobi, "stencil1d": bench_stencil1d, "gemm_ooc": bench_gemm_ooc, "batch": bench_batch,
+          "serve": bench_serve}[args.workload]
+    line = fn(args, L, torch)
     print(json.dumps(line), flush=True)
 
 

@@ -102,7 +102,11 @@ typedef struct lt_config {
                                        previous row touched last)            */
     int32_t drain_workgroups;       /* workgroups of the batch drain kernel;
                                        0 = 1024                               */
-    int32_t reserved[5];
+    int32_t batch_flush_tasks;      /* an open batch issues its queue whenever
+                                       it holds this many tasks, so planning
+                                       of later launches overlaps the drain of
+                                       earlier ones; 0 = only at lt_batch_end */
+    int32_t reserved[4];
 } lt_config;
 
 #define LT_ORDER_ROWMAJOR 0
@@ -118,6 +122,12 @@ lt_status lt_context_create(const lt_config *cfg, lt_context **out);
 /* Waits for all work, releases every array, kernel and pool of the context.
  * Returns the first sticky error, if any. */
 lt_status lt_context_destroy(lt_context *ctx);
+
+/* Updates the tunable fields of a live context from *cfg: exec_mode,
+ * stage_threshold_bytes, sb_order, drain_workgroups, batch_flush_tasks,
+ * trace.  Other fields are ignored.  Pending grouped work and an open batch's
+ * queue are issued first.  Errors: LT_ERR_INVALID. */
+lt_status lt_context_configure(lt_context *ctx, const lt_config *cfg);
 
 /* Message of the last error on ctx; "" if none.  ctx may be NULL for errors
  * of lt_context_create. */
@@ -293,6 +303,20 @@ lt_status lt_wait(lt_context *ctx, uint64_t launch_id);
  * reports LT_ERR_TIMEOUT at the next lt_sync. */
 lt_status lt_batch_begin(lt_context *ctx);
 lt_status lt_batch_end(lt_context *ctx);
+
+/* Graphs: a batch planned once and replayed.  lt_graph_begin opens a batch
+ * whose queue is not issued; lt_graph_end turns it into a HIP graph (queue
+ * upload, counter clear, drain) that owns its device queue and keeps every
+ * chunk it touches pinned in HBM at its current place.  lt_graph_launch
+ * replays it, ordered after earlier work on those chunks like any launch;
+ * each replay recomputes the same tasks on the arrays' current contents.
+ * lt_graph_destroy releases it (after its last replay completes).  Arrays a
+ * graph uses cannot be destroyed while it exists (LT_ERR_INVALID). */
+typedef struct lt_graph lt_graph;
+lt_status lt_graph_begin(lt_context *ctx);
+lt_status lt_graph_end(lt_context *ctx, lt_graph **out);
+lt_status lt_graph_launch(lt_context *ctx, lt_graph *g);
+lt_status lt_graph_destroy(lt_context *ctx, lt_graph *g);
 
 /* ----------------------------------------------------------- introspection
  * Planner output of a launch, for tests and tools.  Task records are kept

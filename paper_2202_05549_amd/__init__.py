@@ -46,7 +46,7 @@ class lt_config(C.Structure):
                 ("dry_run", C.c_int32), ("device_budget_bytes", C.c_uint64),
                 ("stage_threshold_bytes", C.c_uint64), ("device_arena", C.c_void_p),
                 ("arena_bytes", C.c_uint64), ("trace", C.c_int32), ("sb_order", C.c_int32),
-                ("drain_workgroups", C.c_int32), ("reserved", C.c_int32 * 5)]
+                ("drain_workgroups", C.c_int32), ("batch_flush_tasks", C.c_int32), ("reserved", C.c_int32 * 4)]
 
 
 class lt_box(C.Structure):
@@ -116,6 +116,7 @@ _SIGS = [
     ("lt_context_create", C.c_int32, [C.POINTER(lt_config), C.POINTER(_P)]),
     ("lt_context_destroy", C.c_int32, [_P]),
     ("lt_last_error", C.c_char_p, [_P]),
+    ("lt_context_configure", C.c_int32, [_P, C.POINTER(lt_config)]),
     ("lt_array_create", C.c_int32, [_P, C.c_int32, C.c_int32, C.POINTER(C.c_int64), C.POINTER(lt_dist),
                                     C.POINTER(_P)]),
     ("lt_array_create_host", C.c_int32, [_P, C.c_int32, C.c_int32, C.POINTER(C.c_int64),
@@ -140,6 +141,10 @@ _SIGS = [
     ("lt_sync", C.c_int32, [_P]),
     ("lt_batch_begin", C.c_int32, [_P]),
     ("lt_batch_end", C.c_int32, [_P]),
+    ("lt_graph_begin", C.c_int32, [_P]),
+    ("lt_graph_end", C.c_int32, [_P, C.POINTER(_P)]),
+    ("lt_graph_launch", C.c_int32, [_P, _P]),
+    ("lt_graph_destroy", C.c_int32, [_P, _P]),
     ("lt_wait", C.c_int32, [_P, C.c_uint64]),
     ("lt_plan_tasks", C.c_int32, [_P, C.c_uint64, C.POINTER(lt_task_info), C.c_int32, C.POINTER(C.c_int32)]),
     ("lt_plan_regions", C.c_int32, [_P, C.c_uint64, C.POINTER(lt_region_info), C.c_int32,
@@ -262,6 +267,13 @@ class Context:
         self.h = h
         self.cfg = c
         self._kernels = {}
+
+    def configure(self, **cfg):
+        """Change tunable fields (exec_mode, stage_threshold_bytes, sb_order,
+        drain_workgroups, batch_flush_tasks, trace) of the live context."""
+        for k, v in cfg.items():
+            setattr(self.cfg, k, v)
+        check(self.h, lt_context_configure(self.h, C.byref(self.cfg)))
 
     def close(self):
         if self.h:
@@ -395,6 +407,20 @@ class Context:
                 t["kind"][:, j] = LT_ARG_INT
                 t["i"][:, j] = np.asarray(col, dtype=np.int64)
         return t
+
+    def graph_begin(self):
+        check(self.h, lt_graph_begin(self.h))
+
+    def graph_end(self):
+        g = _P()
+        check(self.h, lt_graph_end(self.h, C.byref(g)))
+        return g
+
+    def graph_launch(self, g):
+        check(self.h, lt_graph_launch(self.h, g))
+
+    def graph_destroy(self, g):
+        check(self.h, lt_graph_destroy(self.h, g))
 
     def sync(self):
         check(self.h, lt_sync(self.h))

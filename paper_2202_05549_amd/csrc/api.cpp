@@ -100,6 +100,11 @@ lt_status sync_all(Ctx *ctx) {
                 ctx->sticky_msg = "a dependency wait inside the batch drain exceeded its poll limit";
             }
         ctx->status_next = 0;
+        for (int32_t *gs : ctx->graph_status)
+            if (*gs && ctx->sticky == LT_OK) {
+                ctx->sticky = LT_ERR_TIMEOUT;
+                ctx->sticky_msg = "a dependency wait inside a graph's drain exceeded its poll limit";
+            }
     }
     for (size_t i = 0; i < ctx->staging_used.size(); ++i) {
         ctx->staging_free.push_back(ctx->staging_used[i]);
@@ -372,6 +377,8 @@ lt_status array_fill(Ctx *ctx, Array *arr, const void *scalar) {
 }
 
 lt_status array_destroy(Ctx *ctx, Array *arr) {
+    for (Chunk *c : arr->chunks)
+        if (c->pin > 0) return set_err(ctx, LT_ERR_INVALID, "array is in use by a graph");
     lt_status st = flush_all(ctx);
     if (st) return st;
     arr->dead = true;
@@ -459,6 +466,21 @@ lt_status lt_context_destroy(lt_context *ctx) {
     ctx_release_all(ctx);
     delete ctx;
     return st;
+}
+
+lt_status lt_context_configure(lt_context *ctx, const lt_config *cfg) {
+    if (!ctx || !cfg) return LT_ERR_INVALID;
+    if (cfg->exec_mode != LT_EXEC_PLAIN && cfg->exec_mode != LT_EXEC_GROUPED)
+        return set_err(ctx, LT_ERR_INVALID, "unknown exec_mode %d", cfg->exec_mode);
+    lt_status st = flush_all(ctx);
+    if (st) return st;
+    ctx->cfg.exec_mode = cfg->exec_mode;
+    ctx->cfg.stage_threshold_bytes = cfg->stage_threshold_bytes;
+    ctx->cfg.sb_order = cfg->sb_order;
+    ctx->cfg.drain_workgroups = cfg->drain_workgroups;
+    ctx->cfg.batch_flush_tasks = cfg->batch_flush_tasks;
+    ctx->cfg.trace = cfg->trace;
+    return LT_OK;
 }
 
 const char *lt_last_error(lt_context *ctx) {
@@ -630,6 +652,7 @@ lt_status lt_launch_many(lt_context *ctx, lt_kernel *const *kernels, int32_t cou
 
 lt_status lt_batch_begin(lt_context *ctx) {
     if (!ctx) return LT_ERR_INVALID;
+    if (ctx->batch.capture) return set_err(ctx, LT_ERR_INVALID, "a graph is being recorded");
     lt_status st = flush_group(ctx);
     if (st) return st;
     ctx->batch.open = true;
@@ -638,9 +661,42 @@ lt_status lt_batch_begin(lt_context *ctx) {
 
 lt_status lt_batch_end(lt_context *ctx) {
     if (!ctx) return LT_ERR_INVALID;
+    if (ctx->batch.capture) return set_err(ctx, LT_ERR_INVALID, "a graph is being recorded (lt_graph_end)");
     lt_status st = batch_flush(ctx);
     ctx->batch.open = false;
     return st;
+}
+
+lt_status lt_graph_begin(lt_context *ctx) {
+    if (!ctx) return LT_ERR_INVALID;
+    if (ctx->batch.open) return set_err(ctx, LT_ERR_INVALID, "a batch is already open");
+    // the graph's edges are replay-time edges: start from a drained context
+    lt_status st = sync_all(ctx);
+    if (st) return st;
+    ctx->batch.open = true;
+    ctx->batch.capture = true;
+    return LT_OK;
+}
+
+lt_status lt_graph_end(lt_context *ctx, lt_graph **out) {
+    if (!ctx || !out) return LT_ERR_INVALID;
+    *out = nullptr;
+    lt_status st = graph_end(ctx, out);
+    if (st) {
+        ctx->batch = Batch();
+    }
+    return st;
+}
+
+lt_status lt_graph_launch(lt_context *ctx, lt_graph *g) {
+    if (!ctx || !g) return LT_ERR_INVALID;
+    if (ctx->batch.capture) return set_err(ctx, LT_ERR_INVALID, "cannot replay while recording a graph");
+    return graph_launch(ctx, g);
+}
+
+lt_status lt_graph_destroy(lt_context *ctx, lt_graph *g) {
+    if (!ctx || !g) return LT_ERR_INVALID;
+    return graph_destroy(ctx, g);
 }
 
 lt_status lt_sync(lt_context *ctx) {

@@ -610,7 +610,7 @@ static void *staging_get(Ctx *ctx, uint64_t bytes, lt_status *st) {
 
 lt_status batch_flush(Ctx *ctx) {
     Batch &B = ctx->batch;
-    if (B.q.empty()) return LT_OK;
+    if (B.q.empty() || B.capture) return LT_OK;
     lt_status st = flush_group(ctx);
     if (st) return st;
     const int ntasks = (int)B.q.size();
@@ -647,10 +647,15 @@ lt_status batch_flush(Ctx *ctx) {
         uint32_t zero = 0;
         r = launch_fill(h, base + qalloc, (calloc_ + B.part_bytes) / 4, 4, &zero);
         if (r != hipSuccess) return hip_fail(ctx, r, "batch clear");
+        hipEvent_t pa;
+        st = prof_begin(ctx, s, "drain", &pa);
+        if (st) return st;
         r = launch_drain(h, reinterpret_cast<const DTask *>(base), ntasks,
                          reinterpret_cast<int32_t *>(base + qalloc), ntasks + B.nsignals, B.tiles, nwg,
-                         (int64_t)1 << 24);
+                         (int64_t)1 << 26);
         if (r != hipSuccess) return hip_fail(ctx, r, "drain");
+        st = prof_end(ctx, s, "drain", pa);
+        if (st) return st;
         // error flag back to pinned host memory, checked at lt_sync
         if (ctx->status_next >= ctx->status_slots) {
             int ns = std::max(64, ctx->status_slots * 2);
@@ -689,6 +694,143 @@ lt_status batch_flush(Ctx *ctx) {
     B = Batch();
     B.open = open;
     return LT_OK;
+}
+
+// Builds a HIP graph from the captured batch: queue upload, counter clear,
+// drain and error-flag copy, recorded on compute stream 0.
+lt_status graph_end(Ctx *ctx, lt_graph **out) {
+    Batch &B = ctx->batch;
+    if (!B.capture) return set_err(ctx, LT_ERR_INVALID, "no graph is being recorded");
+    if (B.q.empty()) return set_err(ctx, LT_ERR_INVALID, "the graph has no tasks");
+    if (ctx->dry) return set_err(ctx, LT_ERR_UNSUPPORTED, "graphs need a device");
+    const int ntasks = (int)B.q.size();
+    const int nctr = ntasks + B.nsignals + 2;
+    const int64_t qbytes = (int64_t)ntasks * (int64_t)sizeof(DTask);
+    const int64_t qalloc = (qbytes + 255) / 256 * 256;
+    const int64_t calloc_ = ((int64_t)nctr * 4 + 255) / 256 * 256;
+    const int64_t total = qalloc + calloc_ + B.part_bytes;
+    auto g = std::make_unique<lt_graph>();
+    Fence mem;
+    lt_status st = alloc_range(ctx, total, 2, nullptr, &g->off, &mem);
+    if (st) return st;
+    char *base = ctx->arena_base + g->off;
+    int64_t part_base = (int64_t)(intptr_t)(base + qalloc + calloc_);
+    for (auto &pr : B.patch_y) B.q[pr.first].y += part_base;
+    for (auto &pr : B.patch_x) B.q[pr.first].x += part_base;
+    for (DTask &d : B.q) {
+        if (d.signal <= -2) d.signal = ntasks + (-2 - d.signal);
+        for (int i = 0; i < d.ndeps; ++i)
+            if (d.dep_ctr[i] <= -2) d.dep_ctr[i] = ntasks + (-2 - d.dep_ctr[i]);
+    }
+    hipError_t r = hipHostMalloc(&g->staging, (size_t)qbytes, hipHostMallocDefault);
+    if (r != hipSuccess) return hip_fail(ctx, r, "graph staging");
+    r = hipHostMalloc((void **)&g->status, 4, hipHostMallocDefault);
+    if (r != hipSuccess) return hip_fail(ctx, r, "graph status");
+    *g->status = 0;
+    memcpy(g->staging, B.q.data(), (size_t)qbytes);
+    const int s = 0;
+    g->stream = s;
+    st = stream_wait(ctx, s, mem);
+    if (st) return st;
+    hipStream_t h = ctx->streams[s].h;
+    int nwg = ctx->cfg.drain_workgroups > 0 ? ctx->cfg.drain_workgroups : 1024;
+    r = hipStreamBeginCapture(h, hipStreamCaptureModeThreadLocal);
+    if (r != hipSuccess) return hip_fail(ctx, r, "hipStreamBeginCapture");
+    hipError_t r1 = hipMemcpyAsync(base, g->staging, (size_t)qbytes, hipMemcpyHostToDevice, h);
+    uint32_t zero = 0;
+    hipError_t r2 = launch_fill(h, base + qalloc, (calloc_ + B.part_bytes) / 4, 4, &zero);
+    hipError_t r3 = launch_drain(h, reinterpret_cast<const DTask *>(base), ntasks,
+                                 reinterpret_cast<int32_t *>(base + qalloc), ntasks + B.nsignals, B.tiles, nwg,
+                                 (int64_t)1 << 26);
+    hipError_t r4 = hipMemcpyAsync(g->status, base + qalloc + (int64_t)(ntasks + B.nsignals + 1) * 4, 4,
+                                   hipMemcpyDeviceToHost, h);
+    r = hipStreamEndCapture(h, &g->graph);
+    if (r1 != hipSuccess || r2 != hipSuccess || r3 != hipSuccess || r4 != hipSuccess || r != hipSuccess)
+        return hip_fail(ctx, r != hipSuccess ? r : (r1 != hipSuccess ? r1 : (r2 != hipSuccess ? r2 : (r3 != hipSuccess ? r3 : r4))),
+                        "graph capture");
+    r = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
+    if (r != hipSuccess) return hip_fail(ctx, r, "hipGraphInstantiate");
+    // chunks the graph touches stay where they are while it lives; the
+    // capture recorded no work, so their histories go back to empty
+    for (const ChunkUse &u : B.uses) {
+        auto it = std::find(g->chunks.begin(), g->chunks.end(), u.c);
+        if (it == g->chunks.end()) {
+            g->chunks.push_back(u.c);
+            g->writes.push_back(u.write);
+            u.c->pin++;
+        } else if (u.write) {
+            g->writes[it - g->chunks.begin()] = 1;
+        }
+    }
+    for (Chunk *c : g->chunks) {
+        c->last_writer = 0;
+        c->readers.clear();
+        c->reducers.clear();
+        c->reduce_op = -1;
+    }
+    g->ntasks = ntasks;
+    ctx->graph_status.push_back(g->status);
+    B = Batch();
+    *out = g.release();
+    return LT_OK;
+}
+
+lt_status graph_launch(Ctx *ctx, lt_graph *g) {
+    lt_status st = flush_all(ctx);
+    if (st) return st;
+    TaskRec rec;
+    rec.id = ctx->next_task_id++;
+    rec.kind = LT_TASK_EXEC;
+    Fence wait;
+    for (size_t i = 0; i < g->chunks.size(); ++i) {
+        Chunk *c = g->chunks[i];
+        conflict_edges(c, g->writes[i] ? M_WRITE : M_READ, R_ADD, &rec.deps);
+        wait.merge(c->data_ready);
+        if (g->writes[i]) wait.merge(c->last_access);
+    }
+    wait.merge(task_fence(ctx, rec.deps));
+    st = stream_wait(ctx, g->stream, wait);
+    if (st) return st;
+    hipError_t r = hipGraphLaunch(g->exec, ctx->streams[g->stream].h);
+    if (r != hipSuccess) return hip_fail(ctx, r, "hipGraphLaunch");
+    ctx->stats.dispatches++;
+    uint64_t p = bump(ctx, g->stream);
+    g->last = p;
+    std::vector<ChunkUse> uses;
+    for (size_t i = 0; i < g->chunks.size(); ++i) {
+        record_access(g->chunks[i], g->writes[i] ? M_WRITE : M_READ, R_ADD, rec.id);
+        uses.push_back({g->chunks[i], g->writes[i] != 0});
+    }
+    apply_uses(ctx, uses, g->stream, p);
+    rec.stream = g->stream;
+    rec.seq = p;
+    ctx->tasks.at(rec.id) = std::move(rec);
+    return LT_OK;
+}
+
+lt_status graph_destroy(Ctx *ctx, lt_graph *g) {
+    lt_status st = flush_all(ctx);
+    if (st) return st;
+    if (!ctx->dry) {
+        hipError_t r = hipStreamSynchronize(ctx->streams[g->stream].h);
+        if (r != hipSuccess) st = hip_fail(ctx, r, "hipStreamSynchronize");
+        if (*g->status && ctx->sticky == LT_OK) {
+            ctx->sticky = LT_ERR_TIMEOUT;
+            ctx->sticky_msg = "a dependency wait inside a graph's drain exceeded its poll limit";
+        }
+        if (g->exec) (void)hipGraphExecDestroy(g->exec);
+        if (g->graph) (void)hipGraphDestroy(g->graph);
+        if (g->staging) (void)hipHostFree(g->staging);
+    }
+    for (Chunk *c : g->chunks) c->pin--;
+    Fence done;
+    done.add(g->stream, g->last);
+    ctx->arena.release(g->off, done);
+    auto it = std::find(ctx->graph_status.begin(), ctx->graph_status.end(), g->status);
+    if (it != ctx->graph_status.end()) ctx->graph_status.erase(it);
+    if (!ctx->dry && g->status) (void)hipHostFree(g->status);
+    delete g;
+    return st;
 }
 
 lt_status flush_all(Ctx *ctx) {
@@ -1290,6 +1432,11 @@ lt_status launch(Ctx *ctx, lt_kernel *k, int nd, const int64_t *grid,
     for (uint64_t id : lr.tasks) {
         TaskRec *r = ctx->tasks.get(id);
         if (r && r->seq) lr.done.add(r->stream, r->seq);
+    }
+    if (ctx->batch.open && !ctx->batch.capture && ctx->cfg.batch_flush_tasks > 0 &&
+        (int64_t)ctx->batch.q.size() >= ctx->cfg.batch_flush_tasks) {
+        st = batch_flush(ctx);
+        if (st) return st;
     }
     ctx->stats.plan_seconds += now_s() - t0;
     return LT_OK;

@@ -215,6 +215,19 @@ struct lt_array {
     bool dead = false;
 };
 
+struct lt_graph {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    int64_t off = -1;                  // arena range holding queue, counters, partials
+    void *staging = nullptr;           // pinned copy of the queue
+    int32_t *status = nullptr;         // pinned error flag
+    std::vector<lt::Chunk *> chunks;   // chunks it touches (pinned while it lives)
+    std::vector<char> writes;
+    int stream = 0;
+    uint64_t last = 0;                 // seq of its last replay on `stream`
+    int ntasks = 0;
+};
+
 namespace lt {
 
 // ------------------------------------------------------------------- tasks
@@ -310,6 +323,7 @@ struct ChunkUse {
 
 struct Batch {
     bool open = false;                 // between lt_batch_begin and lt_batch_end
+    bool capture = false;              // building a graph: never issued directly
     std::vector<DTask> q;
     std::vector<uint64_t> ids;         // task id of each queue entry
     uint64_t index_base = 0;           // queue index of task id: index[id - index_base]
@@ -384,6 +398,7 @@ struct lt_context {
     std::vector<void *> staging_free, staging_used;   // pinned upload buffers
     std::vector<uint64_t> staging_size_free, staging_size_used;
     int32_t *status_host = nullptr;    // drain error flags copied back
+    std::vector<int32_t *> graph_status;  // error flags of live graphs
     int status_slots = 0, status_next = 0;
 
     // profiling: (kernel name, start, end) awaiting resolution
@@ -424,6 +439,9 @@ lt_status launch(Ctx *ctx, lt_kernel *k, int nd, const int64_t *grid,
 lt_status sync_all(Ctx *ctx);
 lt_status flush_group(Ctx *ctx);
 lt_status batch_flush(Ctx *ctx);
+lt_status graph_end(Ctx *ctx, lt_graph **out);
+lt_status graph_launch(Ctx *ctx, lt_graph *g);
+lt_status graph_destroy(Ctx *ctx, lt_graph *g);
 lt_status flush_all(Ctx *ctx);
 lt_status prof_begin(Ctx *ctx, int s, const char *name, hipEvent_t *a);
 lt_status prof_end(Ctx *ctx, int s, const char *name, hipEvent_t a);

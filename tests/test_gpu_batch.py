@@ -131,3 +131,61 @@ def test_batch_after_unbatched_work_and_touch(L):
         ctx.sync()
         got = y.read()
     assert np.all(got == 10)
+
+
+def test_auto_flushed_batch_matches(L):
+    say("batch auto flush")
+    plan = synthetic.batch_plan(60, seed=5, hi_log2=17.0)
+    data = [synthetic.batch_data(k, n, i, seed=5) for i, (k, n) in enumerate(plan)]
+    with L.Context(device_budget_bytes=2 << 30, batch_flush_tasks=7) as ctx:
+        arrs = []
+        for (k, n), v in zip(plan, data):
+            x = ctx.array([n], np.float32 if k == 0 else np.int32, chunk=[4096])
+            y = ctx.array([n] if k == 0 else [256], np.float32 if k == 0 else np.int32, chunk=[4096] if k == 0 else None)
+            x.write(v)
+            arrs.append((y, x))
+        ctx.batch_begin()
+        for (k, n), (y, x) in zip(plan, arrs):
+            ctx.launch("stencil1d_f32" if k == 0 else "hist256_i32", [n], [1], [4096], args=[n, y, x])
+        ctx.batch_end()
+        ctx.sync()
+        assert ctx.stats()["dispatches"] > 4  # several drains
+        for (k, n), v, (y, x) in zip(plan, data, arrs):
+            ref = oracle.stencil1d(v) if k == 0 else oracle.hist256(v)
+            assert np.array_equal(y.read(), ref)
+
+
+def test_graph_replays_with_eager_work_between(L):
+    # a graph of two stencil launches (x -> y -> x) and one histogram; every
+    # replay is checked against the eager result, with eager launches and
+    # synchronizations between the replays
+    n = 200_003
+    say("graph replay")
+    x0 = synthetic.stencil1d_input(n, 9)
+    v = synthetic.zipf_values(150_000, np.random.default_rng(9))
+    with L.Context(device_budget_bytes=1 << 30) as ctx:
+        x = ctx.array([n], chunk=[30000])
+        y = ctx.array([n], chunk=[30000])
+        hv = ctx.array([v.size], np.int32, chunk=[40000])
+        h = ctx.array([256], np.int32)
+        z = ctx.array([1000], np.int32)
+        x.write(x0)
+        hv.write(v)
+        z.fill(0)
+        ctx.graph_begin()
+        ctx.launch("stencil1d_f32", [n], [1], [30000], args=[n, y, x])
+        ctx.launch("stencil1d_f32", [n], [1], [30000], args=[n, x, y])
+        ctx.launch("hist256_i32", [v.size], [1], [40000], args=[v.size, h, hv])
+        g = ctx.graph_end()
+        cur = x0
+        for rep in range(4):
+            h.fill(77)
+            ctx.graph_launch(g)
+            ctx.launch("touch_i32", [1000], [1], [100], args=[1000, z])  # eager work
+            ctx.sync()
+            cur = oracle.stencil1d_iter(cur, 2)
+            assert np.array_equal(x.read(), cur), rep
+            assert np.array_equal(h.read(), oracle.hist256(v)), rep
+        assert np.all(z.read() == 4)
+        ctx.graph_destroy(g)
+        ctx.sync()
