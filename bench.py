@@ -451,6 +451,8 @@ def main():
     ap.add_argument("--workload", choices=["jacobi", "stencil1d", "gemm_ooc", "batch", "serve"], default="jacobi")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--rows", type=int, default=8, help="rows per Jacobi tile (8, 16, 32)")
+    ap.add_argument("--serve-full", action="store_true",
+                    help="serving trace at the full size ranges (GEMM to 65536, k-means to 1e9 points)")
     args = ap.parse_args()
     args.steps_given = args.steps is not None
     args.warmup_given = args.warmup is not None

@@ -318,6 +318,74 @@ lt_status lt_graph_end(lt_context *ctx, lt_graph **out);
 lt_status lt_graph_launch(lt_context *ctx, lt_graph *g);
 lt_status lt_graph_destroy(lt_context *ctx, lt_graph *g);
 
+/* ------------------------------------------------------------------ serving
+ * A request loop with continuous batching on one context.  Requests are
+ * queued by lt_server_submit and admitted in arrival order as soon as an
+ * active slot is free and their device footprint fits next to the admitted
+ * ones (a request larger than the budget is admitted alone and runs out of
+ * core through the memory manager).  An admitted request's launches are
+ * issued at once, so the work of all admitted requests overlaps on the
+ * device.  Inputs are host-backed arrays over the caller's buffers, cached
+ * per (kind, dataset, size): a later request on the same dataset finds its
+ * chunks still in HBM unless they were spilled for other work.  Results are
+ * written to the caller's output buffer; a request completes when they are
+ * there.  lt_server_poll advances admission and reports completions without
+ * blocking; lt_server_drain blocks until every submitted request is done.
+ *
+ * Request kinds (host buffers are row-major; pinned memory is faster):
+ *   LT_REQ_JACOBI  n x n float32 field in0, `sweeps` Jacobi sweeps, out = the
+ *                  final field (n x n float32)
+ *   LT_REQ_KMEANS  N x d float32 points in0, K x d float32 centres in1,
+ *                  out = N int32 labels (d <= 32, K <= 256)
+ *   LT_REQ_GEMM    n x n float32 A in0 and B in1, out = C = A B (n x n)
+ * Input buffers of a cached dataset must stay valid and unchanged while the
+ * server lives. */
+#define LT_REQ_JACOBI 0
+#define LT_REQ_KMEANS 1
+#define LT_REQ_GEMM 2
+
+typedef struct lt_server lt_server;
+
+typedef struct lt_server_config {
+    int32_t max_active;        /* admitted requests at once (>= 1)            */
+    int32_t keep_resident;     /* 1: cache dataset arrays across requests     */
+    uint64_t admit_bytes;      /* cap on the summed footprint of admitted
+                                  requests; 0 = the device budget            */
+    int64_t chunk_rows;        /* row chunk / superblock for Jacobi and
+                                  k-means (0 = 512 rows / 2^20 points)        */
+    int64_t gemm_tile;         /* GEMM superblock edge (0 = 4096)            */
+    int32_t reserved[4];
+} lt_server_config;
+
+typedef struct lt_request {
+    int32_t kind;              /* LT_REQ_*                                   */
+    int32_t dataset;           /* cache key with kind and size               */
+    int64_t size;              /* n (Jacobi, GEMM) or N points (k-means)     */
+    int64_t d, K;              /* k-means                                    */
+    int32_t sweeps;            /* Jacobi                                     */
+    int32_t pad;
+    const void *in0, *in1;
+    void *out;
+} lt_request;
+
+typedef struct lt_completion {
+    uint64_t id;
+    int32_t status;            /* LT_OK or the request's error               */
+    int32_t kind;
+    double t_submit, t_admit, t_done;   /* seconds, steady clock             */
+    uint64_t footprint;
+    int32_t cache_hit;         /* inputs were already cached                 */
+    int32_t pad;
+} lt_completion;
+
+lt_status lt_server_create(lt_context *ctx, const lt_server_config *cfg, lt_server **out);
+lt_status lt_server_submit(lt_server *srv, const lt_request *req, uint64_t *id);
+lt_status lt_server_poll(lt_server *srv, lt_completion *out, int32_t cap, int32_t *n);
+lt_status lt_server_drain(lt_server *srv, lt_completion *out, int32_t cap, int32_t *n);
+lt_status lt_server_destroy(lt_server *srv);
+/* Seconds on the clock that lt_completion times use. */
+double lt_now(void);
+
 /* ----------------------------------------------------------- introspection
  * Planner output of a launch, for tests and tools.  Task records are kept
  * until the next lt_sync. */

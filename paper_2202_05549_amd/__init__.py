@@ -92,6 +92,25 @@ class lt_kernel_prof(C.Structure):
                 ("max_ms", C.c_double)]
 
 
+class lt_server_config(C.Structure):
+    _fields_ = [("max_active", C.c_int32), ("keep_resident", C.c_int32), ("admit_bytes", C.c_uint64),
+                ("chunk_rows", C.c_int64), ("gemm_tile", C.c_int64), ("reserved", C.c_int32 * 4)]
+
+
+class lt_request(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("dataset", C.c_int32), ("size", C.c_int64), ("d", C.c_int64),
+                ("K", C.c_int64), ("sweeps", C.c_int32), ("pad", C.c_int32), ("in0", C.c_void_p),
+                ("in1", C.c_void_p), ("out", C.c_void_p)]
+
+
+class lt_completion(C.Structure):
+    _fields_ = [("id", C.c_uint64), ("status", C.c_int32), ("kind", C.c_int32), ("t_submit", C.c_double),
+                ("t_admit", C.c_double), ("t_done", C.c_double), ("footprint", C.c_uint64),
+                ("cache_hit", C.c_int32), ("pad", C.c_int32)]
+
+
+LT_REQ_JACOBI, LT_REQ_KMEANS, LT_REQ_GEMM = 0, 1, 2
+
 # numpy mirror of lt_arg, for building argument tables without Python loops
 ARG_DTYPE = np.dtype([("name", np.uint64), ("kind", np.int32), ("pad", np.int32), ("array", np.uint64),
                       ("i", np.int64), ("f", np.float64)])
@@ -154,6 +173,12 @@ _SIGS = [
     ("lt_stats_reset", C.c_int32, [_P]),
     ("lt_trace_get", C.c_int32, [_P, C.POINTER(lt_trace_rec), C.c_uint64, C.POINTER(C.c_uint64)]),
     ("lt_trace_clear", C.c_int32, [_P]),
+    ("lt_server_create", C.c_int32, [_P, C.POINTER(lt_server_config), C.POINTER(_P)]),
+    ("lt_server_submit", C.c_int32, [_P, C.POINTER(lt_request), C.POINTER(C.c_uint64)]),
+    ("lt_server_poll", C.c_int32, [_P, C.POINTER(lt_completion), C.c_int32, C.POINTER(C.c_int32)]),
+    ("lt_server_drain", C.c_int32, [_P, C.POINTER(lt_completion), C.c_int32, C.POINTER(C.c_int32)]),
+    ("lt_server_destroy", C.c_int32, [_P]),
+    ("lt_now", C.c_double, []),
     ("lt_profile_enable", C.c_int32, [_P, C.c_int32]),
     ("lt_profile_get", C.c_int32, [_P, C.POINTER(lt_kernel_prof), C.c_int32, C.POINTER(C.c_int32)]),
     ("lt_profile_reset", C.c_int32, [_P]),

@@ -159,6 +159,35 @@ lt_status sync_all(Ctx *ctx) {
     return LT_OK;
 }
 
+// Issues the write-back of a host-backed array's dirty chunks to its home
+// buffer without waiting; *out = the point after which the home buffer holds
+// the array's contents.
+lt_status array_flush_async(Ctx *ctx, Array *arr, Fence *out) {
+    lt_status st = flush_all(ctx);
+    if (st) return st;
+    *out = Fence();
+    if (!arr->host_backed) return set_err(ctx, LT_ERR_INVALID, "array is not host-backed");
+    for (Chunk *c : arr->chunks) {
+        if (c->dev_off >= 0 && c->dev_valid && !c->host_valid && c->defined) {
+            st = stream_wait(ctx, ctx->d2h, c->data_ready);
+            if (st) return st;
+            int64_t ext[MAXD];
+            for (int a = 0; a < MAXD; ++a) ext[a] = c->box.hi[a] - c->box.lo[a];
+            st = copy_box(ctx, ctx->d2h, c->host_ptr, c->host_stride, dev_ptr(ctx, c), c->dev_stride, ext,
+                          arr->ndim, arr->esz, hipMemcpyDeviceToHost);
+            if (st) return st;
+            uint64_t p = bump(ctx, ctx->d2h);
+            c->host_valid = true;
+            c->host_ready = Fence();
+            c->host_ready.add(ctx->d2h, p);
+            c->last_access.add(ctx->d2h, p);
+            trace_op(ctx, 2, ctx->d2h, ~0ull, c->id, c->bytes, c->dev_off);
+        }
+        out->merge(c->host_ready);
+    }
+    return LT_OK;
+}
+
 void ctx_release_all(Ctx *ctx) {
     for (Array *arr : ctx->arrays) arr->dead = true;
     (void)sync_all(ctx);

@@ -16,15 +16,36 @@ constexpr int THREADS = 256;
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
+// Views arrive as integer addresses.  Turning them into pointers in the
+// global address space (not generic ones) makes the compiler emit global
+// loads and stores: generic (flat) accesses also count against the LDS
+// counter, so every lane shuffle or LDS read would wait for all global loads
+// still in flight and defeat any prefetching.
+#if defined(__HIP_DEVICE_COMPILE__)
+#define LT_GLOBAL __attribute__((address_space(1)))
+#else
+#define LT_GLOBAL
+#endif
+
 template <class T>
-__device__ __forceinline__ T *at(int64_t base, int64_t idx) {
-    return reinterpret_cast<T *>(base) + idx;
+__device__ __forceinline__ LT_GLOBAL T *gp(int64_t base) {
+    return (LT_GLOBAL T *)base;
+}
+
+template <class T>
+__device__ __forceinline__ LT_GLOBAL T *at(int64_t base, int64_t idx) {
+    return gp<T>(base) + idx;
+}
+
+template <class T>
+__device__ __forceinline__ T ld4(const LT_GLOBAL void *p) {
+    return *(const LT_GLOBAL T *)p;
 }
 
 // 16-byte store without cache retention (streaming output)
-__device__ __forceinline__ void nt_store4(float *p, float4 v) {
+__device__ __forceinline__ void nt_store4(LT_GLOBAL float *p, float4 v) {
     f32x4 w = {v.x, v.y, v.z, v.w};
-    __builtin_nontemporal_store(w, reinterpret_cast<f32x4 *>(p));
+    __builtin_nontemporal_store(w, (LT_GLOBAL f32x4 *)p);
 }
 
 // Physical workgroups are dealt round-robin to the 8 XCDs.  Remap so each
@@ -60,12 +81,12 @@ __device__ __forceinline__ void stencil_span(int64_t xb, int64_t yb, int64_t n, 
     const int64_t end = hi < n ? hi : n;               // outputs [lo, end)
     const int64_t rend = end + 1 < n ? end + 1 : n;    // inputs read: [lo-1, rend)
     const int64_t i0 = span0 + threadIdx.x * 4;
-    const float *X = reinterpret_cast<const float *>(xb);
-    float *Y = reinterpret_cast<float *>(yb);
+    const LT_GLOBAL float *X = gp<const float>(xb);
+    LT_GLOBAL float *Y = gp<float>(yb);
     const bool aligned = ((xb + lo * 4) & 15) == 0 && ((yb + lo * 4) & 15) == 0 && ((span0 - lo) & 3) == 0;
     float v[4];
     if (aligned && i0 + 3 < end) {
-        float4 q = *reinterpret_cast<const float4 *>(X + i0);
+        float4 q = ld4<float4>(X + i0);
         v[0] = q.x;
         v[1] = q.y;
         v[2] = q.z;
@@ -85,11 +106,82 @@ __device__ __forceinline__ void stencil_span(int64_t xb, int64_t yb, int64_t n, 
     o[2] = st_point(v[1], v[2], v[3]);
     o[3] = st_point(v[2], v[3], right);
     if (aligned && i0 + 3 < end) {
-        *reinterpret_cast<float4 *>(Y + i0) = make_float4(o[0], o[1], o[2], o[3]);
+        *(LT_GLOBAL float4 *)(Y + i0) = make_float4(o[0], o[1], o[2], o[3]);
     } else {
         for (int j = 0; j < 4; ++j)
             if (i0 + j < end) Y[i0 + j] = o[j];
     }
+}
+
+// Streaming form for long ranges: outputs [s0, s1) of the task [lo, hi) in
+// groups of G spans of 1024.  A group's loads (the lane's G float4 plus the
+// two wave-edge neighbours) are issued before the previous group is computed
+// and stored, so 2G independent 16-byte loads per lane stay in flight.  The
+// input and output arrays must not overlap (they never do for a stencil:
+// the annotation reads x and writes y).  Ragged ends use stencil_span.
+template <int G>
+struct StGroup {
+    float4 v[G];
+    float l[G], r[G];
+};
+
+template <int G>
+__device__ __forceinline__ void st_load(const LT_GLOBAL float *__restrict__ X, int64_t n, int64_t g0, int lane,
+                                        StGroup<G> &q) {
+#pragma unroll
+    for (int u = 0; u < G; ++u) {
+        const int64_t i0 = g0 + u * 1024 + threadIdx.x * 4;
+        q.v[u] = ld4<float4>(X + i0);
+        q.l[u] = (lane == 0 && i0 - 1 >= 0) ? X[i0 - 1] : 0.f;
+        q.r[u] = (lane == WAVE - 1 && i0 + 4 < n) ? X[i0 + 4] : 0.f;
+    }
+}
+
+template <int G>
+__device__ __forceinline__ void st_store(LT_GLOBAL float *__restrict__ Y, int64_t g0, int lane,
+                                         const StGroup<G> &q) {
+#pragma unroll
+    for (int u = 0; u < G; ++u) {
+        const int64_t i0 = g0 + u * 1024 + threadIdx.x * 4;
+        float left = __shfl_up(q.v[u].w, 1);
+        float right = __shfl_down(q.v[u].x, 1);
+        if (lane == 0) left = q.l[u];
+        if (lane == WAVE - 1) right = q.r[u];
+        float4 o;
+        o.x = st_point(left, q.v[u].x, q.v[u].y);
+        o.y = st_point(q.v[u].x, q.v[u].y, q.v[u].z);
+        o.z = st_point(q.v[u].y, q.v[u].z, q.v[u].w);
+        o.w = st_point(q.v[u].z, q.v[u].w, right);
+        nt_store4(Y + i0, o);
+    }
+}
+
+template <int G>
+__device__ __forceinline__ void stencil_stream(int64_t xb, int64_t yb, int64_t n, int64_t lo, int64_t hi,
+                                               int64_t s0, int64_t s1) {
+    const int64_t end = hi < n ? hi : n;
+    if (s1 > end) s1 = end;
+    const bool aligned = ((xb + lo * 4) & 15) == 0 && ((yb + lo * 4) & 15) == 0 && ((s0 - lo) & 3) == 0;
+    int64_t g = s0;
+    if (aligned) {
+        const int64_t step = (int64_t)G * 1024;
+        const int64_t full = s0 + (s1 - s0) / step * step;
+        const LT_GLOBAL float *X = gp<const float>(xb);
+        LT_GLOBAL float *Y = gp<float>(yb);
+        const int lane = threadIdx.x & (WAVE - 1);
+        if (full > s0) {
+            StGroup<G> cur;
+            st_load<G>(X, n, g, lane, cur);
+            for (; g < full; g += step) {
+                StGroup<G> nxt;
+                const bool more = g + step < full;
+                if (more) st_load<G>(X, n, g + step, lane, nxt);
+                st_store<G>(Y, g, lane, cur);
+                if (more) cur = nxt;
+            }
+        }
+    }
+    for (; g < s1; g += 1024) stencil_span(xb, yb, n, lo, hi, g);
 }
 
 // ---------------------------------------------------------------- jacobi2d
@@ -122,8 +214,8 @@ __device__ __forceinline__ void jacobi_tile(const JView &t, int64_t n, int64_t m
     const int64_t rcend = cend + 1 < m ? cend + 1 : m;     // inputs read up to rcend
     const int64_t col = t.c0 + ((int64_t)txi * THREADS + threadIdx.x) * 4;
     const bool active = col < cend;
-    const float *X = reinterpret_cast<const float *>(t.x);
-    float *Y = reinterpret_cast<float *>(t.y);
+    const LT_GLOBAL float *X = gp<const float>(t.x);
+    LT_GLOBAL float *Y = gp<float>(t.y);
     const int lane = threadIdx.x & (WAVE - 1);
 
     if (t.vec && r1 - r0 == RB) {
@@ -132,7 +224,7 @@ __device__ __forceinline__ void jacobi_tile(const JView &t, int64_t n, int64_t m
         for (int i = 0; i < RB + 2; ++i) {
             const int64_t r = r0 - 1 + i;
             if (active && r >= 0 && r < n)
-                v[i] = *reinterpret_cast<const float4 *>(X + r * t.xs + col);
+                v[i] = ld4<float4>(X + r * t.xs + col);
             else
                 v[i] = make_float4(0.f, 0.f, 0.f, 0.f);
         }
@@ -142,7 +234,7 @@ __device__ __forceinline__ void jacobi_tile(const JView &t, int64_t n, int64_t m
             const float4 up = v[i - 1], mid = v[i], dn = v[i + 1];
             float left = __shfl_up(mid.w, 1);
             float right = __shfl_down(mid.x, 1);
-            const float *row = X + r * t.xs;
+            const LT_GLOBAL float *row = X + r * t.xs;
             if (active && lane == 0) left = (col - 1 >= 0) ? row[col - 1] : 0.f;
             if (active && (lane == WAVE - 1 || col + 4 >= cend)) right = (col + 4 < m) ? row[col + 4] : 0.f;
             if (active) {
@@ -164,9 +256,9 @@ __device__ __forceinline__ void jacobi_tile(const JView &t, int64_t n, int64_t m
             v[0] = v[1] = v[2] = v[3] = 0.f;
             return;
         }
-        const float *p = X + r * t.xs + col;
+        const LT_GLOBAL float *p = X + r * t.xs + col;
         if (t.vec && active) {
-            float4 q = *reinterpret_cast<const float4 *>(p);
+            float4 q = ld4<float4>(p);
             v[0] = q.x;
             v[1] = q.y;
             v[2] = q.z;
@@ -182,7 +274,7 @@ __device__ __forceinline__ void jacobi_tile(const JView &t, int64_t n, int64_t m
         load4(r + 1, dn);
         float left = __shfl_up(mid[3], 1);
         float right = __shfl_down(mid[0], 1);
-        const float *row = X + r * t.xs;
+        const LT_GLOBAL float *row = X + r * t.xs;
         if (active && lane == 0) left = (col - 1 >= 0) ? row[col - 1] : 0.f;
         if (active && lane == WAVE - 1 && col + 3 < cend) right = (col + 4 < m) ? row[col + 4] : 0.f;
         if (active) {
@@ -191,9 +283,9 @@ __device__ __forceinline__ void jacobi_tile(const JView &t, int64_t n, int64_t m
             float o1 = jpoint(up[1], dn[1], mid[0], mid[2]);
             float o2 = jpoint(up[2], dn[2], mid[1], mid[3]);
             float o3 = jpoint(up[3], dn[3], mid[2], right);
-            float *q = Y + r * t.ys + col;
+            LT_GLOBAL float *q = Y + r * t.ys + col;
             if (t.vec) {
-                *reinterpret_cast<float4 *>(q) = make_float4(o0, o1, o2, o3);
+                *(LT_GLOBAL float4 *)q = make_float4(o0, o1, o2, o3);
             } else {
                 float o[4] = {o0, o1, o2, o3};
                 for (int j = 0; j < 4; ++j)
@@ -208,14 +300,52 @@ __device__ __forceinline__ void jacobi_tile(const JView &t, int64_t n, int64_t m
 }
 
 // ---------------------------------------------------------------- hist256
-// Counts v[i] for i in [s0, s1) into the wave's LDS sub-histogram sh[wave];
-// values outside [0, 256) are ignored.  Grid-stride over `stride` elements.
+// Counts v[i] into the wave's LDS sub-histogram sh[wave] for the 4096-element
+// chunks of [s0, s1) that start at s0, s0 + stride, s0 + 2*stride, ...;
+// values outside [0, 256) are ignored.  Full aligned chunks load four
+// 16-byte groups per lane before counting; ragged chunks go one by one.
+__device__ __forceinline__ void hist_count(int *mine, int32_t b) {
+    if ((uint32_t)b < 256u) atomicAdd(&mine[b], 1);
+}
+
 __device__ __forceinline__ void hist_span(int64_t vb, int64_t s0, int64_t s1, int64_t stride, int *sh) {
-    const int32_t *V = reinterpret_cast<const int32_t *>(vb);
+    const LT_GLOBAL int32_t *V = gp<const int32_t>(vb);
     int *mine = sh + (threadIdx.x >> 6) * 256;
-    for (int64_t i = s0 + threadIdx.x; i < s1; i += stride) {
-        int32_t b = V[i];
-        if ((uint32_t)b < 256u) atomicAdd(&mine[b], 1);
+    // the workgroup owns the 4096-element chunks starting at s0, s0 + stride,
+    // ...; full aligned chunks are pipelined: the next chunk's four 16-byte
+    // loads per lane are issued before the current chunk is counted
+    const bool vec = ((vb + s0 * 4) & 15) == 0 && (stride % 4096) == 0;
+    int64_t c = s0;
+    if (vec && c + 4096 <= s1) {
+        int4 cur[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) cur[u] = ld4<int4>(V + c + u * 1024 + threadIdx.x * 4);
+        for (;;) {
+            const int64_t cn = c + stride;
+            const bool more = cn + 4096 <= s1;
+            int4 nxt[4];
+            if (more) {
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+                    nxt[u] = ld4<int4>(V + cn + u * 1024 + threadIdx.x * 4);
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                hist_count(mine, cur[u].x);
+                hist_count(mine, cur[u].y);
+                hist_count(mine, cur[u].z);
+                hist_count(mine, cur[u].w);
+            }
+            c = cn;
+            if (!more) break;
+#pragma unroll
+            for (int u = 0; u < 4; ++u) cur[u] = nxt[u];
+        }
+    }
+    // ragged or unaligned chunks, one element per lane at a time
+    for (; c < s1; c += stride) {
+        const int64_t ce = c + 4096 < s1 ? c + 4096 : s1;
+        for (int64_t j = c + threadIdx.x; j < ce; j += THREADS) hist_count(mine, V[j]);
     }
 }
 
@@ -223,10 +353,10 @@ __device__ __forceinline__ void hist_span(int64_t vb, int64_t s0, int64_t s1, in
 // and order-free) and clears them.
 __device__ __forceinline__ void hist_flush(int64_t hb, int *sh) {
     __syncthreads();
-    int32_t *H = reinterpret_cast<int32_t *>(hb);
+    LT_GLOBAL int32_t *H = gp<int32_t>(hb);
     const int b = threadIdx.x;
     int s = sh[b] + sh[256 + b] + sh[512 + b] + sh[768 + b];
-    if (s) atomicAdd(H + b, s);
+    if (s) __hip_atomic_fetch_add(H + b, s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     sh[b] = sh[256 + b] = sh[512 + b] = sh[768 + b] = 0;
     __syncthreads();
 }

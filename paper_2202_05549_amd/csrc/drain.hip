@@ -28,10 +28,8 @@ __device__ __forceinline__ void run_tile(const DTask &t, int64_t local, int *sh)
         case DK_STENCIL1D: {
             const int64_t end = t.hi0 < t.n ? t.hi0 : t.n;
             const int64_t s0 = t.lo0 + local * DSPAN;
-            for (int64_t sp = 0; sp < DSPAN; sp += 1024) {
-                if (s0 + sp >= end) break;
-                stencil_span(t.x, t.y, t.n, t.lo0, t.hi0, s0 + sp);
-            }
+            if (s0 >= end) break;
+            stencil_stream<4>(t.x, t.y, t.n, t.lo0, t.hi0, s0, s0 + DSPAN < end ? s0 + DSPAN : end);
             break;
         }
         case DK_JACOBI2D: {
@@ -58,14 +56,14 @@ __device__ __forceinline__ void run_tile(const DTask &t, int64_t local, int *sh)
             const int64_t end = t.hi0 < t.n ? t.hi0 : t.n;
             const int64_t s0 = t.lo0 + local * DSPAN;
             const int64_t s1 = s0 + DSPAN < end ? s0 + DSPAN : end;
-            hist_span(t.x, s0, s1, THREADS, sh);
+            hist_span(t.x, s0, s1, 4096, sh);
             hist_flush(t.y, sh);
             break;
         }
         case DK_SUM_PARTIALS: {
             // y[e] = sum over p of partial p at element e, e in [lo0, hi0);
             // partials are dense blocks of m elements starting at x
-            const int32_t *P = reinterpret_cast<const int32_t *>(t.x);
+            const LT_GLOBAL int32_t *P = gp<const int32_t>(t.x);
             for (int64_t e = t.lo0 + threadIdx.x; e < t.hi0; e += THREADS) {
                 int32_t acc = 0;
                 for (int64_t p = 0; p < t.aux; ++p) acc += P[p * t.m + (e - t.lo0)];
@@ -84,8 +82,15 @@ __global__ __launch_bounds__(256) void k_drain(const DTask *q, int ntasks, int32
     __shared__ int s_tile, s_task, s_ok;
     for (int i = threadIdx.x; i < 4 * 256; i += THREADS) sh[i] = 0;
     int cur = 0;
+    int next = 0;
+    if (threadIdx.x == 0) next = atomicAdd(&ctr[ticket_idx], 1);
     for (;;) {
-        if (threadIdx.x == 0) s_tile = atomicAdd(&ctr[ticket_idx], 1);
+        if (threadIdx.x == 0) {
+            const int tile = next;
+            // claim the following ticket now; its latency overlaps this tile
+            if (tile < total) next = atomicAdd(&ctr[ticket_idx], 1);
+            s_tile = tile;
+        }
         __syncthreads();
         const int64_t tile = s_tile;
         if (tile >= total) break;
@@ -105,7 +110,7 @@ __global__ __launch_bounds__(256) void k_drain(const DTask *q, int ntasks, int32
                     }
                 }
             }
-            __threadfence();  // acquire: see the predecessors' writes
+            if (t.ndeps) __threadfence();  // acquire: see the predecessors' writes
             s_task = cur;
             s_ok = ok;
         }
@@ -114,7 +119,9 @@ __global__ __launch_bounds__(256) void k_drain(const DTask *q, int ntasks, int32
         if (s_ok) run_tile(t, tile - t.tile_begin, sh);
         __syncthreads();
         if (threadIdx.x == 0) {
-            __threadfence();  // release: this tile's writes before the count
+            const int32_t fl = t.flags;
+            if (fl & DF_RELEASE) __threadfence();           // plain stores become visible
+            else if (fl & DF_ATOMIC) __builtin_amdgcn_s_waitcnt(0);  // atomics performed
             int prev = atomicAdd(&ctr[s_task], 1);
             if (prev == t.ntiles - 1 && t.signal >= 0) atomicAdd(&ctr[t.signal], 1);
         }

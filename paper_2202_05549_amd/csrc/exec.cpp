@@ -399,6 +399,7 @@ static lt_status batch_dep(Ctx *ctx, DTask &d, uint64_t dep) {
     d.dep_ctr[d.ndeps] = qi;
     d.dep_val[d.ndeps] = B.q[qi].ntiles;
     d.ndeps++;
+    B.q[qi].flags |= DF_RELEASE;  // its stores are read by a later task of the batch
     return LT_OK;
 }
 
@@ -518,7 +519,10 @@ static lt_status batch_add_exec(Ctx *ctx, const KernelDef *def, TaskPlan &tp, Ta
         if (!a.used || a.mode == M_REDUCE) continue;
         for (Chunk *c : a.chunks) record_access(c, a.mode, a.op, tp.id);
     }
-    if (partial_y) B.patch_y.push_back({(int)B.q.size(), 0});
+    if (partial_y) {
+        B.patch_y.push_back({(int)B.q.size(), 0});
+        d.flags |= DF_ATOMIC;  // its partial is built with device-scope atomics
+    }
     batch_push(ctx, d, tp.id);
     B.uses.insert(B.uses.end(), uses.begin(), uses.end());
     if (B.launches.empty() || B.launches.back() != rec.launch) B.launches.push_back(rec.launch);

@@ -13,6 +13,7 @@
 
 #include <cstdint>
 
+#include "bodies.h"
 #include "kernels.h"
 
 namespace lt {
@@ -71,9 +72,11 @@ __global__ __launch_bounds__(256, 1) void k_gemm(GArgs g) {
     const int64_t m0 = t.i0 + (int64_t)tmi * BM;
     const int64_t n0 = t.j0 + (int64_t)tni * BN;
     const int64_t K = g.K;
-    const float *A = reinterpret_cast<const float *>(t.a);
-    const float *B = reinterpret_cast<const float *>(t.b);
-    float *C = reinterpret_cast<float *>(t.c);
+    // global-address-space pointers: global (not flat) loads do not hold up
+    // the LDS reads that feed the matrix cores
+    const LT_GLOBAL float *A = body::gp<const float>(t.a);
+    const LT_GLOBAL float *B = body::gp<const float>(t.b);
+    LT_GLOBAL float *C = body::gp<float>(t.c);
 
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
@@ -92,7 +95,7 @@ __global__ __launch_bounds__(256, 1) void k_gemm(GArgs g) {
             const int64_t r = m0 + a_row + 32 * j;
             const int64_t k = k0 + a_k4 * 4;
             if (t.vec && r < t.i1 && k + 3 < K) {
-                ra[j] = *reinterpret_cast<const float4 *>(A + r * t.as + k);
+                ra[j] = body::ld4<float4>(A + r * t.as + k);
             } else {
                 float v[4];
                 for (int q = 0; q < 4; ++q) v[q] = (r < t.i1 && k + q < K) ? A[r * t.as + k + q] : 0.f;
@@ -104,7 +107,7 @@ __global__ __launch_bounds__(256, 1) void k_gemm(GArgs g) {
             const int64_t k = k0 + b_k + 4 * j;
             const int64_t c = n0 + b_n4 * 4;
             if (t.vec && k < K && c + 3 < t.j1) {
-                rb[j] = *reinterpret_cast<const float4 *>(B + k * t.bs + c);
+                rb[j] = body::ld4<float4>(B + k * t.bs + c);
             } else {
                 float v[4];
                 for (int q = 0; q < 4; ++q) v[q] = (k < K && c + q < t.j1) ? B[k * t.bs + c + q] : 0.f;

@@ -91,7 +91,7 @@ namespace lt {
 // tile finishes also bumps counters[signal] once.
 enum DKind { DK_TOUCH = 0, DK_STENCIL1D = 1, DK_JACOBI2D = 2, DK_HIST256 = 3, DK_SUM_PARTIALS = 4 };
 constexpr int DMAXDEP = 8;
-constexpr int64_t DSPAN = 16384;  // elements per tile of the 1-D bodies
+constexpr int64_t DSPAN = 65536;  // elements per tile of the 1-D bodies
 constexpr int DJROWS = 32;        // rows per Jacobi tile (four 8-row passes)
 
 struct DTask {
@@ -109,7 +109,18 @@ struct DTask {
     int32_t tx;                    // Jacobi column tiles
     int32_t vec;                   // Jacobi float4 layout
     int64_t aux;                   // DK_SUM_PARTIALS: number of partials
+    int32_t flags;                 // DF_* below
+    int32_t pad;
 };
+
+// DTask.flags: what a finished tile must do before counting itself done.
+// DF_RELEASE: a later task of the batch reads this task's plain stores:
+//   agent-scope release (write back this XCD's L2) before the count.
+// DF_ATOMIC: every global write of the body is a device-scope atomic
+//   (coherent across XCDs): waiting for their completion is enough.
+// Tasks without consumers skip both.
+constexpr int32_t DF_RELEASE = 1;
+constexpr int32_t DF_ATOMIC = 2;
 
 // counters: ntasks + nsignals task/signal counters, then the ticket, then an
 // error flag (bit 0: a dependency wait gave up after spin_limit polls).

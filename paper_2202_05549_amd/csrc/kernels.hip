@@ -91,7 +91,8 @@ struct StArgs {
 __global__ __launch_bounds__(256) void k_stencil1d(StArgs a) {
     int ti = find_task(a.begin, a.ntask, blockIdx.x);
     const StTask &t = a.t[ti];
-    stencil_span(t.x, t.y, a.n, t.lo, t.hi, t.lo + (int64_t)(blockIdx.x - a.begin[ti]) * 1024);
+    const int64_t s0 = t.lo + (int64_t)(blockIdx.x - a.begin[ti]) * 8192;
+    stencil_stream<4>(t.x, t.y, a.n, t.lo, t.hi, s0, s0 + 8192);
 }
 
 hipError_t launch_stencil1d_f32(const KLaunch &L) {
@@ -106,7 +107,7 @@ hipError_t launch_stencil1d_f32(const KLaunch &L) {
         a.t[i].y = L.tasks[i].v[1].base;
         a.t[i].x = L.tasks[i].v[2].base;
         int64_t e = std::min(a.t[i].hi, a.n) - a.t[i].lo;
-        nb += e > 0 ? (e + 1023) / 1024 : 0;
+        nb += e > 0 ? (e + 8191) / 8192 : 0;
     }
     a.begin[L.ntask] = (int)nb;
     if (nb == 0) return hipSuccess;
@@ -206,7 +207,7 @@ __global__ __launch_bounds__(256) void k_hist256(HArgs a) {
     __syncthreads();
     const int64_t end = t.hi < a.n ? t.hi : a.n;
     const int nblk = a.begin[ti + 1] - a.begin[ti];
-    hist_span(t.v, t.lo + (int64_t)(blockIdx.x - a.begin[ti]) * 256, end, (int64_t)nblk * 256, sh);
+    hist_span(t.v, t.lo + (int64_t)(blockIdx.x - a.begin[ti]) * 4096, end, (int64_t)nblk * 4096, sh);
     hist_flush(t.h, sh);
 }
 
@@ -221,7 +222,7 @@ hipError_t launch_hist256_i32(const KLaunch &L) {
         a.t[i].h = L.tasks[i].v[1].base;
         a.t[i].v = L.tasks[i].v[2].base;
         int64_t e = std::min(a.t[i].hi, a.n) - a.t[i].lo;
-        int64_t blocks = e > 0 ? std::min<int64_t>((e + 4095) / 4096, 2048) : 0;
+        int64_t blocks = e > 0 ? std::min<int64_t>((e + 16383) / 16384, 2048) : 0;
         a.begin[i] = (int)nb;
         nb += blocks;
     }
@@ -257,13 +258,13 @@ __global__ __launch_bounds__(256) void k_kmeans(KArgs a) {
     const KTaskK &t = a.t[ti];
     const int d = D > 0 ? D : (int)a.d;
     const int K = (int)a.K;
-    const float *C = reinterpret_cast<const float *>(t.c);
+    const LT_GLOBAL float *C = gp<const float>(t.c);
     for (int i = threadIdx.x; i < K * d; i += 256) cen[i] = C[(i / d) * t.cs + (i % d)];
     __syncthreads();
     const int64_t end = t.hi < a.N ? t.hi : a.N;
     int64_t p = t.lo + (int64_t)(blockIdx.x - a.begin[ti]) * 256 + threadIdx.x;
     if (p >= end) return;
-    const float *X = reinterpret_cast<const float *>(t.x) + p * t.xs;
+    const LT_GLOBAL float *X = gp<const float>(t.x) + p * t.xs;
     float x[KM_MAXD];
 #pragma unroll
     for (int j = 0; j < (D > 0 ? D : KM_MAXD); ++j)
@@ -383,7 +384,7 @@ __global__ __launch_bounds__(256) void k_combine(CombineArgs a) {
         int64_t i2 = f % e2, r = f / e2;
         int64_t i1 = r % e1, i0 = r / e1;
         int64_t g[3] = {a.lo[0] + i0, a.lo[1] + i1, a.lo[2] + i2};
-        T *tp = reinterpret_cast<T *>(a.target.base) + g[0] * a.target.s[0] + g[1] * a.target.s[1] +
+        LT_GLOBAL T *tp = gp<T>(a.target.base) + g[0] * a.target.s[0] + g[1] * a.target.s[1] +
                 g[2] * a.target.s[2];
         T acc = a.accumulate ? *tp : identity<T>(a.op);
         for (int p = 0; p < a.nparts; ++p) {
@@ -397,7 +398,7 @@ __global__ __launch_bounds__(256) void k_combine(CombineArgs a) {
             int64_t off = (g[0] - q.lo[0]) * s0;
             if (a.ndim > 1) off += (g[1] - q.lo[1]) * s1;
             if (a.ndim > 2) off += g[2] - q.lo[2];
-            acc = rop<T>(a.op, acc, reinterpret_cast<const T *>(a.part_base)[q.off + off]);
+            acc = rop<T>(a.op, acc, gp<const T>(a.part_base)[q.off + off]);
         }
         *tp = acc;
     }

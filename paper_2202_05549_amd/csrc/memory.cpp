@@ -206,6 +206,26 @@ lt_status stream_wait(Ctx *ctx, int s, const Fence &f) {
     return LT_OK;
 }
 
+// Non-blocking: has every stream reached its entry of f?  Learns completed
+// sequence numbers along the way.
+bool fence_done(Ctx *ctx, const Fence &f) {
+    if (ctx->dry) return true;
+    for (int t = 0; t < ctx->nstreams; ++t) {
+        if (f.s[t] <= ctx->streams[t].done) continue;
+        hipEvent_t ev;
+        uint64_t mseq;
+        if (mark_at(ctx, t, f.s[t], &ev, &mseq)) return false;
+        hipError_t r = hipEventQuery(ev);
+        if (r == hipErrorNotReady) return false;
+        if (r != hipSuccess) {
+            hip_fail(ctx, r, "hipEventQuery");
+            return true;
+        }
+        if (mseq > ctx->streams[t].done) ctx->streams[t].done = mseq;
+    }
+    return true;
+}
+
 lt_status wait_fence(Ctx *ctx, const Fence &f) {
     if (ctx->dry) return LT_OK;
     for (int t = 0; t < ctx->nstreams; ++t) {

@@ -167,6 +167,20 @@ def kmeans_blobs(N: int, d: int = 16, K: int = 64, seed: int = 4,
 # ------------------------------------------------------------------- serving
 
 
+def dense_normal(shape, seed, out=None, band: int = 4096) -> np.ndarray:
+    """~N(0, 1) float32 of ``shape`` (2-D), row bands from sub-streams
+    ``[*seed, band]`` (serving GEMM operands of arbitrary size)."""
+    seed = list(seed) if isinstance(seed, (list, tuple)) else [seed]
+    if out is None:
+        out = np.empty(shape, dtype=np.float32)
+    for b, r0 in enumerate(range(0, shape[0], band)):
+        r1 = min(shape[0], r0 + band)
+        np.random.default_rng(seed + [b]).standard_normal((r1 - r0, shape[1]), dtype=np.float32,
+                                                            out=out[r0:r1])
+    return out
+
+
+
 def serving_trace(count: int = 512, rate: float = 200.0, seed: int = 4,
                   jacobi_range=(1024, 32768), kmeans_range=(1e5, 1e9),
                   gemm_range=(1024, 65536), pool: int = 8):
