@@ -51,6 +51,9 @@ def lib():
         L.or_kmeans_assign_f32.argtypes = [i64, i64, i64, p, p, p]
         L.or_kmeans_dist_f64.argtypes = [i64, p, p]
         L.or_kmeans_dist_f64.restype = C.c_double
+        L.or_reduce_rows_f64.argtypes = [i64, i64, i32, p, p, p]
+        L.or_kmeans_update_f64.argtypes = [i64, i64, i64, p, p, p, p, p]
+        L.or_kmeans_centres_f32.argtypes = [i64, i64, p, p, p]
         L.or_touch_i32.argtypes = [i64, i64, p]
         L.or_num_threads.restype = i32
         _lib = L
@@ -179,6 +182,58 @@ def kmeans_dist64(x: np.ndarray, c: np.ndarray) -> float:
     x = np.ascontiguousarray(x, dtype=np.float32)
     c = np.ascontiguousarray(c, dtype=np.float32)
     return float(lib().or_kmeans_dist_f64(x.size, _ptr(x), _ptr(c)))
+
+
+REDUCE_OPS = {"+": 0, "*": 1, "min": 2, "max": 3}
+
+
+def reduce_rows(A: np.ndarray, op: str = "+"):
+    """Row fold out[i] = op over j of A[i, j] in float64 (Sec. 2.3 example).
+    Returns (out float64 (n,), sum_j |A[i, j]| float64 (n,))."""
+    A = np.ascontiguousarray(A, dtype=np.float32)
+    n, m = A.shape
+    out = np.empty(n, dtype=np.float64)
+    sa = np.empty(n, dtype=np.float64)
+    lib().or_reduce_rows_f64(n, m, REDUCE_OPS[op], _ptr(A), _ptr(out), _ptr(sa))
+    return out, sa
+
+
+def kmeans_update(X: np.ndarray, lab: np.ndarray, K: int):
+    """Per-cluster sums (float64 (K, d)), counts (int64 (K,)) and sums of
+    absolute values (float64 (K, d)) of the points with each label."""
+    X = np.ascontiguousarray(X, dtype=np.float32)
+    lab = np.ascontiguousarray(lab, dtype=np.int32)
+    N, d = X.shape
+    sums = np.empty((K, d), dtype=np.float64)
+    counts = np.empty(K, dtype=np.int64)
+    abss = np.empty((K, d), dtype=np.float64)
+    lib().or_kmeans_update_f64(N, d, K, _ptr(X), _ptr(lab), _ptr(sums), _ptr(counts), _ptr(abss))
+    return sums, counts, abss
+
+
+def kmeans_centres(sums: np.ndarray, counts: np.ndarray, cen: np.ndarray) -> np.ndarray:
+    """New float32 centres sums / counts (rounded once); empty clusters keep
+    the centre in ``cen``.  Returns a new array."""
+    sums = np.ascontiguousarray(sums, dtype=np.float64)
+    counts = np.ascontiguousarray(counts, dtype=np.int64)
+    out = np.array(cen, dtype=np.float32, copy=True)
+    K, d = out.shape
+    lib().or_kmeans_centres_f32(K, d, _ptr(sums), _ptr(counts), _ptr(out))
+    return out
+
+
+def kmeans_lloyd(X: np.ndarray, cen0: np.ndarray, iters: int):
+    """The K-Means benchmark's loop: ``iters`` rounds of assignment then
+    centre update.  Returns a list of (labels, sums, counts, centres) per
+    round."""
+    cen = np.array(cen0, dtype=np.float32, copy=True)
+    out = []
+    for _ in range(iters):
+        lab = kmeans_assign(X, cen)
+        sums, counts, _ = kmeans_update(X, lab, cen.shape[0])
+        cen = kmeans_centres(sums, counts, cen)
+        out.append((lab, sums, counts, cen))
+    return out
 
 
 def num_threads() -> int:

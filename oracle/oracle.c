@@ -209,6 +209,80 @@ double or_kmeans_dist_f64(int64_t dim, const float *x, const float *c)
     return acc;
 }
 
+/* -------------------------------------------------------------- reductions
+ * reduce(f) (Sec. 2.3): the contributions of all threads are folded with f
+ * into the target, which is overwritten by the fold; the fold starts from
+ * f's identity (0 for +, 1 for *, +inf for min, -inf for max), so a target
+ * element nobody contributes to ends as the identity.  Here the fold runs in
+ * float64 over float32 contributions, in index order; min and max are exact
+ * in any order.
+ *
+ * Row reduction -- the Sec. 2.3 example "global [i, j] => read A[i,j],
+ * reduce(+) sum[i]":  out[i] = f over j of A[i][j] for an n x m matrix A.
+ * op: 0 = +, 1 = *, 2 = min, 3 = max.  abs_out (may be NULL) receives the
+ * sum over j of |A[i][j]|, the scale of the rounding bound of a float sum.
+ */
+void or_reduce_rows_f64(int64_t n, int64_t m, int op, const float *A, double *out, double *abs_out)
+{
+    for (int64_t i = 0; i < n; ++i) {
+        double acc = op == 0 ? 0.0 : op == 1 ? 1.0 : op == 2 ? INFINITY : -INFINITY;
+        double sa = 0.0;
+        for (int64_t j = 0; j < m; ++j) {
+            const double a = (double)A[i * m + j];
+            if (op == 0) acc += a;
+            else if (op == 1) acc *= a;
+            else if (op == 2) acc = a < acc ? a : acc;
+            else acc = a > acc ? a : acc;
+            sa += fabs(a);
+        }
+        out[i] = acc;
+        if (abs_out) abs_out[i] = sa;
+    }
+}
+
+/* K-means centre update (the reduction step of the K-Means benchmark,
+ * Sec. 4.1, whose centre calculation runs on the GPU through reduce(+)):
+ *     sums[k][j] = sum over points p with lab[p] = k of X[p][j]   (float64)
+ *     counts[k]  = number of points p with lab[p] = k
+ *     abss[k][j] = sum over the same p of |X[p][j]|   (rounding scale; may be NULL)
+ * Points are visited in index order.  Labels outside [0, K) contribute
+ * nothing.
+ */
+void or_kmeans_update_f64(int64_t N, int64_t dim, int64_t K, const float *X, const int32_t *lab,
+                          double *sums, int64_t *counts, double *abss)
+{
+    for (int64_t e = 0; e < K * dim; ++e) {
+        sums[e] = 0.0;
+        if (abss) abss[e] = 0.0;
+    }
+    for (int64_t k = 0; k < K; ++k)
+        counts[k] = 0;
+    for (int64_t p = 0; p < N; ++p) {
+        const int32_t k = lab[p];
+        if (k < 0 || k >= K)
+            continue;
+        counts[k] += 1;
+        for (int64_t j = 0; j < dim; ++j) {
+            sums[k * dim + j] += (double)X[p * dim + j];
+            if (abss) abss[k * dim + j] += fabs((double)X[p * dim + j]);
+        }
+    }
+}
+
+/* New centres from the update: cen[k][j] = sums[k][j] / counts[k], computed
+ * in float64 and rounded once to float32; a cluster with no points keeps its
+ * previous centre (cen is updated in place).
+ */
+void or_kmeans_centres_f32(int64_t K, int64_t dim, const double *sums, const int64_t *counts, float *cen)
+{
+    for (int64_t k = 0; k < K; ++k) {
+        if (counts[k] == 0)
+            continue;
+        for (int64_t j = 0; j < dim; ++j)
+            cen[k * dim + j] = (float)(sums[k * dim + j] / (double)counts[k]);
+    }
+}
+
 /* ------------------------------------------------------------------- touch
  * Exactly-once probe: every thread index i of the grid with i < n adds one to
  * y[i].  Running it over the whole grid leaves y[i] = y0[i] + 1 for i < n.

@@ -213,6 +213,108 @@ def test_kmeans_matches_float64_argmin_on_blobs():
 
 # ------------------------------------------------------------------- touch
 
+# ----------------------------------------------------------------- reductions
+
+@pytest.mark.parametrize("op,np_fn", [("+", np.sum), ("min", np.min), ("max", np.max)])
+def test_reduce_rows_matches_numpy_folds(op, np_fn):
+    rng = np.random.default_rng(11)
+    A = rng.standard_normal((37, 1001)).astype(np.float32)
+    out, sa = oracle.reduce_rows(A, op)
+    ref = np_fn(A.astype(np.float64), axis=1)
+    if op == "+":
+        # float64 sums of 1001 float32 values: both within 1001 u64 sum|a|
+        assert np.all(np.abs(out - ref) <= 1001 * 2.0 ** -53 * sa)
+        assert np.allclose(sa, np.abs(A.astype(np.float64)).sum(axis=1))
+    else:
+        assert np.array_equal(out, ref)  # min and max are exact
+
+
+def test_reduce_rows_closed_forms():
+    m = 4096
+    ramp = np.tile(np.arange(m, dtype=np.float32), (3, 1))
+    out, _ = oracle.reduce_rows(ramp, "+")
+    assert np.all(out == m * (m - 1) / 2)  # exact: integers below 2^53
+    # products of powers of two are exact: 2^(sum of exponents)
+    e = np.random.default_rng(2).integers(-3, 4, (5, 60))
+    P = np.ldexp(np.ones_like(e, dtype=np.float32), e)
+    prod, _ = oracle.reduce_rows(P, "*")
+    assert np.array_equal(prod, np.ldexp(1.0, e.sum(axis=1)))
+    # a sign flip: the max of -A is minus the min of A
+    A = np.random.default_rng(3).uniform(-5, 5, (4, 100)).astype(np.float32)
+    assert np.array_equal(oracle.reduce_rows(-A, "max")[0], -oracle.reduce_rows(A, "min")[0])
+
+
+def test_reduce_rows_empty_fold_is_identity():
+    A = np.zeros((3, 0), np.float32)
+    assert np.array_equal(oracle.reduce_rows(A, "+")[0], np.zeros(3))
+    assert np.array_equal(oracle.reduce_rows(A, "*")[0], np.ones(3))
+    assert np.all(oracle.reduce_rows(A, "min")[0] == np.inf)
+    assert np.all(oracle.reduce_rows(A, "max")[0] == -np.inf)
+
+
+def test_kmeans_update_matches_bincount():
+    rng = np.random.default_rng(5)
+    N, d, K = 20000, 7, 13
+    X = rng.standard_normal((N, d)).astype(np.float32)
+    lab = rng.integers(0, K, N).astype(np.int32)
+    sums, counts, abss = oracle.kmeans_update(X, lab, K)
+    assert np.array_equal(counts, np.bincount(lab, minlength=K))
+    assert counts.sum() == N
+    for j in range(d):
+        ref = np.bincount(lab, weights=X[:, j].astype(np.float64), minlength=K)
+        assert np.all(np.abs(sums[:, j] - ref) <= N * 2.0 ** -53 * abss[:, j])
+        aref = np.bincount(lab, weights=np.abs(X[:, j]).astype(np.float64), minlength=K)
+        assert np.allclose(abss[:, j], aref, rtol=1e-12)
+    # every point lands in exactly one cluster: cluster sums add up to column sums
+    assert np.allclose(sums.sum(axis=0), X.astype(np.float64).sum(axis=0), rtol=0, atol=1e-9 * np.abs(X).sum())
+
+
+def test_kmeans_update_points_at_integer_centres_exact():
+    # centres with small integer coordinates; points exactly at them: sums are
+    # counts times the centre, exactly, and the new centres equal the old ones
+    K, d = 9, 5
+    cen = np.arange(K * d, dtype=np.float32).reshape(K, d) - 20
+    z = np.random.default_rng(6).integers(0, K - 1, 3000).astype(np.int32)  # cluster K-1 stays empty
+    X = cen[z]
+    lab = oracle.kmeans_assign(X, cen)
+    assert np.array_equal(lab, z)
+    sums, counts, _ = oracle.kmeans_update(X, lab, K)
+    assert np.array_equal(sums, counts[:, None] * cen.astype(np.float64))
+    assert counts[K - 1] == 0
+    moved = cen.copy()
+    moved[K - 1] = 99.0  # an empty cluster keeps whatever centre it had
+    new = oracle.kmeans_centres(sums, counts, moved)
+    assert np.array_equal(new[:K - 1], cen[:K - 1]) and np.all(new[K - 1] == 99.0)
+
+
+def test_kmeans_update_ignores_out_of_range_labels():
+    X = np.ones((6, 2), np.float32)
+    lab = np.array([0, 1, -1, 2, 5, 1], np.int32)
+    sums, counts, _ = oracle.kmeans_update(X, lab, 3)
+    assert list(counts) == [1, 2, 1] and sums[1, 0] == 2.0
+
+
+def test_kmeans_lloyd_on_separated_blobs():
+    # started from the true means of well-separated blobs, the first round
+    # labels every point with its own blob and moves each centre to the mean
+    # of its blob's points; the within-cluster sum of squares never increases
+    X, mu, z = synthetic.kmeans_blobs(30000, 16, 64, seed=8)
+    rounds = oracle.kmeans_lloyd(X, mu, 5)
+    lab1, _, counts1, cen1 = rounds[0]
+    assert np.array_equal(lab1, z)
+    X64 = X.astype(np.float64)
+    for k in range(64):
+        if counts1[k]:
+            ref = X64[z == k].mean(axis=0)
+            assert np.all(np.abs(cen1[k] - ref) <= 2 * np.abs(ref) * 2.0 ** -24 + 1e-12)
+    sse = []
+    cen = mu
+    for lab, _, _, new in rounds:
+        sse.append(float(((X64 - cen.astype(np.float64)[lab]) ** 2).sum()))
+        cen = new
+    assert all(b <= a * (1 + 1e-9) for a, b in zip(sse, sse[1:]))
+
+
 def test_touch_exactly_once_within_n():
     y = oracle.touch(np.zeros(100, np.int32), grid=128)
     assert np.all(y == 1)
