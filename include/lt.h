@@ -106,7 +106,12 @@ typedef struct lt_config {
                                        it holds this many tasks, so planning
                                        of later launches overlaps the drain of
                                        earlier ones; 0 = only at lt_batch_end */
-    int32_t reserved[4];
+    int32_t drain_vectors;          /* 16-byte vectors per lane per group in
+                                       the drain's streaming bodies (two groups
+                                       are in flight): 2 (fewer registers, more
+                                       waves) or 4; 0 = 4.  Changes speed
+                                       only, never results.                   */
+    int32_t reserved[3];
 } lt_config;
 
 #define LT_ORDER_ROWMAJOR 0
@@ -224,6 +229,24 @@ lt_status lt_host_free(lt_context *ctx, void *ptr);
  *                               global i => read X[i, :], read Cen[:, :], write lab[i]
  *       lab[i] = argmin_k sum_j (X[i,j] - Cen[k,j])^2, float32 fma chain,
  *       ties to the smallest k
+ *   rowreduce_f32(n, m, out, A) global [i, j] => read A[i, j], reduce(+) out[i]
+ *       out[i] = f over j of A[i, j], the reduction example of Sec. 2.3; f is
+ *       the annotation's operator (+, *, min or max: define the kernel with
+ *       e.g. "reduce(max) out[i]").  Each superblock folds its part of a row
+ *       in float64 (min/max exact), rounds once to float32, and the partials
+ *       of a row are folded in superblock order: the result depends on the
+ *       superblock shape, never on scheduling or distributions.
+ *   kmeans_update_f32(N, d, K, sums, counts, X, lab)
+ *                               global i => read X[i, :], read lab[i],
+ *                                           reduce(+) sums[:, :], reduce(+) counts[:]
+ *       sums (float64 K x d) and counts (int32 K) of the points with each
+ *       label (labels outside [0, K) are skipped): the centre update of the
+ *       K-Means benchmark (Sec. 4.1).  Float64 folds in a fixed order, one
+ *       partial slot per workgroup.  d <= 32, K <= 256, K*d <= 1536.
+ *   kmeans_centres_f32(K, d, Cen, sums, counts)
+ *                               global [k, j] => read sums[k, j], read counts[k], readwrite Cen[k, j]
+ *       Cen[k, j] = sums[k, j] / counts[k] in float64 rounded once to
+ *       float32; clusters with no points keep their centre
  *
  * lt_kernel_get: the built-in with its default annotation.
  * lt_kernel_define: the built-in body `base` under another annotation (it must

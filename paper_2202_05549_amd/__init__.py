@@ -46,7 +46,8 @@ class lt_config(C.Structure):
                 ("dry_run", C.c_int32), ("device_budget_bytes", C.c_uint64),
                 ("stage_threshold_bytes", C.c_uint64), ("device_arena", C.c_void_p),
                 ("arena_bytes", C.c_uint64), ("trace", C.c_int32), ("sb_order", C.c_int32),
-                ("drain_workgroups", C.c_int32), ("batch_flush_tasks", C.c_int32), ("reserved", C.c_int32 * 4)]
+                ("drain_workgroups", C.c_int32), ("batch_flush_tasks", C.c_int32), ("drain_vectors", C.c_int32),
+                ("reserved", C.c_int32 * 3)]
 
 
 class lt_box(C.Structure):
@@ -295,7 +296,8 @@ class Context:
 
     def configure(self, **cfg):
         """Change tunable fields (exec_mode, stage_threshold_bytes, sb_order,
-        drain_workgroups, batch_flush_tasks, trace) of the live context."""
+        drain_workgroups, batch_flush_tasks, drain_vectors, trace) of the live
+        context."""
         for k, v in cfg.items():
             setattr(self.cfg, k, v)
         check(self.h, lt_context_configure(self.h, C.byref(self.cfg)))

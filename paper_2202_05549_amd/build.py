@@ -21,7 +21,7 @@ BUILD = os.path.join(HERE, "_build")
 ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 
 HOST_SRC = ["annot.cpp", "plan.cpp", "memory.cpp", "exec.cpp", "api.cpp", "serve.cpp"]
-HIP_SRC = ["kernels.hip", "gemm.hip", "drain.hip"]
+HIP_SRC = ["kernels.hip", "gemm.hip", "drain.hip", "reduce.hip"]
 
 HOST_FLAGS = ["-O2", "-g", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",
               "-D__HIP_PLATFORM_AMD__", "-I" + INC, "-I" + CSRC, "-I" + os.path.join(ROCM, "include")]

@@ -36,6 +36,25 @@ static const KernelDef kBuiltins[] = {
       {"X", P_ARRAY, LT_F32, 2},
       {"Cen", P_ARRAY, LT_F32, 2}},
      1, launch_kmeans_assign_f32, KMAXG, -1},
+    {"rowreduce_f32", "global [i, j] => read A[i, j], reduce(+) out[i]", 4,
+     {{"n", P_INT, LT_F32, 0}, {"m", P_INT, LT_F32, 0}, {"out", P_ARRAY, LT_F32, 1}, {"A", P_ARRAY, LT_F32, 2}},
+     2, launch_rowreduce_f32, 1, -1},
+    {"kmeans_update_f32", "global i => read X[i, :], read lab[i], reduce(+) sums[:, :], reduce(+) counts[:]", 7,
+     {{"N", P_INT, LT_F32, 0},
+      {"d", P_INT, LT_F32, 0},
+      {"K", P_INT, LT_F32, 0},
+      {"sums", P_ARRAY, LT_F64, 2},
+      {"counts", P_ARRAY, LT_I32, 1},
+      {"X", P_ARRAY, LT_F32, 2},
+      {"lab", P_ARRAY, LT_I32, 1}},
+     1, launch_kmeans_update_f32, 1, -1, kmeans_update_slots},
+    {"kmeans_centres_f32", "global [k, j] => read sums[k, j], read counts[k], readwrite Cen[k, j]", 5,
+     {{"K", P_INT, LT_F32, 0},
+      {"d", P_INT, LT_F32, 0},
+      {"Cen", P_ARRAY, LT_F32, 2},
+      {"sums", P_ARRAY, LT_F64, 2},
+      {"counts", P_ARRAY, LT_I32, 1}},
+     2, launch_kmeans_centres_f32, KMAXG, -1},
 };
 
 const KernelDef *find_builtin(const char *name) {
@@ -460,6 +479,10 @@ lt_status lt_context_create(const lt_config *cfg_in, lt_context **out) {
         g_create_err = "arena_bytes must be > 0 with device_arena";
         return LT_ERR_INVALID;
     }
+    if (cfg.drain_vectors != 0 && cfg.drain_vectors != 2 && cfg.drain_vectors != 4) {
+        g_create_err = "drain_vectors must be 0, 2 or 4";
+        return LT_ERR_INVALID;
+    }
     Ctx *ctx = new Ctx();
     ctx->cfg = cfg;
     ctx->dry = cfg.dry_run != 0;
@@ -501,6 +524,8 @@ lt_status lt_context_configure(lt_context *ctx, const lt_config *cfg) {
     if (!ctx || !cfg) return LT_ERR_INVALID;
     if (cfg->exec_mode != LT_EXEC_PLAIN && cfg->exec_mode != LT_EXEC_GROUPED)
         return set_err(ctx, LT_ERR_INVALID, "unknown exec_mode %d", cfg->exec_mode);
+    if (cfg->drain_vectors != 0 && cfg->drain_vectors != 2 && cfg->drain_vectors != 4)
+        return set_err(ctx, LT_ERR_INVALID, "drain_vectors must be 0, 2 or 4");
     lt_status st = flush_all(ctx);
     if (st) return st;
     ctx->cfg.exec_mode = cfg->exec_mode;
@@ -508,6 +533,7 @@ lt_status lt_context_configure(lt_context *ctx, const lt_config *cfg) {
     ctx->cfg.sb_order = cfg->sb_order;
     ctx->cfg.drain_workgroups = cfg->drain_workgroups;
     ctx->cfg.batch_flush_tasks = cfg->batch_flush_tasks;
+    ctx->cfg.drain_vectors = cfg->drain_vectors;
     ctx->cfg.trace = cfg->trace;
     return LT_OK;
 }

@@ -27,6 +27,18 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 #define LT_GLOBAL
 #endif
 
+// Task lookup in a dispatch that covers several tasks: the task t with
+// begin[t] <= b < begin[t+1].
+__device__ __forceinline__ int find_task(const int *begin, int ntask, int b) {
+    int lo = 0, hi = ntask - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (begin[mid] <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
 template <class T>
 __device__ __forceinline__ LT_GLOBAL T *gp(int64_t base) {
     return (LT_GLOBAL T *)base;

@@ -18,21 +18,26 @@ namespace lt {
 
 using namespace body;
 
+template <int G, uint32_t KINDS>
 __device__ __forceinline__ void run_tile(const DTask &t, int64_t local, int *sh) {
+    // a build only carries the bodies in KINDS (the host never queues others)
     switch (t.kind) {
         case DK_TOUCH: {
+            if constexpr (!(KINDS & (1u << DK_TOUCH))) break;
             const int64_t s0 = t.lo0 + local * DSPAN;
             for (int64_t sp = 0; sp < DSPAN; sp += THREADS) touch_span(t.y, t.n, t.lo0, t.hi0, s0 + sp);
             break;
         }
         case DK_STENCIL1D: {
+            if constexpr (!(KINDS & (1u << DK_STENCIL1D))) break;
             const int64_t end = t.hi0 < t.n ? t.hi0 : t.n;
             const int64_t s0 = t.lo0 + local * DSPAN;
             if (s0 >= end) break;
-            stencil_stream<4>(t.x, t.y, t.n, t.lo0, t.hi0, s0, s0 + DSPAN < end ? s0 + DSPAN : end);
+            stencil_stream<G>(t.x, t.y, t.n, t.lo0, t.hi0, s0, s0 + DSPAN < end ? s0 + DSPAN : end);
             break;
         }
         case DK_JACOBI2D: {
+            if constexpr (!(KINDS & (1u << DK_JACOBI2D))) break;
             JView v;
             v.r0 = t.lo0;
             v.r1 = t.hi0;
@@ -53,6 +58,7 @@ __device__ __forceinline__ void run_tile(const DTask &t, int64_t local, int *sh)
             break;
         }
         case DK_HIST256: {
+            if constexpr (!(KINDS & (1u << DK_HIST256))) break;
             const int64_t end = t.hi0 < t.n ? t.hi0 : t.n;
             const int64_t s0 = t.lo0 + local * DSPAN;
             const int64_t s1 = s0 + DSPAN < end ? s0 + DSPAN : end;
@@ -61,6 +67,7 @@ __device__ __forceinline__ void run_tile(const DTask &t, int64_t local, int *sh)
             break;
         }
         case DK_SUM_PARTIALS: {
+            if constexpr (!(KINDS & (1u << DK_SUM_PARTIALS))) break;
             // y[e] = sum over p of partial p at element e, e in [lo0, hi0);
             // partials are dense blocks of m elements starting at x
             const LT_GLOBAL int32_t *P = gp<const int32_t>(t.x);
@@ -76,8 +83,9 @@ __device__ __forceinline__ void run_tile(const DTask &t, int64_t local, int *sh)
     }
 }
 
-__global__ __launch_bounds__(256) void k_drain(const DTask *q, int ntasks, int32_t *ctr, int ticket_idx,
-                                               int64_t total, int64_t spin_limit) {
+template <int G, uint32_t KINDS>
+__device__ __forceinline__ void drain_loop(const DTask *q, int ntasks, int32_t *ctr, int ticket_idx,
+                                           int64_t total, int64_t spin_limit) {
     __shared__ int sh[4 * 256];
     __shared__ int s_tile, s_task, s_ok;
     for (int i = threadIdx.x; i < 4 * 256; i += THREADS) sh[i] = 0;
@@ -92,7 +100,7 @@ __global__ __launch_bounds__(256) void k_drain(const DTask *q, int ntasks, int32
             s_tile = tile;
         }
         __syncthreads();
-        const int64_t tile = s_tile;
+        const int64_t tile = __builtin_amdgcn_readfirstlane(s_tile);
         if (tile >= total) break;
         if (threadIdx.x == 0) {
             while (cur + 1 < ntasks && q[cur + 1].tile_begin <= tile) ++cur;
@@ -115,26 +123,49 @@ __global__ __launch_bounds__(256) void k_drain(const DTask *q, int ntasks, int32
             s_ok = ok;
         }
         __syncthreads();
-        const DTask &t = q[s_task];
-        if (s_ok) run_tile(t, tile - t.tile_begin, sh);
+        const int task = __builtin_amdgcn_readfirstlane(s_task);
+        const DTask &t = q[task];
+        if (__builtin_amdgcn_readfirstlane(s_ok)) run_tile<G, KINDS>(t, tile - t.tile_begin, sh);
         __syncthreads();
         if (threadIdx.x == 0) {
             const int32_t fl = t.flags;
             if (fl & DF_RELEASE) __threadfence();           // plain stores become visible
             else if (fl & DF_ATOMIC) __builtin_amdgcn_s_waitcnt(0);  // atomics performed
-            int prev = atomicAdd(&ctr[s_task], 1);
+            int prev = atomicAdd(&ctr[task], 1);
             if (prev == t.ntiles - 1 && t.signal >= 0) atomicAdd(&ctr[t.signal], 1);
         }
     }
 }
 
+// Builds of the same loop for common sets of bodies and group sizes.  Each
+// is a separate kernel so that its register allocation covers only the
+// bodies it can meet: the 1-D streaming bodies with 2-vector groups fit in
+// 64 VGPRs (eight waves per SIMD); with 4-vector groups, or with every
+// body, a build takes 82-93 (five waves) but keeps more loads in flight.
+constexpr uint32_t KB_TOUCH = 1u << DK_TOUCH, KB_ST = 1u << DK_STENCIL1D, KB_JAC = 1u << DK_JACOBI2D,
+                   KB_HIST = 1u << DK_HIST256, KB_SUM = 1u << DK_SUM_PARTIALS;
+constexpr uint32_t KB_1D = KB_TOUCH | KB_ST | KB_HIST | KB_SUM;
+constexpr uint32_t KB_ALL = KB_1D | KB_JAC;
+
+template <uint32_t KINDS, int G>
+__global__ __launch_bounds__(256) void k_drain(const DTask *q, int ntasks, int32_t *ctr, int ticket_idx,
+                                               int64_t total, int64_t spin_limit) {
+    drain_loop<G, KINDS>(q, ntasks, ctr, ticket_idx, total, spin_limit);
+}
+
 hipError_t launch_drain(hipStream_t s, const DTask *q, int ntasks, int32_t *counters, int ticket_idx,
-                        int64_t total_tiles, int nwg, int64_t spin_limit) {
+                        int64_t total_tiles, int nwg, int64_t spin_limit, uint32_t kinds, int vectors) {
     if (total_tiles <= 0 || ntasks <= 0) return hipSuccess;
     if (nwg < 1) nwg = 1;
     if ((int64_t)nwg > total_tiles) nwg = (int)total_tiles;
-    hipLaunchKernelGGL(k_drain, dim3((unsigned)nwg), dim3(256), 0, s, q, ntasks, counters, ticket_idx,
-                       total_tiles, spin_limit);
+    const bool one_d = (kinds & ~KB_1D) == 0;
+    if (vectors == 0) vectors = 4;
+    void (*k)(const DTask *, int, int32_t *, int, int64_t, int64_t);
+    if (one_d) k = vectors == 2 ? k_drain<KB_1D, 2> : k_drain<KB_1D, 4>;
+    else if ((kinds & ~(KB_JAC | KB_SUM)) == 0) k = k_drain<KB_JAC | KB_SUM, 4>;
+    else k = vectors == 2 ? k_drain<KB_ALL, 2> : k_drain<KB_ALL, 4>;
+    hipLaunchKernelGGL(k, dim3((unsigned)nwg), dim3(256), 0, s, q, ntasks, counters, ticket_idx, total_tiles,
+                       spin_limit);
     return hipGetLastError();
 }
 

@@ -45,6 +45,7 @@ struct TaskPlan {
     Box sb;
     ArgPlan arg[MAXPARAM];
     int64_t footprint = 0;
+    int64_t slots = 1;      // partial slots per reduce parameter
 };
 
 
@@ -408,6 +409,7 @@ static void batch_push(Ctx *ctx, DTask &d, uint64_t id) {
     if (d.ntiles < 1) d.ntiles = 1;  // an empty task still completes (and signals)
     d.tile_begin = B.tiles;
     B.tiles += d.ntiles;
+    B.kinds |= 1u << d.kind;
     if (B.index.empty()) B.index_base = id;
     if (id - B.index_base >= B.index.size()) B.index.resize(id - B.index_base + 1, -1);
     B.index[id - B.index_base] = (int)B.q.size();
@@ -432,8 +434,12 @@ static lt_status batch_add_exec(Ctx *ctx, const KernelDef *def, TaskPlan &tp, Ta
             Partials *P = nullptr;
             for (auto &x : parts)
                 if (x.param == p) P = &x;
+            if (tp.slots > 1)
+                return set_err(ctx, LT_ERR_UNSUPPORTED, "%s folds floats over several partial slots and cannot "
+                               "run inside a batch", def->name);
             CombinePart cp;
             cp.off = P->cursor;
+            cp.count = 1;
             P->cursor += a.region.volume(arr->ndim);
             int64_t org = 0, s = 1;
             for (int q = MAXD - 1; q >= 0; --q) {
@@ -656,7 +662,7 @@ lt_status batch_flush(Ctx *ctx) {
         if (st) return st;
         r = launch_drain(h, reinterpret_cast<const DTask *>(base), ntasks,
                          reinterpret_cast<int32_t *>(base + qalloc), ntasks + B.nsignals, B.tiles, nwg,
-                         (int64_t)1 << 26);
+                         (int64_t)1 << 26, B.kinds, ctx->cfg.drain_vectors);
         if (r != hipSuccess) return hip_fail(ctx, r, "drain");
         st = prof_end(ctx, s, "drain", pa);
         if (st) return st;
@@ -745,7 +751,7 @@ lt_status graph_end(Ctx *ctx, lt_graph **out) {
     hipError_t r2 = launch_fill(h, base + qalloc, (calloc_ + B.part_bytes) / 4, 4, &zero);
     hipError_t r3 = launch_drain(h, reinterpret_cast<const DTask *>(base), ntasks,
                                  reinterpret_cast<int32_t *>(base + qalloc), ntasks + B.nsignals, B.tiles, nwg,
-                                 (int64_t)1 << 26);
+                                 (int64_t)1 << 26, B.kinds, ctx->cfg.drain_vectors);
     hipError_t r4 = hipMemcpyAsync(g->status, base + qalloc + (int64_t)(ntasks + B.nsignals + 1) * 4, 4,
                                    hipMemcpyDeviceToHost, h);
     r = hipStreamEndCapture(h, &g->graph);
@@ -977,7 +983,9 @@ static lt_status issue_exec(Ctx *ctx, lt_kernel *k, TaskPlan &tp, uint64_t L,
             // this superblock's partial
             CombinePart cp;
             cp.off = P->cursor;
-            P->cursor += a.region.volume(arr->ndim);
+            cp.count = tp.slots;
+            P->cursor += a.region.volume(arr->ndim) * tp.slots;
+            kt.slot[p] = tp.slots > 1 ? a.region.volume(arr->ndim) : 0;
             for (int d = 0; d < KMAXD; ++d) {
                 cp.lo[d] = a.region.lo[d];
                 cp.hi[d] = a.region.hi[d];
@@ -1166,6 +1174,26 @@ static lt_status issue_combine(Ctx *ctx, Partials &P, Array *arr, uint64_t L) {
             if (!st) st = copy_region(ctx, s, c, t, arr->esz, nd, true);
         bump(ctx, s);
     }
+    bool slotted = false;
+    for (auto &q : P.parts) slotted |= q.count > 1;
+    for (size_t i = 0; slotted && i < P.parts.size() && !st; i += KMAXPART) {
+        // first level: the slots of each superblock's partial, in slot order
+        CombineArgs ca;
+        memset(&ca, 0, sizeof ca);
+        ca.ndim = nd;
+        ca.dtype = arr->dtype;
+        ca.op = P.op;
+        ca.part_base = (int64_t)(intptr_t)(ctx->arena_base + P.off);
+        ca.nparts = (int)std::min<size_t>(KMAXPART, P.parts.size() - i);
+        for (int j = 0; j < ca.nparts; ++j) ca.parts[j] = P.parts[i + j];
+        ctx->stats.dispatches++;
+        trace_op(ctx, 0, s, rec.id, 0, ca.nparts, 1);
+        if (!ctx->dry) {
+            hipError_t r = launch_fold_slots(ctx->streams[s].h, ca);
+            if (r != hipSuccess) st = hip_fail(ctx, r, "fold slots");
+        }
+        bump(ctx, s);
+    }
     for (size_t i = 0; i < P.parts.size() && !st; i += KMAXPART) {
         CombineArgs ca;
         memset(&ca, 0, sizeof ca);
@@ -1337,12 +1365,13 @@ lt_status launch(Ctx *ctx, lt_kernel *k, int nd, const int64_t *grid,
             a.op = pop[p];
         }
         seen.clear();
+        if (def->slots) tp.slots = std::max<int64_t>(1, def->slots(tp.sb.lo, tp.sb.hi, iparams));
         for (int p = 0; p < def->nparam; ++p) {
             ArgPlan &a = tp.arg[p];
             if (!a.used) continue;
             Array *arr = arrs[p];
             if (a.mode == M_REDUCE) {
-                tp.footprint += a.region.volume(arr->ndim) * arr->esz;
+                tp.footprint += a.region.volume(arr->ndim) * arr->esz * tp.slots;
                 continue;
             }
             chunks_overlapping(arr, a.region, &a.chunks);
@@ -1367,7 +1396,7 @@ lt_status launch(Ctx *ctx, lt_kernel *k, int nd, const int64_t *grid,
         P.param = p;
         P.op = pop[p];
         for (auto &tp : plans)
-            if (tp.arg[p].used) P.total_elems += tp.arg[p].region.volume(arrs[p]->ndim);
+            if (tp.arg[p].used) P.total_elems += tp.arg[p].region.volume(arrs[p]->ndim) * tp.slots;
         P.bytes = (P.total_elems * arrs[p]->esz + 255) / 256 * 256;
         part_bytes += P.bytes;
         parts.push_back(P);
@@ -1389,6 +1418,8 @@ lt_status launch(Ctx *ctx, lt_kernel *k, int nd, const int64_t *grid,
     }
     for (int a = 0; a < MAXD; ++a) proto.block[a] = B[a];
     proto.variant = k->variant;
+    for (int p = 0; p < def->nparam && p < KMAXP; ++p)
+        if (pany[p] && pmode[p] == M_REDUCE) proto.rop[p] = (int32_t)pop[p];
     for (auto &P : parts) {
         if (P.total_elems == 0) continue;
         if (ctx->batch.open) {

@@ -42,21 +42,6 @@ struct GArgs {
     GTask t[GMAX];
 };
 
-__device__ __forceinline__ int find_task_g(const int *begin, int ntask, int b) {
-    int lo = 0, hi = ntask - 1;
-    while (lo < hi) {
-        int mid = (lo + hi + 1) >> 1;
-        if (begin[mid] <= b) lo = mid;
-        else hi = mid - 1;
-    }
-    return lo;
-}
-
-__device__ __forceinline__ int xcd_remap_g(int b, int nb) {
-    int per = nb >> 3;
-    if (b >= (per << 3)) return b;
-    return (b & 7) * per + (b >> 3);
-}
 
 }  // namespace
 
@@ -64,8 +49,8 @@ __global__ __launch_bounds__(256, 1) void k_gemm(GArgs g) {
     __shared__ float As[2][BK][LDA];
     __shared__ float Bs[2][BK][LDB];
 
-    const int b = xcd_remap_g(blockIdx.x, g.nblocks);
-    const int ti = find_task_g(g.begin, g.ntask, b);
+    const int b = body::xcd_remap(blockIdx.x, g.nblocks);
+    const int ti = body::find_task(g.begin, g.ntask, b);
     const GTask &t = g.t[ti];
     const int local = b - g.begin[ti];
     const int tmi = local / t.tn, tni = local - tmi * t.tn;

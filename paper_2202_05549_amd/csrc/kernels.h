@@ -32,6 +32,10 @@ struct KTask {
     int64_t lo[KMAXD];       // superblock thread box, global indices, half-open
     int64_t hi[KMAXD];
     KView v[KMAXP];          // indexed by parameter number (scalars unused)
+    // reduce(f) parameters whose body writes several partials per task
+    // (one per workgroup slot, so float folds stay in a fixed order): the
+    // element distance between consecutive slots; 0 = one slot
+    int64_t slot[KMAXP];
 };
 
 struct KLaunch {
@@ -43,6 +47,7 @@ struct KLaunch {
     double farg[KMAXP];
     int64_t block[KMAXD];    // logical block shape of the launch
     int variant;             // tuning variant (0 = default)
+    int32_t rop[KMAXP];      // reduce(f) operator per parameter (ROp: 0 +, 1 *, 2 min, 3 max)
 };
 
 typedef hipError_t (*KernelFn)(const KLaunch &);
@@ -54,6 +59,29 @@ hipError_t launch_jacobi2d_f32(const KLaunch &);
 hipError_t launch_gemm_f32(const KLaunch &);
 hipError_t launch_hist256_i32(const KLaunch &);
 hipError_t launch_kmeans_assign_f32(const KLaunch &);
+hipError_t launch_rowreduce_f32(const KLaunch &);
+hipError_t launch_kmeans_update_f32(const KLaunch &);
+hipError_t launch_kmeans_centres_f32(const KLaunch &);
+
+// k-means update: points per workgroup tile and the largest number of
+// workgroups (= partial slots) per task.  A task of p points gets
+// kmu_slots(p) workgroups; workgroup w takes tiles w, w + slots, ... in
+// order and writes slot w, so the float folds never depend on scheduling.
+constexpr int64_t KMU_TILE = 4096;
+constexpr int64_t KMU_MAXSLOTS = 1024;  // about as many workgroups as fit on the chip at once
+inline int64_t kmu_slots(int64_t points) {
+    if (points <= 0) return 1;
+    int64_t t = (points + KMU_TILE - 1) / KMU_TILE;
+    return t < KMU_MAXSLOTS ? t : KMU_MAXSLOTS;
+}
+constexpr int KMU_MAXD = 32;
+constexpr int KMU_MAXK = 256;
+constexpr int KMU_MAXKD = 1536;   // K * d limit: four float64 copies stay under 64 KiB of LDS
+// partial slots of a k-means update task over points [lo, min(hi, N))
+inline int64_t kmeans_update_slots(const int64_t *lo, const int64_t *hi, const int64_t *iarg) {
+    const int64_t end = hi[0] < iarg[0] ? hi[0] : iarg[0];
+    return kmu_slots(end - lo[0]);
+}
 
 // Runtime helpers.
 // Sets `count` elements of size esz (1, 4 or 8 bytes) at dst to *value.
@@ -67,6 +95,7 @@ hipError_t launch_fill(hipStream_t s, void *dst, int64_t count, int esz,
 struct CombinePart {
     int64_t off;             // element offset of the partial
     int64_t lo[KMAXD], hi[KMAXD];
+    int64_t count;           // slots: dense copies of the box, back to back (0 or 1 = one)
 };
 constexpr int KMAXPART = 24;
 struct CombineArgs {
@@ -78,6 +107,10 @@ struct CombineArgs {
     CombinePart parts[KMAXPART];
 };
 hipError_t launch_combine(hipStream_t s, const CombineArgs &a);
+// Folds the slots of each part into its first slot in a fixed order: up to
+// 16 runs of consecutive slots, each folded in slot order, then the runs in
+// run order.
+hipError_t launch_fold_slots(hipStream_t s, const CombineArgs &a);
 
 }  // namespace lt
 
@@ -124,7 +157,12 @@ constexpr int32_t DF_ATOMIC = 2;
 
 // counters: ntasks + nsignals task/signal counters, then the ticket, then an
 // error flag (bit 0: a dependency wait gave up after spin_limit polls).
+// kinds: bit k set when the queue holds a task of body DK k; the drain is
+// built once per common set of bodies (a build that carries only the bodies
+// it needs uses fewer registers, so more waves fit per SIMD)
+// vectors: 16-byte vectors per lane per group of the streaming bodies (2 or
+// 4; 0 = 4)
 hipError_t launch_drain(hipStream_t s, const DTask *q, int ntasks, int32_t *counters, int ticket_idx,
-                        int64_t total_tiles, int nwg, int64_t spin_limit);
+                        int64_t total_tiles, int nwg, int64_t spin_limit, uint32_t kinds, int vectors);
 
 }  // namespace lt

@@ -22,17 +22,6 @@ using namespace body;
 
 namespace {
 
-// Task lookup: begin[t] <= b < begin[t+1].
-__device__ __forceinline__ int find_task(const int *begin, int ntask, int b) {
-    int lo = 0, hi = ntask - 1;
-    while (lo < hi) {
-        int mid = (lo + hi + 1) >> 1;
-        if (begin[mid] <= b) lo = mid;
-        else hi = mid - 1;
-    }
-    return lo;
-}
-
 inline unsigned grid_of(int64_t blocks) { return (unsigned)blocks; }
 
 }  // namespace
@@ -342,79 +331,6 @@ hipError_t launch_fill(hipStream_t s, void *dst, int64_t count, int esz, const v
         hipLaunchKernelGGL(k_fill<uint8_t>, dim3((unsigned)blocks), dim3(256), 0, s, (uint8_t *)dst, count, v);
     } else {
         return hipErrorInvalidValue;
-    }
-    return hipGetLastError();
-}
-
-// ================================================================ combine
-template <class T>
-__device__ __forceinline__ T rop(int op, T a, T b) {
-    switch (op) {
-        case 0: return a + b;
-        case 1: return a * b;
-        case 2: return b < a ? b : a;
-        default: return b > a ? b : a;
-    }
-}
-
-template <class T>
-__device__ __forceinline__ T identity(int op);
-template <>
-__device__ __forceinline__ float identity<float>(int op) {
-    return op == 0 ? 0.f : op == 1 ? 1.f : op == 2 ? INFINITY : -INFINITY;
-}
-template <>
-__device__ __forceinline__ double identity<double>(int op) {
-    return op == 0 ? 0. : op == 1 ? 1. : op == 2 ? INFINITY : -INFINITY;
-}
-template <>
-__device__ __forceinline__ int32_t identity<int32_t>(int op) {
-    return op == 0 ? 0 : op == 1 ? 1 : op == 2 ? INT_MAX : INT_MIN;
-}
-template <>
-__device__ __forceinline__ int64_t identity<int64_t>(int op) {
-    return op == 0 ? 0 : op == 1 ? 1 : op == 2 ? LLONG_MAX : LLONG_MIN;
-}
-
-template <class T>
-__global__ __launch_bounds__(256) void k_combine(CombineArgs a) {
-    int64_t e1 = a.hi[1] - a.lo[1], e2 = a.hi[2] - a.lo[2];
-    int64_t total = (a.hi[0] - a.lo[0]) * e1 * e2;
-    for (int64_t f = (int64_t)blockIdx.x * 256 + threadIdx.x; f < total; f += (int64_t)gridDim.x * 256) {
-        int64_t i2 = f % e2, r = f / e2;
-        int64_t i1 = r % e1, i0 = r / e1;
-        int64_t g[3] = {a.lo[0] + i0, a.lo[1] + i1, a.lo[2] + i2};
-        LT_GLOBAL T *tp = gp<T>(a.target.base) + g[0] * a.target.s[0] + g[1] * a.target.s[1] +
-                g[2] * a.target.s[2];
-        T acc = a.accumulate ? *tp : identity<T>(a.op);
-        for (int p = 0; p < a.nparts; ++p) {
-            const CombinePart &q = a.parts[p];
-            bool in = true;
-            for (int x = 0; x < a.ndim; ++x)
-                if (g[x] < q.lo[x] || g[x] >= q.hi[x]) in = false;
-            if (!in) continue;
-            int64_t s1 = a.ndim > 2 ? q.hi[2] - q.lo[2] : 1;
-            int64_t s0 = a.ndim > 1 ? (q.hi[1] - q.lo[1]) * s1 : 1;
-            int64_t off = (g[0] - q.lo[0]) * s0;
-            if (a.ndim > 1) off += (g[1] - q.lo[1]) * s1;
-            if (a.ndim > 2) off += g[2] - q.lo[2];
-            acc = rop<T>(a.op, acc, gp<const T>(a.part_base)[q.off + off]);
-        }
-        *tp = acc;
-    }
-}
-
-hipError_t launch_combine(hipStream_t s, const CombineArgs &a) {
-    int64_t total = 1;
-    for (int x = 0; x < KMAXD; ++x) total *= (a.hi[x] - a.lo[x]);
-    if (total <= 0) return hipSuccess;
-    unsigned blocks = (unsigned)std::min<int64_t>((total + 255) / 256, 4096);
-    switch (a.dtype) {
-        case 0: hipLaunchKernelGGL(k_combine<float>, dim3(blocks), dim3(256), 0, s, a); break;
-        case 1: hipLaunchKernelGGL(k_combine<int32_t>, dim3(blocks), dim3(256), 0, s, a); break;
-        case 2: hipLaunchKernelGGL(k_combine<double>, dim3(blocks), dim3(256), 0, s, a); break;
-        case 3: hipLaunchKernelGGL(k_combine<int64_t>, dim3(blocks), dim3(256), 0, s, a); break;
-        default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }

@@ -129,6 +129,9 @@ struct KernelDef {
     KernelFn fn;            // host launcher
     int max_group;          // tasks per grouped dispatch
     int dkind;              // body id in the batch drain (DK_*), -1 = not batchable
+    // partial slots per task of a reduce parameter (nullptr = 1): a body that
+    // folds floats over several workgroups writes one partial per workgroup
+    int64_t (*slots)(const int64_t *lo, const int64_t *hi, const int64_t *iarg);
 };
 
 const KernelDef *find_builtin(const char *name);
@@ -337,6 +340,7 @@ struct Batch {
     int64_t part_bytes = 0;
     int nsignals = 0;
     int64_t tiles = 0;
+    uint32_t kinds = 0;                // bit k set: a task of body DK k is queued
     std::vector<ChunkUse> uses;
     Fence wait;                        // dependencies issued before the batch
 };

@@ -1,0 +1,82 @@
+"""CPU (dry-run) tests of the planner for float reductions.
+
+A body that spreads one superblock over several workgroups gets one partial
+slot per workgroup; the planner sizes the partials accordingly and folds
+them with a slot fold and a combine per reduce argument.  No device work.
+"""
+import numpy as np
+import pytest
+
+import paper_2202_05549_amd as L
+
+
+def dry(**kw):
+    kw.setdefault("device_budget_bytes", 1 << 30)
+    kw.setdefault("trace", 1)
+    return L.Context(dry_run=1, **kw)
+
+
+def _kmu_slots(points, tile=4096, cap=1024):
+    return max(1, min(cap, -(-points // tile)))
+
+
+@pytest.mark.parametrize("N,sb", [(300000, 65536), (777, 256), (20000, 1 << 20)])
+def test_kmeans_update_plan(N, sb):
+    d, K = 16, 64
+    with dry() as ctx:
+        x = ctx.array([N, d])
+        lb = ctx.array([N], np.int32)
+        sums = ctx.array([K, d], np.float64)
+        counts = ctx.array([K], np.int32)
+        lid = ctx.launch("kmeans_update_f32", [N], [1], [sb], args=[N, d, K, sums, counts, x, lb])
+        tasks = ctx.tasks(lid)
+        ex = [t for t in tasks if t.kind == L.LT_TASK_EXEC]
+        comb = [t for t in tasks if t.kind == L.LT_TASK_COMBINE]
+        nsb = -(-N // sb)
+        assert len(ex) == nsb and len(comb) == 2  # one combine per reduce argument
+        # each combine waits for every superblock task
+        for c in comb:
+            assert set(ctx.deps(c.id)) >= {t.id for t in ex}
+        # partial bytes: slots x (K d float64 + K int32) per task; the fills
+        # of the two partial blocks appear in the trace with their sizes
+        want = [0, 0]
+        for t in ex:
+            s = _kmu_slots(min(t.sb_hi[0], N) - t.sb_lo[0])
+            want[0] += s * K * d * 8
+            want[1] += s * K * 4
+        fills = [op for op in ctx.trace() if op.kind == 4]
+        got = sorted(int(f.bytes) for f in fills)
+        assert got == sorted((w + 255) // 256 * 256 for w in want)
+        ctx.sync()
+
+
+def test_float_slots_refused_inside_a_batch():
+    N, d, K = 50000, 16, 64
+    with dry() as ctx:
+        x = ctx.array([N, d])
+        lb = ctx.array([N], np.int32)
+        sums = ctx.array([K, d], np.float64)
+        counts = ctx.array([K], np.int32)
+        ctx.batch_begin()
+        with pytest.raises(L.LtError) as e:
+            ctx.launch("kmeans_update_f32", [N], [1], [N], args=[N, d, K, sums, counts, x, lb])
+        assert e.value.status == L.LT_ERR_UNSUPPORTED
+        ctx.batch_end()
+
+
+def test_rowreduce_partials_per_column_superblock():
+    n, m = 300, 5000
+    with dry() as ctx:
+        a = ctx.array([n, m])
+        out = ctx.array([n])
+        lid = ctx.launch("rowreduce_f32", [n, m], [1, 64], [64, 2048], args=[n, m, out, a],
+                         kernel_annotation="global [i, j] => read A[i, j], reduce(min) out[i]")
+        tasks = ctx.tasks(lid)
+        ex = [t for t in tasks if t.kind == L.LT_TASK_EXEC]
+        assert len(ex) == 5 * 3
+        # every task's partial is its own rows of out
+        for t in ex:
+            regs = ctx.regions(t.id)
+            r = [g for g in regs if g.arg == 2][0]
+            assert (r.lo[0], r.hi[0]) == (t.sb_lo[0], min(t.sb_hi[0], n))
+        ctx.sync()
