@@ -371,24 +371,112 @@ __device__ __forceinline__ void kmu_step(double *acc, int *cnt, int d, int q, in
     }
 }
 
+// The task's fields, copied to registers once: the compiler barrier between
+// rounds would otherwise make it re-read them from memory at every step.
+struct KUReg {
+    int64_t lo, hi, xs, sslot, cslot, ss0, ss1, cs0;
+    const LT_GLOBAL float *X;
+    const LT_GLOBAL int32_t *LB;
+    LT_GLOBAL double *S;
+    LT_GLOBAL int32_t *C;
+    int nslots;
+};
+
+__device__ __forceinline__ KUReg kmu_regs(const KUTask &t) {
+    KUReg r;
+    r.lo = t.lo;
+    r.hi = t.hi;
+    r.xs = t.xs;
+    r.sslot = t.sslot;
+    r.cslot = t.cslot;
+    r.ss0 = t.ss0;
+    r.ss1 = t.ss1;
+    r.cs0 = t.cs0;
+    r.X = gp<const float>(t.x);
+    r.LB = gp<const int32_t>(t.lab);
+    r.S = gp<double>(t.sums);
+    r.C = gp<int32_t>(t.counts);
+    r.nslots = t.nslots;
+    return r;
+}
+
+__device__ __forceinline__ void kmu_clear(double *lds, int KD, int K) {
+    int *cnt_all = reinterpret_cast<int *>(lds + 4 * KD);
+    for (int i = threadIdx.x; i < 4 * KD; i += 256) lds[i] = 0.0;
+    for (int i = threadIdx.x; i < 4 * K; i += 256) cnt_all[i] = 0;
+    __syncthreads();
+}
+
+// Adds the four wave copies in wave order and writes partial slot w.
+__device__ __forceinline__ void kmu_flush(const double *lds, int d, int K, const KUReg &t, int w) {
+    const int KD = K * d;
+    const int *cnt_all = reinterpret_cast<const int *>(lds + 4 * KD);
+    __syncthreads();
+    LT_GLOBAL double *S = t.S + (int64_t)w * t.sslot;
+    for (int e = threadIdx.x; e < KD; e += 256) {
+        double s = lds[e];
+        s += lds[KD + e];
+        s += lds[2 * KD + e];
+        s += lds[3 * KD + e];
+        const int k = e / d, jj = e - (e / d) * d;
+        S[k * t.ss0 + jj * t.ss1] = s;
+    }
+    LT_GLOBAL int32_t *Cn = t.C + (int64_t)w * t.cslot;
+    for (int k = threadIdx.x; k < K; k += 256)
+        Cn[k * t.cs0] = cnt_all[k] + cnt_all[K + k] + cnt_all[2 * K + k] + cnt_all[3 * K + k];
+}
+
+// Rank of this lane's point among the step's P points (earlier points with
+// the same cluster) and the largest rank of the step; point q2 of the step
+// is held by lane q2 * LP.
+template <int LP>
+__device__ __forceinline__ void kmu_rank(int k, int q, int &rank, int &mr) {
+    constexpr int P = 64 / LP;
+    rank = 0;
+    mr = 0;
+    if constexpr (P <= 16) {
+#pragma unroll
+        for (int q2 = 0; q2 < P; ++q2) {
+            const int k2 = __builtin_amdgcn_readlane(k, q2 * LP);
+            rank += (q2 < q && k2 == k) ? 1 : 0;
+        }
+#pragma unroll
+        for (int q2 = 0; q2 < P; ++q2) {
+            const int r2 = __builtin_amdgcn_readlane(rank, q2 * LP);
+            const int k2 = __builtin_amdgcn_readlane(k, q2 * LP);
+            if (k2 >= 0 && r2 > mr) mr = r2;
+        }
+    } else {
+        // many points per step (d <= 2): rolled loops keep the scalar
+        // registers in bounds
+#pragma unroll 1
+        for (int q2 = 0; q2 < P; ++q2) {
+            const int k2 = __builtin_amdgcn_readlane(k, q2 * LP);
+            rank += (q2 < q && k2 == k) ? 1 : 0;
+        }
+#pragma unroll 1
+        for (int q2 = 0; q2 < P; ++q2) {
+            const int r2 = __builtin_amdgcn_readlane(rank, q2 * LP);
+            const int k2 = __builtin_amdgcn_readlane(k, q2 * LP);
+            if (k2 >= 0 && r2 > mr) mr = r2;
+        }
+    }
+}
+
+// Any d: one feature per lane (DP lanes per point).
 template <int DP>
 __global__ __launch_bounds__(256) void k_kmeans_update(KUArgs a) {
     constexpr int P = 64 / DP;
     extern __shared__ double lds[];
     const int ti = find_task(a.begin, a.ntask, blockIdx.x);
-    const KUTask &t = a.t[ti];
+    const KUReg t = kmu_regs(a.t[ti]);
     const int w = blockIdx.x - a.begin[ti];
     const int d = a.d, K = a.K, KD = K * d;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    int *cnt_all = reinterpret_cast<int *>(lds + 4 * KD);
-    for (int i = threadIdx.x; i < 4 * KD; i += 256) lds[i] = 0.0;
-    for (int i = threadIdx.x; i < 4 * K; i += 256) cnt_all[i] = 0;
-    __syncthreads();
+    kmu_clear(lds, KD, K);
     double *acc = lds + wave * KD;
-    int *cnt = cnt_all + wave * K;
+    int *cnt = reinterpret_cast<int *>(lds + 4 * KD) + wave * K;
     const int q = lane / DP, j = lane % DP;
-    const LT_GLOBAL float *X = gp<const float>(t.x);
-    const LT_GLOBAL int32_t *LB = gp<const int32_t>(t.lab);
     constexpr int64_t QUARTER = KMU_TILE / 4;
     constexpr int64_t BATCH = (int64_t)KMU_U * P;
     for (int64_t tile = w; t.lo + tile * KMU_TILE < t.hi; tile += t.nslots) {
@@ -397,10 +485,10 @@ __global__ __launch_bounds__(256) void k_kmeans_update(KUArgs a) {
         if (p0 >= p1) continue;
         float xv[KMU_U], xn[KMU_U];
         int kv[KMU_U], kn[KMU_U];
-        kmu_load<DP>(X, t.xs, LB, p0, p1, q, j, d, K, xv, kv);
+        kmu_load<DP>(t.X, t.xs, t.LB, p0, p1, q, j, d, K, xv, kv);
         for (int64_t pb = p0; pb < p1; pb += BATCH) {
             const bool more = pb + BATCH < p1;
-            if (more) kmu_load<DP>(X, t.xs, LB, pb + BATCH, p1, q, j, d, K, xn, kn);
+            if (more) kmu_load<DP>(t.X, t.xs, t.LB, pb + BATCH, p1, q, j, d, K, xn, kn);
 #pragma unroll
             for (int u = 0; u < KMU_U; ++u) kmu_step<DP>(acc, cnt, d, q, j, xv[u], kv[u]);
             if (more) {
@@ -412,19 +500,92 @@ __global__ __launch_bounds__(256) void k_kmeans_update(KUArgs a) {
             }
         }
     }
-    __syncthreads();
-    LT_GLOBAL double *S = gp<double>(t.sums) + (int64_t)w * t.sslot;
-    for (int e = threadIdx.x; e < KD; e += 256) {
-        double s = lds[e];
-        s += lds[KD + e];
-        s += lds[2 * KD + e];
-        s += lds[3 * KD + e];
-        const int k = e / d, jj = e - (e / d) * d;
-        S[k * t.ss0 + jj * t.ss1] = s;
+    kmu_flush(lds, d, K, t, w);
+}
+
+// d = VD in {4, 8, 16, 32} with dense, 16-byte aligned rows: lane l holds
+// features 4c .. 4c+3 (c = l % LP, LP = VD / 4) of point l / LP, so one
+// 16-byte load per lane brings 64 / LP whole points; the additions per
+// element are the same as in the one-feature-per-lane body.
+constexpr int KMV_U = 4;  // steps per load batch; two batches are in flight
+
+template <int VD>
+__device__ __forceinline__ void kmv_load(const KUReg &t, int64_t pb, int64_t p1, int lane, int q, int K, bool full,
+                                         float4 *xv, int *kv) {
+    constexpr int LP = VD / 4, P = 64 / LP;
+#pragma unroll
+    for (int u = 0; u < KMV_U; ++u) {
+        const int64_t pu = pb + (int64_t)u * P;
+        const int64_t p = pu + q;
+        int k;
+        if (full) {
+            xv[u] = ld4<float4>(t.X + pu * VD + 4 * lane);
+            k = t.LB[p];
+        } else {
+            const bool act = p < p1;
+            xv[u] = act ? ld4<float4>(t.X + pu * VD + 4 * lane) : make_float4(0.f, 0.f, 0.f, 0.f);
+            k = act ? t.LB[p] : -1;
+        }
+        kv[u] = (k >= 0 && k < K) ? k : -1;
     }
-    LT_GLOBAL int32_t *Cn = gp<int32_t>(t.counts) + (int64_t)w * t.cslot;
-    for (int k = threadIdx.x; k < K; k += 256)
-        Cn[k * t.cs0] = cnt_all[k] + cnt_all[K + k] + cnt_all[2 * K + k] + cnt_all[3 * K + k];
+}
+
+template <int VD>
+__device__ __forceinline__ void kmv_step(double *acc, int *cnt, int q, int c, float4 x, int k) {
+    constexpr int LP = VD / 4;
+    int rank, mr;
+    kmu_rank<LP>(k, q, rank, mr);
+    for (int r = 0; r <= mr; ++r) {
+        if (k >= 0 && rank == r) {
+            double *e = acc + k * VD + 4 * c;
+            e[0] += (double)x.x;
+            e[1] += (double)x.y;
+            e[2] += (double)x.z;
+            e[3] += (double)x.w;
+            if (c == 0) cnt[k] += 1;
+        }
+        asm volatile("" ::: "memory");
+    }
+}
+
+template <int VD>
+__global__ __launch_bounds__(256) void k_kmeans_update_v(KUArgs a) {
+    constexpr int LP = VD / 4, P = 64 / LP;
+    extern __shared__ double lds[];
+    const int ti = find_task(a.begin, a.ntask, blockIdx.x);
+    const KUReg t = kmu_regs(a.t[ti]);
+    const int w = blockIdx.x - a.begin[ti];
+    const int K = a.K, KD = K * VD;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    kmu_clear(lds, KD, K);
+    double *acc = lds + wave * KD;
+    int *cnt = reinterpret_cast<int *>(lds + 4 * KD) + wave * K;
+    const int q = lane / LP, c = lane % LP;
+    constexpr int64_t QUARTER = KMU_TILE / 4;
+    constexpr int64_t BATCH = (int64_t)KMV_U * P;
+    for (int64_t tile = w; t.lo + tile * KMU_TILE < t.hi; tile += t.nslots) {
+        const int64_t p0 = t.lo + tile * KMU_TILE + wave * QUARTER;
+        const int64_t p1 = p0 + QUARTER < t.hi ? p0 + QUARTER : t.hi;
+        if (p0 >= p1) continue;
+        float4 xv[KMV_U], xn[KMV_U];
+        int kv[KMV_U], kn[KMV_U];
+        kmv_load<VD>(t, p0, p1, lane, q, K, p0 + BATCH <= p1, xv, kv);
+        for (int64_t pb = p0; pb < p1; pb += BATCH) {
+            const int64_t nb = pb + BATCH;
+            const bool more = nb < p1;
+            if (more) kmv_load<VD>(t, nb, p1, lane, q, K, nb + BATCH <= p1, xn, kn);
+#pragma unroll
+            for (int u = 0; u < KMV_U; ++u) kmv_step<VD>(acc, cnt, q, c, xv[u], kv[u]);
+            if (more) {
+#pragma unroll
+                for (int u = 0; u < KMV_U; ++u) {
+                    xv[u] = xn[u];
+                    kv[u] = kn[u];
+                }
+            }
+        }
+    }
+    kmu_flush(lds, VD, K, t, w);
 }
 
 hipError_t launch_kmeans_update_f32(const KLaunch &L) {
@@ -465,6 +626,18 @@ hipError_t launch_kmeans_update_f32(const KLaunch &L) {
     if (nb == 0) return hipSuccess;
     const size_t lds = (size_t)4 * a.K * a.d * sizeof(double) + (size_t)4 * a.K * sizeof(int);
     const dim3 g((unsigned)nb), b(256);
+    bool vec = a.d == a.dp && a.d >= 4;  // d in {4, 8, 16, 32}
+    for (int i = 0; i < L.ntask && vec; ++i)
+        vec = a.t[i].xs == a.d && a.t[i].x % 16 == 0 && (a.t[i].lo * a.d * 4) % 16 == 0;
+    if (vec) {
+        switch (a.d) {
+            case 4: hipLaunchKernelGGL(k_kmeans_update_v<4>, g, b, lds, L.stream, a); break;
+            case 8: hipLaunchKernelGGL(k_kmeans_update_v<8>, g, b, lds, L.stream, a); break;
+            case 16: hipLaunchKernelGGL(k_kmeans_update_v<16>, g, b, lds, L.stream, a); break;
+            default: hipLaunchKernelGGL(k_kmeans_update_v<32>, g, b, lds, L.stream, a); break;
+        }
+        return hipGetLastError();
+    }
     switch (a.dp) {
         case 1: hipLaunchKernelGGL(k_kmeans_update<1>, g, b, lds, L.stream, a); break;
         case 2: hipLaunchKernelGGL(k_kmeans_update<2>, g, b, lds, L.stream, a); break;

@@ -150,7 +150,9 @@ def _update(L, ctx, X, lab, K, sb, chunk=None):
 
 
 @pytest.mark.parametrize("N,d,K,sb", [(312345, 16, 64, 65536), (100000, 3, 5, 100000), (50001, 32, 48, 4096),
-                                      (20000, 16, 96, 1 << 20), (777, 4, 40, 256)])
+                                      (20000, 16, 96, 1 << 20), (777, 4, 40, 256), (30001, 1, 7, 8192),
+                                      (30001, 2, 256, 8192), (40000, 5, 33, 16384), (40000, 12, 100, 16383),
+                                      (9000, 8, 64, 1000)])
 def test_kmeans_update_against_oracle(L, N, d, K, sb):
     say("kmeans update", N, d, K, sb)
     X, _, z = synthetic.kmeans_blobs(N, d, K, seed=12)
