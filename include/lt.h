@@ -487,7 +487,9 @@ lt_status lt_trace_clear(lt_context *ctx);
 /* ----------------------------------------------------------------- profile
  * With profiling on, every kernel dispatch is bracketed by timing events on
  * the stream it runs on; durations are summed per built-in body and collected
- * at lt_sync.  Meant for measurement runs (the events add a little overhead).
+ * at lt_sync.  Batch drains are entered as "drain" and graph replays as
+ * "graph" (the whole replay).  Meant for measurement runs (the events add a
+ * little overhead).
  */
 typedef struct lt_kernel_prof {
     char name[32];

@@ -801,8 +801,13 @@ lt_status graph_launch(Ctx *ctx, lt_graph *g) {
     wait.merge(task_fence(ctx, rec.deps));
     st = stream_wait(ctx, g->stream, wait);
     if (st) return st;
+    hipEvent_t pa;
+    st = prof_begin(ctx, g->stream, "graph", &pa);
+    if (st) return st;
     hipError_t r = hipGraphLaunch(g->exec, ctx->streams[g->stream].h);
     if (r != hipSuccess) return hip_fail(ctx, r, "hipGraphLaunch");
+    st = prof_end(ctx, g->stream, "graph", pa);
+    if (st) return st;
     ctx->stats.dispatches++;
     uint64_t p = bump(ctx, g->stream);
     g->last = p;
