@@ -145,7 +145,9 @@ def jacobi_run(L, torch, x0, executor, steps, warmup, rows=None):
 
         for _ in range(warmup):
             step()
-        ctx.profile(executor != "plain")  # plain: per-dispatch events would slow the host path
+        # HIP events on every 10th dispatch (grouped: one per sweep) during the
+        # timed steps; plain: per-task events would slow its host path
+        ctx.profile(executor != "plain", every=10 if executor == "grouped" else 1)
         ctx.profile_reset()
         ctx.reset_stats()
         torch.cuda.synchronize()
@@ -264,6 +266,10 @@ def bench_stencil1d(args, L, torch):
         steps = max(args.steps, 200)
         for _ in range(max(args.warmup, 10)):
             step()
+        # HIP events on one dispatch per step (plain: every 8th of the 8
+        # per-task dispatches) during the timed steps
+        ctx.profile(True, every=8 if ex == "plain" else 1)
+        ctx.profile_reset()
         times = []
         t0 = time.perf_counter()
         for _ in range(steps):
@@ -271,12 +277,6 @@ def bench_stencil1d(args, L, torch):
             step()
             times.append(time.perf_counter() - s0)
         total = time.perf_counter() - t0
-        # kernel durations from separate profiled steps (the timing events
-        # would add host work to the launches timed above)
-        ctx.profile(True)
-        ctx.profile_reset()
-        for _ in range(steps):
-            step()
         prof = ctx.profile_get()
         ctx.close()
         del arena
@@ -287,7 +287,7 @@ def bench_stencil1d(args, L, torch):
         res[ex] = {"gbs": n * 8 / (total / steps) / 1e9, "us_per_launch": total / steps * 1e6,
                    "p50_us": pct(times, 50) * 1e3, "p99_us": pct(times, 99) * 1e3,
                    "kernel_gbs": per_dispatch / (avg_ms * 1e-3) / 1e9, "kernel_avg_us": avg_ms * 1e3,
-                   "dispatches_per_launch": k["dispatches"] / steps, "steps": steps}
+                   "dispatches_per_launch": {"plain": 8, "grouped": 1, "drain": 1}[ex], "steps": steps}
         log("%s: %s" % (ex, json.dumps(res[ex])))
     m = res["plain"]
     line = base_line({"workload": "stencil1d 2^20 f32 ~U(-1,1) seed 0, 8 chunks of 2^17, one launch per step, "

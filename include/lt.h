@@ -261,7 +261,9 @@ lt_status lt_kernel_define(lt_context *ctx, const char *base,
 /* Selects a tuning variant of a built-in body for later launches through
  * this handle (0 = default).  Variants change only the work mapping, never
  * the per-element arithmetic: jacobi2d_f32 takes 8, 16 or 32 rows per
- * workgroup tile.  Unknown variants fall back to the default. */
+ * workgroup tile, all loaded at once, or 132, 164 or 228 for tiles of 32, 64
+ * or 128 rows marched in groups of 8 (each input row loaded once per tile).
+ * Unknown variants fall back to the default (16). */
 lt_status lt_kernel_tune(lt_context *ctx, lt_kernel *k, int32_t variant);
 
 /* ------------------------------------------------------------------- launch */
@@ -489,7 +491,9 @@ lt_status lt_trace_clear(lt_context *ctx);
  * the stream it runs on; durations are summed per built-in body and collected
  * at lt_sync.  Batch drains are entered as "drain" and graph replays as
  * "graph" (the whole replay).  Meant for measurement runs (the events add a
- * little overhead).
+ * little overhead).  lt_profile_enable(ctx, k): 0 off, 1 every dispatch, k > 1
+ * every k-th dispatch of each body (a sample with 1/k of the overhead; the
+ * returned counts and totals cover the sampled dispatches).
  */
 typedef struct lt_kernel_prof {
     char name[32];

@@ -844,8 +844,9 @@ lt_status lt_trace_get(lt_context *ctx, lt_trace_rec *out, uint64_t cap, uint64_
 }
 
 lt_status lt_profile_enable(lt_context *ctx, int32_t on) {
-    if (!ctx) return LT_ERR_INVALID;
-    ctx->prof = on != 0;
+    if (!ctx || on < 0) return LT_ERR_INVALID;
+    ctx->prof = on;
+    ctx->prof_seen.clear();
     return LT_OK;
 }
 
@@ -863,6 +864,7 @@ lt_status lt_profile_get(lt_context *ctx, lt_kernel_prof *out, int32_t cap, int3
 lt_status lt_profile_reset(lt_context *ctx) {
     if (!ctx) return LT_ERR_INVALID;
     ctx->prof_acc.clear();
+    ctx->prof_seen.clear();
     return LT_OK;
 }
 

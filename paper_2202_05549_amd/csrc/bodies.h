@@ -311,6 +311,63 @@ __device__ __forceinline__ void jacobi_tile(const JView &t, int64_t n, int64_t m
     }
 }
 
+// Rows [tr0, tr0 + 8 NG) of the 1024-column tile txi, marched down in groups
+// of 8 rows: the two rows above a group are carried over in registers from
+// the group before, so each input row is loaded once per tile and only the
+// tile's first group reads a halo row above it (plus one below the last).
+// A group's 8 loads per lane are issued together before its arithmetic.
+// Ragged tiles fall back to jacobi_tile per group.
+template <int NG>
+__device__ __forceinline__ void jacobi_march(const JView &t, int64_t n, int64_t m, int64_t tr0, int txi) {
+    constexpr int RB = 8;
+    const int64_t rend = t.r1 < n ? t.r1 : n;
+    const int64_t r1 = tr0 + RB * NG < rend ? tr0 + RB * NG : rend;
+    if (!t.vec || r1 - tr0 != RB * NG) {
+        for (int g = 0; g < NG; ++g) {
+            if (tr0 + g * RB >= rend) break;
+            jacobi_tile<RB>(t, n, m, tr0 + g * RB, txi);
+        }
+        return;
+    }
+    const int64_t cend = t.c1 < m ? t.c1 : m;
+    const int64_t col = t.c0 + ((int64_t)txi * THREADS + threadIdx.x) * 4;
+    const bool active = col < cend;
+    const LT_GLOBAL float *X = gp<const float>(t.x);
+    LT_GLOBAL float *Y = gp<float>(t.y);
+    const int lane = threadIdx.x & (WAVE - 1);
+    auto load = [&](int64_t r) {
+        return (active && r >= 0 && r < n) ? ld4<float4>(X + r * t.xs + col) : make_float4(0.f, 0.f, 0.f, 0.f);
+    };
+    float4 v[RB + 2];
+    v[0] = load(tr0 - 1);
+    v[1] = load(tr0);
+    for (int g = 0; g < NG; ++g) {
+        const int64_t rb = tr0 + (int64_t)g * RB;
+#pragma unroll
+        for (int i = 0; i < RB; ++i) v[i + 2] = load(rb + 1 + i);
+#pragma unroll
+        for (int i = 1; i <= RB; ++i) {
+            const int64_t r = rb - 1 + i;
+            const float4 up = v[i - 1], mid = v[i], dn = v[i + 1];
+            float left = __shfl_up(mid.w, 1);
+            float right = __shfl_down(mid.x, 1);
+            const LT_GLOBAL float *row = X + r * t.xs;
+            if (active && lane == 0) left = (col - 1 >= 0) ? row[col - 1] : 0.f;
+            if (active && (lane == WAVE - 1 || col + 4 >= cend)) right = (col + 4 < m) ? row[col + 4] : 0.f;
+            if (active) {
+                float4 o;
+                o.x = jpoint(up.x, dn.x, left, mid.y);
+                o.y = jpoint(up.y, dn.y, mid.x, mid.z);
+                o.z = jpoint(up.z, dn.z, mid.y, mid.w);
+                o.w = jpoint(up.w, dn.w, mid.z, right);
+                nt_store4(Y + r * t.ys + col, o);
+            }
+        }
+        v[0] = v[RB];
+        v[1] = v[RB + 1];
+    }
+}
+
 // ---------------------------------------------------------------- hist256
 // Counts v[i] into the wave's LDS sub-histogram sh[wave] for the 4096-element
 // chunks of [s0, s1) that start at s0, s0 + stride, s0 + 2*stride, ...;

@@ -170,9 +170,9 @@ static hipEvent_t prof_event(Ctx *ctx) {
 }
 
 lt_status prof_begin(Ctx *ctx, int s, const char *name, hipEvent_t *a) {
-    (void)name;
     *a = nullptr;
     if (!ctx->prof || ctx->dry) return LT_OK;
+    if (ctx->prof > 1 && ctx->prof_seen[name]++ % (uint64_t)ctx->prof != 0) return LT_OK;  // sampled
     *a = prof_event(ctx);
     hipError_t r = hipEventRecord(*a, ctx->streams[s].h);
     if (r != hipSuccess) return hip_fail(ctx, r, "hipEventRecord(profile)");

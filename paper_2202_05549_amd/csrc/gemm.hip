@@ -45,27 +45,23 @@ struct GArgs {
 
 }  // namespace
 
-__global__ __launch_bounds__(256, 1) void k_gemm(GArgs g) {
-    __shared__ float As[2][BK][LDA];
-    __shared__ float Bs[2][BK][LDB];
+// The fields of one task, held in registers for the whole block.
+struct GReg {
+    int64_t i1, j1, as, bs, cs, K;
+    const LT_GLOBAL float *A;
+    const LT_GLOBAL float *B;
+    LT_GLOBAL float *C;
+};
 
-    const int b = body::xcd_remap(blockIdx.x, g.nblocks);
-    const int ti = body::find_task(g.begin, g.ntask, b);
-    const GTask &t = g.t[ti];
-    const int local = b - g.begin[ti];
-    const int tmi = local / t.tn, tni = local - tmi * t.tn;
-    const int64_t m0 = t.i0 + (int64_t)tmi * BM;
-    const int64_t n0 = t.j0 + (int64_t)tni * BN;
-    const int64_t K = g.K;
-    // global-address-space pointers: global (not flat) loads do not hold up
-    // the LDS reads that feed the matrix cores
-    const LT_GLOBAL float *A = body::gp<const float>(t.a);
-    const LT_GLOBAL float *B = body::gp<const float>(t.b);
-    LT_GLOBAL float *C = body::gp<float>(t.c);
-
+// One 256 x 256 block of C.  FULL: the block lies inside the matrix, K is a
+// multiple of 32 and 16-byte loads are usable, so the loads carry no guards.
+template <bool FULL>
+__device__ __forceinline__ void gemm_block(const GReg &t, int64_t m0, int64_t n0, float (*As)[BK][LDA],
+                                           float (*Bs)[BK][LDB], int vec) {
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
     const int wm = (wave >> 1) * 128, wn = (wave & 1) * 128;
+    const int64_t K = t.K;
 
     // global -> register staging of one K tile
     // A: thread covers rows tid/8 + 32*j, k4 = tid%8 (8 float4)
@@ -73,30 +69,39 @@ __global__ __launch_bounds__(256, 1) void k_gemm(GArgs g) {
     float4 ra[8], rb[8];
     const int a_row = tid >> 3, a_k4 = tid & 7;
     const int b_k = tid >> 6, b_n4 = tid & 63;
+    const LT_GLOBAL float *Ab = t.A + (m0 + a_row) * t.as + a_k4 * 4;
+    const LT_GLOBAL float *Bb = t.B + (int64_t)b_k * t.bs + n0 + b_n4 * 4;
 
     auto load_tile = [&](int64_t k0) {
+        if constexpr (FULL) {
 #pragma unroll
-        for (int j = 0; j < 8; ++j) {
-            const int64_t r = m0 + a_row + 32 * j;
-            const int64_t k = k0 + a_k4 * 4;
-            if (t.vec && r < t.i1 && k + 3 < K) {
-                ra[j] = body::ld4<float4>(A + r * t.as + k);
-            } else {
-                float v[4];
-                for (int q = 0; q < 4; ++q) v[q] = (r < t.i1 && k + q < K) ? A[r * t.as + k + q] : 0.f;
-                ra[j] = make_float4(v[0], v[1], v[2], v[3]);
+            for (int j = 0; j < 8; ++j) ra[j] = body::ld4<float4>(Ab + 32 * j * t.as + k0);
+#pragma unroll
+            for (int j = 0; j < 8; ++j) rb[j] = body::ld4<float4>(Bb + (k0 + 4 * j) * t.bs);
+        } else {
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const int64_t r = m0 + a_row + 32 * j;
+                const int64_t k = k0 + a_k4 * 4;
+                if (vec && r < t.i1 && k + 3 < K) {
+                    ra[j] = body::ld4<float4>(t.A + r * t.as + k);
+                } else {
+                    float v[4];
+                    for (int q = 0; q < 4; ++q) v[q] = (r < t.i1 && k + q < K) ? t.A[r * t.as + k + q] : 0.f;
+                    ra[j] = make_float4(v[0], v[1], v[2], v[3]);
+                }
             }
-        }
 #pragma unroll
-        for (int j = 0; j < 8; ++j) {
-            const int64_t k = k0 + b_k + 4 * j;
-            const int64_t c = n0 + b_n4 * 4;
-            if (t.vec && k < K && c + 3 < t.j1) {
-                rb[j] = body::ld4<float4>(B + k * t.bs + c);
-            } else {
-                float v[4];
-                for (int q = 0; q < 4; ++q) v[q] = (k < K && c + q < t.j1) ? B[k * t.bs + c + q] : 0.f;
-                rb[j] = make_float4(v[0], v[1], v[2], v[3]);
+            for (int j = 0; j < 8; ++j) {
+                const int64_t k = k0 + b_k + 4 * j;
+                const int64_t c = n0 + b_n4 * 4;
+                if (vec && k < K && c + 3 < t.j1) {
+                    rb[j] = body::ld4<float4>(t.B + k * t.bs + c);
+                } else {
+                    float v[4];
+                    for (int q = 0; q < 4; ++q) v[q] = (k < K && c + q < t.j1) ? t.B[k * t.bs + c + q] : 0.f;
+                    rb[j] = make_float4(v[0], v[1], v[2], v[3]);
+                }
             }
         }
     };
@@ -130,22 +135,31 @@ __global__ __launch_bounds__(256, 1) void k_gemm(GArgs g) {
         const int buf = kt & 1;
         const bool more = kt + 1 < nk;
         if (more) load_tile((int64_t)(kt + 1) * BK);
-        // the next tile goes into the other LDS buffer half-way through this
-        // one, so its stores overlap the matrix-core work
+        // fragments of k-step s + 1 are read from LDS before the matrix-core
+        // instructions of step s are issued, so their latency is hidden
+        float av[2][4], bv[2][4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) av[0][i] = As[buf][half][wm + 32 * i + l32];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) bv[0][j] = Bs[buf][half][wn + 32 * j + l32];
 #pragma unroll
         for (int s = 0; s < BK / 2; ++s) {
+            const int cur = s & 1;
+            if (s + 1 < BK / 2) {
+                const int k = 2 * (s + 1) + half;
+#pragma unroll
+                for (int i = 0; i < 4; ++i) av[cur ^ 1][i] = As[buf][k][wm + 32 * i + l32];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) bv[cur ^ 1][j] = Bs[buf][k][wn + 32 * j + l32];
+            }
+            // the next tile goes into the other LDS buffer half-way through
+            // this one, so its stores overlap the matrix-core work
             if (s == BK / 4 && more) store_tile(buf ^ 1);
-            const int k = 2 * s + half;
-            float av[4], bv[4];
-#pragma unroll
-            for (int i = 0; i < 4; ++i) av[i] = As[buf][k][wm + 32 * i + l32];
-#pragma unroll
-            for (int j = 0; j < 4; ++j) bv[j] = Bs[buf][k][wn + 32 * j + l32];
 #pragma unroll
             for (int i = 0; i < 4; ++i)
 #pragma unroll
                 for (int j = 0; j < 4; ++j)
-                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[i], bv[j], acc[i][j], 0, 0, 0);
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[cur][i], bv[cur][j], acc[i][j], 0, 0, 0);
         }
         __syncthreads();
     }
@@ -160,9 +174,39 @@ __global__ __launch_bounds__(256, 1) void k_gemm(GArgs g) {
 #pragma unroll
             for (int v = 0; v < 16; ++v) {
                 const int64_t row = m0 + wm + 32 * i + 8 * (v >> 2) + 4 * half + (v & 3);
-                if (row < t.i1 && col < t.j1) C[row * t.cs + col] = acc[i][j][v];
+                if (FULL || (row < t.i1 && col < t.j1)) t.C[row * t.cs + col] = acc[i][j][v];
             }
         }
+}
+
+__global__ __launch_bounds__(256, 1) void k_gemm(GArgs g) {
+    __shared__ float As[2][BK][LDA];
+    __shared__ float Bs[2][BK][LDB];
+
+    const int b = body::xcd_remap(blockIdx.x, g.nblocks);
+    const int ti = body::find_task(g.begin, g.ntask, b);
+    const GTask &tk = g.t[ti];
+    const int local = b - g.begin[ti];
+    const int tmi = local / tk.tn, tni = local - tmi * tk.tn;
+    const int64_t m0 = tk.i0 + (int64_t)tmi * BM;
+    const int64_t n0 = tk.j0 + (int64_t)tni * BN;
+    // global-address-space pointers: global (not flat) loads do not hold up
+    // the LDS reads that feed the matrix cores
+    GReg t;
+    t.i1 = tk.i1;
+    t.j1 = tk.j1;
+    t.as = tk.as;
+    t.bs = tk.bs;
+    t.cs = tk.cs;
+    t.K = g.K;
+    t.A = body::gp<const float>(tk.a);
+    t.B = body::gp<const float>(tk.b);
+    t.C = body::gp<float>(tk.c);
+    const int vec = tk.vec;
+    if (vec && m0 + BM <= t.i1 && n0 + BN <= t.j1 && t.K % BK == 0)
+        gemm_block<true>(t, m0, n0, As, Bs, vec);
+    else
+        gemm_block<false>(t, m0, n0, As, Bs, vec);
 }
 
 hipError_t launch_gemm_f32(const KLaunch &L) {

@@ -131,13 +131,26 @@ __global__ __launch_bounds__(256) void k_jacobi2d(JArgs a) {
     jacobi_tile<RB>(t.v, a.n, a.m, t.v.r0 + (int64_t)tyi * RB, txi);
 }
 
+// Marching tiles of 8 NG rows (jacobi_march).
+template <int NG>
+__global__ __launch_bounds__(256) void k_jacobi2d_march(JArgs a) {
+    const int b = xcd_remap(blockIdx.x, a.nblocks);
+    const int ti = find_task(a.begin, a.ntask, b);
+    const JTask &t = a.t[ti];
+    const int local = b - a.begin[ti];
+    const int tyi = local / t.tx, txi = local - tyi * t.tx;
+    jacobi_march<NG>(t.v, a.n, a.m, t.v.r0 + (int64_t)tyi * 8 * NG, txi);
+}
+
 hipError_t launch_jacobi2d_f32(const KLaunch &L) {
     JArgs a;
     a.n = L.iarg[0];
     a.m = L.iarg[1];
     a.ntask = L.ntask;
-    // rows per tile: 8, 16 (default) or 32
-    a.rows = (L.variant == 8 || L.variant == 32) ? L.variant : 16;
+    // rows per tile: 8, 16 (default) or 32 (all rows loaded at once), or 32,
+    // 64 or 128 marched in groups of 8 (variants 132, 164, 228: 100 + rows)
+    const bool march = L.variant == 132 || L.variant == 164 || L.variant == 228;
+    a.rows = march ? L.variant - 100 : (L.variant == 8 || L.variant == 32) ? L.variant : 16;
     int64_t nb = 0;
     for (int i = 0; i < L.ntask; ++i) {
         const KTask &k = L.tasks[i];
@@ -162,7 +175,14 @@ hipError_t launch_jacobi2d_f32(const KLaunch &L) {
     a.begin[L.ntask] = (int)nb;
     a.nblocks = (int)nb;
     if (nb == 0) return hipSuccess;
-    if (a.rows == 8)
+    if (march) {
+        if (a.rows == 32)
+            hipLaunchKernelGGL(k_jacobi2d_march<4>, dim3(grid_of(nb)), dim3(256), 0, L.stream, a);
+        else if (a.rows == 64)
+            hipLaunchKernelGGL(k_jacobi2d_march<8>, dim3(grid_of(nb)), dim3(256), 0, L.stream, a);
+        else
+            hipLaunchKernelGGL(k_jacobi2d_march<16>, dim3(grid_of(nb)), dim3(256), 0, L.stream, a);
+    } else if (a.rows == 8)
         hipLaunchKernelGGL(k_jacobi2d<8>, dim3(grid_of(nb)), dim3(256), 0, L.stream, a);
     else if (a.rows == 32)
         hipLaunchKernelGGL(k_jacobi2d<32>, dim3(grid_of(nb)), dim3(256), 0, L.stream, a);

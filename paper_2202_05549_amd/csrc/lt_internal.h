@@ -406,7 +406,8 @@ struct lt_context {
     int status_slots = 0, status_next = 0;
 
     // profiling: (kernel name, start, end) awaiting resolution
-    bool prof = false;
+    int prof = 0;                      // 0 off; k: every k-th dispatch of each body is timed
+    std::map<std::string, uint64_t> prof_seen;
     struct ProfPending {
         const char *name;
         hipEvent_t a, b;

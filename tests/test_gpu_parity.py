@@ -154,6 +154,29 @@ def test_jacobi_small_bit_exact(L, shape, chunk, sb, mode):
     assert np.array_equal(got, oracle.jacobi2d(x0, 5))
 
 
+@pytest.mark.parametrize("variant", [8, 16, 32, 132, 164, 228])
+@pytest.mark.parametrize("shape,chunk,sb", [((1000, 2051), (96, 0), (96, 0)), ((777, 1024), (0, 0), (256, 0)),
+                                            ((300, 4096), (128, 0), (128, 1024)), ((513, 515), (0, 0), (0, 0))])
+def test_jacobi_tile_variants_bit_exact(L, variant, shape, chunk, sb):
+    # every tiling of the body (rows loaded at once, or marched in groups of
+    # 8) gives the same bits, on full and ragged tiles
+    say("jacobi variant", variant, shape, chunk, sb)
+    n, m = shape
+    x0 = synthetic.jacobi2d_input(n, m, seed=11)
+    with ctx_of(L, exec_mode=1) as ctx:
+        ctx.tune("jacobi2d_f32", variant)
+        a = ctx.array([n, m], chunk=list(chunk))
+        b = ctx.array([n, m], chunk=list(chunk))
+        a.write(x0)
+        inp, out = a, b
+        for _ in range(3):
+            ctx.launch("jacobi2d_f32", [n, m], [1, 1], list(sb), args=[n, m, out, inp])
+            inp, out = out, inp
+        ctx.sync()
+        got = inp.read()
+    assert np.array_equal(got, oracle.jacobi2d(x0, 3))
+
+
 def test_jacobi_out_of_core_matches(L):
     n, m = 1024, 1024
     say("jacobi spill")
