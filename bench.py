@@ -313,7 +313,9 @@ def bench_gemm_ooc(args, L, torch):
     n, T = 65536, 4096
     steps = args.steps if args.steps_given else 1
     warmup = args.warmup if args.warmup_given else 0
-    ctx = L.Context(device_budget_bytes=16 << 30, stage_threshold_bytes=8 << 30, sb_order=L.LT_ORDER_SERPENTINE)
+    streams = args.compute_streams or 1
+    ctx = L.Context(device_budget_bytes=16 << 30, stage_threshold_bytes=8 << 30, sb_order=L.LT_ORDER_SERPENTINE,
+                    n_compute_streams=streams)
     try:
         log("allocating 48 GiB of pinned host memory")
         A = ctx.pinned((n, n))
@@ -354,7 +356,8 @@ def bench_gemm_ooc(args, L, torch):
     d2h = st["bytes_d2h"] / steps
     line = base_line({"workload": "out-of-core GEMM 65536^3 f32 ~N(0,1) seed 2, A/B/C in pinned host memory "
                                   "(48 GiB), device budget 16 GiB, 4096^2 superblocks in serpentine order",
-                      "executor": "plain", "stage_threshold_bytes": 8 << 30}, steps, warmup)
+                      "executor": "plain", "stage_threshold_bytes": 8 << 30, "compute_streams": streams},
+                     steps, warmup)
     line.update({"value": round(compulsory / wall / 1e9, 2), "unit": "GB/s", "ms_per_step": round(wall * 1e3, 2),
                  "dtype": "f32", "tflops_wall": round(flops / wall / 1e12, 2),
                  "mfma_frac_wall": round(flops / wall / 1e12 / MFMA_FP32_PEAK, 4),
@@ -603,6 +606,8 @@ def main():
     ap.add_argument("--rows", type=int, default=8, help="rows per Jacobi tile (8, 16, 32)")
     ap.add_argument("--executor", choices=["all", "grouped", "drain", "plain"], default="all",
                     help="jacobi: executors to run (all = grouped, drain and plain)")
+    ap.add_argument("--compute-streams", type=int, default=0,
+                    help="gemm_ooc: compute streams of the context (0 = 1)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one 1 GiB float32 device copy first (the reference kernel for HBM counter scaling)")
     ap.add_argument("--serve-full", action="store_true",
