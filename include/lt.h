@@ -146,12 +146,21 @@ const char *lt_last_error(lt_context *ctx);
  *                  tiled = {r, c}.  Edge chunks may be short.
  *   LT_DIST_CUSTOM nboxes explicit boxes; they must be disjoint, lie inside
  *                  the domain and cover it.
- * Overlapping (halo) chunks are not supported by this build: a halo read is
- * resolved from neighbouring chunks instead (a region spanning several
- * chunks, Sec. 2.4).
+ *   LT_DIST_STENCIL the BLOCK cores of chunk[a], each stored with halo[a]
+ *                  extra elements on both sides along axis a (clipped to the
+ *                  domain), so neighbouring chunks overlap (Sec. 2.2).  Every
+ *                  element is owned by the chunk whose core holds it; the
+ *                  copies in other chunks' halos are replicas, kept coherent
+ *                  by the runtime: a read whose region fits in one chunk's
+ *                  stored box is served from that chunk alone, after any
+ *                  replica older than its owner is refreshed from the owner
+ *                  (a device-to-device copy of just those elements).  Writes
+ *                  go to the owners' cores.  Results never depend on the
+ *                  distribution (Sec. 2.4).
  */
 #define LT_DIST_BLOCK 0
 #define LT_DIST_CUSTOM 1
+#define LT_DIST_STENCIL 2
 
 typedef struct lt_box {
     int64_t lo[3];
@@ -161,8 +170,9 @@ typedef struct lt_box {
 typedef struct lt_dist {
     int32_t kind;
     int32_t nboxes;       /* LT_DIST_CUSTOM                          */
-    int64_t chunk[3];     /* LT_DIST_BLOCK; unused axes ignored       */
+    int64_t chunk[3];     /* LT_DIST_BLOCK / _STENCIL; unused axes ignored */
     const lt_box *boxes;  /* LT_DIST_CUSTOM; copied at array creation */
+    int64_t halo[3];      /* LT_DIST_STENCIL: halo width per axis (>= 0) */
 } lt_dist;
 
 /* ------------------------------------------------------------------- arrays
@@ -461,6 +471,7 @@ typedef struct lt_stats {
     uint64_t throttle_waits;
     uint64_t assembled_regions, direct_regions;
     double plan_seconds;           /* host time spent planning and issuing */
+    uint64_t halo_copies;          /* replica refreshes of halo distributions */
 } lt_stats;
 
 lt_status lt_stats_get(lt_context *ctx, lt_stats *out);

@@ -36,7 +36,7 @@ NP2LT = {np.dtype(v): k for k, v in DTYPES.items()}
 
 LT_EXEC_PLAIN, LT_EXEC_GROUPED = 0, 1
 LT_ORDER_ROWMAJOR, LT_ORDER_SERPENTINE = 0, 1
-LT_DIST_BLOCK, LT_DIST_CUSTOM = 0, 1
+LT_DIST_BLOCK, LT_DIST_CUSTOM, LT_DIST_STENCIL = 0, 1, 2
 LT_ARG_ARRAY, LT_ARG_INT, LT_ARG_FLOAT = 0, 1, 2
 LT_TASK_EXEC, LT_TASK_COMBINE, LT_TASK_IO = 0, 1, 2
 
@@ -56,7 +56,7 @@ class lt_box(C.Structure):
 
 class lt_dist(C.Structure):
     _fields_ = [("kind", C.c_int32), ("nboxes", C.c_int32), ("chunk", C.c_int64 * 3),
-                ("boxes", C.POINTER(lt_box))]
+                ("boxes", C.POINTER(lt_box)), ("halo", C.c_int64 * 3)]
 
 
 class lt_arg(C.Structure):
@@ -80,7 +80,7 @@ class lt_stats(C.Structure):
         "launches", "tasks", "dispatches", "bytes_h2d", "bytes_d2h", "bytes_d2d", "copies_h2d",
         "copies_d2h", "copies_d2d", "evictions_clean", "evictions_dirty", "resident_bytes",
         "peak_resident_bytes", "staged_peak_bytes", "throttle_waits", "assembled_regions",
-        "direct_regions")] + [("plan_seconds", C.c_double)]
+        "direct_regions")] + [("plan_seconds", C.c_double), ("halo_copies", C.c_uint64)]
 
 
 class lt_trace_rec(C.Structure):
@@ -211,9 +211,11 @@ def _i64(vals, n=3, fill=0):
     return arr
 
 
-def make_dist(chunk=None, boxes=None):
-    """BLOCK distribution with per-axis chunk extents (0 = whole axis), or a
-    CUSTOM distribution from half-open boxes [(lo, hi), ...]."""
+def make_dist(chunk=None, boxes=None, halo=None):
+    """BLOCK distribution with per-axis chunk extents (0 = whole axis), a
+    STENCIL distribution (the same cores stored with ``halo`` extra elements
+    per side and axis), or a CUSTOM distribution from half-open boxes
+    [(lo, hi), ...]."""
     d = lt_dist()
     if boxes is not None:
         arr = (lt_box * len(boxes))()
@@ -226,9 +228,10 @@ def make_dist(chunk=None, boxes=None):
         d.boxes = arr
         d._keep = arr
     else:
-        d.kind = LT_DIST_BLOCK
+        d.kind = LT_DIST_BLOCK if halo is None else LT_DIST_STENCIL
         for a in range(3):
             d.chunk[a] = (chunk[a] if chunk is not None and a < len(chunk) else 0)
+            d.halo[a] = (halo[a] if halo is not None and a < len(halo) else 0)
     return d
 
 
@@ -323,19 +326,19 @@ class Context:
         except Exception:
             pass
 
-    def array(self, shape, dtype=np.float32, chunk=None, boxes=None) -> Array:
+    def array(self, shape, dtype=np.float32, chunk=None, boxes=None, halo=None) -> Array:
         shape = tuple(shape)
         dt = NP2LT[np.dtype(dtype)]
-        d = make_dist(chunk, boxes)
+        d = make_dist(chunk, boxes, halo)
         h = _P()
         check(self.h, lt_array_create(self.h, dt, len(shape), _i64(shape, len(shape)), C.byref(d), C.byref(h)))
         return Array(self, h, dtype, shape)
 
-    def array_host(self, buf: np.ndarray, chunk=None, boxes=None) -> Array:
+    def array_host(self, buf: np.ndarray, chunk=None, boxes=None, halo=None) -> Array:
         """Host-backed array over ``buf`` (kept alive by the handle)."""
         assert buf.flags["C_CONTIGUOUS"]
         dt = NP2LT[buf.dtype]
-        d = make_dist(chunk, boxes)
+        d = make_dist(chunk, boxes, halo)
         h = _P()
         check(self.h, lt_array_create_host(self.h, dt, buf.ndim, _i64(buf.shape, buf.ndim), C.byref(d),
                                            C.c_void_p(buf.ctypes.data), C.byref(h)))

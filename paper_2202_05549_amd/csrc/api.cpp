@@ -90,21 +90,9 @@ lt_status sync_all(Ctx *ctx) {
         for (Chunk *c : arr->chunks) {
             if (st) break;
             if (c->dev_off < 0 || !c->dev_valid || c->host_valid || !c->defined) continue;
-            st = ensure_host_copy(ctx, c);
-            if (!st) st = stream_wait(ctx, ctx->d2h, c->data_ready);
-            int64_t ext[MAXD];
-            for (int a = 0; a < MAXD; ++a) ext[a] = c->box.hi[a] - c->box.lo[a];
-            if (!st)
-                st = copy_box(ctx, ctx->d2h, c->host_ptr, c->host_stride, dev_ptr(ctx, c), c->dev_stride, ext,
-                              arr->ndim, arr->esz, hipMemcpyDeviceToHost);
-            if (!st) {
-                uint64_t p = bump(ctx, ctx->d2h);
-                c->host_valid = true;
-                c->host_ready = Fence();
-                c->host_ready.add(ctx->d2h, p);
-                c->last_access.add(ctx->d2h, p);
-                trace_op(ctx, 2, ctx->d2h, ~0ull, c->id, c->bytes, c->dev_off);
-            }
+            uint64_t p = 0;
+            st = write_back(ctx, c, &p);
+            if (!st) c->last_access.add(ctx->d2h, p);
         }
     }
     if (!ctx->dry) {
@@ -188,19 +176,10 @@ lt_status array_flush_async(Ctx *ctx, Array *arr, Fence *out) {
     if (!arr->host_backed) return set_err(ctx, LT_ERR_INVALID, "array is not host-backed");
     for (Chunk *c : arr->chunks) {
         if (c->dev_off >= 0 && c->dev_valid && !c->host_valid && c->defined) {
-            st = stream_wait(ctx, ctx->d2h, c->data_ready);
+            uint64_t p = 0;
+            st = write_back(ctx, c, &p);
             if (st) return st;
-            int64_t ext[MAXD];
-            for (int a = 0; a < MAXD; ++a) ext[a] = c->box.hi[a] - c->box.lo[a];
-            st = copy_box(ctx, ctx->d2h, c->host_ptr, c->host_stride, dev_ptr(ctx, c), c->dev_stride, ext,
-                          arr->ndim, arr->esz, hipMemcpyDeviceToHost);
-            if (st) return st;
-            uint64_t p = bump(ctx, ctx->d2h);
-            c->host_valid = true;
-            c->host_ready = Fence();
-            c->host_ready.add(ctx->d2h, p);
             c->last_access.add(ctx->d2h, p);
-            trace_op(ctx, 2, ctx->d2h, ~0ull, c->id, c->bytes, c->dev_off);
         }
         out->merge(c->host_ready);
     }
@@ -229,6 +208,20 @@ void ctx_release_all(Ctx *ctx) {
 }
 
 // --------------------------------------------------------------- array I/O
+// After a whole-array write or fill every stored copy, halo replicas
+// included, holds the new contents.
+static void all_copies_current(Array *arr) {
+    for (Chunk *c : arr->chunks) {
+        c->version++;
+        if (c->host_valid) c->host_version = c->version;
+    }
+    for (Chunk *c : arr->chunks)
+        for (HaloSrc &h : c->halo) {
+            h.ver = h.k->version;
+            h.valid = true;
+        }
+}
+
 // Writes from `src` (row-major whole array) into every chunk.  Device copies
 // are overwritten after all earlier uses; chunks of a host-backed array that
 // are not on the device are written in their home buffer.
@@ -298,6 +291,7 @@ lt_status array_write(Ctx *ctx, Array *arr, const void *src, bool device_src) {
     }
     rec.seq = ctx->streams[ctx->h2d].seq;
     ctx->tasks.at(rec.id) = std::move(rec);
+    all_copies_current(arr);
     if (!ctx->dry) {
         hipError_t r = hipStreamSynchronize(ctx->streams[ctx->h2d].h);
         if (r != hipSuccess) return hip_fail(ctx, r, "hipStreamSynchronize");
@@ -311,18 +305,14 @@ lt_status array_read(Ctx *ctx, Array *arr, void *dst, bool device_dst) {
     if (st) return st;
     const int nd = arr->ndim;
     bool need_host = false;
+    const int64_t zero[MAXD] = {0, 0, 0};
     for (Chunk *c : arr->chunks) {
-        int64_t off = 0, ext[MAXD];
-        for (int a = 0; a < MAXD; ++a) {
-            off += (a < nd ? c->box.lo[a] : 0) * arr->strides[a];
-            ext[a] = c->box.hi[a] - c->box.lo[a];
-        }
-        char *dp = (char *)dst + off * arr->esz;
+        // each chunk contributes the elements it owns (its core)
         if (c->dev_off >= 0 && c->dev_valid) {
             st = stream_wait(ctx, ctx->d2h, c->data_ready);
             if (st) return st;
-            st = copy_box(ctx, ctx->d2h, dp, arr->strides, dev_ptr(ctx, c), c->dev_stride, ext, nd, arr->esz,
-                          device_dst ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost);
+            st = copy_sub(ctx, ctx->d2h, (char *)dst, zero, arr->strides, dev_ptr(ctx, c), c->box.lo, c->dev_stride,
+                          c->core, nd, arr->esz, device_dst ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost);
             if (st) return st;
             uint64_t p = bump(ctx, ctx->d2h);
             c->last_access.add(ctx->d2h, p);
@@ -335,16 +325,12 @@ lt_status array_read(Ctx *ctx, Array *arr, void *dst, bool device_dst) {
     if (need_host) {
         for (Chunk *c : arr->chunks) {
             if ((c->dev_off >= 0 && c->dev_valid) || !c->host_valid || !c->host_ptr) continue;
-            int64_t off = 0, ext[MAXD];
-            for (int a = 0; a < MAXD; ++a) {
-                off += (a < nd ? c->box.lo[a] : 0) * arr->strides[a];
-                ext[a] = c->box.hi[a] - c->box.lo[a];
-            }
-            char *dp = (char *)dst + off * arr->esz;
-            if (dp == c->host_ptr) continue;
+            int64_t off = 0;
+            for (int a = 0; a < nd; ++a) off += c->box.lo[a] * arr->strides[a];
+            if ((char *)dst + off * arr->esz == c->host_ptr) continue;  // the home buffer itself
             // host -> host or host -> device through the copy helper on d2h
-            st = copy_box(ctx, ctx->d2h, dp, arr->strides, c->host_ptr, c->host_stride, ext, nd, arr->esz,
-                          device_dst ? hipMemcpyHostToDevice : hipMemcpyHostToHost);
+            st = copy_sub(ctx, ctx->d2h, (char *)dst, zero, arr->strides, c->host_ptr, c->box.lo, c->host_stride,
+                          c->core, nd, arr->esz, device_dst ? hipMemcpyHostToDevice : hipMemcpyHostToHost);
             if (st) return st;
         }
         r = hipStreamSynchronize(ctx->streams[ctx->d2h].h);
@@ -421,6 +407,7 @@ lt_status array_fill(Ctx *ctx, Array *arr, const void *scalar) {
     }
     rec.seq = ctx->streams[0].seq;
     ctx->tasks.at(rec.id) = std::move(rec);
+    all_copies_current(arr);
     return LT_OK;
 }
 

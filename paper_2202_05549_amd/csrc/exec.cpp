@@ -38,6 +38,9 @@ struct ArgPlan {
     ROp op = R_ADD;
     Box region;
     std::vector<Chunk *> chunks;
+    // a read served by one chunk of a halo array: the other owners of the
+    // region's elements (their writes reach the task through halo refreshes)
+    std::vector<Chunk *> halo_owners;
 };
 
 struct TaskPlan {
@@ -153,6 +156,7 @@ static void apply_uses(Ctx *ctx, const std::vector<ChunkUse> &uses, int s, uint6
             c->data_ready.add(s, p);
             c->host_valid = false;
             c->defined = true;
+            c->version++;
         }
     }
     (void)ctx;
@@ -293,7 +297,11 @@ static lt_status stage_chunk(Ctx *ctx, Chunk *c, Mode m, const Box &region,
     }
     if (!c->dev_valid) {
         lt_status st;
-        bool overwrite = (m == M_WRITE) && region.contains(c->box, nd);
+        // a write that covers the whole core need not load the chunk; its
+        // halo replicas are then refreshed before they are next read
+        bool overwrite = (m == M_WRITE) && region.contains(c->core, nd);
+        if (overwrite)
+            for (HaloSrc &h : c->halo) h.valid = false;
         if (c->host_valid && c->defined && !overwrite) {
             if (!*staged_copy) {
                 st = throttle(ctx, footprint);
@@ -302,6 +310,13 @@ static lt_status stage_chunk(Ctx *ctx, Chunk *c, Mode m, const Box &region,
             }
             Fence f = mem;
             f.merge(c->host_ready);
+            if (c->arr->host_backed)
+                // the halo comes from the owners' cores in the home buffer
+                for (HaloSrc &h : c->halo) {
+                    f.merge(h.k->host_ready);
+                    h.ver = h.k->host_version;
+                    h.valid = true;
+                }
             st = stream_wait(ctx, ctx->h2d, f);
             if (st) return st;
             int64_t ext[MAXD];
@@ -321,6 +336,10 @@ static lt_status stage_chunk(Ctx *ctx, Chunk *c, Mode m, const Box &region,
         }
         c->dev_valid = true;
     }
+    if (!c->halo.empty() && m != M_WRITE && m != M_REDUCE) {
+        lt_status st = refresh_halo(ctx, c, region);
+        if (st) return st;
+    }
     wait->merge(c->data_ready);
     // a write must also follow every earlier use of the memory
     if (m != M_READ) wait->merge(c->last_access);
@@ -337,8 +356,10 @@ struct Temp {
     bool scatter;
 };
 
+// Copies between chunk c and a temporary: the part of the region that c
+// owns (its core), so halo replicas are never read or written here.
 static lt_status copy_region(Ctx *ctx, int s, Chunk *c, const Temp &t, int esz, int nd, bool to_temp) {
-    Box o = intersect(c->box, t.region, nd);
+    Box o = intersect(c->core, t.region, nd);
     if (o.empty(nd)) return LT_OK;
     int64_t coff = 0, toff = 0, ext[MAXD];
     for (int a = 0; a < MAXD; ++a) {
@@ -465,6 +486,12 @@ static lt_status batch_add_exec(Ctx *ctx, const KernelDef *def, TaskPlan &tp, Ta
             return set_err(ctx, LT_ERR_UNSUPPORTED,
                            "inside a batch every chunk a task touches must be resident and contiguous (%s)",
                            def->params[p].name);
+        if (a.mode != M_WRITE)
+            for (Chunk *c : a.chunks)
+                if (halo_stale(c, a.region))
+                    return set_err(ctx, LT_ERR_UNSUPPORTED,
+                                   "inside a batch a halo read needs replicas refreshed before the batch (%s)",
+                                   def->params[p].name);
         for (Chunk *c : a.chunks) {
             c->lru = ++ctx->lru_clock;
             uses.push_back({c, a.mode != M_READ});
@@ -524,6 +551,7 @@ static lt_status batch_add_exec(Ctx *ctx, const KernelDef *def, TaskPlan &tp, Ta
         ArgPlan &a = tp.arg[p];
         if (!a.used || a.mode == M_REDUCE) continue;
         for (Chunk *c : a.chunks) record_access(c, a.mode, a.op, tp.id);
+        for (Chunk *k : a.halo_owners) record_access(k, M_READ, a.op, tp.id);
     }
     if (partial_y) {
         B.patch_y.push_back({(int)B.q.size(), 0});
@@ -875,6 +903,7 @@ static lt_status issue_exec(Ctx *ctx, lt_kernel *k, TaskPlan &tp, uint64_t L,
             continue;  // the combine task accesses the target
         }
         for (Chunk *c : a.chunks) conflict_edges(c, a.mode, a.op, &rec.deps);
+        for (Chunk *k : a.halo_owners) conflict_edges(k, M_READ, a.op, &rec.deps);
     }
 
     if (ctx->batch.open) return batch_add_exec(ctx, def, tp, rec, proto, arrs, parts);
@@ -892,6 +921,10 @@ static lt_status issue_exec(Ctx *ctx, lt_kernel *k, TaskPlan &tp, uint64_t L,
             ArgPlan &a = tp.arg[p];
             if (!a.used) continue;
             if (!direct_view(ctx, arrs[p], a.chunks, &kt.v[p])) simple = false;
+            // halo replicas to refresh first: take the staging path
+            if (a.mode != M_WRITE)
+                for (Chunk *c : a.chunks)
+                    if (halo_stale(c, a.region)) simple = false;
         }
     bool in_group = false;
     if (simple && ctx->cfg.exec_mode == LT_EXEC_GROUPED && g.open && g.launch == L && g.def == def) {
@@ -922,6 +955,7 @@ static lt_status issue_exec(Ctx *ctx, lt_kernel *k, TaskPlan &tp, uint64_t L,
                                                  {a.region.hi[0], a.region.hi[1], a.region.hi[2]}});
             ctx->stats.direct_regions++;
             for (Chunk *c : a.chunks) record_access(c, a.mode, a.op, tp.id);
+        for (Chunk *k : a.halo_owners) record_access(k, M_READ, a.op, tp.id);
         }
         if (!g.open) {
             g.open = true;
@@ -1083,6 +1117,7 @@ static lt_status issue_exec(Ctx *ctx, lt_kernel *k, TaskPlan &tp, uint64_t L,
         ArgPlan &a = tp.arg[p];
         if (!a.used || a.mode == M_REDUCE) continue;
         for (Chunk *c : a.chunks) record_access(c, a.mode, a.op, tp.id);
+        for (Chunk *k : a.halo_owners) record_access(k, M_READ, a.op, tp.id);
     }
     apply_uses(ctx, uses, s, pt);
     Fence done;
@@ -1380,6 +1415,14 @@ lt_status launch(Ctx *ctx, lt_kernel *k, int nd, const int64_t *grid,
                 continue;
             }
             chunks_overlapping(arr, a.region, &a.chunks);
+            if (arr->has_halo && a.mode == M_READ && a.chunks.size() > 1) {
+                // a read inside one chunk's stored box is served by that chunk
+                if (Chunk *e = enclosing_chunk(arr, a.region)) {
+                    for (Chunk *k : a.chunks)
+                        if (k != e) a.halo_owners.push_back(k);
+                    a.chunks.assign(1, e);
+                }
+            }
             bool multi = a.chunks.size() > 1;
             for (Chunk *c : a.chunks)
                 if (std::find(seen.begin(), seen.end(), c) == seen.end()) {

@@ -46,6 +46,11 @@ struct Box {
             if (o.lo[a] < lo[a] || o.hi[a] > hi[a]) return false;
         return true;
     }
+    bool contains_point(const int64_t *p, int nd) const {
+        for (int a = 0; a < nd; ++a)
+            if (p[a] < lo[a] || p[a] >= hi[a]) return false;
+        return true;
+    }
     bool equals(const Box &o, int nd) const {
         for (int a = 0; a < nd; ++a)
             if (o.lo[a] != lo[a] || o.hi[a] != hi[a]) return false;
@@ -163,12 +168,28 @@ struct Fence {
 using Array = ::lt_array;  // declared in lt.h, defined below
 
 // ------------------------------------------------------------------ chunks
+struct Chunk;
+
+// One piece of a chunk's halo: the elements `box` (inside the chunk's stored
+// box) are owned by chunk k; `ver` is the version of k they hold.
+struct HaloSrc {
+    Chunk *k = nullptr;
+    Box box;
+    uint64_t ver = 0;
+    bool valid = true;   // false: the piece holds no copy at all (never loaded)
+};
+
 struct Chunk {
     uint64_t id = 0;
     Array *arr = nullptr;
     int index = 0;
-    Box box;
+    Box box;                   // stored elements (the core plus any halo)
+    Box core;                  // owned elements; the cores of an array's chunks partition it
     int64_t elems = 0, bytes = 0;
+    // halo coherence (Sec. 2.2 overlapping distributions): version counts the
+    // writes of the core; host_version is the version in the host copy's core
+    uint64_t version = 0, host_version = 0;
+    std::vector<HaloSrc> halo;
 
     // device copy
     int64_t dev_off = -1;      // arena offset; -1 = not allocated
@@ -211,6 +232,8 @@ struct lt_array {
     bool host_backed = false;
     char *host_base = nullptr;
     bool row_slab = false;   // every chunk spans full trailing axes
+    bool has_halo = false;   // chunks store a halo around their core (LT_DIST_STENCIL)
+    int64_t halo[lt::MAXD] = {0, 0, 0};
     int dist_kind = LT_DIST_BLOCK;
     int64_t dist_chunk[lt::MAXD] = {0, 0, 0};  // BLOCK
     int64_t nch[lt::MAXD] = {1, 1, 1};         // BLOCK: chunks per axis
@@ -435,7 +458,12 @@ bool access_region(const Access &a, int nd_grid, const int64_t *block,
                    const VarRange &vr, const int64_t *params, const Array *arr,
                    Box *out);
 lt_status make_chunks(Ctx *ctx, Array *arr, const lt_dist *dist);
+// chunks whose core intersects r (the owners of r's elements)
 void chunks_overlapping(const Array *arr, const Box &r, std::vector<Chunk *> *out);
+// halo arrays: a chunk whose stored box (core plus halo) contains r, or null
+Chunk *enclosing_chunk(const Array *arr, const Box &r);
+// halo pieces of c inside `region` that hold an older version than their owner
+bool halo_stale(const Chunk *c, const Box &region);
 
 // executor (exec.cpp)
 lt_status launch(Ctx *ctx, lt_kernel *k, int nd, const int64_t *grid,
@@ -467,6 +495,17 @@ lt_status stream_wait(Ctx *ctx, int stream, const Fence &f);
 lt_status copy_box(Ctx *ctx, int stream, char *dst, const int64_t *ds,
                    const char *src, const int64_t *ss, const int64_t *ext,
                    int nd, int esz, hipMemcpyKind kind);
+// copies the elements `sub` between two buffers holding boxes with origins
+// dlo / slo and element strides ds / ss
+lt_status copy_sub(Ctx *ctx, int stream, char *dst, const int64_t *dlo, const int64_t *ds, const char *src,
+                   const int64_t *slo, const int64_t *ss, const Box &sub, int nd, int esz, hipMemcpyKind kind);
+// D2H of a dirty chunk to its host copy on the D2H stream (after its data is
+// ready): the core for host-backed arrays (the halo belongs to other
+// chunks), the whole stored box for spill buffers.  Returns the D2H seq.
+lt_status write_back(Ctx *ctx, Chunk *c, uint64_t *seq);
+// brings the halo pieces of c that `region` touches up to their owners'
+// versions (copies on the H2D stream); c must be valid on the device
+lt_status refresh_halo(Ctx *ctx, Chunk *c, const Box &region);
 lt_status alloc_range(Ctx *ctx, int64_t size, int kind, Chunk *owner,
                       int64_t *off, Fence *fence);
 lt_status alloc_chunk(Ctx *ctx, Chunk *c, Fence *fence);

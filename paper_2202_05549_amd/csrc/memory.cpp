@@ -364,26 +364,98 @@ static void chunk_ext(const Chunk *c, int64_t *ext) {
 
 char *dev_ptr(Ctx *ctx, const Chunk *c) { return ctx->arena_base + c->dev_off; }
 
+lt_status copy_sub(Ctx *ctx, int stream, char *dst, const int64_t *dlo, const int64_t *ds, const char *src,
+                   const int64_t *slo, const int64_t *ss, const Box &sub, int nd, int esz, hipMemcpyKind kind) {
+    int64_t doff = 0, soff = 0, ext[MAXD];
+    for (int a = 0; a < MAXD; ++a) {
+        const int64_t lo = a < nd ? sub.lo[a] : 0;
+        doff += (lo - (a < nd ? dlo[a] : 0)) * ds[a];
+        soff += (lo - (a < nd ? slo[a] : 0)) * ss[a];
+        ext[a] = a < nd ? sub.hi[a] - sub.lo[a] : 1;
+    }
+    return copy_box(ctx, stream, dst + doff * esz, ds, src + soff * esz, ss, ext, nd, esz, kind);
+}
+
+lt_status write_back(Ctx *ctx, Chunk *c, uint64_t *seq) {
+    lt_status st = ensure_host_copy(ctx, c);
+    if (st) return st;
+    st = stream_wait(ctx, ctx->d2h, c->data_ready);
+    if (st) return st;
+    const Array *arr = c->arr;
+    const Box &part = arr->host_backed ? c->core : c->box;
+    st = copy_sub(ctx, ctx->d2h, c->host_ptr, c->box.lo, c->host_stride, dev_ptr(ctx, c), c->box.lo,
+                  c->dev_stride, part, arr->ndim, arr->esz, hipMemcpyDeviceToHost);
+    if (st) return st;
+    *seq = bump(ctx, ctx->d2h);
+    c->host_ready = Fence();
+    c->host_ready.add(ctx->d2h, *seq);
+    c->host_valid = true;
+    c->host_version = c->version;
+    trace_op(ctx, 2, ctx->d2h, ~0ull, c->id, c->bytes, c->dev_off);
+    return LT_OK;
+}
+
+lt_status refresh_halo(Ctx *ctx, Chunk *c, const Box &region) {
+    const Array *arr = c->arr;
+    const int nd = arr->ndim;
+    for (HaloSrc &h : c->halo) {
+        Chunk *k = h.k;
+        if ((h.valid && h.ver >= k->version) || intersect(h.box, region, nd).empty(nd)) continue;
+        if (!k->defined) {
+            h.ver = k->version;
+            h.valid = true;
+            continue;
+        }
+        // the copy overwrites part of c: after every earlier use of c; it
+        // reads k: after k's last write (or load)
+        Fence f = c->last_access;
+        f.merge(c->data_ready);
+        lt_status st;
+        if (k->dev_off >= 0 && k->dev_valid) {
+            f.merge(k->data_ready);
+            st = stream_wait(ctx, ctx->h2d, f);
+            if (st) return st;
+            st = copy_sub(ctx, ctx->h2d, dev_ptr(ctx, c), c->box.lo, c->dev_stride, dev_ptr(ctx, k), k->box.lo,
+                          k->dev_stride, h.box, nd, arr->esz, hipMemcpyDeviceToDevice);
+            if (st) return st;
+            ctx->stats.halo_copies++;
+            trace_op(ctx, 3, ctx->h2d, ~0ull, c->id, (uint64_t)(h.box.volume(nd) * arr->esz), c->dev_off);
+        } else {
+            // the owner is not on the device: its newest copy is the host one
+            if (!k->host_valid || !k->host_ptr)
+                return set_err(ctx, LT_ERR_INVALID, "internal: halo owner chunk %llu has no valid copy",
+                               (unsigned long long)k->id);
+            f.merge(k->host_ready);
+            st = stream_wait(ctx, ctx->h2d, f);
+            if (st) return st;
+            st = copy_sub(ctx, ctx->h2d, dev_ptr(ctx, c), c->box.lo, c->dev_stride, k->host_ptr, k->box.lo,
+                          k->host_stride, h.box, nd, arr->esz, hipMemcpyHostToDevice);
+            if (st) return st;
+            ctx->stats.halo_copies++;
+            trace_op(ctx, 1, ctx->h2d, ~0ull, c->id, (uint64_t)(h.box.volume(nd) * arr->esz), c->dev_off);
+        }
+        const uint64_t p = bump(ctx, ctx->h2d);
+        c->data_ready.add(ctx->h2d, p);
+        c->last_access.add(ctx->h2d, p);
+        if (k->dev_off >= 0) k->last_access.add(ctx->h2d, p);
+        // a spill buffer holds the whole stored box, so it no longer matches;
+        // a host-backed home buffer only ever receives c's core
+        if (!arr->host_backed) c->host_valid = false;
+        h.ver = k->version;
+        h.valid = true;
+    }
+    return LT_OK;
+}
+
 // Evicts one unpinned chunk: write back if its device copy is newer.
 lt_status evict_chunk(Ctx *ctx, Chunk *c) {
     Fence f = c->last_access;
     if (c->dev_valid && !c->host_valid && c->defined) {
-        lt_status st = ensure_host_copy(ctx, c);
+        uint64_t p = 0;
+        lt_status st = write_back(ctx, c, &p);
         if (st) return st;
-        st = stream_wait(ctx, ctx->d2h, c->data_ready);
-        if (st) return st;
-        int64_t ext[MAXD];
-        chunk_ext(c, ext);
-        st = copy_box(ctx, ctx->d2h, c->host_ptr, c->host_stride, dev_ptr(ctx, c), c->dev_stride,
-                      ext, c->arr->ndim, c->arr->esz, hipMemcpyDeviceToHost);
-        if (st) return st;
-        uint64_t p = bump(ctx, ctx->d2h);
-        c->host_ready = Fence();
-        c->host_ready.add(ctx->d2h, p);
-        c->host_valid = true;
         f.add(ctx->d2h, p);
         ctx->stats.evictions_dirty++;
-        trace_op(ctx, 2, ctx->d2h, ~0ull, c->id, c->bytes, c->dev_off);
     } else {
         ctx->stats.evictions_clean++;
     }

@@ -10,7 +10,8 @@
 //
 // Distributions (Sec. 2.2): a BLOCK policy cuts every axis into pieces of a
 // fixed length (row-wise, column-wise, tiled); CUSTOM takes explicit disjoint
-// boxes that cover the domain.
+// boxes that cover the domain; STENCIL stores each BLOCK core with a halo of
+// replicas of its neighbours' elements.
 #include <algorithm>
 
 #include "lt_internal.h"
@@ -84,8 +85,16 @@ bool access_region(const Access &a, int nd_grid, const int64_t *block,
 lt_status make_chunks(Ctx *ctx, Array *arr, const lt_dist *dist) {
     const int nd = arr->ndim;
     std::vector<Box> boxes;
-    if (!dist || dist->kind == LT_DIST_BLOCK) {
+    if (!dist || dist->kind == LT_DIST_BLOCK || dist->kind == LT_DIST_STENCIL) {
         arr->dist_kind = LT_DIST_BLOCK;
+        if (dist && dist->kind == LT_DIST_STENCIL) {
+            for (int a = 0; a < MAXD; ++a) {
+                const int64_t h = a < nd ? dist->halo[a] : 0;
+                if (h < 0) return set_err(ctx, LT_ERR_INVALID, "negative halo on axis %d", a);
+                arr->halo[a] = h;
+                if (h > 0) arr->has_halo = true;
+            }
+        }
         for (int a = 0; a < MAXD; ++a) {
             int64_t c = (dist && a < nd) ? dist->chunk[a] : 0;
             if (c < 0) return set_err(ctx, LT_ERR_INVALID, "negative chunk extent on axis %d", a);
@@ -107,7 +116,7 @@ lt_status make_chunks(Ctx *ctx, Array *arr, const lt_dist *dist) {
                     }
                     boxes.push_back(b);
                 }
-        arr->row_slab = true;
+        arr->row_slab = !arr->has_halo;  // overlapping chunks never form one dense slab
         for (int a = 1; a < nd; ++a)
             if (arr->nch[a] != 1) arr->row_slab = false;
     } else if (dist->kind == LT_DIST_CUSTOM) {
@@ -145,7 +154,12 @@ lt_status make_chunks(Ctx *ctx, Array *arr, const lt_dist *dist) {
         c->id = ctx->next_chunk_id++;
         c->arr = arr;
         c->index = (int)i;
+        c->core = boxes[i];
         c->box = boxes[i];
+        for (int a = 0; a < nd; ++a) {
+            c->box.lo[a] = std::max<int64_t>(0, c->core.lo[a] - arr->halo[a]);
+            c->box.hi[a] = std::min<int64_t>(arr->shape[a], c->core.hi[a] + arr->halo[a]);
+        }
         c->elems = c->box.volume(nd);
         c->bytes = c->elems * arr->esz;
         // dense row-major storage of the chunk box on the device
@@ -156,7 +170,40 @@ lt_status make_chunks(Ctx *ctx, Array *arr, const lt_dist *dist) {
         }
         arr->chunks.push_back(c);
     }
+    if (arr->has_halo) {
+        // halo pieces: the parts of a chunk's stored box owned by other chunks
+        for (Chunk *c : arr->chunks) {
+            std::vector<Chunk *> owners;
+            chunks_overlapping(arr, c->box, &owners);
+            for (Chunk *k : owners) {
+                if (k == c) continue;
+                HaloSrc h;
+                h.k = k;
+                h.box = intersect(k->core, c->box, nd);
+                if (!h.box.empty(nd)) c->halo.push_back(h);
+            }
+        }
+    }
     return LT_OK;
+}
+
+Chunk *enclosing_chunk(const Array *arr, const Box &r) {
+    const int nd = arr->ndim;
+    std::vector<Chunk *> owners;
+    chunks_overlapping(arr, r, &owners);
+    // prefer the owner of the region's first element, then any owner
+    for (Chunk *c : owners)
+        if (c->core.contains_point(r.lo, nd) && c->box.contains(r, nd)) return c;
+    for (Chunk *c : owners)
+        if (c->box.contains(r, nd)) return c;
+    return nullptr;
+}
+
+bool halo_stale(const Chunk *c, const Box &region) {
+    const int nd = c->arr->ndim;
+    for (const HaloSrc &h : c->halo)
+        if ((!h.valid || h.ver < h.k->version) && !intersect(h.box, region, nd).empty(nd)) return true;
+    return false;
 }
 
 void chunks_overlapping(const Array *arr, const Box &r, std::vector<Chunk *> *out) {
@@ -176,7 +223,7 @@ void chunks_overlapping(const Array *arr, const Box &r, std::vector<Chunk *> *ou
                     out->push_back(arr->chunks[(i * arr->nch[1] + j) * arr->nch[2] + k]);
     } else {
         for (Chunk *c : arr->chunks)
-            if (!intersect(c->box, r, nd).empty(nd)) out->push_back(c);
+            if (!intersect(c->core, r, nd).empty(nd)) out->push_back(c);
     }
 }
 

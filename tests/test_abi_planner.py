@@ -178,12 +178,14 @@ def _launch_seq(ctx, rng, n, arrays, steps):
     return tasks, ids
 
 
+@pytest.mark.parametrize("halo", [None, 1, 3])
 @pytest.mark.parametrize("seed", range(6))
-def test_dag_contains_every_required_ordering(seed):
+def test_dag_contains_every_required_ordering(seed, halo):
     rng = np.random.default_rng(seed)
     ctx = dry()
     n = 40
-    arrays = [ctx.array([n], chunk=[int(rng.choice([5, 8, 40]))]) for _ in range(3)]
+    arrays = [ctx.array([n], chunk=[int(rng.choice([5, 8, 40]))], halo=None if halo is None else [halo])
+              for _ in range(3)]
     tasks, ids = _launch_seq(ctx, rng, n, arrays, 6)
     # transitive closure of the planner's edges
     pos = {tid: k for k, tid in enumerate(ids)}
@@ -292,4 +294,64 @@ def test_custom_distribution_validation():
         ctx.array([10], boxes=[((0,), (4,)), ((5,), (10,))])  # gap
     a = ctx.array([10], boxes=[((4,), (10,)), ((0,), (4,))])
     assert a.id > 0
+    ctx.close()
+
+
+# ------------------------------------------------- halo distributions (f2)
+
+def _jacobi_sweeps(ctx, n, m, chunk, halo, sweeps, sb):
+    a = ctx.array([n, m], chunk=chunk, halo=halo)
+    b = ctx.array([n, m], chunk=chunk, halo=halo)
+    a.fill(1.0)
+    b.fill(0.0)
+    inp, out = a, b
+    for _ in range(sweeps):
+        ctx.launch("jacobi2d_f32", [n, m], [1, 64], sb, args=[n, m, out, inp])
+        inp, out = out, inp
+    ctx.sync()
+
+
+def test_halo_reads_are_served_by_one_chunk():
+    n, m = 256, 512
+    ctx = dry()
+    _jacobi_sweeps(ctx, n, m, [64, 128], [1, 1], 4, [64, 128])
+    s = ctx.stats()
+    # every tile's halo read fits the tile's stored box: no assembled copies
+    assert s["assembled_regions"] == 0
+    # after the first sweep each written tile's neighbours refresh their replicas:
+    # 16 tiles, 3 sweeps that read freshly written data, one piece per neighbour
+    # (4 edge + 4 corner neighbours for interior tiles)
+    nb = 0
+    for i in range(4):
+        for j in range(4):
+            nb += sum(1 for di in (-1, 0, 1) for dj in (-1, 0, 1)
+                      if (di or dj) and 0 <= i + di < 4 and 0 <= j + dj < 4)
+    assert s["halo_copies"] == 3 * nb
+    ctx.close()
+    # the same tiles without a halo assemble every read from up to 9 chunks
+    ctx = dry()
+    _jacobi_sweeps(ctx, n, m, [64, 128], None, 4, [64, 128])
+    s = ctx.stats()
+    assert s["assembled_regions"] == 4 * 16 and s["halo_copies"] == 0
+    ctx.close()
+
+
+def test_halo_stores_cores_with_replicas():
+    ctx = dry()
+    x = ctx.array([100], chunk=[30], halo=[2])
+    y = ctx.array([100], chunk=[30], halo=[2])
+    x.fill(0.0)
+    lid = ctx.launch("stencil1d_f32", [100], [1], [30], args=[100, y, x])
+    for t in ctx.tasks(lid):
+        for r in ctx.regions(t.id):
+            assert r.resolved == 0  # direct views
+    ctx.sync()
+    ctx.close()
+
+
+def test_halo_distribution_validation():
+    ctx = dry()
+    with pytest.raises(L.LtError) as e:
+        ctx.array([100], chunk=[30], halo=[-1])
+    assert e.value.status == L.LT_ERR_INVALID
     ctx.close()
