@@ -500,6 +500,72 @@ def bench_batch(args, L, torch):
 
 
 # ==================================================================== serve
+# ============================================================ jacobi_tiled
+def bench_jacobi_tiled(args, L, torch):
+    """The same Jacobi sweeps over a tiled distribution (2048 x 2048 tiles,
+    superblock = tile): plain tiles, whose halo reads must be assembled from
+    up to 9 chunks, against halo tiles (STENCIL, halo 1), whose reads are
+    served by one chunk after its replicas are refreshed from their owners;
+    row slabs (512 rows, contiguous in HBM) for reference."""
+    import synthetic
+
+    n, sweeps, T = 16384, 20, 2048
+    x0 = synthetic.jacobi2d_input(n, seed=1)
+    step_bytes = sweeps * n * n * 8
+    budget = 4 * n * n * 4 + (1 << 30)
+    res = {}
+    for name, chunk, halo, sb in (("halo_tiles", [T, T], [1, 1], [T, T]), ("plain_tiles", [T, T], None, [T, T]),
+                                  ("row_slabs", [512, 0], None, [512, 0])):
+        arena = torch_arena(torch, budget)
+        ctx = L.Context(device_budget_bytes=budget, device_arena=arena.data_ptr(), arena_bytes=budget,
+                        exec_mode=L.LT_EXEC_GROUPED)
+        try:
+            ctx.tune("jacobi2d_f32", 8)
+            a = ctx.array([n, n], chunk=chunk, halo=halo)
+            b = ctx.array([n, n], chunk=chunk, halo=halo)
+            a.write(x0)
+            b.fill(0.0)
+            ctx.sync()
+
+            def step():
+                inp, out = a, b
+                for _ in range(sweeps):
+                    ctx.launch("jacobi2d_f32", [n, n], [1, 256], sb, args=[n, n, out, inp])
+                    inp, out = out, inp
+                ctx.sync()
+
+            for _ in range(args.warmup):
+                step()
+            ctx.reset_stats()
+            times = []
+            for _ in range(args.steps):
+                s0 = time.perf_counter()
+                step()
+                times.append(time.perf_counter() - s0)
+            st = ctx.stats()
+        finally:
+            ctx.close()
+            del arena
+        wall = float(np.mean(times))
+        res[name] = {"gbs": step_bytes / wall / 1e9, "ms_per_step": wall * 1e3,
+                     "d2d_gb_per_step": st["bytes_d2d"] / args.steps / 1e9,
+                     "assembled_per_step": st["assembled_regions"] / args.steps,
+                     "halo_copies_per_step": st["halo_copies"] / args.steps,
+                     "dispatches_per_step": st["dispatches"] / args.steps}
+        log("%s: %s" % (name, json.dumps(res[name])))
+    m = res["halo_tiles"]
+    line = base_line({"workload": "jacobi2d 16384x16384 f32, 20 sweeps, 2048x2048 tiles with a one-element halo "
+                                  "(STENCIL distribution), superblock = tile, in HBM",
+                      "executor": "grouped"}, args.steps, args.warmup)
+    line.update({"value": round(m["gbs"], 2), "unit": "GB/s", "ms_per_step": round(m["ms_per_step"], 3),
+                 "dtype": "f32", "hbm_frac": round(m["gbs"] / HBM_PEAK_GBS, 4),
+                 "plain_tiles": {k: round(v, 3) for k, v in res["plain_tiles"].items()},
+                 "row_slabs": {k: round(v, 3) for k, v in res["row_slabs"].items()},
+                 "halo_over_plain_tiles": round(m["gbs"] / res["plain_tiles"]["gbs"], 3),
+                 "halo_tiles": {k: round(v, 3) for k, v in m.items()}})
+    return line
+
+
 # =================================================================== kmeans
 def bench_kmeans(args, L, torch):
     """The K-Means loop: assignment, centre update (reduce(+) of per-cluster
@@ -600,7 +666,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=None)
-    ap.add_argument("--workload", choices=["jacobi", "stencil1d", "gemm_ooc", "batch", "serve", "kmeans"],
+    ap.add_argument("--workload", choices=["jacobi", "stencil1d", "gemm_ooc", "batch", "serve", "kmeans",
+                                           "jacobi_tiled"],
                     default="jacobi")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--rows", type=int, default=8, help="rows per Jacobi tile (8, 16, 32)")
@@ -633,7 +700,7 @@ def main():
     if args.calibrate_copy:
         calibration_copy(torch)
     fn = {"jacobi": bench_jacobi, "stencil1d": bench_stencil1d, "gemm_ooc": bench_gemm_ooc, "batch": bench_batch,
-          "serve": bench_serve, "kmeans": bench_kmeans}[args.workload]
+          "serve": bench_serve, "kmeans": bench_kmeans, "jacobi_tiled": bench_jacobi_tiled}[args.workload]
     line = fn(args, L, torch)
     print(json.dumps(line), flush=True)
 

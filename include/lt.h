@@ -156,7 +156,9 @@ const char *lt_last_error(lt_context *ctx);
  *                  replica older than its owner is refreshed from the owner
  *                  (a device-to-device copy of just those elements).  Writes
  *                  go to the owners' cores.  Results never depend on the
- *                  distribution (Sec. 2.4).
+ *                  distribution (Sec. 2.4).  Along the last axis the stored
+ *                  halo is rounded up to whole 16-byte words, so rows keep
+ *                  the alignment of vector loads.
  */
 #define LT_DIST_BLOCK 0
 #define LT_DIST_CUSTOM 1

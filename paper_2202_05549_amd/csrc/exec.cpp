@@ -492,6 +492,11 @@ static lt_status batch_add_exec(Ctx *ctx, const KernelDef *def, TaskPlan &tp, Ta
                     return set_err(ctx, LT_ERR_UNSUPPORTED,
                                    "inside a batch a halo read needs replicas refreshed before the batch (%s)",
                                    def->params[p].name);
+        // device work on these chunks outside any task (halo refreshes)
+        for (Chunk *c : a.chunks) {
+            B.wait.merge(c->data_ready);
+            if (a.mode != M_READ) B.wait.merge(c->last_access);
+        }
         for (Chunk *c : a.chunks) {
             c->lru = ++ctx->lru_clock;
             uses.push_back({c, a.mode != M_READ});
@@ -644,6 +649,126 @@ static void *staging_get(Ctx *ctx, uint64_t bytes, lt_status *st) {
     ctx->staging_used.push_back(p);
     ctx->staging_size_used.push_back(sz);
     return p;
+}
+
+// Halo replicas that the reads of a launch will use, refreshed up front from
+// owners on the device with one copy dispatch (per element size), so the
+// launch's tasks find their halos current and keep their direct views and
+// grouped dispatch.  Pieces whose owner is not on the device are left to the
+// per-task staging (refresh_halo).
+static lt_status refresh_launch_halos(Ctx *ctx, std::vector<TaskPlan> &plans, Array **arrs, int nparam) {
+    std::vector<std::pair<Chunk *, HaloSrc *>> pieces;
+    std::vector<HaloSrc *> seen;
+    for (auto &tp : plans)
+        for (int p = 0; p < nparam; ++p) {
+            ArgPlan &a = tp.arg[p];
+            if (!a.used || a.mode == M_WRITE || a.mode == M_REDUCE || a.chunks.size() != 1) continue;
+            Array *arr = arrs[p];
+            if (!arr->has_halo) continue;
+            Chunk *c = a.chunks[0];
+            if (c->dev_off < 0 || !c->dev_valid) continue;
+            const int nd = arr->ndim;
+            for (HaloSrc &h : c->halo) {
+                Chunk *k = h.k;
+                if ((h.valid && h.ver >= k->version) || intersect(h.box, a.region, nd).empty(nd)) continue;
+                if (!k->defined) {
+                    h.ver = k->version;
+                    h.valid = true;
+                    continue;
+                }
+                if (k->dev_off < 0 || !k->dev_valid) continue;
+                if (std::find(seen.begin(), seen.end(), &h) != seen.end()) continue;
+                seen.push_back(&h);
+                pieces.push_back({c, &h});
+            }
+        }
+    if (pieces.empty()) return LT_OK;
+    lt_status st = flush_group(ctx);
+    if (st) return st;
+    for (int esz : {1, 4, 8}) {
+        std::vector<CopyBoxEntry> table;
+        std::vector<std::pair<Chunk *, HaloSrc *>> mine;
+        Fence wait;
+        int64_t max_elems = 0;
+        for (auto &pc : pieces) {
+            Chunk *c = pc.first;
+            HaloSrc &h = *pc.second;
+            Chunk *k = h.k;
+            const Array *arr = c->arr;
+            if (arr->esz != esz) continue;
+            const int nd = arr->ndim;
+            CopyBoxEntry e;
+            int64_t so = 0, dof = 0, vol = 1;
+            for (int a = 0; a < 3; ++a) {
+                const bool in = a < nd;
+                so += in ? (h.box.lo[a] - k->box.lo[a]) * k->dev_stride[a] : 0;
+                dof += in ? (h.box.lo[a] - c->box.lo[a]) * c->dev_stride[a] : 0;
+                e.ext[a] = in ? h.box.hi[a] - h.box.lo[a] : 1;
+                e.ss[a] = k->dev_stride[a];
+                e.ds[a] = c->dev_stride[a];
+                vol *= e.ext[a];
+            }
+            e.src = (int64_t)(intptr_t)(dev_ptr(ctx, k) + so * esz);
+            e.dst = (int64_t)(intptr_t)(dev_ptr(ctx, c) + dof * esz);
+            max_elems = std::max(max_elems, vol);
+            table.push_back(e);
+            mine.push_back(pc);
+            wait.merge(k->data_ready);
+            wait.merge(c->data_ready);
+            wait.merge(c->last_access);
+        }
+        for (size_t b = 0; b < table.size(); b += 65535) {
+            const int n = (int)std::min<size_t>(65535, table.size() - b);
+            const int64_t bytes = (int64_t)n * (int64_t)sizeof(CopyBoxEntry);
+            // the table's arena range must not evict the chunks being copied
+            for (size_t i = b; i < b + n; ++i) {
+                mine[i].first->pin++;
+                mine[i].second->k->pin++;
+            }
+            int64_t off;
+            Fence mem;
+            st = alloc_range(ctx, (bytes + 255) / 256 * 256, 2, nullptr, &off, &mem);
+            for (size_t i = b; i < b + n; ++i) {
+                mine[i].first->pin--;
+                mine[i].second->k->pin--;
+            }
+            if (st) return st;
+            void *stage = staging_get(ctx, (uint64_t)bytes, &st);
+            if (!stage) return st;
+            memcpy(stage, table.data() + b, (size_t)bytes);
+            Fence f = wait;
+            f.merge(mem);
+            const int s = pick_stream(ctx, f);
+            st = stream_wait(ctx, s, f);
+            if (st) return st;
+            if (!ctx->dry) {
+                hipStream_t hs = ctx->streams[s].h;
+                hipError_t r = hipMemcpyAsync(ctx->arena_base + off, stage, (size_t)bytes, hipMemcpyHostToDevice, hs);
+                if (r != hipSuccess) return hip_fail(ctx, r, "halo table upload");
+                r = launch_copy_boxes(hs, reinterpret_cast<const CopyBoxEntry *>(ctx->arena_base + off), n, esz,
+                                      max_elems);
+                if (r != hipSuccess) return hip_fail(ctx, r, "halo refresh");
+            }
+            const uint64_t p = bump(ctx, s);
+            ctx->stats.dispatches++;
+            trace_op(ctx, 0, s, ~0ull, 0, (uint64_t)n, 2);
+            Fence done;
+            done.add(s, p);
+            ctx->arena.release(off, done);
+            for (size_t i = b; i < b + n; ++i) {
+                Chunk *c = mine[i].first;
+                HaloSrc &h = *mine[i].second;
+                c->data_ready.add(s, p);
+                c->last_access.add(s, p);
+                h.k->last_access.add(s, p);
+                if (!c->arr->host_backed) c->host_valid = false;
+                h.ver = h.k->version;
+                h.valid = true;
+                ctx->stats.halo_copies++;
+            }
+        }
+    }
+    return LT_OK;
 }
 
 lt_status batch_flush(Ctx *ctx) {
@@ -1498,6 +1623,8 @@ lt_status launch(Ctx *ctx, lt_kernel *k, int nd, const int64_t *grid,
         }
         P.ready.add(s, bump(ctx, s));
     }
+    st = refresh_launch_halos(ctx, plans, arrs, def->nparam);
+    if (st) return st;
     for (auto &tp : plans) {
         tp.id = ctx->next_task_id++;
         ctx->launches.at(L).tasks.push_back(tp.id);

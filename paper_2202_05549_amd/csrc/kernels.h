@@ -84,6 +84,16 @@ inline int64_t kmeans_update_slots(const int64_t *lo, const int64_t *hi, const i
 }
 
 // Runtime helpers.
+// Copies boxes of elements between device buffers: entry i copies ext[0] x
+// ext[1] x ext[2] elements (last axis fastest) from src to dst with the given
+// element strides.  One dispatch for many small pieces (halo refreshes).
+struct CopyBoxEntry {
+    int64_t src, dst;        // byte addresses of the first element
+    int64_t ext[3];
+    int64_t ss[3], ds[3];
+};
+hipError_t launch_copy_boxes(hipStream_t s, const CopyBoxEntry *table, int n, int esz, int64_t max_elems);
+
 // Sets `count` elements of size esz (1, 4 or 8 bytes) at dst to *value.
 hipError_t launch_fill(hipStream_t s, void *dst, int64_t count, int esz,
                        const void *value);

@@ -328,6 +328,38 @@ hipError_t launch_kmeans_assign_f32(const KLaunch &L) {
     return hipGetLastError();
 }
 
+// ============================================================== copy boxes
+// blockIdx.y = entry; threads stride over the entry's elements.
+template <class T>
+__global__ __launch_bounds__(256) void k_copy_boxes(const CopyBoxEntry *table) {
+    const CopyBoxEntry &e = table[blockIdx.y];
+    const int64_t n2 = e.ext[2], n1 = e.ext[1];
+    const int64_t total = e.ext[0] * n1 * n2;
+    const LT_GLOBAL T *S = gp<const T>(e.src);
+    LT_GLOBAL T *D = gp<T>(e.dst);
+    for (int64_t f = (int64_t)blockIdx.x * 256 + threadIdx.x; f < total; f += (int64_t)gridDim.x * 256) {
+        const int64_t i2 = f % n2, r = f / n2;
+        const int64_t i1 = r % n1, i0 = r / n1;
+        D[i0 * e.ds[0] + i1 * e.ds[1] + i2 * e.ds[2]] = S[i0 * e.ss[0] + i1 * e.ss[1] + i2 * e.ss[2]];
+    }
+}
+
+hipError_t launch_copy_boxes(hipStream_t s, const CopyBoxEntry *table, int n, int esz, int64_t max_elems) {
+    if (n <= 0 || max_elems <= 0) return hipSuccess;
+    if (n > 65535) return hipErrorInvalidValue;
+    const int64_t bx = std::min<int64_t>((max_elems + 255) / 256, 64);
+    const dim3 grid((unsigned)bx, (unsigned)n);
+    if (esz == 4)
+        hipLaunchKernelGGL(k_copy_boxes<uint32_t>, grid, dim3(256), 0, s, table);
+    else if (esz == 8)
+        hipLaunchKernelGGL(k_copy_boxes<uint64_t>, grid, dim3(256), 0, s, table);
+    else if (esz == 1)
+        hipLaunchKernelGGL(k_copy_boxes<uint8_t>, grid, dim3(256), 0, s, table);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
 // =================================================================== fill
 template <class T>
 __global__ __launch_bounds__(256) void k_fill(T *p, int64_t count, T v) {

@@ -89,8 +89,13 @@ lt_status make_chunks(Ctx *ctx, Array *arr, const lt_dist *dist) {
         arr->dist_kind = LT_DIST_BLOCK;
         if (dist && dist->kind == LT_DIST_STENCIL) {
             for (int a = 0; a < MAXD; ++a) {
-                const int64_t h = a < nd ? dist->halo[a] : 0;
+                int64_t h = a < nd ? dist->halo[a] : 0;
                 if (h < 0) return set_err(ctx, LT_ERR_INVALID, "negative halo on axis %d", a);
+                // along the contiguous axis the stored halo is a whole number
+                // of 16-byte words, so rows of a chunk keep 16-byte alignment
+                // (vector loads) whenever the core width allows it
+                const int64_t w = arr->esz < 16 ? 16 / arr->esz : 1;
+                if (a == nd - 1 && h > 0) h = (h + w - 1) / w * w;
                 arr->halo[a] = h;
                 if (h > 0) arr->has_halo = true;
             }

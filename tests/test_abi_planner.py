@@ -336,6 +336,25 @@ def test_halo_reads_are_served_by_one_chunk():
     ctx.close()
 
 
+def test_halo_refreshes_are_batched_per_launch():
+    # grouped executor: one refresh dispatch and one kernel dispatch per sweep
+    n, m = 256, 512
+    ctx = dry(exec_mode=1)
+    a = ctx.array([n, m], chunk=[64, 128], halo=[1, 1])
+    b = ctx.array([n, m], chunk=[64, 128], halo=[1, 1])
+    a.fill(1.0)
+    b.fill(0.0)
+    ctx.reset_stats()
+    inp, out = a, b
+    for _ in range(4):
+        ctx.launch("jacobi2d_f32", [n, m], [1, 64], [64, 128], args=[n, m, out, inp])
+        inp, out = out, inp
+    ctx.sync()
+    s = ctx.stats()
+    assert s["dispatches"] == 4 + 3 and s["bytes_d2d"] == 0 and s["assembled_regions"] == 0
+    ctx.close()
+
+
 def test_halo_stores_cores_with_replicas():
     ctx = dry()
     x = ctx.array([100], chunk=[30], halo=[2])
