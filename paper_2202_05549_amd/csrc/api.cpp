@@ -166,6 +166,16 @@ lt_status sync_all(Ctx *ctx) {
     return LT_OK;
 }
 
+// The point after which every chunk of the array holds its final data on
+// the device (pending grouped work is issued first).
+lt_status array_ready_fence(Ctx *ctx, Array *arr, Fence *out) {
+    lt_status st = flush_all(ctx);
+    if (st) return st;
+    *out = Fence();
+    for (Chunk *c : arr->chunks) out->merge(c->data_ready);
+    return LT_OK;
+}
+
 // Issues the write-back of a host-backed array's dirty chunks to its home
 // buffer without waiting; *out = the point after which the home buffer holds
 // the array's contents.

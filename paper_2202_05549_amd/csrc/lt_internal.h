@@ -482,6 +482,7 @@ void prof_collect(Ctx *ctx);
 lt_status wait_fence(Ctx *ctx, const Fence &f);
 bool fence_done(Ctx *ctx, const Fence &f);
 lt_status array_flush_async(Ctx *ctx, Array *arr, Fence *out);
+lt_status array_ready_fence(Ctx *ctx, Array *arr, Fence *out);
 lt_status array_write(Ctx *ctx, Array *arr, const void *src, bool device_src);
 lt_status array_read(Ctx *ctx, Array *arr, void *dst, bool device_dst);
 lt_status array_fill(Ctx *ctx, Array *arr, const void *scalar);

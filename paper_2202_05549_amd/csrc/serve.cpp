@@ -25,7 +25,10 @@ struct SReq {
     uint64_t id = 0;
     lt_request r;
     double t_submit = 0, t_admit = 0;
-    Fence done;
+    Fence computed;          // the output's device copy is final after this
+    Fence done;              // ... and back in host memory after this
+    bool flushed = false;
+    lt_array *out = nullptr;
     int64_t footprint = 0;
     bool hit = false;
     std::vector<lt_array *> owned;
@@ -179,7 +182,22 @@ lt_status admit(lt_server *s, SReq *q) {
         st = lt_launch(ctx, s->kg, 2, grid, block, sb, nullptr, a, 6, nullptr);
         if (st) return st;
     }
-    return array_flush_async(ctx, out, &q->done);
+    // the write-back is issued once the result is computed (progress): the
+    // D2H queue then never holds a copy that waits on unfinished work ahead
+    // of copies that could run
+    q->out = out;
+    return array_ready_fence(ctx, out, &q->computed);
+}
+
+// Issues the output write-back of requests whose compute has finished.
+lt_status flush_ready(lt_server *s) {
+    for (SReq *q : s->active) {
+        if (q->flushed || !fence_done(s->ctx, q->computed)) continue;
+        lt_status st = array_flush_async(s->ctx, q->out, &q->done);
+        if (st) return st;
+        q->flushed = true;
+    }
+    return LT_OK;
 }
 
 void release(lt_server *s, SReq *q) {
@@ -215,9 +233,14 @@ void finish(lt_server *s, SReq *q, lt_status st) {
 // Completes finished requests, then admits queued ones in arrival order while
 // a slot is free and the footprint fits.
 void progress(lt_server *s) {
+    lt_status fs = flush_ready(s);
+    if (fs != LT_OK && s->ctx->sticky == LT_OK) {
+        s->ctx->sticky = fs;
+        s->ctx->sticky_msg = s->ctx->err;
+    }
     for (size_t i = 0; i < s->active.size();) {
         SReq *q = s->active[i];
-        if (fence_done(s->ctx, q->done)) {
+        if (q->flushed && fence_done(s->ctx, q->done)) {
             s->admitted -= q->footprint;
             s->active.erase(s->active.begin() + i);
             lt_status st = s->ctx->sticky;
@@ -306,8 +329,9 @@ lt_status lt_server_drain(lt_server *s, lt_completion *out, int32_t cap, int32_t
     while (!s->queue.empty() || !s->active.empty()) {
         progress(s);
         if (s->active.empty()) continue;
-        // block on the oldest active request
-        lt_status st = wait_fence(s->ctx, s->active.front()->done);
+        // block on the oldest active request: its compute, then its copy
+        SReq *q = s->active.front();
+        lt_status st = wait_fence(s->ctx, q->flushed ? q->done : q->computed);
         if (st) return st;
     }
     *n = take(s, out, out ? cap : 0);
