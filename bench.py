@@ -580,6 +580,57 @@ def bench_jacobi_tiled(args, L, torch):
     return line
 
 
+# ===================================================================== disk
+def bench_disk(args, L, torch):
+    """Out-of-core Jacobi through the memory hierarchy: 8192 x 8192 float32
+    ping-pong fields (512 MiB) with a 128 MiB device budget.  Spilled chunks
+    live in pinned host memory (no host budget), or, with a 128 MiB host
+    budget, the rest move to the spill file (the disk tier)."""
+    import tempfile
+
+    import synthetic
+
+    n, sweeps, rows = 8192, 10, 512
+    x0 = synthetic.jacobi2d_input(n, seed=1)
+    step_bytes = sweeps * n * n * 8
+    res = {}
+    spill_dir = tempfile.mkdtemp(prefix="lt_bench_")
+    for name, hb in (("host_tier", 0), ("disk_tier", 128 << 20)):
+        ctx = L.Context(device_budget_bytes=128 << 20, host_budget_bytes=hb, spill_dir=spill_dir,
+                        stage_threshold_bytes=64 << 20)
+        try:
+            a = ctx.array([n, n], chunk=[rows, 0])
+            b = ctx.array([n, n], chunk=[rows, 0])
+            a.write(x0)
+            b.fill(0.0)
+            ctx.sync()
+            ctx.reset_stats()
+            s0 = time.perf_counter()
+            inp, out = a, b
+            for _ in range(sweeps):
+                ctx.launch("jacobi2d_f32", [n, n], [1, 256], [rows, 0], args=[n, n, out, inp])
+                inp, out = out, inp
+            ctx.sync()
+            wall = time.perf_counter() - s0
+            st = ctx.stats()
+        finally:
+            ctx.close()
+        res[name] = {"gbs": step_bytes / wall / 1e9, "ms_per_step": wall * 1e3,
+                     "h2d_gb": st["bytes_h2d"] / 1e9, "d2h_gb": st["bytes_d2h"] / 1e9,
+                     "disk_write_gb": st["bytes_disk_write"] / 1e9, "disk_read_gb": st["bytes_disk_read"] / 1e9,
+                     "disk_gbs": (st["bytes_disk_write"] + st["bytes_disk_read"]) / wall / 1e9}
+        log("%s: %s" % (name, json.dumps(res[name])))
+    m = res["disk_tier"]
+    line = base_line({"workload": "jacobi2d 8192x8192 f32, 10 sweeps, 512-row chunks, device budget 128 MiB, "
+                                  "host spill budget 128 MiB, the rest in a spill file (disk tier)",
+                      "executor": "plain"}, 1, 0)
+    line.update({"value": round(m["gbs"], 2), "unit": "GB/s", "ms_per_step": round(m["ms_per_step"], 2),
+                 "dtype": "f32", "disk_tier": {k: round(v, 3) for k, v in m.items()},
+                 "host_tier": {k: round(v, 3) for k, v in res["host_tier"].items()},
+                 "disk_over_host": round(m["gbs"] / res["host_tier"]["gbs"], 3)})
+    return line
+
+
 # =================================================================== kmeans
 def bench_kmeans(args, L, torch):
     """The K-Means loop: assignment, centre update (reduce(+) of per-cluster
@@ -681,7 +732,7 @@ def main():
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=None)
     ap.add_argument("--workload", choices=["jacobi", "stencil1d", "gemm_ooc", "batch", "serve", "kmeans",
-                                           "jacobi_tiled"],
+                                           "jacobi_tiled", "disk"],
                     default="jacobi")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--rows", type=int, default=8, help="rows per Jacobi tile (8, 16, 32)")
@@ -714,7 +765,8 @@ def main():
     if args.calibrate_copy:
         calibration_copy(torch)
     fn = {"jacobi": bench_jacobi, "stencil1d": bench_stencil1d, "gemm_ooc": bench_gemm_ooc, "batch": bench_batch,
-          "serve": bench_serve, "kmeans": bench_kmeans, "jacobi_tiled": bench_jacobi_tiled}[args.workload]
+          "serve": bench_serve, "kmeans": bench_kmeans, "jacobi_tiled": bench_jacobi_tiled,
+          "disk": bench_disk}[args.workload]
     line = fn(args, L, torch)
     print(json.dumps(line), flush=True)
 

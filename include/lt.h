@@ -112,6 +112,16 @@ typedef struct lt_config {
                                        waves) or 4; 0 = 4.  Changes speed
                                        only, never results.                   */
     int32_t reserved[3];
+    uint64_t host_budget_bytes;     /* cap on the pinned host memory of spill
+                                       buffers (chunks of device-home arrays
+                                       evicted from the device); beyond it the
+                                       least recently used ones move to a file
+                                       in spill_dir (Sec. 3.4 disk tier);
+                                       0 = no cap, no disk                     */
+    const char *spill_dir;          /* directory of the spill file; NULL =
+                                       $TMPDIR or /tmp.  The file is unlinked
+                                       at creation and vanishes with the
+                                       context.                                 */
 } lt_config;
 
 #define LT_ORDER_ROWMAJOR 0
@@ -474,6 +484,9 @@ typedef struct lt_stats {
     uint64_t assembled_regions, direct_regions;
     double plan_seconds;           /* host time spent planning and issuing */
     uint64_t halo_copies;          /* replica refreshes of halo distributions */
+    uint64_t bytes_disk_write;     /* spill buffers moved to the disk tier  */
+    uint64_t bytes_disk_read;      /* ... and read back                      */
+    uint64_t host_spill_bytes;     /* pinned spill memory held now          */
 } lt_stats;
 
 lt_status lt_stats_get(lt_context *ctx, lt_stats *out);
@@ -482,7 +495,7 @@ lt_status lt_stats_reset(lt_context *ctx);
 /* ------------------------------------------------------------------- trace
  * With cfg.trace = 1 every device operation is recorded in order:
  * kind 0 kernel dispatch, 1 H2D, 2 D2H, 3 D2D, 4 fill, 5 evict (no copy),
- * 6 alloc, 7 free.  `task` is the task id (or ~0), `a`/`b` carry
+ * 6 alloc, 7 free, 8 spill buffer written to the disk tier, 9 read back.  `task` is the task id (or ~0), `a`/`b` carry
  * kind-specific values (bytes, arena offset, chunk id), resident is the
  * device bytes held after the operation. */
 typedef struct lt_trace_rec {

@@ -47,7 +47,7 @@ class lt_config(C.Structure):
                 ("stage_threshold_bytes", C.c_uint64), ("device_arena", C.c_void_p),
                 ("arena_bytes", C.c_uint64), ("trace", C.c_int32), ("sb_order", C.c_int32),
                 ("drain_workgroups", C.c_int32), ("batch_flush_tasks", C.c_int32), ("drain_vectors", C.c_int32),
-                ("reserved", C.c_int32 * 3)]
+                ("reserved", C.c_int32 * 3), ("host_budget_bytes", C.c_uint64), ("spill_dir", C.c_char_p)]
 
 
 class lt_box(C.Structure):
@@ -80,7 +80,9 @@ class lt_stats(C.Structure):
         "launches", "tasks", "dispatches", "bytes_h2d", "bytes_d2h", "bytes_d2d", "copies_h2d",
         "copies_d2h", "copies_d2d", "evictions_clean", "evictions_dirty", "resident_bytes",
         "peak_resident_bytes", "staged_peak_bytes", "throttle_waits", "assembled_regions",
-        "direct_regions")] + [("plan_seconds", C.c_double), ("halo_copies", C.c_uint64)]
+        "direct_regions")] + [("plan_seconds", C.c_double), ("halo_copies", C.c_uint64),
+                              ("bytes_disk_write", C.c_uint64), ("bytes_disk_read", C.c_uint64),
+                              ("host_spill_bytes", C.c_uint64)]
 
 
 class lt_trace_rec(C.Structure):
@@ -288,6 +290,8 @@ class Context:
         for k, v in cfg.items():
             if k == "device_arena":
                 v = C.c_void_p(v)
+            if k == "spill_dir" and isinstance(v, str):
+                v = v.encode()
             setattr(c, k, v)
         h = _P()
         st = lt_context_create(C.byref(c), C.byref(h))

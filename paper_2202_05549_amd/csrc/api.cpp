@@ -1,4 +1,6 @@
 // C ABI of the runtime: contexts, arrays, kernels, launch/sync, introspection.
+#include <unistd.h>
+
 #include <algorithm>
 #include <cstdio>
 #include <cstring>
@@ -145,10 +147,7 @@ lt_status sync_all(Ctx *ctx) {
             continue;
         }
         for (Chunk *c : arr->chunks) {
-            if (c->host_owned && c->host_ptr) {
-                if (ctx->dry) free(c->host_ptr);
-                else (void)hipHostFree(c->host_ptr);
-            }
+            free_spill(ctx, c);
             delete c;
         }
         arr->magic = 0;
@@ -208,6 +207,8 @@ void ctx_release_all(Ctx *ctx) {
         for (void *p : ctx->host_allocs) (void)hipHostFree(p);
         for (void *p : ctx->staging_free) (void)hipHostFree(p);
         if (ctx->status_host) (void)hipHostFree(ctx->status_host);
+        if (ctx->spill_fd >= 0) (void)close(ctx->spill_fd);
+        ctx->spill_fd = -1;
     } else {
         for (void *p : ctx->staging_free) free(p);
     }
@@ -326,7 +327,7 @@ lt_status array_read(Ctx *ctx, Array *arr, void *dst, bool device_dst) {
             if (st) return st;
             uint64_t p = bump(ctx, ctx->d2h);
             c->last_access.add(ctx->d2h, p);
-        } else if (c->host_valid && c->host_ptr) {
+        } else if (c->host_valid && (c->host_ptr || c->disk_valid)) {
             need_host = true;
         }
     }
@@ -334,7 +335,10 @@ lt_status array_read(Ctx *ctx, Array *arr, void *dst, bool device_dst) {
     if (r != hipSuccess) return hip_fail(ctx, r, "hipStreamSynchronize");
     if (need_host) {
         for (Chunk *c : arr->chunks) {
-            if ((c->dev_off >= 0 && c->dev_valid) || !c->host_valid || !c->host_ptr) continue;
+            if ((c->dev_off >= 0 && c->dev_valid) || !c->host_valid) continue;
+            st = host_resident(ctx, c);
+            if (st) return st;
+            if (!c->host_ptr) continue;
             int64_t off = 0;
             for (int a = 0; a < nd; ++a) off += c->box.lo[a] * arr->strides[a];
             if ((char *)dst + off * arr->esz == c->host_ptr) continue;  // the home buffer itself
@@ -482,6 +486,8 @@ lt_status lt_context_create(const lt_config *cfg_in, lt_context **out) {
     }
     Ctx *ctx = new Ctx();
     ctx->cfg = cfg;
+    if (cfg.spill_dir) ctx->spill_dir = cfg.spill_dir;
+    ctx->cfg.spill_dir = ctx->spill_dir.empty() ? nullptr : ctx->spill_dir.c_str();
     ctx->dry = cfg.dry_run != 0;
     ctx->ncompute = cfg.n_compute_streams;
     ctx->h2d = ctx->ncompute;

@@ -317,6 +317,8 @@ static lt_status stage_chunk(Ctx *ctx, Chunk *c, Mode m, const Box &region,
                     h.ver = h.k->host_version;
                     h.valid = true;
                 }
+            st = host_resident(ctx, c);  // back from the disk tier if it was moved there
+            if (st) return st;
             st = stream_wait(ctx, ctx->h2d, f);
             if (st) return st;
             int64_t ext[MAXD];

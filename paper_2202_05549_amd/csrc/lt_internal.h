@@ -199,6 +199,8 @@ struct Chunk {
     char *host_ptr = nullptr;  // address of element box.lo
     int64_t host_stride[MAXD] = {0, 0, 0};
     bool host_owned = false;   // runtime-allocated pinned spill buffer
+    int64_t disk_off = -1;     // offset of the chunk's slot in the spill file (-1 = none)
+    bool disk_valid = false;   // the spill file slot holds the current host copy
     bool host_valid = false;
     bool defined = false;      // holds data written by someone (else undefined)
 
@@ -397,6 +399,11 @@ struct lt_context {
     char *arena_base = nullptr;
     bool arena_owned = false;
     uint64_t lru_clock = 0;
+    // disk tier: pinned spill memory in use, the spill file and its next free slot
+    int64_t host_spill_bytes = 0;
+    int spill_fd = -1;
+    int64_t disk_next = 0;
+    std::string spill_dir;             // copy of cfg.spill_dir
 
     // objects
     uint64_t next_array_id = 1, next_chunk_id = 1, next_task_id = 1;
@@ -514,6 +521,11 @@ bool alloc_slab(Ctx *ctx, Array *arr);
 lt_status place_run(Ctx *ctx, const std::vector<Chunk *> &run, Fence *mem);
 lt_status evict_chunk(Ctx *ctx, Chunk *c);
 lt_status ensure_host_copy(Ctx *ctx, Chunk *c);
+// makes the host copy of c readable in memory (reads it back from the disk
+// tier when it was moved there); call before using c->host_ptr as a source
+lt_status host_resident(Ctx *ctx, Chunk *c);
+// releases c's pinned spill buffer (and its disk slot stays reserved)
+void free_spill(Ctx *ctx, Chunk *c);
 char *dev_ptr(Ctx *ctx, const Chunk *c);
 void trace_op(Ctx *ctx, int kind, int stream, uint64_t task, uint64_t chunk,
               uint64_t bytes, uint64_t offset);

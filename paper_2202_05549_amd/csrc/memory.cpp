@@ -14,9 +14,16 @@
 // fence of its last users, and whoever reuses it first waits for that fence
 // on the device (an event wait), so the host issues the whole schedule ahead
 // and never waits for the GPU except in lt_sync / lt_wait / lt_array_read.
+#include <fcntl.h>
+#include <unistd.h>
+
 #include <algorithm>
+#include <cerrno>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
 
 #include "lt_internal.h"
 
@@ -334,6 +341,106 @@ static void note_resident(Ctx *ctx) {
         ctx->stats.peak_resident_bytes = ctx->stats.resident_bytes;
 }
 
+// ------------------------------------------------------------ disk tier
+// Spill buffers of device-home arrays live in pinned host memory up to
+// cfg.host_budget_bytes; beyond it the least recently used ones move to a
+// spill file (one slot per chunk) and come back on demand (Sec. 3.4: the
+// memory hierarchy continues below host memory).  Moving a buffer waits on
+// the host for every copy into or out of it.
+
+static lt_status open_spill_file(Ctx *ctx) {
+    if (ctx->spill_fd >= 0 || ctx->dry) return LT_OK;
+    const char *env = getenv("TMPDIR");
+    std::string dir = ctx->cfg.spill_dir ? ctx->cfg.spill_dir : (env && *env ? env : "/tmp");
+    std::string path = dir + "/lt_spill_XXXXXX";
+    std::vector<char> name(path.begin(), path.end());
+    name.push_back('\0');
+    int fd = mkstemp(name.data());
+    if (fd < 0) return set_err(ctx, LT_ERR_OOM, "cannot create a spill file in %s: %s", dir.c_str(), strerror(errno));
+    unlink(name.data());  // the file lives as long as the descriptor
+    ctx->spill_fd = fd;
+    return LT_OK;
+}
+
+void free_spill(Ctx *ctx, Chunk *c) {
+    if (!c->host_owned || !c->host_ptr) return;
+    if (ctx->dry) free(c->host_ptr);
+    else (void)hipHostFree(c->host_ptr);
+    c->host_ptr = nullptr;
+    ctx->host_spill_bytes -= c->bytes;
+    ctx->stats.host_spill_bytes = (uint64_t)ctx->host_spill_bytes;
+}
+
+// Moves one spill buffer to the spill file (if it holds data the file does
+// not have yet) and frees it.
+static lt_status demote(Ctx *ctx, Chunk *c) {
+    Fence f = c->host_ready;
+    f.merge(c->last_access);
+    lt_status st = wait_fence(ctx, f);
+    if (st) return st;
+    if (c->host_valid && c->defined && !c->disk_valid) {
+        st = open_spill_file(ctx);
+        if (st) return st;
+        if (c->disk_off < 0) {
+            c->disk_off = ctx->disk_next;
+            ctx->disk_next += round_up(c->bytes, 4096);
+        }
+        if (!ctx->dry) {
+            int64_t done = 0;
+            while (done < c->bytes) {
+                ssize_t w = pwrite(ctx->spill_fd, c->host_ptr + done, (size_t)(c->bytes - done), c->disk_off + done);
+                if (w <= 0) return set_err(ctx, LT_ERR_OOM, "spill file write: %s", strerror(errno));
+                done += w;
+            }
+        }
+        c->disk_valid = true;
+        ctx->stats.bytes_disk_write += (uint64_t)c->bytes;
+        trace_op(ctx, 8, -1, ~0ull, c->id, (uint64_t)c->bytes, (uint64_t)c->disk_off);
+    }
+    free_spill(ctx, c);
+    return LT_OK;
+}
+
+// Frees pinned spill memory until `need` more bytes fit under the budget.
+static lt_status make_host_room(Ctx *ctx, int64_t need, const Chunk *keep) {
+    const int64_t cap = (int64_t)ctx->cfg.host_budget_bytes;
+    if (cap <= 0) return LT_OK;
+    if (need > cap)
+        return set_err(ctx, LT_ERR_BUDGET, "a %lld-byte spill buffer exceeds the host budget of %lld bytes",
+                       (long long)need, (long long)cap);
+    while (ctx->host_spill_bytes + need > cap) {
+        // any other buffer may go: a host copy is only read right after it
+        // is made resident, and demote() waits for the copies using it
+        Chunk *victim = nullptr;
+        for (Array *arr : ctx->arrays)
+            for (Chunk *c : arr->chunks)
+                if (c != keep && c->host_owned && c->host_ptr && (!victim || c->lru < victim->lru)) victim = c;
+        if (!victim)
+            return set_err(ctx, LT_ERR_BUDGET, "the host budget of %lld bytes is held by spill buffers in use",
+                           (long long)cap);
+        lt_status st = demote(ctx, victim);
+        if (st) return st;
+    }
+    return LT_OK;
+}
+
+lt_status host_resident(Ctx *ctx, Chunk *c) {
+    if (c->host_ptr || !c->host_owned || !c->disk_valid) return LT_OK;
+    lt_status st = ensure_host_copy(ctx, c);
+    if (st) return st;
+    if (!ctx->dry) {
+        int64_t done = 0;
+        while (done < c->bytes) {
+            ssize_t r = pread(ctx->spill_fd, c->host_ptr + done, (size_t)(c->bytes - done), c->disk_off + done);
+            if (r <= 0) return set_err(ctx, LT_ERR_OOM, "spill file read: %s", strerror(errno));
+            done += r;
+        }
+    }
+    ctx->stats.bytes_disk_read += (uint64_t)c->bytes;
+    trace_op(ctx, 9, -1, ~0ull, c->id, (uint64_t)c->bytes, (uint64_t)c->disk_off);
+    return LT_OK;
+}
+
 lt_status ensure_host_copy(Ctx *ctx, Chunk *c) {
     if (c->host_ptr) return LT_OK;
     Array *arr = c->arr;
@@ -344,6 +451,8 @@ lt_status ensure_host_copy(Ctx *ctx, Chunk *c) {
         for (int a = 0; a < MAXD; ++a) c->host_stride[a] = arr->strides[a];
         return LT_OK;
     }
+    lt_status st = make_host_room(ctx, c->bytes, c);
+    if (st) return st;
     void *p = nullptr;
     if (ctx->dry) {
         p = malloc(1);
@@ -354,6 +463,8 @@ lt_status ensure_host_copy(Ctx *ctx, Chunk *c) {
     }
     c->host_ptr = (char *)p;
     c->host_owned = true;
+    ctx->host_spill_bytes += c->bytes;
+    ctx->stats.host_spill_bytes = (uint64_t)ctx->host_spill_bytes;
     for (int a = 0; a < MAXD; ++a) c->host_stride[a] = c->dev_stride[a];
     return LT_OK;
 }
@@ -390,6 +501,7 @@ lt_status write_back(Ctx *ctx, Chunk *c, uint64_t *seq) {
     c->host_ready = Fence();
     c->host_ready.add(ctx->d2h, *seq);
     c->host_valid = true;
+    c->disk_valid = false;
     c->host_version = c->version;
     trace_op(ctx, 2, ctx->d2h, ~0ull, c->id, c->bytes, c->dev_off);
     return LT_OK;
@@ -422,6 +534,8 @@ lt_status refresh_halo(Ctx *ctx, Chunk *c, const Box &region) {
             trace_op(ctx, 3, ctx->h2d, ~0ull, c->id, (uint64_t)(h.box.volume(nd) * arr->esz), c->dev_off);
         } else {
             // the owner is not on the device: its newest copy is the host one
+            st = host_resident(ctx, k);
+            if (st) return st;
             if (!k->host_valid || !k->host_ptr)
                 return set_err(ctx, LT_ERR_INVALID, "internal: halo owner chunk %llu has no valid copy",
                                (unsigned long long)k->id);
@@ -437,7 +551,7 @@ lt_status refresh_halo(Ctx *ctx, Chunk *c, const Box &region) {
         const uint64_t p = bump(ctx, ctx->h2d);
         c->data_ready.add(ctx->h2d, p);
         c->last_access.add(ctx->h2d, p);
-        if (k->dev_off >= 0) k->last_access.add(ctx->h2d, p);
+        k->last_access.add(ctx->h2d, p);  // the copy reads k's device or host copy
         // a spill buffer holds the whole stored box, so it no longer matches;
         // a host-backed home buffer only ever receives c's core
         if (!arr->host_backed) c->host_valid = false;

@@ -374,3 +374,61 @@ def test_halo_distribution_validation():
         ctx.array([100], chunk=[30], halo=[-1])
     assert e.value.status == L.LT_ERR_INVALID
     ctx.close()
+
+
+# --------------------------------------------------------- disk tier (f4)
+
+def test_disk_tier_keeps_spill_memory_under_the_host_budget():
+    chunk = 1 << 14
+    n = 16 * chunk
+    hb = 3 * chunk * 4
+    ctx = dry(device_budget_bytes=4 * chunk * 4, host_budget_bytes=hb, trace=1, stage_threshold_bytes=1 << 40)
+    x = ctx.array([n], chunk=[chunk])
+    y = ctx.array([n], chunk=[chunk])
+    x.fill(1.0)
+    y.fill(0.0)
+    for _ in range(4):
+        ctx.launch("stencil1d_f32", [n], [256], [chunk], args=[n, y, x])
+        x, y = y, x
+    ctx.sync()
+    s = ctx.stats()
+    assert s["host_spill_bytes"] <= hb
+    assert s["bytes_disk_write"] > 0 and s["bytes_disk_read"] > 0
+    tr = ctx.trace()
+    writes = sum(r.bytes for r in tr if r.kind == 8)
+    reads = sum(r.bytes for r in tr if r.kind == 9)
+    assert writes == s["bytes_disk_write"] and reads == s["bytes_disk_read"]
+    # a chunk only comes back from disk after it went there
+    assert reads <= writes
+    ctx.close()
+
+
+def test_disk_tier_off_without_host_budget():
+    chunk = 1 << 14
+    n = 16 * chunk
+    ctx = dry(device_budget_bytes=4 * chunk * 4, stage_threshold_bytes=1 << 40)
+    x = ctx.array([n], chunk=[chunk])
+    y = ctx.array([n], chunk=[chunk])
+    x.fill(1.0)
+    for _ in range(3):
+        ctx.launch("stencil1d_f32", [n], [256], [chunk], args=[n, y, x])
+        x, y = y, x
+    ctx.sync()
+    s = ctx.stats()
+    assert s["bytes_disk_write"] == 0 and s["host_spill_bytes"] > 0
+    ctx.close()
+
+
+def test_host_budget_smaller_than_a_chunk_is_an_error():
+    chunk = 1 << 14
+    n = 8 * chunk
+    ctx = dry(device_budget_bytes=3 * chunk * 4, host_budget_bytes=chunk, stage_threshold_bytes=1 << 40)
+    x = ctx.array([n], chunk=[chunk])
+    y = ctx.array([n], chunk=[chunk])
+    with pytest.raises(L.LtError) as e:
+        x.fill(1.0)  # spilling the filled chunks already needs a spill buffer
+        for _ in range(3):
+            ctx.launch("stencil1d_f32", [n], [256], [chunk], args=[n, y, x])
+            x, y = y, x
+        ctx.sync()
+    assert e.value.status == L.LT_ERR_BUDGET

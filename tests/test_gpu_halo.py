@@ -118,3 +118,31 @@ def test_touch_on_halo_array_writes_owners_once(L):
         ctx.sync()
         got = y.read()
     assert np.all(got == 3)
+
+
+# ------------------------------------------------------------ disk tier
+
+@pytest.mark.parametrize("halo", [None, [1, 1]])
+def test_jacobi_through_the_disk_tier(L, halo, tmp_path):
+    # device budget of 20 of the 32 tiles and a host budget of 6 more: the
+    # other spill buffers live in the spill file and come back on demand
+    n, m = 1024, 1024
+    say("jacobi disk tier", halo)
+    x0 = synthetic.jacobi2d_input(n, m, seed=23)
+    tile = 256 * 256 * 4
+    with L.Context(device_budget_bytes=20 * tile, host_budget_bytes=6 * tile, spill_dir=str(tmp_path),
+                   stage_threshold_bytes=1 << 40) as ctx:
+        a = ctx.array([n, m], chunk=[256, 256], halo=halo)
+        b = ctx.array([n, m], chunk=[256, 256], halo=halo)
+        a.write(x0)
+        b.fill(0.0)
+        inp, out = a, b
+        for _ in range(5):
+            ctx.launch("jacobi2d_f32", [n, m], [1, 1], [256, 256], args=[n, m, out, inp])
+            inp, out = out, inp
+        ctx.sync()
+        got = inp.read()
+        st = ctx.stats()
+    assert st["bytes_disk_write"] > 0 and st["bytes_disk_read"] > 0
+    assert st["host_spill_bytes"] <= 6 * tile
+    assert np.array_equal(got, oracle.jacobi2d(x0, 5))
