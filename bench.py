@@ -85,22 +85,31 @@ def calibration_copy(torch, nbytes=1 << 30):
 # FETCH_SIZE and WRITE_SIZE passes scaled by the calibration copy, with the
 # digest of the kernel sources they were taken on: once the sources change,
 # the figure no longer describes the kernel and ``traffic`` is null.
-# the code of k_jacobi2d<8>: its body, the kernel and its launcher
+# the code of k_jacobi2d_stack<4>: its body (with the window it falls back
+# to), the kernel and its launcher
 JACOBI_SOURCES = [
     ("bodies.h", "// ---------------------------------------------------------------- jacobi2d",
      "// Rows [tr0, tr0 + 8 NG)"),
     ("kernels.hip", "// ================================================================= jacobi2d",
      "// Marching tiles of 8 NG rows"),
-    ("kernels.hip", "hipError_t launch_jacobi2d_f32(const KLaunch &L) {", "// ================================================================ hist256"),
+    ("kernels.hip", "// Stacked tiles of 4 RB rows", "// ================================================================ hist256"),
 ]
 
 TRAFFIC = {
-    # k_jacobi2d<8>, one 16384 x 16384 sweep per dispatch: FETCH_SIZE 593,272 KiB
-    # x 2.000 (the 1 GiB copy reads 524,309 KiB) + WRITE_SIZE 1,048,603 KiB x
-    # 1.000 (the copy writes 1,048,576 KiB)
-    "k_jacobi2d": {"sources": JACOBI_SOURCES, "digest": "474426d4977aea07",
-                   "bytes_per_dispatch": 593272 * 1024 * 2.000 + 1048603 * 1024},
+    # k_jacobi2d_stack<4>, one 16384 x 16384 sweep per dispatch: FETCH_SIZE
+    # 528,412 KiB x 2.000 (the 1 GiB copy reads 524,309 KiB) + WRITE_SIZE
+    # 1,048,826 KiB x 1.000 (the copy writes 1,048,576 KiB)
+    "k_jacobi2d_stack": {"sources": JACOBI_SOURCES, "digest": "e7b9d79b7799ba4e",
+                         "bytes_per_dispatch": 528412 * 1024 * 2.000 + 1048826 * 1024},
 }
+
+
+def jacobi_kernel_name(variant):
+    if variant in (8, 16, 32):
+        return "k_jacobi2d"
+    if variant in (132, 164, 228):
+        return "k_jacobi2d_march"
+    return "k_jacobi2d_stack"
 
 
 def kernel_digest(sources):
@@ -227,6 +236,7 @@ def bench_jacobi(args, L, torch):
         log("%s: %s" % (ex, json.dumps(res[ex])))
     best = max([e for e in ("grouped", "drain") if e in res] or list(res), key=lambda e: res[e]["gbs"])
     m = res[best]
+    jk = jacobi_kernel_name(args.rows)
     line = base_line({"workload": "jacobi2d 16384x16384 f32 ~U[0,1) seed 1, 100 ping-pong sweeps, 512-row chunks "
                                   "and superblocks, in HBM", "executor": best, "sweeps_per_step": SWEEPS,
                       "tasks_per_step": SWEEPS * N // CHUNK_ROWS}, args.steps, args.warmup)
@@ -235,8 +245,8 @@ def bench_jacobi(args, L, torch):
                  "p99_ms": round(m["p99_ms"], 3),
                  "roofline": {"bound": "hbm", "achieved": round(m["kernel_gbs"], 2), "peak": HBM_PEAK_GBS,
                               "unit": "GB/s", "frac": round(m["kernel_gbs"] / HBM_PEAK_GBS, 4),
-                              "traffic": traffic_for("k_jacobi2d") if best == "grouped" else None,
-                              "kernel": "k_drain" if best == "drain" else "k_jacobi2d",
+                              "traffic": traffic_for(jk) if best == "grouped" else None,
+                              "kernel": "k_drain" if best == "drain" else jk,
                               "kernel_avg_ms": round(m["kernel_avg_ms"], 4)}})
     for ex in execs:
         if ex == best:
@@ -534,7 +544,6 @@ def bench_jacobi_tiled(args, L, torch):
         ctx = L.Context(device_budget_bytes=budget, device_arena=arena.data_ptr(), arena_bytes=budget,
                         exec_mode=L.LT_EXEC_GROUPED)
         try:
-            ctx.tune("jacobi2d_f32", 8)
             a = ctx.array([n, n], chunk=chunk, halo=halo)
             b = ctx.array([n, n], chunk=chunk, halo=halo)
             a.write(x0)
@@ -735,7 +744,8 @@ def main():
                                            "jacobi_tiled", "disk"],
                     default="jacobi")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--rows", type=int, default=8, help="rows per Jacobi tile (8, 16, 32)")
+    ap.add_argument("--rows", type=int, default=0,
+                    help="Jacobi tile variant (lt_kernel_tune: 8/16/32, 132/164/228, 302/304/308; 0 = default)")
     ap.add_argument("--executor", choices=["all", "grouped", "drain", "plain"], default="all",
                     help="jacobi: executors to run (all = grouped, drain and plain)")
     ap.add_argument("--compute-streams", type=int, default=0,

@@ -282,10 +282,13 @@ lt_status lt_kernel_define(lt_context *ctx, const char *base,
 
 /* Selects a tuning variant of a built-in body for later launches through
  * this handle (0 = default).  Variants change only the work mapping, never
- * the per-element arithmetic: jacobi2d_f32 takes 8, 16 or 32 rows per
- * workgroup tile, all loaded at once, or 132, 164 or 228 for tiles of 32, 64
- * or 128 rows marched in groups of 8 (each input row loaded once per tile).
- * Unknown variants fall back to the default (16). */
+ * the per-element arithmetic.  jacobi2d_f32 takes:
+ *   8, 16 or 32: tiles of 1024 columns and that many rows, all loaded at once;
+ *   132, 164 or 228: tiles of 1024 columns and 32, 64 or 128 rows, marched in
+ *     groups of 8 (each input row loaded once per tile);
+ *   302, 304 or 308: tiles of 256 columns and 4 bands of 2, 4 or 8 rows, one
+ *     band per wave, the rows between bands exchanged on chip.
+ * Unknown variants fall back to the default (304). */
 lt_status lt_kernel_tune(lt_context *ctx, lt_kernel *k, int32_t variant);
 
 /* ------------------------------------------------------------------- launch */

@@ -213,56 +213,19 @@ struct JView {
     int vec;                  // float4 layout usable
 };
 
-// Rows [tr0, tr0 + RB) (within the task) of the 1024-column tile txi.
-// Full tiles load all RB + 2 rows of the lane's four columns before any
-// arithmetic (RB + 2 independent 16-byte loads in flight per lane) and write
-// with non-temporal stores; ragged tiles slide a three-row window.
-template <int RB>
-__device__ __forceinline__ void jacobi_tile(const JView &t, int64_t n, int64_t m, int64_t tr0, int txi) {
-    const int64_t r0 = tr0;
-    const int64_t r1e = r0 + RB < t.r1 ? r0 + RB : t.r1;
-    const int64_t r1 = r1e < n ? r1e : n;
-    const int64_t cend = t.c1 < m ? t.c1 : m;            // outputs [c0, cend)
-    const int64_t rcend = cend + 1 < m ? cend + 1 : m;     // inputs read up to rcend
-    const int64_t col = t.c0 + ((int64_t)txi * THREADS + threadIdx.x) * 4;
+// Sliding three-row window over rows [r0, r1) for the lane's four columns
+// starting at col (consecutive lanes hold consecutive column groups); any
+// tile shape, alignment or raggedness.  Lanes past the last output column
+// still load the halo column cend (read by their left neighbour lane) when
+// it lies inside the field.
+__device__ __forceinline__ void jacobi_window(const JView &t, int64_t n, int64_t m, int64_t col, int64_t r0,
+                                              int64_t r1) {
+    const int64_t cend = t.c1 < m ? t.c1 : m;
+    const int64_t rcend = cend + 1 < m ? cend + 1 : m;
     const bool active = col < cend;
     const LT_GLOBAL float *X = gp<const float>(t.x);
     LT_GLOBAL float *Y = gp<float>(t.y);
     const int lane = threadIdx.x & (WAVE - 1);
-
-    if (t.vec && r1 - r0 == RB) {
-        float4 v[RB + 2];
-#pragma unroll
-        for (int i = 0; i < RB + 2; ++i) {
-            const int64_t r = r0 - 1 + i;
-            if (active && r >= 0 && r < n)
-                v[i] = ld4<float4>(X + r * t.xs + col);
-            else
-                v[i] = make_float4(0.f, 0.f, 0.f, 0.f);
-        }
-#pragma unroll
-        for (int i = 1; i <= RB; ++i) {
-            const int64_t r = r0 - 1 + i;
-            const float4 up = v[i - 1], mid = v[i], dn = v[i + 1];
-            float left = __shfl_up(mid.w, 1);
-            float right = __shfl_down(mid.x, 1);
-            const LT_GLOBAL float *row = X + r * t.xs;
-            if (active && lane == 0) left = (col - 1 >= 0) ? row[col - 1] : 0.f;
-            if (active && (lane == WAVE - 1 || col + 4 >= cend)) right = (col + 4 < m) ? row[col + 4] : 0.f;
-            if (active) {
-                float4 o;
-                o.x = jpoint(up.x, dn.x, left, mid.y);
-                o.y = jpoint(up.y, dn.y, mid.x, mid.z);
-                o.z = jpoint(up.z, dn.z, mid.y, mid.w);
-                o.w = jpoint(up.w, dn.w, mid.z, right);
-                nt_store4(Y + r * t.ys + col, o);
-            }
-        }
-        return;
-    }
-
-    // lanes past the last output column still load the halo column cend
-    // (read by their left neighbour lane) when it lies inside the field
     auto load4 = [&](int64_t r, float *v) {
         if (r < 0 || r >= n || col >= rcend) {
             v[0] = v[1] = v[2] = v[3] = 0.f;
@@ -308,6 +271,110 @@ __device__ __forceinline__ void jacobi_tile(const JView &t, int64_t n, int64_t m
             up[j] = mid[j];
             mid[j] = dn[j];
         }
+    }
+}
+
+// Rows [tr0, tr0 + RB) (within the task) of the 1024-column tile txi.
+// Full tiles load all RB + 2 rows of the lane's four columns before any
+// arithmetic (RB + 2 independent 16-byte loads in flight per lane) and write
+// with non-temporal stores; ragged tiles slide a three-row window.
+template <int RB>
+__device__ __forceinline__ void jacobi_tile(const JView &t, int64_t n, int64_t m, int64_t tr0, int txi) {
+    const int64_t r0 = tr0;
+    const int64_t r1e = r0 + RB < t.r1 ? r0 + RB : t.r1;
+    const int64_t r1 = r1e < n ? r1e : n;
+    const int64_t cend = t.c1 < m ? t.c1 : m;            // outputs [c0, cend)
+    const int64_t col = t.c0 + ((int64_t)txi * THREADS + threadIdx.x) * 4;
+    const bool active = col < cend;
+    const LT_GLOBAL float *X = gp<const float>(t.x);
+    LT_GLOBAL float *Y = gp<float>(t.y);
+    const int lane = threadIdx.x & (WAVE - 1);
+
+    if (t.vec && r1 - r0 == RB) {
+        float4 v[RB + 2];
+#pragma unroll
+        for (int i = 0; i < RB + 2; ++i) {
+            const int64_t r = r0 - 1 + i;
+            if (active && r >= 0 && r < n)
+                v[i] = ld4<float4>(X + r * t.xs + col);
+            else
+                v[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+#pragma unroll
+        for (int i = 1; i <= RB; ++i) {
+            const int64_t r = r0 - 1 + i;
+            const float4 up = v[i - 1], mid = v[i], dn = v[i + 1];
+            float left = __shfl_up(mid.w, 1);
+            float right = __shfl_down(mid.x, 1);
+            const LT_GLOBAL float *row = X + r * t.xs;
+            if (active && lane == 0) left = (col - 1 >= 0) ? row[col - 1] : 0.f;
+            if (active && (lane == WAVE - 1 || col + 4 >= cend)) right = (col + 4 < m) ? row[col + 4] : 0.f;
+            if (active) {
+                float4 o;
+                o.x = jpoint(up.x, dn.x, left, mid.y);
+                o.y = jpoint(up.y, dn.y, mid.x, mid.z);
+                o.z = jpoint(up.z, dn.z, mid.y, mid.w);
+                o.w = jpoint(up.w, dn.w, mid.z, right);
+                nt_store4(Y + r * t.ys + col, o);
+            }
+        }
+        return;
+    }
+
+    jacobi_window(t, n, m, col, r0, r1);
+}
+
+// Tiles of 256 columns and 4 RB rows starting at row tr0: wave w owns rows
+// [tr0 + w RB, tr0 + (w + 1) RB) of its lanes' four columns each.  In a full
+// tile only the two halo rows outside the tile come from memory; the rows
+// between waves pass through LDS, so a tile loads 4 RB + 2 rows rather than
+// 4 (RB + 2).  Ragged tiles slide a window per wave.  Called once per
+// workgroup (the LDS rows are not reused).
+template <int RB>
+__device__ __forceinline__ void jacobi_stack(const JView &t, int64_t n, int64_t m, int64_t tr0, int txi) {
+    const int w = threadIdx.x / WAVE, lane = threadIdx.x & (WAVE - 1);
+    const int64_t rend = t.r1 < n ? t.r1 : n;
+    const int64_t cend = t.c1 < m ? t.c1 : m;
+    const int64_t cw = t.c0 + (int64_t)txi * (WAVE * 4);
+    const int64_t col = cw + lane * 4;
+    const int64_t r0 = tr0 + (int64_t)w * RB;
+    // the branch is uniform over the workgroup: the full path has a barrier
+    if (!t.vec || tr0 + 4 * RB > rend || cw + WAVE * 4 > cend) {
+        const int64_t r1 = r0 + RB < rend ? r0 + RB : rend;
+        if (r0 < r1) jacobi_window(t, n, m, col, r0, r1);
+        return;
+    }
+    const LT_GLOBAL float *X = gp<const float>(t.x);
+    LT_GLOBAL float *Y = gp<float>(t.y);
+    __shared__ float4 s_first[THREADS / WAVE][WAVE], s_last[THREADS / WAVE][WAVE];
+    constexpr int NW = THREADS / WAVE;
+    float4 v[RB + 2];
+#pragma unroll
+    for (int i = 1; i <= RB; ++i) v[i] = ld4<float4>(X + (r0 - 1 + i) * t.xs + col);
+    v[0] = make_float4(0.f, 0.f, 0.f, 0.f);
+    v[RB + 1] = v[0];
+    if (w == 0 && r0 >= 1) v[0] = ld4<float4>(X + (r0 - 1) * t.xs + col);
+    if (w == NW - 1 && r0 + RB < n) v[RB + 1] = ld4<float4>(X + (r0 + RB) * t.xs + col);
+    s_first[w][lane] = v[1];
+    s_last[w][lane] = v[RB];
+    __syncthreads();
+    if (w > 0) v[0] = s_last[w - 1][lane];
+    if (w < NW - 1) v[RB + 1] = s_first[w + 1][lane];
+#pragma unroll
+    for (int i = 1; i <= RB; ++i) {
+        const int64_t r = r0 - 1 + i;
+        const float4 up = v[i - 1], mid = v[i], dn = v[i + 1];
+        float left = __shfl_up(mid.w, 1);
+        float right = __shfl_down(mid.x, 1);
+        const LT_GLOBAL float *row = X + r * t.xs;
+        if (lane == 0) left = (col - 1 >= 0) ? row[col - 1] : 0.f;
+        if (lane == WAVE - 1) right = (col + 4 < m) ? row[col + 4] : 0.f;
+        float4 o;
+        o.x = jpoint(up.x, dn.x, left, mid.y);
+        o.y = jpoint(up.y, dn.y, mid.x, mid.z);
+        o.z = jpoint(up.z, dn.z, mid.y, mid.w);
+        o.w = jpoint(up.w, dn.w, mid.z, right);
+        nt_store4(Y + r * t.ys + col, o);
     }
 }
 

@@ -106,10 +106,10 @@ hipError_t launch_stencil1d_f32(const KLaunch &L) {
 
 // ================================================================= jacobi2d
 // y[r][c] = 0.25*((x[r-1][c] + x[r+1][c]) + (x[r][c-1] + x[r][c+1])), zero
-// outside the n x m field.  A workgroup owns 1024 columns (4 per thread) of
-// RB consecutive rows and slides a three-row window down them, so every
-// input row is loaded once per tile; horizontal neighbours come from the
-// adjacent lanes.
+// outside the n x m field.  Each lane computes 4 adjacent columns and takes
+// its horizontal neighbours from the adjacent lanes.  A workgroup owns a
+// tile of either 1024 columns x RB rows (jacobi_tile, jacobi_march) or 256
+// columns x 4 RB rows, one RB-row band per wave (jacobi_stack, the default).
 struct JTask {
     JView v;
     int tx;           // column tiles
@@ -142,15 +142,32 @@ __global__ __launch_bounds__(256) void k_jacobi2d_march(JArgs a) {
     jacobi_march<NG>(t.v, a.n, a.m, t.v.r0 + (int64_t)tyi * 8 * NG, txi);
 }
 
+// Stacked tiles of 4 RB rows x 256 columns (jacobi_stack).
+template <int RB>
+__global__ __launch_bounds__(256) void k_jacobi2d_stack(JArgs a) {
+    const int b = xcd_remap(blockIdx.x, a.nblocks);
+    const int ti = find_task(a.begin, a.ntask, b);
+    const JTask &t = a.t[ti];
+    const int local = b - a.begin[ti];
+    const int tyi = local / t.tx, txi = local - tyi * t.tx;
+    jacobi_stack<RB>(t.v, a.n, a.m, t.v.r0 + (int64_t)tyi * 4 * RB, txi);
+}
+
 hipError_t launch_jacobi2d_f32(const KLaunch &L) {
     JArgs a;
     a.n = L.iarg[0];
     a.m = L.iarg[1];
     a.ntask = L.ntask;
-    // rows per tile: 8, 16 (default) or 32 (all rows loaded at once), or 32,
-    // 64 or 128 marched in groups of 8 (variants 132, 164, 228: 100 + rows)
+    // tiles of 1024 columns and 8, 16 or 32 rows (all rows loaded at once),
+    // or 32, 64 or 128 rows marched in groups of 8 (variants 132, 164, 228:
+    // 100 + rows); or 256 columns and 4 waves of 2, 4 (default) or 8 rows
+    // (variants 302, 304, 308: 300 + rows per wave)
     const bool march = L.variant == 132 || L.variant == 164 || L.variant == 228;
-    a.rows = march ? L.variant - 100 : (L.variant == 8 || L.variant == 32) ? L.variant : 16;
+    const bool plain = L.variant == 8 || L.variant == 16 || L.variant == 32;
+    const bool stack = !march && !plain;
+    const int wrows = L.variant == 302 ? 2 : L.variant == 308 ? 8 : 4;
+    a.rows = march ? L.variant - 100 : plain ? L.variant : 4 * wrows;
+    const int64_t tcols = stack ? 256 : 1024;
     int64_t nb = 0;
     for (int i = 0; i < L.ntask; ++i) {
         const KTask &k = L.tasks[i];
@@ -167,7 +184,7 @@ hipError_t launch_jacobi2d_f32(const KLaunch &L) {
         t.vec = ((t.x + t.c0 * 4) & 15) == 0 && ((t.y + t.c0 * 4) & 15) == 0 && (t.xs & 3) == 0 &&
                 (t.ys & 3) == 0 && ((t.c1 - t.c0) & 3) == 0;
         int64_t cols = t.c1 - t.c0, rows = t.r1 - t.r0;
-        jt.tx = cols > 0 ? (int)((cols + 1023) / 1024) : 0;
+        jt.tx = cols > 0 ? (int)((cols + tcols - 1) / tcols) : 0;
         int64_t ty = rows > 0 ? (rows + a.rows - 1) / a.rows : 0;
         a.begin[i] = (int)nb;
         nb += (int64_t)jt.tx * ty;
@@ -175,7 +192,14 @@ hipError_t launch_jacobi2d_f32(const KLaunch &L) {
     a.begin[L.ntask] = (int)nb;
     a.nblocks = (int)nb;
     if (nb == 0) return hipSuccess;
-    if (march) {
+    if (stack) {
+        if (wrows == 2)
+            hipLaunchKernelGGL(k_jacobi2d_stack<2>, dim3(grid_of(nb)), dim3(256), 0, L.stream, a);
+        else if (wrows == 8)
+            hipLaunchKernelGGL(k_jacobi2d_stack<8>, dim3(grid_of(nb)), dim3(256), 0, L.stream, a);
+        else
+            hipLaunchKernelGGL(k_jacobi2d_stack<4>, dim3(grid_of(nb)), dim3(256), 0, L.stream, a);
+    } else if (march) {
         if (a.rows == 32)
             hipLaunchKernelGGL(k_jacobi2d_march<4>, dim3(grid_of(nb)), dim3(256), 0, L.stream, a);
         else if (a.rows == 64)
