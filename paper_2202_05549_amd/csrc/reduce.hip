@@ -324,48 +324,70 @@ __device__ __forceinline__ void kmu_load(const LT_GLOBAL float *X, int64_t xs, c
     }
 }
 
-// Adds one step's P points into the wave's copy.  Lanes whose points share
-// a cluster add in rounds, in point order: a point's rank is the number of
-// earlier points of the step with its cluster, and round r adds the points
-// of rank r.  Labels are read with readlane (scalar, no LDS traffic).  A
-// wave's LDS operations complete in issue order, so round r + 1 reads what
-// round r wrote; the empty asm only stops the compiler from reordering or
-// caching LDS values across rounds.
-template <int DP>
-__device__ __forceinline__ void kmu_step(double *acc, int *cnt, int d, int q, int j, float x, int k) {
-    constexpr int P = 64 / DP;
-    int rank = 0, mr = 0;
-    if constexpr (P <= 16) {
+// Rank of this lane's point among the step's P = 64 / LP points: the number
+// of earlier points of the step (point q holds lanes q LP .. q LP + LP - 1)
+// with the same cluster.  With LP >= 4 the comparisons are spread over the
+// point's lanes: lane (q, c) compares with points c, c + LP, ... (fetched by
+// lane permutes) and the LP lanes add their counts, so a step costs P / LP
+// permutes per lane instead of P scalar reads.  Labels of -1 never add, so
+// their ranks do not matter.
+template <int LP>
+__device__ __forceinline__ int kmu_rank(int k, int q, int c) {
+    constexpr int P = 64 / LP;
+    int rank = 0;
+    if constexpr (LP >= 4) {
 #pragma unroll
-        for (int q2 = 0; q2 < P; ++q2) {
-            const int k2 = __builtin_amdgcn_readlane(k, q2 * DP);
+        for (int q2 = c; q2 < P; q2 += LP) {
+            const int k2 = __shfl(k, q2 * LP);
             rank += (q2 < q && k2 == k) ? 1 : 0;
         }
 #pragma unroll
+        for (int off = 1; off < LP; off <<= 1) rank += __shfl_xor(rank, off);
+    } else if constexpr (P <= 32) {
+#pragma unroll
         for (int q2 = 0; q2 < P; ++q2) {
-            const int r2 = __builtin_amdgcn_readlane(rank, q2 * DP);
-            const int k2 = __builtin_amdgcn_readlane(k, q2 * DP);
-            if (k2 >= 0 && r2 > mr) mr = r2;
+            const int k2 = __builtin_amdgcn_readlane(k, q2 * LP);
+            rank += (q2 < q && k2 == k) ? 1 : 0;
         }
     } else {
-        // many points per step (d <= 2): rolled loops keep the scalar
-        // registers in bounds
+        // one lane per point: a rolled loop keeps the scalar registers in bounds
 #pragma unroll 1
         for (int q2 = 0; q2 < P; ++q2) {
-            const int k2 = __builtin_amdgcn_readlane(k, q2 * DP);
+            const int k2 = __builtin_amdgcn_readlane(k, q2 * LP);
             rank += (q2 < q && k2 == k) ? 1 : 0;
         }
-#pragma unroll 1
-        for (int q2 = 0; q2 < P; ++q2) {
-            const int r2 = __builtin_amdgcn_readlane(rank, q2 * DP);
-            const int k2 = __builtin_amdgcn_readlane(k, q2 * DP);
-            if (k2 >= 0 && r2 > mr) mr = r2;
-        }
     }
-    for (int r = 0; r <= mr; ++r) {
-        if (k >= 0 && rank == r) {
-            if (j < d) acc[k * d + j] += (double)x;
-            if (j == 0) cnt[k] += 1;
+    return rank;
+}
+
+// LDS adds that return nothing (ds_add_f64, ds_add_u32): the wave issues
+// them without waiting for the old value.  No two of them ever touch the
+// same word concurrently (each wave owns its copy, and the rounds below
+// keep equal clusters out of one instruction), so the atomicity is never
+// exercised: they are ordinary read-add-writes, each correctly rounded, and
+// a wave's LDS operations complete in issue order.
+__device__ __forceinline__ void lds_add(double *p, double v) {
+    __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+__device__ __forceinline__ void lds_add(int *p, int v) {
+    __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+// Adds one step's points into the wave's copy.  Lanes whose points share a
+// cluster add in rounds, in point order: round r adds the points of rank r.
+// The ranks of one cluster are 0, 1, 2, ..., so the first round with no
+// point ends the step.  A wave's LDS operations complete in issue order, so
+// round r + 1 adds after round r; the empty asm only stops the compiler
+// from moving LDS operations across rounds.
+template <int DP>
+__device__ __forceinline__ void kmu_step(double *acc, int *cnt, int d, int ks, int q, int j, float x, int k) {
+    const int rank = kmu_rank<DP>(k, q, j);
+    for (int r = 0;; ++r) {
+        const bool mine = k >= 0 && rank == r;
+        if (!__ballot(mine)) break;
+        if (mine) {
+            if (j < d) lds_add(&acc[k * ks + j], (double)x);
+            if (j == 0) lds_add(&cnt[k], 1);
         }
         asm volatile("" ::: "memory");
     }
@@ -400,67 +422,37 @@ __device__ __forceinline__ KUReg kmu_regs(const KUTask &t) {
     return r;
 }
 
-__device__ __forceinline__ void kmu_clear(double *lds, int KD, int K) {
-    int *cnt_all = reinterpret_cast<int *>(lds + 4 * KD);
-    for (int i = threadIdx.x; i < 4 * KD; i += 256) lds[i] = 0.0;
+// A wave's copy holds cluster k's sums at k * KS .. k * KS + d - 1 with the
+// odd stride KS = d | 1: in one LDS instruction the lanes of different
+// points then spread over the banks instead of all landing on the bank of
+// feature j (an even stride of 16 doubles maps every cluster to one bank).
+__device__ __forceinline__ int kmu_stride(int d) { return d | 1; }
+
+__device__ __forceinline__ void kmu_clear(double *lds, int KDP, int K) {
+    int *cnt_all = reinterpret_cast<int *>(lds + 4 * KDP);
+    for (int i = threadIdx.x; i < 4 * KDP; i += 256) lds[i] = 0.0;
     for (int i = threadIdx.x; i < 4 * K; i += 256) cnt_all[i] = 0;
     __syncthreads();
 }
 
 // Adds the four wave copies in wave order and writes partial slot w.
 __device__ __forceinline__ void kmu_flush(const double *lds, int d, int K, const KUReg &t, int w) {
-    const int KD = K * d;
-    const int *cnt_all = reinterpret_cast<const int *>(lds + 4 * KD);
+    const int ks = kmu_stride(d), KDP = K * ks;
+    const int *cnt_all = reinterpret_cast<const int *>(lds + 4 * KDP);
     __syncthreads();
     LT_GLOBAL double *S = t.S + (int64_t)w * t.sslot;
-    for (int e = threadIdx.x; e < KD; e += 256) {
-        double s = lds[e];
-        s += lds[KD + e];
-        s += lds[2 * KD + e];
-        s += lds[3 * KD + e];
+    for (int e = threadIdx.x; e < K * d; e += 256) {
         const int k = e / d, jj = e - (e / d) * d;
+        const int i = k * ks + jj;
+        double s = lds[i];
+        s += lds[KDP + i];
+        s += lds[2 * KDP + i];
+        s += lds[3 * KDP + i];
         S[k * t.ss0 + jj * t.ss1] = s;
     }
     LT_GLOBAL int32_t *Cn = t.C + (int64_t)w * t.cslot;
     for (int k = threadIdx.x; k < K; k += 256)
         Cn[k * t.cs0] = cnt_all[k] + cnt_all[K + k] + cnt_all[2 * K + k] + cnt_all[3 * K + k];
-}
-
-// Rank of this lane's point among the step's P points (earlier points with
-// the same cluster) and the largest rank of the step; point q2 of the step
-// is held by lane q2 * LP.
-template <int LP>
-__device__ __forceinline__ void kmu_rank(int k, int q, int &rank, int &mr) {
-    constexpr int P = 64 / LP;
-    rank = 0;
-    mr = 0;
-    if constexpr (P <= 16) {
-#pragma unroll
-        for (int q2 = 0; q2 < P; ++q2) {
-            const int k2 = __builtin_amdgcn_readlane(k, q2 * LP);
-            rank += (q2 < q && k2 == k) ? 1 : 0;
-        }
-#pragma unroll
-        for (int q2 = 0; q2 < P; ++q2) {
-            const int r2 = __builtin_amdgcn_readlane(rank, q2 * LP);
-            const int k2 = __builtin_amdgcn_readlane(k, q2 * LP);
-            if (k2 >= 0 && r2 > mr) mr = r2;
-        }
-    } else {
-        // many points per step (d <= 2): rolled loops keep the scalar
-        // registers in bounds
-#pragma unroll 1
-        for (int q2 = 0; q2 < P; ++q2) {
-            const int k2 = __builtin_amdgcn_readlane(k, q2 * LP);
-            rank += (q2 < q && k2 == k) ? 1 : 0;
-        }
-#pragma unroll 1
-        for (int q2 = 0; q2 < P; ++q2) {
-            const int r2 = __builtin_amdgcn_readlane(rank, q2 * LP);
-            const int k2 = __builtin_amdgcn_readlane(k, q2 * LP);
-            if (k2 >= 0 && r2 > mr) mr = r2;
-        }
-    }
 }
 
 // Any d: one feature per lane (DP lanes per point).
@@ -471,11 +463,11 @@ __global__ __launch_bounds__(256) void k_kmeans_update(KUArgs a) {
     const int ti = find_task(a.begin, a.ntask, blockIdx.x);
     const KUReg t = kmu_regs(a.t[ti]);
     const int w = blockIdx.x - a.begin[ti];
-    const int d = a.d, K = a.K, KD = K * d;
+    const int d = a.d, K = a.K, ks = kmu_stride(d), KDP = K * ks;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    kmu_clear(lds, KD, K);
-    double *acc = lds + wave * KD;
-    int *cnt = reinterpret_cast<int *>(lds + 4 * KD) + wave * K;
+    kmu_clear(lds, KDP, K);
+    double *acc = lds + wave * KDP;
+    int *cnt = reinterpret_cast<int *>(lds + 4 * KDP) + wave * K;
     const int q = lane / DP, j = lane % DP;
     constexpr int64_t QUARTER = KMU_TILE / 4;
     constexpr int64_t BATCH = (int64_t)KMU_U * P;
@@ -490,7 +482,7 @@ __global__ __launch_bounds__(256) void k_kmeans_update(KUArgs a) {
             const bool more = pb + BATCH < p1;
             if (more) kmu_load<DP>(t.X, t.xs, t.LB, pb + BATCH, p1, q, j, d, K, xn, kn);
 #pragma unroll
-            for (int u = 0; u < KMU_U; ++u) kmu_step<DP>(acc, cnt, d, q, j, xv[u], kv[u]);
+            for (int u = 0; u < KMU_U; ++u) kmu_step<DP>(acc, cnt, d, ks, q, j, xv[u], kv[u]);
             if (more) {
 #pragma unroll
                 for (int u = 0; u < KMU_U; ++u) {
@@ -533,16 +525,17 @@ __device__ __forceinline__ void kmv_load(const KUReg &t, int64_t pb, int64_t p1,
 template <int VD>
 __device__ __forceinline__ void kmv_step(double *acc, int *cnt, int q, int c, float4 x, int k) {
     constexpr int LP = VD / 4;
-    int rank, mr;
-    kmu_rank<LP>(k, q, rank, mr);
-    for (int r = 0; r <= mr; ++r) {
-        if (k >= 0 && rank == r) {
-            double *e = acc + k * VD + 4 * c;
-            e[0] += (double)x.x;
-            e[1] += (double)x.y;
-            e[2] += (double)x.z;
-            e[3] += (double)x.w;
-            if (c == 0) cnt[k] += 1;
+    const int rank = kmu_rank<LP>(k, q, c);
+    for (int r = 0;; ++r) {
+        const bool mine = k >= 0 && rank == r;
+        if (!__ballot(mine)) break;
+        if (mine) {
+            double *e = acc + k * (VD | 1) + 4 * c;
+            lds_add(e, (double)x.x);
+            lds_add(e + 1, (double)x.y);
+            lds_add(e + 2, (double)x.z);
+            lds_add(e + 3, (double)x.w);
+            if (c == 0) lds_add(&cnt[k], 1);
         }
         asm volatile("" ::: "memory");
     }
@@ -555,11 +548,11 @@ __global__ __launch_bounds__(256) void k_kmeans_update_v(KUArgs a) {
     const int ti = find_task(a.begin, a.ntask, blockIdx.x);
     const KUReg t = kmu_regs(a.t[ti]);
     const int w = blockIdx.x - a.begin[ti];
-    const int K = a.K, KD = K * VD;
+    const int K = a.K, KDP = K * (VD | 1);
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    kmu_clear(lds, KD, K);
-    double *acc = lds + wave * KD;
-    int *cnt = reinterpret_cast<int *>(lds + 4 * KD) + wave * K;
+    kmu_clear(lds, KDP, K);
+    double *acc = lds + wave * KDP;
+    int *cnt = reinterpret_cast<int *>(lds + 4 * KDP) + wave * K;
     const int q = lane / LP, c = lane % LP;
     constexpr int64_t QUARTER = KMU_TILE / 4;
     constexpr int64_t BATCH = (int64_t)KMV_U * P;
@@ -624,7 +617,9 @@ hipError_t launch_kmeans_update_f32(const KLaunch &L) {
     }
     a.begin[L.ntask] = (int)nb;
     if (nb == 0) return hipSuccess;
-    const size_t lds = (size_t)4 * a.K * a.d * sizeof(double) + (size_t)4 * a.K * sizeof(int);
+    // four wave copies of K x (d | 1) float64 sums and K int32 counts: at
+    // most 4 x (1536 + 256) x 8 + 4 x 256 x 4 = 61,440 bytes
+    const size_t lds = (size_t)4 * a.K * (a.d | 1) * sizeof(double) + (size_t)4 * a.K * sizeof(int);
     const dim3 g((unsigned)nb), b(256);
     bool vec = a.d == a.dp && a.d >= 4;  // d in {4, 8, 16, 32}
     for (int i = 0; i < L.ntask && vec; ++i)
