@@ -1251,6 +1251,15 @@ static lt_status issue_exec(Ctx *ctx, lt_kernel *k, TaskPlan &tp, uint64_t L,
     done.add(s, pt);
     for (Temp &t : temps) ctx->arena.release(t.off, done);
     if (staged_copy) {
+        // the throttle will make the copy stream wait for this task: mark its
+        // end now, while it is the stream's last operation (the host runs
+        // ahead of the device, so a mark taken later would also cover tasks
+        // issued after it)
+        st = mark_tail(ctx, s);
+        if (st) {
+            unpin();
+            return st;
+        }
         ctx->staged.push_back({done, tp.footprint});
         ctx->staged_bytes += tp.footprint;
         ctx->stats.staged_peak_bytes = std::max<uint64_t>(ctx->stats.staged_peak_bytes, ctx->staged_bytes);

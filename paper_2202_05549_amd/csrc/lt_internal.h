@@ -500,6 +500,9 @@ void ctx_release_all(Ctx *ctx);
 // memory manager and streams (memory.cpp)
 uint64_t bump(Ctx *ctx, int stream);
 lt_status stream_wait(Ctx *ctx, int stream, const Fence &f);
+// Records an event at stream s's current end, so that a later wait for what
+// has been issued so far waits for exactly that and not for work issued after.
+lt_status mark_tail(Ctx *ctx, int s);
 lt_status copy_box(Ctx *ctx, int stream, char *dst, const int64_t *ds,
                    const char *src, const int64_t *ss, const int64_t *ext,
                    int nd, int esz, hipMemcpyKind kind);

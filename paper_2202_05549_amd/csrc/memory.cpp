@@ -173,15 +173,20 @@ static hipEvent_t get_event(Ctx *ctx) {
 
 uint64_t bump(Ctx *ctx, int s) { return ++ctx->streams[s].seq; }
 
-// Event whose completion implies stream t has executed through `seq`.
+// Event whose completion implies stream t has executed through `seq`: the
+// first mark at or after seq, else a new mark at the stream's current end
+// (which also covers everything issued after seq, so a wait on it may be
+// longer than needed; mark_tail avoids that for fences known to be waited on).
 static lt_status mark_at(Ctx *ctx, int t, uint64_t seq, hipEvent_t *ev, uint64_t *mseq) {
     Stream &S = ctx->streams[t];
-    for (auto &m : S.marks)
-        if (m.seq >= seq) {
-            *ev = m.ev;
-            *mseq = m.seq;
-            return LT_OK;
-        }
+    // marks are recorded in increasing seq order
+    auto it = std::lower_bound(S.marks.begin(), S.marks.end(), seq,
+                               [](const Mark &m, uint64_t v) { return m.seq < v; });
+    if (it != S.marks.end()) {
+        *ev = it->ev;
+        *mseq = it->seq;
+        return LT_OK;
+    }
     hipEvent_t e = get_event(ctx);
     if (!e) return set_err(ctx, LT_ERR_DEVICE, "hipEventCreate failed");
     hipError_t r = hipEventRecord(e, S.h);
@@ -190,6 +195,15 @@ static lt_status mark_at(Ctx *ctx, int t, uint64_t seq, hipEvent_t *ev, uint64_t
     *ev = e;
     *mseq = S.seq;
     return LT_OK;
+}
+
+lt_status mark_tail(Ctx *ctx, int s) {
+    if (ctx->dry) return LT_OK;
+    Stream &S = ctx->streams[s];
+    if (!S.marks.empty() && S.marks.back().seq == S.seq) return LT_OK;
+    hipEvent_t ev;
+    uint64_t mseq;
+    return mark_at(ctx, s, S.seq, &ev, &mseq);
 }
 
 lt_status stream_wait(Ctx *ctx, int s, const Fence &f) {
