@@ -118,7 +118,10 @@ __device__ __forceinline__ void drain_loop(const DTask *q, int ntasks, int32_t *
                     }
                 }
             }
-            if (t.ndeps) __threadfence();  // acquire: see the predecessors' writes
+            // acquire at device scope: invalidates this XCD's caches so the
+            // predecessors' writes are seen (a full fence would also write
+            // back the whole L2, which only a release needs)
+            if (t.ndeps) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
             s_task = cur;
             s_ok = ok;
         }
@@ -129,7 +132,9 @@ __device__ __forceinline__ void drain_loop(const DTask *q, int ntasks, int32_t *
         __syncthreads();
         if (threadIdx.x == 0) {
             const int32_t fl = t.flags;
-            if (fl & DF_RELEASE) __threadfence();           // plain stores become visible
+            // release at device scope: the workgroup's plain stores (complete
+            // at the barrier above) are written back from this XCD's L2
+            if (fl & DF_RELEASE) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
             else if (fl & DF_ATOMIC) __builtin_amdgcn_s_waitcnt(0);  // atomics performed
             int prev = atomicAdd(&ctr[task], 1);
             if (prev == t.ntiles - 1 && t.signal >= 0) atomicAdd(&ctr[t.signal], 1);
