@@ -49,12 +49,9 @@ __device__ __forceinline__ void run_tile(const DTask &t, int64_t local, int *sh)
             v.xs = t.xs;
             v.vec = t.vec;
             const int tyi = (int)(local / t.tx), txi = (int)(local - (int64_t)tyi * t.tx);
-            const int64_t rend = t.hi0 < t.n ? t.hi0 : t.n;
-            for (int sub = 0; sub < DJROWS / 8; ++sub) {
-                const int64_t tr0 = t.lo0 + (int64_t)tyi * DJROWS + sub * 8;
-                if (tr0 >= rend) break;
-                jacobi_tile<8>(v, t.n, t.m, tr0, txi);
-            }
+            // the tile's DJROWS rows marched in groups of 8 (each input row
+            // loaded once); jacobi_march clips at the task's last row
+            jacobi_march<DJROWS / 8>(v, t.n, t.m, t.lo0 + (int64_t)tyi * DJROWS, txi);
             break;
         }
         case DK_HIST256: {

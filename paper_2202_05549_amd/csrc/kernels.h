@@ -135,7 +135,7 @@ namespace lt {
 enum DKind { DK_TOUCH = 0, DK_STENCIL1D = 1, DK_JACOBI2D = 2, DK_HIST256 = 3, DK_SUM_PARTIALS = 4 };
 constexpr int DMAXDEP = 8;
 constexpr int64_t DSPAN = 65536;  // elements per tile of the 1-D bodies
-constexpr int DJROWS = 32;        // rows per Jacobi tile (four 8-row passes)
+constexpr int DJROWS = 128;       // rows per Jacobi tile (marched in groups of 8)
 
 struct DTask {
     int32_t kind;

@@ -95,18 +95,20 @@ def test_batched_stencil_pingpong_dependencies(L, wg):
     assert np.array_equal(got, oracle.stencil1d_iter(x0, 12))
 
 
-def test_batched_jacobi_sweeps(L):
-    n, m = 1000, 1500
-    say("batch jacobi")
+@pytest.mark.parametrize("n,m,sb", [(1000, 1500, 64), (1000, 1024, 256), (777, 2048, 384), (300, 4096, 128)])
+def test_batched_jacobi_sweeps(L, n, m, sb):
+    # superblocks smaller than a drain tile (ragged tiles), and larger ones
+    # whose full tiles take the marching path, with ragged last tasks
+    say("batch jacobi", n, m, sb)
     x0 = synthetic.jacobi2d_input(n, m, seed=14)
     with L.Context(device_budget_bytes=1 << 30) as ctx:
-        a = ctx.array([n, m], chunk=[64, 0])
-        b = ctx.array([n, m], chunk=[64, 0])
+        a = ctx.array([n, m], chunk=[sb, 0])
+        b = ctx.array([n, m], chunk=[sb, 0])
         a.write(x0)
         ctx.batch_begin()
         inp, out = a, b
         for _ in range(9):
-            ctx.launch("jacobi2d_f32", [n, m], [1, 1], [64, 0], args=[n, m, out, inp])
+            ctx.launch("jacobi2d_f32", [n, m], [1, 1], [sb, 0], args=[n, m, out, inp])
             inp, out = out, inp
         ctx.batch_end()
         ctx.sync()
