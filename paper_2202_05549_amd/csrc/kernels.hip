@@ -69,6 +69,7 @@ hipError_t launch_touch_i32(const KLaunch &L) {
 struct StTask {
     int64_t lo, hi;
     int64_t y, x;
+    int64_t span;     // outputs per workgroup: 1024 (one pass) or 8192 (streamed)
 };
 struct StArgs {
     int64_t n;
@@ -77,11 +78,16 @@ struct StArgs {
     StTask t[KMAXG];
 };
 
+// Small tasks (up to 2^21 outputs) take one span of 1024 outputs per
+// workgroup, so even a 2^17-element chunk spreads over 128 workgroups;
+// large ones stream 8192 outputs per workgroup with loads kept in flight,
+// which measured faster for tasks of 2^24 elements.
 __global__ __launch_bounds__(256) void k_stencil1d(StArgs a) {
     int ti = find_task(a.begin, a.ntask, blockIdx.x);
     const StTask &t = a.t[ti];
-    const int64_t s0 = t.lo + (int64_t)(blockIdx.x - a.begin[ti]) * 8192;
-    stencil_stream<4>(t.x, t.y, a.n, t.lo, t.hi, s0, s0 + 8192);
+    const int64_t s0 = t.lo + (int64_t)(blockIdx.x - a.begin[ti]) * t.span;
+    if (t.span == 1024) stencil_span(t.x, t.y, a.n, t.lo, t.hi, s0);
+    else stencil_stream<4>(t.x, t.y, a.n, t.lo, t.hi, s0, s0 + t.span);
 }
 
 hipError_t launch_stencil1d_f32(const KLaunch &L) {
@@ -96,7 +102,8 @@ hipError_t launch_stencil1d_f32(const KLaunch &L) {
         a.t[i].y = L.tasks[i].v[1].base;
         a.t[i].x = L.tasks[i].v[2].base;
         int64_t e = std::min(a.t[i].hi, a.n) - a.t[i].lo;
-        nb += e > 0 ? (e + 8191) / 8192 : 0;
+        a.t[i].span = e > (1 << 21) ? 8192 : 1024;
+        nb += e > 0 ? (e + a.t[i].span - 1) / a.t[i].span : 0;
     }
     a.begin[L.ntask] = (int)nb;
     if (nb == 0) return hipSuccess;

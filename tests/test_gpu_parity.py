@@ -69,7 +69,9 @@ def test_stencil1d_config1_bit_exact(L, mode):
 
 
 @pytest.mark.parametrize("n,chunk,block,sb", [(1000003, 99991, 1, 77777), (5, 2, 1, 1), (4099, 4096, 4, 8),
-                                              (123457, 1 << 14, 32, 96)])
+                                              (123457, 1 << 14, 32, 96),
+                                              # tasks above 2^21 elements take the streamed body
+                                              (5000011, 0, 1, 2500001), (4194304 + 8191, 0, 1, 4194304 + 8191)])
 def test_stencil1d_ragged_bit_exact(L, n, chunk, block, sb):
     say("stencil1d ragged", n, chunk, block, sb)
     x0 = synthetic.stencil1d_input(n, 17)
