@@ -77,6 +77,9 @@ typedef struct lt_kernel lt_kernel;
 #define LT_EXEC_PLAIN 0
 #define LT_EXEC_GROUPED 1
 
+#define LT_EVICT_NEXT_USE 0
+#define LT_EVICT_LRU 1
+
 typedef struct lt_config {
     int32_t device;                 /* HIP device ordinal                      */
     int32_t n_compute_streams;      /* >= 1; default 1                          */
@@ -111,7 +114,15 @@ typedef struct lt_config {
                                        are in flight): 2 (fewer registers, more
                                        waves) or 4; 0 = 4.  Changes speed
                                        only, never results.                   */
-    int32_t reserved[3];
+    int32_t evict_policy;           /* which chunks leave the device when the
+                                       budget is full (Sec. 3.4 evicts the least
+                                       recently used): LT_EVICT_NEXT_USE (0,
+                                       default) prefers chunks that the tasks
+                                       of the launch being issued need latest
+                                       or never, then the least recently used;
+                                       LT_EVICT_LRU (1) uses recency only.
+                                       Changes traffic only, never results.   */
+    int32_t reserved[2];
     uint64_t host_budget_bytes;     /* cap on the pinned host memory of spill
                                        buffers (chunks of device-home arrays
                                        evicted from the device); beyond it the

@@ -35,6 +35,8 @@ DTYPES = {LT_F32: np.float32, LT_I32: np.int32, LT_F64: np.float64, LT_I64: np.i
 NP2LT = {np.dtype(v): k for k, v in DTYPES.items()}
 
 LT_EXEC_PLAIN, LT_EXEC_GROUPED = 0, 1
+LT_EVICT_NEXT_USE = 0
+LT_EVICT_LRU = 1
 LT_ORDER_ROWMAJOR, LT_ORDER_SERPENTINE = 0, 1
 LT_DIST_BLOCK, LT_DIST_CUSTOM, LT_DIST_STENCIL = 0, 1, 2
 LT_ARG_ARRAY, LT_ARG_INT, LT_ARG_FLOAT = 0, 1, 2
@@ -47,7 +49,8 @@ class lt_config(C.Structure):
                 ("stage_threshold_bytes", C.c_uint64), ("device_arena", C.c_void_p),
                 ("arena_bytes", C.c_uint64), ("trace", C.c_int32), ("sb_order", C.c_int32),
                 ("drain_workgroups", C.c_int32), ("batch_flush_tasks", C.c_int32), ("drain_vectors", C.c_int32),
-                ("reserved", C.c_int32 * 3), ("host_budget_bytes", C.c_uint64), ("spill_dir", C.c_char_p)]
+                ("evict_policy", C.c_int32), ("reserved", C.c_int32 * 2), ("host_budget_bytes", C.c_uint64),
+                ("spill_dir", C.c_char_p)]
 
 
 class lt_box(C.Structure):
@@ -303,8 +306,8 @@ class Context:
 
     def configure(self, **cfg):
         """Change tunable fields (exec_mode, stage_threshold_bytes, sb_order,
-        drain_workgroups, batch_flush_tasks, drain_vectors, trace) of the live
-        context."""
+        drain_workgroups, batch_flush_tasks, drain_vectors, evict_policy,
+        trace) of the live context."""
         for k, v in cfg.items():
             setattr(self.cfg, k, v)
         check(self.h, lt_context_configure(self.h, C.byref(self.cfg)))

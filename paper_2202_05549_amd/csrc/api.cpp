@@ -484,6 +484,10 @@ lt_status lt_context_create(const lt_config *cfg_in, lt_context **out) {
         g_create_err = "drain_vectors must be 0, 2 or 4";
         return LT_ERR_INVALID;
     }
+    if (cfg.evict_policy != LT_EVICT_NEXT_USE && cfg.evict_policy != LT_EVICT_LRU) {
+        g_create_err = "evict_policy must be LT_EVICT_NEXT_USE or LT_EVICT_LRU";
+        return LT_ERR_INVALID;
+    }
     Ctx *ctx = new Ctx();
     ctx->cfg = cfg;
     if (cfg.spill_dir) ctx->spill_dir = cfg.spill_dir;
@@ -529,6 +533,8 @@ lt_status lt_context_configure(lt_context *ctx, const lt_config *cfg) {
         return set_err(ctx, LT_ERR_INVALID, "unknown exec_mode %d", cfg->exec_mode);
     if (cfg->drain_vectors != 0 && cfg->drain_vectors != 2 && cfg->drain_vectors != 4)
         return set_err(ctx, LT_ERR_INVALID, "drain_vectors must be 0, 2 or 4");
+    if (cfg->evict_policy != LT_EVICT_NEXT_USE && cfg->evict_policy != LT_EVICT_LRU)
+        return set_err(ctx, LT_ERR_INVALID, "evict_policy must be LT_EVICT_NEXT_USE or LT_EVICT_LRU");
     lt_status st = flush_all(ctx);
     if (st) return st;
     ctx->cfg.exec_mode = cfg->exec_mode;
@@ -537,6 +543,7 @@ lt_status lt_context_configure(lt_context *ctx, const lt_config *cfg) {
     ctx->cfg.drain_workgroups = cfg->drain_workgroups;
     ctx->cfg.batch_flush_tasks = cfg->batch_flush_tasks;
     ctx->cfg.drain_vectors = cfg->drain_vectors;
+    ctx->cfg.evict_policy = cfg->evict_policy;
     ctx->cfg.trace = cfg->trace;
     return LT_OK;
 }

@@ -1115,26 +1115,31 @@ static lt_status issue_exec(Ctx *ctx, lt_kernel *k, TaskPlan &tp, uint64_t L,
     };
     bool staged_copy = false;
     std::vector<ChunkUse> uses;
-    for (int p = 0; p < def->nparam; ++p) {
-        ArgPlan &a = tp.arg[p];
-        if (!a.used || a.mode == M_REDUCE) continue;
-        Fence placed;
-        if (a.chunks.size() > 1 && arrs[p]->row_slab) {
-            st = place_run(ctx, a.chunks, &placed);
-            if (st) {
-                unpin();
-                return st;
+    // runs of neighbouring chunks that must sit contiguously go first, while
+    // the arena has the most room for them; single chunks fit any gap
+    for (int pass = 0; pass < 2; ++pass)
+        for (int p = 0; p < def->nparam; ++p) {
+            ArgPlan &a = tp.arg[p];
+            if (!a.used || a.mode == M_REDUCE) continue;
+            const bool run = a.chunks.size() > 1 && arrs[p]->row_slab;
+            if (run != (pass == 0)) continue;
+            Fence placed;
+            if (run) {
+                st = place_run(ctx, a.chunks, &placed);
+                if (st) {
+                    unpin();
+                    return st;
+                }
+            }
+            for (Chunk *c : a.chunks) {
+                st = stage_chunk(ctx, c, a.mode, a.region, &wait, &staged_copy, tp.footprint, placed);
+                if (st) {
+                    unpin();
+                    return st;
+                }
+                uses.push_back({c, a.mode != M_READ});
             }
         }
-        for (Chunk *c : a.chunks) {
-            st = stage_chunk(ctx, c, a.mode, a.region, &wait, &staged_copy, tp.footprint, placed);
-            if (st) {
-                unpin();
-                return st;
-            }
-            uses.push_back({c, a.mode != M_READ});
-        }
-    }
     // views: direct, assembled temporaries, partials
     std::vector<Temp> temps;
     for (int p = 0; p < def->nparam; ++p) {
@@ -1636,13 +1641,37 @@ lt_status launch(Ctx *ctx, lt_kernel *k, int nd, const int64_t *grid,
     }
     st = refresh_launch_halos(ctx, plans, arrs, def->nparam);
     if (st) return st;
-    for (auto &tp : plans) {
+    // which of this launch's tasks use each chunk, for eviction by next use
+    for (size_t i = 0; i < plans.size(); ++i) {
+        auto note = [&](Chunk *c) {
+            if (c->fut_launch != L) {
+                c->fut.clear();
+                c->fut_pos = 0;
+                c->fut_launch = L;
+            }
+            if (c->fut.empty() || c->fut.back() != (int32_t)i) c->fut.push_back((int32_t)i);
+        };
+        for (int p = 0; p < def->nparam; ++p) {
+            const ArgPlan &a = plans[i].arg[p];
+            if (!a.used) continue;
+            for (Chunk *c : a.chunks) note(c);
+            for (Chunk *c : a.halo_owners) note(c);
+        }
+    }
+    ctx->cur_launch = L;
+    for (size_t i = 0; i < plans.size(); ++i) {
+        TaskPlan &tp = plans[i];
+        ctx->cur_task = (int32_t)i;
         tp.id = ctx->next_task_id++;
         ctx->launches.at(L).tasks.push_back(tp.id);
         st = issue_exec(ctx, k, tp, L, proto, arrs, parts, nd);
-        if (st) return st;
+        if (st) {
+            ctx->cur_launch = ~0ull;
+            return st;
+        }
         ctx->stats.tasks++;
     }
+    ctx->cur_launch = ~0ull;
     st = flush_group(ctx);
     if (st) return st;
     for (auto &P : parts) {

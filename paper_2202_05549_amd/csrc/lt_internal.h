@@ -215,6 +215,12 @@ struct Chunk {
     Fence host_ready;   // host copy complete (after a write-back)
     uint64_t lru = 0;
     int pin = 0;
+
+    // the tasks (indices within the launch being issued) that will use this
+    // chunk, in order; valid while fut_launch is that launch
+    std::vector<int32_t> fut;
+    size_t fut_pos = 0;
+    uint64_t fut_launch = ~0ull;
 };
 
 // ------------------------------------------------------------------ arrays
@@ -399,6 +405,8 @@ struct lt_context {
     char *arena_base = nullptr;
     bool arena_owned = false;
     uint64_t lru_clock = 0;
+    uint64_t cur_launch = ~0ull;  // launch whose tasks are being issued
+    int32_t cur_task = 0;         // index of the task being issued in it
     // disk tier: pinned spill memory in use, the spill file and its next free slot
     int64_t host_spill_bytes = 0;
     int spill_fd = -1;

@@ -18,6 +18,7 @@
 #include <unistd.h>
 
 #include <algorithm>
+#include <climits>
 #include <cerrno>
 #include <cstdarg>
 #include <cstdio>
@@ -595,9 +596,23 @@ lt_status evict_chunk(Ctx *ctx, Chunk *c) {
     return LT_OK;
 }
 
-// Allocates `size` bytes of the arena, evicting least-recently-used unpinned
-// chunks when no free range is large enough.  `fence` receives the point
-// after which the memory may be overwritten.
+// Eviction rank of chunk c under the next-use policy (higher = evict
+// first): the index of the next task of the launch being issued that uses c,
+// INT32_MAX when none does.  A chunk used by one of the last EVICT_RECENT
+// tasks ranks -1 whatever its next use: those tasks have most likely not run
+// yet (the host issues ahead of the device), so reusing the chunk's memory
+// would make the current task wait for them and for the chunk's write-back.
+constexpr int32_t EVICT_RECENT = 2;
+static int32_t evict_rank(Ctx *ctx, Chunk *c) {
+    if (ctx->cur_launch == ~0ull || c->fut_launch != ctx->cur_launch) return INT32_MAX;
+    while (c->fut_pos < c->fut.size() && c->fut[c->fut_pos] <= ctx->cur_task) ++c->fut_pos;
+    if (c->fut_pos > 0 && ctx->cur_task - c->fut[c->fut_pos - 1] <= EVICT_RECENT) return -1;
+    return c->fut_pos < c->fut.size() ? c->fut[c->fut_pos] : INT32_MAX;
+}
+
+// Allocates `size` bytes of the arena, evicting unpinned chunks when no free
+// range is large enough.  `fence` receives the point after which the memory
+// may be overwritten.
 lt_status alloc_range(Ctx *ctx, int64_t size, int kind, Chunk *owner,
                       int64_t *off, Fence *fence) {
     lt_status st = ensure_arena(ctx);
@@ -605,31 +620,41 @@ lt_status alloc_range(Ctx *ctx, int64_t size, int kind, Chunk *owner,
     Arena &A = ctx->arena;
     int64_t o = A.take_free(size, fence, kind, owner);
     if (o < 0) {
-        // choose the contiguous window of free or evictable segments whose
-        // most recently used chunk is the oldest (exact LRU when chunks have
-        // equal sizes); pinned chunks and temporaries block a window
+        // choose a contiguous window of free or evictable segments; pinned
+        // chunks and temporaries block a window.  LRU: the window whose most
+        // recently used chunk is the oldest (exact LRU when chunks have equal
+        // sizes).  Next use: first the window whose lowest-ranked chunk
+        // (evict_rank) ranks highest, then LRU among equals.
+        const bool by_use = ctx->cfg.evict_policy == LT_EVICT_NEXT_USE;
         std::vector<Seg *> order;
         order.reserve(A.segs.size());
         for (auto &kv : A.segs) order.push_back(&kv.second);
         int64_t best_start = -1;
         uint64_t best_cost = ~0ull;
+        int32_t best_use = INT32_MIN;
         size_t n = order.size();
         for (size_t i = 0; i < n; ++i) {
             int64_t sum = 0;
             uint64_t cost = 0;
+            int32_t use = INT32_MAX;
             size_t j = i;
             bool ok = false;
             for (; j < n; ++j) {
                 Seg *s = order[j];
                 if (s->kind == 2 || (s->kind == 1 && s->chunk->pin > 0)) break;
-                if (s->kind == 1) cost = std::max<uint64_t>(cost, s->chunk->lru + 1);
+                if (s->kind == 1) {
+                    cost = std::max<uint64_t>(cost, s->chunk->lru + 1);
+                    if (by_use) use = std::min(use, evict_rank(ctx, s->chunk));
+                }
                 sum += s->size;
                 if (sum >= size) {
                     ok = true;
                     break;
                 }
             }
-            if (ok && cost < best_cost) {
+            if (!ok) continue;
+            if (use > best_use || (use == best_use && cost < best_cost)) {
+                best_use = use;
                 best_cost = cost;
                 best_start = order[i]->off;
             }
