@@ -432,3 +432,44 @@ def test_host_budget_smaller_than_a_chunk_is_an_error():
             x, y = y, x
         ctx.sync()
     assert e.value.status == L.LT_ERR_BUDGET
+
+
+# ------------------------------------------------------------ eviction policy
+
+def _ooc_gemm_h2d(policy):
+    # the out-of-core GEMM pattern at small scale: 8 x 8 C tiles, A row panels
+    # and B column panels of 8 tiles, a budget of 12 panels for 24 panels' data
+    n, T = 4096, 512
+    tile = T * T * 4
+    ctx = dry(device_budget_bytes=12 * 8 * tile, stage_threshold_bytes=1 << 40,
+              sb_order=L.LT_ORDER_SERPENTINE, evict_policy=policy, trace=1)
+    a = ctx.array([n, n], chunk=[T, 0])
+    b = ctx.array([n, n], chunk=[0, T])
+    c = ctx.array([n, n], chunk=[T, T])
+    a.fill(1.0)
+    b.fill(1.0)
+    ctx.sync()
+    ctx.reset_stats()
+    ctx.clear_trace()
+    ctx.launch("gemm_f32", [n, n], [1, 1], [T, T], args=[n, n, n, c, a, b])
+    ctx.sync()
+    s = ctx.stats()
+    ctx.close()
+    return s["bytes_h2d"], s["evictions_clean"] + s["evictions_dirty"]
+
+
+def test_next_use_eviction_moves_no_more_than_lru():
+    nu, nu_ev = _ooc_gemm_h2d(L.LT_EVICT_NEXT_USE)
+    lru, lru_ev = _ooc_gemm_h2d(L.LT_EVICT_LRU)
+    assert nu_ev > 0 and lru_ev > 0  # the budget binds under both
+    assert nu <= lru, (nu, lru)
+
+
+def test_evict_policy_validated():
+    with pytest.raises(L.LtError):
+        dry(evict_policy=7)
+    ctx = dry()
+    with pytest.raises(L.LtError):
+        ctx.configure(evict_policy=-1)
+    ctx.configure(evict_policy=L.LT_EVICT_LRU)
+    ctx.close()

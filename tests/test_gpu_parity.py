@@ -179,11 +179,13 @@ def test_jacobi_tile_variants_bit_exact(L, variant, shape, chunk, sb):
     assert np.array_equal(got, oracle.jacobi2d(x0, 3))
 
 
-def test_jacobi_out_of_core_matches(L):
+@pytest.mark.parametrize("policy", [0, 1])
+def test_jacobi_out_of_core_matches(L, policy):
+    # both eviction policies (next use, LRU) give the oracle's bits
     n, m = 1024, 1024
-    say("jacobi spill")
+    say("jacobi spill", policy)
     x0 = synthetic.jacobi2d_input(n, m, seed=10)
-    with ctx_of(L, device_budget_bytes=10 * 64 * m * 4) as ctx:
+    with ctx_of(L, device_budget_bytes=10 * 64 * m * 4, evict_policy=policy) as ctx:
         a = ctx.array([n, m], chunk=[64, 0])
         b = ctx.array([n, m], chunk=[64, 0])
         a.write(x0)
