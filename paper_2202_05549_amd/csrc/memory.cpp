@@ -736,8 +736,11 @@ static void carve(Ctx *ctx, int64_t off, int64_t total, const std::vector<Chunk 
 
 // Makes a run of neighbouring chunks of a row-slab array resident in one
 // contiguous range, in order, so that a region spanning them is a direct
-// view.  Resident members that are scattered are evicted first (their data
-// goes back to the host copy) and everything is reloaded into the window.
+// view.  Scattered members are moved into a new window with device-to-device
+// copies (dirty ones stay dirty: nothing goes through the host); members not
+// resident are loaded afterwards by stage_chunk.  Only when the window does
+// not fit beside the old copies are the resident members evicted (their data
+// goes back to the host copy) and everything reloaded into the window.
 // Returns the fence after which the window's memory may be written.
 lt_status place_run(Ctx *ctx, const std::vector<Chunk *> &run, Fence *mem) {
     bool contiguous = true;
@@ -770,6 +773,53 @@ lt_status place_run(Ctx *ctx, const std::vector<Chunk *> &run, Fence *mem) {
         for (size_t i = 1; i < run.size(); ++i)
             if (run[i]->dev_off != run[i - 1]->dev_off + run[i - 1]->bytes) cont = false;
         if (cont) return LT_OK;
+    }
+    // move: the resident members keep their pins, so the window cannot
+    // take their old ranges, which are released once the copies are issued
+    for (Chunk *c : run)
+        if (c->dev_off >= 0 && !c->dev_valid) {  // placed above but not loaded yet
+            ctx->arena.release(c->dev_off, Fence());
+            c->dev_off = -1;
+        }
+    {
+        int64_t total = 0;
+        for (Chunk *c : run) total += c->bytes;
+        const int64_t rounded = round_up(total, 256);
+        int64_t off;
+        Fence f;
+        if (alloc_range(ctx, rounded, 1, nullptr, &off, &f) == LT_OK) {
+            std::vector<std::pair<Chunk *, int64_t>> moved;
+            for (Chunk *c : run)
+                if (c->dev_off >= 0) moved.push_back({c, c->dev_off});
+            carve(ctx, off, rounded, run, f);
+            for (auto &mv : moved) {
+                Chunk *c = mv.first;
+                Fence w = f;
+                w.merge(c->data_ready);
+                lt_status st = stream_wait(ctx, ctx->h2d, w);
+                if (st) return st;
+                const int64_t one = 1, ext = c->bytes;
+                st = copy_box(ctx, ctx->h2d, ctx->arena_base + c->dev_off, &one, ctx->arena_base + mv.second, &one,
+                              &ext, 1, 1, hipMemcpyDeviceToDevice);
+                if (st) return st;
+                const uint64_t p = bump(ctx, ctx->h2d);
+                trace_op(ctx, 3, ctx->h2d, ~0ull, c->id, (uint64_t)c->bytes, (uint64_t)c->dev_off);
+                Fence rel = c->last_access;
+                rel.add(ctx->h2d, p);
+                ctx->arena.release(mv.second, rel);
+                c->data_ready = Fence();
+                c->data_ready.add(ctx->h2d, p);
+                c->last_access = c->data_ready;
+            }
+            for (Chunk *c : run) {
+                bool was = false;
+                for (auto &mv : moved) was = was || mv.first == c;
+                if (!was) c->dev_valid = false;
+            }
+            mem->merge(f);
+            note_resident(ctx);
+            return LT_OK;
+        }
     }
     // evict every resident member and reload the run into one window
     for (Chunk *c : run)
