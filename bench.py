@@ -613,14 +613,17 @@ def bench_disk(args, L, torch):
             a.write(x0)
             b.fill(0.0)
             ctx.sync()
-            ctx.reset_stats()
-            s0 = time.perf_counter()
             inp, out = a, b
-            for _ in range(sweeps):
-                ctx.launch("jacobi2d_f32", [n, n], [1, 256], [rows, 0], args=[n, n, out, inp])
-                inp, out = out, inp
-            ctx.sync()
-            wall = time.perf_counter() - s0
+            # one untimed pass pins the spill buffers (first touch), then a
+            # timed pass of the same sweeps
+            for timed in (False, True):
+                ctx.reset_stats()
+                s0 = time.perf_counter()
+                for _ in range(sweeps):
+                    ctx.launch("jacobi2d_f32", [n, n], [1, 256], [rows, 0], args=[n, n, out, inp])
+                    inp, out = out, inp
+                ctx.sync()
+                wall = time.perf_counter() - s0
             st = ctx.stats()
         finally:
             ctx.close()
@@ -632,7 +635,7 @@ def bench_disk(args, L, torch):
     m = res["disk_tier"]
     line = base_line({"workload": "jacobi2d 8192x8192 f32, 10 sweeps, 512-row chunks, device budget 128 MiB, "
                                   "host spill budget 128 MiB, the rest in a spill file (disk tier)",
-                      "executor": "plain"}, 1, 0)
+                      "executor": "plain"}, 1, 1)
     line.update({"value": round(m["gbs"], 2), "unit": "GB/s", "ms_per_step": round(m["ms_per_step"], 2),
                  "dtype": "f32", "disk_tier": {k: round(v, 3) for k, v in m.items()},
                  "host_tier": {k: round(v, 3) for k, v in res["host_tier"].items()},

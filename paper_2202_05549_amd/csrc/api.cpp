@@ -198,6 +198,7 @@ lt_status array_flush_async(Ctx *ctx, Array *arr, Fence *out) {
 void ctx_release_all(Ctx *ctx) {
     for (Array *arr : ctx->arrays) arr->dead = true;
     (void)sync_all(ctx);
+    drain_pin_pool(ctx);
     if (!ctx->dry) {
         for (int s = 0; s < ctx->nstreams; ++s)
             if (ctx->streams[s].h) (void)hipStreamDestroy(ctx->streams[s].h);

@@ -409,6 +409,8 @@ struct lt_context {
     int32_t cur_task = 0;         // index of the task being issued in it
     // disk tier: pinned spill memory in use, the spill file and its next free slot
     int64_t host_spill_bytes = 0;
+    std::multimap<int64_t, char *> pin_pool;  // recycled pinned spill buffers by size
+    int64_t pin_pooled = 0;
     int spill_fd = -1;
     int64_t disk_next = 0;
     std::string spill_dir;             // copy of cfg.spill_dir
@@ -537,6 +539,8 @@ lt_status ensure_host_copy(Ctx *ctx, Chunk *c);
 lt_status host_resident(Ctx *ctx, Chunk *c);
 // releases c's pinned spill buffer (and its disk slot stays reserved)
 void free_spill(Ctx *ctx, Chunk *c);
+// Unpins every recycled spill buffer (context teardown).
+void drain_pin_pool(Ctx *ctx);
 char *dev_ptr(Ctx *ctx, const Chunk *c);
 void trace_op(Ctx *ctx, int kind, int stream, uint64_t task, uint64_t chunk,
               uint64_t bytes, uint64_t offset);

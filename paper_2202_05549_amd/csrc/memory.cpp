@@ -377,10 +377,51 @@ static lt_status open_spill_file(Ctx *ctx) {
     return LT_OK;
 }
 
+// Pinned spill buffers are recycled through a pool keyed by size: pinning
+// and unpinning host memory costs milliseconds per buffer (hipHostFree may
+// also wait for the device), while chunks of one array all have one size.
+// Pooled buffers count against the host budget; without a budget the pool
+// keeps at most PIN_POOL_CAP bytes.
+constexpr int64_t PIN_POOL_CAP = (int64_t)2 << 30;
+
+static void pin_release(Ctx *ctx, char *p) {
+    if (ctx->dry) free(p);
+    else (void)hipHostFree(p);
+}
+
+static char *pool_take(Ctx *ctx, int64_t bytes) {
+    auto it = ctx->pin_pool.find(bytes);
+    if (it == ctx->pin_pool.end()) return nullptr;
+    char *p = it->second;
+    ctx->pin_pool.erase(it);
+    ctx->pin_pooled -= bytes;
+    return p;
+}
+
+// Frees one pooled buffer (the largest); false when the pool is empty.
+static bool pool_shrink(Ctx *ctx) {
+    if (ctx->pin_pool.empty()) return false;
+    auto it = std::prev(ctx->pin_pool.end());
+    ctx->pin_pooled -= it->first;
+    pin_release(ctx, it->second);
+    ctx->pin_pool.erase(it);
+    return true;
+}
+
+void drain_pin_pool(Ctx *ctx) {
+    while (pool_shrink(ctx)) {
+    }
+}
+
 void free_spill(Ctx *ctx, Chunk *c) {
     if (!c->host_owned || !c->host_ptr) return;
-    if (ctx->dry) free(c->host_ptr);
-    else (void)hipHostFree(c->host_ptr);
+    const int64_t cap = (int64_t)ctx->cfg.host_budget_bytes;
+    if (cap > 0 || ctx->pin_pooled + c->bytes <= PIN_POOL_CAP) {
+        ctx->pin_pool.emplace(c->bytes, c->host_ptr);
+        ctx->pin_pooled += c->bytes;
+    } else {
+        pin_release(ctx, c->host_ptr);
+    }
     c->host_ptr = nullptr;
     ctx->host_spill_bytes -= c->bytes;
     ctx->stats.host_spill_bytes = (uint64_t)ctx->host_spill_bytes;
@@ -416,14 +457,23 @@ static lt_status demote(Ctx *ctx, Chunk *c) {
     return LT_OK;
 }
 
-// Frees pinned spill memory until `need` more bytes fit under the budget.
-static lt_status make_host_room(Ctx *ctx, int64_t need, const Chunk *keep) {
+// A pinned buffer of `need` bytes for chunk `keep`: from the pool when one of
+// that size is there, else newly pinned once the held and pooled buffers
+// leave room under the host budget.  Room is made by freeing pooled
+// buffers, then by moving the least recently used spill buffer to the disk
+// tier (its buffer returns to the pool and is taken here when it fits).
+static lt_status pinned_for(Ctx *ctx, int64_t need, const Chunk *keep, char **out) {
     const int64_t cap = (int64_t)ctx->cfg.host_budget_bytes;
-    if (cap <= 0) return LT_OK;
-    if (need > cap)
+    if (cap > 0 && need > cap)
         return set_err(ctx, LT_ERR_BUDGET, "a %lld-byte spill buffer exceeds the host budget of %lld bytes",
                        (long long)need, (long long)cap);
-    while (ctx->host_spill_bytes + need > cap) {
+    for (;;) {
+        if (char *p = pool_take(ctx, need)) {
+            *out = p;
+            return LT_OK;
+        }
+        if (cap <= 0 || ctx->host_spill_bytes + ctx->pin_pooled + need <= cap) break;
+        if (pool_shrink(ctx)) continue;
         // any other buffer may go: a host copy is only read right after it
         // is made resident, and demote() waits for the copies using it
         Chunk *victim = nullptr;
@@ -436,6 +486,15 @@ static lt_status make_host_room(Ctx *ctx, int64_t need, const Chunk *keep) {
         lt_status st = demote(ctx, victim);
         if (st) return st;
     }
+    void *p = nullptr;
+    if (ctx->dry) {
+        p = malloc(1);
+    } else {
+        hipError_t r = hipHostMalloc(&p, (size_t)need, hipHostMallocDefault);
+        if (r != hipSuccess) return set_err(ctx, LT_ERR_OOM, "pinned spill buffer of %lld bytes: %s",
+                                            (long long)need, hipGetErrorString(r));
+    }
+    *out = (char *)p;
     return LT_OK;
 }
 
@@ -466,17 +525,10 @@ lt_status ensure_host_copy(Ctx *ctx, Chunk *c) {
         for (int a = 0; a < MAXD; ++a) c->host_stride[a] = arr->strides[a];
         return LT_OK;
     }
-    lt_status st = make_host_room(ctx, c->bytes, c);
+    char *p = nullptr;
+    lt_status st = pinned_for(ctx, c->bytes, c, &p);
     if (st) return st;
-    void *p = nullptr;
-    if (ctx->dry) {
-        p = malloc(1);
-    } else {
-        hipError_t r = hipHostMalloc(&p, (size_t)c->bytes, hipHostMallocDefault);
-        if (r != hipSuccess) return set_err(ctx, LT_ERR_OOM, "pinned spill buffer of %lld bytes: %s",
-                                            (long long)c->bytes, hipGetErrorString(r));
-    }
-    c->host_ptr = (char *)p;
+    c->host_ptr = p;
     c->host_owned = true;
     ctx->host_spill_bytes += c->bytes;
     ctx->stats.host_spill_bytes = (uint64_t)ctx->host_spill_bytes;
