@@ -1255,16 +1255,19 @@ static lt_status issue_exec(Ctx *ctx, lt_kernel *k, TaskPlan &tp, uint64_t L,
     Fence done;
     done.add(s, pt);
     for (Temp &t : temps) ctx->arena.release(t.off, done);
-    if (staged_copy) {
-        // the throttle will make the copy stream wait for this task: mark its
-        // end now, while it is the stream's last operation (the host runs
-        // ahead of the device, so a mark taken later would also cover tasks
-        // issued after it)
+    // Mark this task's end now, while it is the stream's last operation, when
+    // the copy streams will wait for it: the throttle waits for staged tasks,
+    // and once the budget binds, write-backs and reloads wait for the last
+    // users of the chunks they evict.  A mark taken later would also cover
+    // every task issued since (the host runs ahead of the device).
+    if (staged_copy || ctx->stats.evictions_clean + ctx->stats.evictions_dirty > 0) {
         st = mark_tail(ctx, s);
         if (st) {
             unpin();
             return st;
         }
+    }
+    if (staged_copy) {
         ctx->staged.push_back({done, tp.footprint});
         ctx->staged_bytes += tp.footprint;
         ctx->stats.staged_peak_bytes = std::max<uint64_t>(ctx->stats.staged_peak_bytes, ctx->staged_bytes);
