@@ -473,3 +473,30 @@ def test_evict_policy_validated():
         ctx.configure(evict_policy=-1)
     ctx.configure(evict_policy=L.LT_EVICT_LRU)
     ctx.close()
+
+
+def test_scattered_runs_move_on_device_instead_of_reloading():
+    # out-of-core Jacobi with a budget of 8 row slabs: each task reads a run of
+    # three neighbouring slabs, which must sit contiguously.  Runs whose
+    # members are resident but scattered move device-to-device, so each sweep
+    # loads every input slab about once from the host
+    n, rows, sweeps = 2048, 128, 6
+    slab = rows * n * 4
+    ctx = dry(device_budget_bytes=8 * slab, stage_threshold_bytes=4 * slab)
+    a = ctx.array([n, n], chunk=[rows, 0])
+    b = ctx.array([n, n], chunk=[rows, 0])
+    a.fill(1.0)
+    b.fill(0.0)
+    ctx.sync()
+    ctx.reset_stats()
+    inp, out = a, b
+    for _ in range(sweeps):
+        ctx.launch("jacobi2d_f32", [n, n], [1, 256], [rows, 0], args=[n, n, out, inp])
+        inp, out = out, inp
+    ctx.sync()
+    s = ctx.stats()
+    ctx.close()
+    field = n * n * 4
+    assert s["bytes_d2d"] > 0
+    assert s["bytes_h2d"] <= 1.15 * sweeps * field, s["bytes_h2d"] / (sweeps * field)
+    assert s["bytes_d2h"] <= 1.15 * sweeps * field
