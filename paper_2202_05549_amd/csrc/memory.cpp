@@ -201,6 +201,12 @@ static lt_status mark_at(Ctx *ctx, int t, uint64_t seq, hipEvent_t *ev, uint64_t
 lt_status mark_tail(Ctx *ctx, int s) {
     if (ctx->dry) return LT_OK;
     Stream &S = ctx->streams[s];
+    // marks at or before what is known to have completed are never needed
+    // again (waits already enqueued on them keep their own snapshot)
+    while (!S.marks.empty() && S.marks.front().seq <= S.done) {
+        ctx->event_pool.push_back(S.marks.front().ev);
+        S.marks.pop_front();
+    }
     if (!S.marks.empty() && S.marks.back().seq == S.seq) return LT_OK;
     hipEvent_t ev;
     uint64_t mseq;
