@@ -299,7 +299,9 @@ lt_status lt_kernel_define(lt_context *ctx, const char *base,
  *     groups of 8 (each input row loaded once per tile);
  *   302, 304 or 308: tiles of 256 columns and 4 bands of 2, 4 or 8 rows, one
  *     band per wave, the rows between bands exchanged on chip.
- * Unknown variants fall back to the default (304). */
+ * Unknown variants fall back to the default (304).  kmeans_update_f32 takes
+ * 2 for two features per lane instead of four (d of 8, 16 or 32); the sums
+ * are bit-identical either way. */
 lt_status lt_kernel_tune(lt_context *ctx, lt_kernel *k, int32_t variant);
 
 /* ------------------------------------------------------------------- launch */

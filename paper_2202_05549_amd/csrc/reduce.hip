@@ -496,54 +496,72 @@ __global__ __launch_bounds__(256) void k_kmeans_update(KUArgs a) {
 }
 
 // d = VD in {4, 8, 16, 32} with dense, 16-byte aligned rows: lane l holds
-// features 4c .. 4c+3 (c = l % LP, LP = VD / 4) of point l / LP, so one
-// 16-byte load per lane brings 64 / LP whole points; the additions per
-// element are the same as in the one-feature-per-lane body.
+// features FPL c .. FPL c + FPL - 1 (c = l % LP, LP = VD / FPL) of point
+// l / LP, so one FPL-float load per lane brings 64 / LP whole points; the
+// additions per element are the same as in the one-feature-per-lane body,
+// and in the same order (point order), whatever FPL is.
 constexpr int KMV_U = 4;  // steps per load batch; two batches are in flight
 
-template <int VD>
+template <int FPL>
+struct KmvVec;
+template <>
+struct KmvVec<4> {
+    using T = float4;
+    static __device__ __forceinline__ float get(const T &v, int i) { return i == 0 ? v.x : i == 1 ? v.y : i == 2 ? v.z : v.w; }
+    static __device__ __forceinline__ T zero() { return make_float4(0.f, 0.f, 0.f, 0.f); }
+};
+template <>
+struct KmvVec<2> {
+    using T = float2;
+    static __device__ __forceinline__ float get(const T &v, int i) { return i == 0 ? v.x : v.y; }
+    static __device__ __forceinline__ T zero() { return make_float2(0.f, 0.f); }
+};
+
+template <int VD, int FPL>
 __device__ __forceinline__ void kmv_load(const KUReg &t, int64_t pb, int64_t p1, int lane, int q, int K, bool full,
-                                         float4 *xv, int *kv) {
-    constexpr int LP = VD / 4, P = 64 / LP;
+                                         typename KmvVec<FPL>::T *xv, int *kv) {
+    using V = KmvVec<FPL>;
+    constexpr int LP = VD / FPL, P = 64 / LP;
 #pragma unroll
     for (int u = 0; u < KMV_U; ++u) {
         const int64_t pu = pb + (int64_t)u * P;
         const int64_t p = pu + q;
         int k;
         if (full) {
-            xv[u] = ld4<float4>(t.X + pu * VD + 4 * lane);
+            xv[u] = ld4<typename V::T>(t.X + pu * VD + FPL * lane);
             k = t.LB[p];
         } else {
             const bool act = p < p1;
-            xv[u] = act ? ld4<float4>(t.X + pu * VD + 4 * lane) : make_float4(0.f, 0.f, 0.f, 0.f);
+            xv[u] = act ? ld4<typename V::T>(t.X + pu * VD + FPL * lane) : V::zero();
             k = act ? t.LB[p] : -1;
         }
         kv[u] = (k >= 0 && k < K) ? k : -1;
     }
 }
 
-template <int VD>
-__device__ __forceinline__ void kmv_step(double *acc, int *cnt, int q, int c, float4 x, int k) {
-    constexpr int LP = VD / 4;
+template <int VD, int FPL>
+__device__ __forceinline__ void kmv_step(double *acc, int *cnt, int q, int c, const typename KmvVec<FPL>::T &x,
+                                         int k) {
+    using V = KmvVec<FPL>;
+    constexpr int LP = VD / FPL;
     const int rank = kmu_rank<LP>(k, q, c);
     for (int r = 0;; ++r) {
         const bool mine = k >= 0 && rank == r;
         if (!__ballot(mine)) break;
         if (mine) {
-            double *e = acc + k * (VD | 1) + 4 * c;
-            lds_add(e, (double)x.x);
-            lds_add(e + 1, (double)x.y);
-            lds_add(e + 2, (double)x.z);
-            lds_add(e + 3, (double)x.w);
+            double *e = acc + k * (VD | 1) + FPL * c;
+#pragma unroll
+            for (int i = 0; i < FPL; ++i) lds_add(e + i, (double)V::get(x, i));
             if (c == 0) lds_add(&cnt[k], 1);
         }
         asm volatile("" ::: "memory");
     }
 }
 
-template <int VD>
+template <int VD, int FPL>
 __global__ __launch_bounds__(256) void k_kmeans_update_v(KUArgs a) {
-    constexpr int LP = VD / 4, P = 64 / LP;
+    using VT = typename KmvVec<FPL>::T;
+    constexpr int LP = VD / FPL, P = 64 / LP;
     extern __shared__ double lds[];
     const int ti = find_task(a.begin, a.ntask, blockIdx.x);
     const KUReg t = kmu_regs(a.t[ti]);
@@ -560,15 +578,15 @@ __global__ __launch_bounds__(256) void k_kmeans_update_v(KUArgs a) {
         const int64_t p0 = t.lo + tile * KMU_TILE + wave * QUARTER;
         const int64_t p1 = p0 + QUARTER < t.hi ? p0 + QUARTER : t.hi;
         if (p0 >= p1) continue;
-        float4 xv[KMV_U], xn[KMV_U];
+        VT xv[KMV_U], xn[KMV_U];
         int kv[KMV_U], kn[KMV_U];
-        kmv_load<VD>(t, p0, p1, lane, q, K, p0 + BATCH <= p1, xv, kv);
+        kmv_load<VD, FPL>(t, p0, p1, lane, q, K, p0 + BATCH <= p1, xv, kv);
         for (int64_t pb = p0; pb < p1; pb += BATCH) {
             const int64_t nb = pb + BATCH;
             const bool more = nb < p1;
-            if (more) kmv_load<VD>(t, nb, p1, lane, q, K, nb + BATCH <= p1, xn, kn);
+            if (more) kmv_load<VD, FPL>(t, nb, p1, lane, q, K, nb + BATCH <= p1, xn, kn);
 #pragma unroll
-            for (int u = 0; u < KMV_U; ++u) kmv_step<VD>(acc, cnt, q, c, xv[u], kv[u]);
+            for (int u = 0; u < KMV_U; ++u) kmv_step<VD, FPL>(acc, cnt, q, c, xv[u], kv[u]);
             if (more) {
 #pragma unroll
                 for (int u = 0; u < KMV_U; ++u) {
@@ -626,10 +644,22 @@ hipError_t launch_kmeans_update_f32(const KLaunch &L) {
         vec = a.t[i].xs == a.d && a.t[i].x % 16 == 0 && (a.t[i].lo * a.d * 4) % 16 == 0;
     if (vec) {
         switch (a.d) {
-            case 4: hipLaunchKernelGGL(k_kmeans_update_v<4>, g, b, lds, L.stream, a); break;
-            case 8: hipLaunchKernelGGL(k_kmeans_update_v<8>, g, b, lds, L.stream, a); break;
-            case 16: hipLaunchKernelGGL(k_kmeans_update_v<16>, g, b, lds, L.stream, a); break;
-            default: hipLaunchKernelGGL(k_kmeans_update_v<32>, g, b, lds, L.stream, a); break;
+            // four features per lane; variant 2 takes two (d >= 8): fewer add
+            // rounds per point, but measured slower (3.24 against 3.45 TB/s at
+            // d = 16, K = 64), the LDS being bound by lanes, not instructions
+            case 4: hipLaunchKernelGGL((k_kmeans_update_v<4, 4>), g, b, lds, L.stream, a); break;
+            case 8:
+                if (L.variant == 2) hipLaunchKernelGGL((k_kmeans_update_v<8, 2>), g, b, lds, L.stream, a);
+                else hipLaunchKernelGGL((k_kmeans_update_v<8, 4>), g, b, lds, L.stream, a);
+                break;
+            case 16:
+                if (L.variant == 2) hipLaunchKernelGGL((k_kmeans_update_v<16, 2>), g, b, lds, L.stream, a);
+                else hipLaunchKernelGGL((k_kmeans_update_v<16, 4>), g, b, lds, L.stream, a);
+                break;
+            default:
+                if (L.variant == 2) hipLaunchKernelGGL((k_kmeans_update_v<32, 2>), g, b, lds, L.stream, a);
+                else hipLaunchKernelGGL((k_kmeans_update_v<32, 4>), g, b, lds, L.stream, a);
+                break;
         }
         return hipGetLastError();
     }

@@ -249,3 +249,21 @@ def test_kmeans_lloyd_five_rounds(L):
             if len(bad) == 0:
                 ulps = np.abs(cen_g.view(np.int32).astype(np.int64) - cen_r.view(np.int32).astype(np.int64))
                 assert ulps.max() <= 1, it
+
+
+@pytest.mark.parametrize("d", [8, 16, 32])
+def test_kmeans_update_lane_widths_bit_identical(L, d):
+    # two or four features per lane add the same values in the same order
+    N, K, sb = 70001, 40 if d == 32 else 64, 16384
+    say("kmeans update lane widths", d)
+    X, _, z = synthetic.kmeans_blobs(N, d, K, seed=21)
+    outs = []
+    for variant in (0, 2):
+        with ctx_of(L) as ctx:
+            if variant:
+                ctx.tune("kmeans_update_f32", variant)
+            outs.append(_update(L, ctx, X, z, K, sb))
+    assert np.array_equal(outs[0][0].view(np.uint64), outs[1][0].view(np.uint64))
+    assert np.array_equal(outs[0][1], outs[1][1])
+    rs, rc, ra = oracle.kmeans_update(X, z, K)
+    assert np.array_equal(outs[0][1].astype(np.int64), rc)
