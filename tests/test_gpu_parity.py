@@ -348,3 +348,49 @@ def test_gemm_config3_out_of_core(L):
         assert np.all(np.abs(Cm[ii, jj] - val) <= 1e-5 * av)
         say("gemm config3: Freivalds")
         assert oracle.freivalds(A, B, Cm, trials=2) < 1e-5
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 4, 5, 1023, 1025])
+def test_stencil1d_degenerate_sizes(L, n):
+    say("stencil1d tiny", n)
+    x0 = synthetic.stencil1d_input(n, 3)
+    for mode in (0, 1):
+        with ctx_of(L, exec_mode=mode) as ctx:
+            x = ctx.array([n])
+            y = ctx.array([n])
+            x.write(x0)
+            y.fill(9.0)
+            ctx.launch("stencil1d_f32", [n], [1], [max(1, n // 2)], args=[n, y, x])
+            ctx.sync()
+            assert np.array_equal(y.read(), oracle.stencil1d(x0)), (n, mode)
+
+
+@pytest.mark.parametrize("shape", [(1, 1), (1, 5), (5, 1), (2, 2), (3, 257), (17, 4)])
+def test_jacobi_degenerate_shapes(L, shape):
+    n, m = shape
+    say("jacobi tiny", shape)
+    x0 = synthetic.jacobi2d_input(n, m, seed=8)
+    with ctx_of(L) as ctx:
+        a = ctx.array([n, m])
+        b = ctx.array([n, m])
+        a.write(x0)
+        inp, out = a, b
+        for _ in range(3):
+            ctx.launch("jacobi2d_f32", [n, m], [1, 1], [max(1, n // 2), 0], args=[n, m, out, inp])
+            inp, out = out, inp
+        ctx.sync()
+        got = inp.read()
+    assert np.array_equal(got, oracle.jacobi2d(x0, 3))
+
+
+def test_empty_grid_launch_is_a_no_op(L):
+    n = 64
+    say("empty grid")
+    with ctx_of(L) as ctx:
+        x = ctx.array([n])
+        y = ctx.array([n])
+        x.fill(1.0)
+        y.fill(7.0)
+        ctx.launch("stencil1d_f32", [0], [1], [1], args=[n, y, x])
+        ctx.sync()
+        assert np.all(y.read() == 7.0)

@@ -267,3 +267,33 @@ def test_kmeans_update_lane_widths_bit_identical(L, d):
     assert np.array_equal(outs[0][1], outs[1][1])
     rs, rc, ra = oracle.kmeans_update(X, z, K)
     assert np.array_equal(outs[0][1].astype(np.int64), rc)
+
+
+@pytest.mark.parametrize("N,d,K", [(1, 4, 1), (3, 16, 5), (7, 3, 64), (2, 32, 2)])
+def test_kmeans_degenerate_sizes(L, N, d, K):
+    # one point, more clusters than points, clusters left empty
+    say("kmeans tiny", N, d, K)
+    rng = np.random.default_rng([22, N, d, K])
+    X = rng.standard_normal((N, d)).astype(np.float32)
+    cen0 = rng.standard_normal((K, d)).astype(np.float32)
+    with ctx_of(L) as ctx:
+        x = ctx.array([N, d])
+        cen = ctx.array([K, d])
+        lb = ctx.array([N], np.int32)
+        sums = ctx.array([K, d], np.float64)
+        counts = ctx.array([K], np.int32)
+        x.write(X)
+        cen.write(cen0)
+        ctx.launch("kmeans_assign_f32", [N], [1], [0], args=[N, d, K, lb, x, cen])
+        ctx.launch("kmeans_update_f32", [N], [1], [0], args=[N, d, K, sums, counts, x, lb])
+        ctx.launch("kmeans_centres_f32", [K, d], [1, 1], [K, d], args=[K, d, cen, sums, counts])
+        ctx.sync()
+        lab, s, c, got = lb.read(), sums.read(), counts.read(), cen.read()
+    ref_lab = oracle.kmeans_assign(X, cen0)
+    assert np.array_equal(lab, ref_lab)
+    rs, rc, ra = oracle.kmeans_update(X, ref_lab, K)
+    assert np.array_equal(c.astype(np.int64), rc)
+    assert np.all(np.abs(s - rs) <= 2 * N * 2.0 ** -53 * ra)
+    ref = oracle.kmeans_centres(rs, rc, cen0)
+    ulps = np.abs(got.view(np.int32).astype(np.int64) - ref.view(np.int32).astype(np.int64))
+    assert ulps.max() <= 1
