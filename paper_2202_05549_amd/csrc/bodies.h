@@ -436,17 +436,26 @@ __device__ __forceinline__ void jacobi_march(const JView &t, int64_t n, int64_t 
 }
 
 // ---------------------------------------------------------------- hist256
-// Counts v[i] into the wave's LDS sub-histogram sh[wave] for the 4096-element
-// chunks of [s0, s1) that start at s0, s0 + stride, s0 + 2*stride, ...;
-// values outside [0, 256) are ignored.  Full aligned chunks load four
-// 16-byte groups per lane before counting; ragged chunks go one by one.
+// Counts v[i] into LDS sub-histograms for the 4096-element chunks of [s0, s1)
+// that start at s0, s0 + stride, s0 + 2*stride, ...; values outside [0, 256)
+// are ignored.  Full aligned chunks load four 16-byte groups per lane before
+// counting; ragged chunks go one by one.
+//
+// There are HIST_COPIES sub-histograms per workgroup: each wave has four,
+// and lane l counts into copy l % 4, so lanes that see the same value (a
+// skewed distribution puts a fifth of all values in one bin) are spread over
+// four addresses.  Copies are HIST_STRIDE = 257 words apart, so one bin's
+// copies sit in different LDS banks.
+constexpr int HIST_COPIES = 16;
+constexpr int HIST_STRIDE = 257;
+constexpr int HIST_WORDS = HIST_COPIES * HIST_STRIDE;
 __device__ __forceinline__ void hist_count(int *mine, int32_t b) {
     if ((uint32_t)b < 256u) atomicAdd(&mine[b], 1);
 }
 
 __device__ __forceinline__ void hist_span(int64_t vb, int64_t s0, int64_t s1, int64_t stride, int *sh) {
     const LT_GLOBAL int32_t *V = gp<const int32_t>(vb);
-    int *mine = sh + (threadIdx.x >> 6) * 256;
+    int *mine = sh + ((threadIdx.x >> 6) * 4 + (threadIdx.x & 3)) * HIST_STRIDE;
     // the workgroup owns the 4096-element chunks starting at s0, s0 + stride,
     // ...; full aligned chunks are pipelined: the next chunk's four 16-byte
     // loads per lane are issued before the current chunk is counted
@@ -485,15 +494,19 @@ __device__ __forceinline__ void hist_span(int64_t vb, int64_t s0, int64_t s1, in
     }
 }
 
-// Adds the four sub-histograms into the partial h (integer atomics: exact
-// and order-free) and clears them.
+// Adds the sub-histograms into the partial h (integer atomics: exact and
+// order-free) and clears them.
 __device__ __forceinline__ void hist_flush(int64_t hb, int *sh) {
     __syncthreads();
     LT_GLOBAL int32_t *H = gp<int32_t>(hb);
     const int b = threadIdx.x;
-    int s = sh[b] + sh[256 + b] + sh[512 + b] + sh[768 + b];
+    int s = 0;
+#pragma unroll
+    for (int k = 0; k < HIST_COPIES; ++k) {
+        s += sh[k * HIST_STRIDE + b];
+        sh[k * HIST_STRIDE + b] = 0;
+    }
     if (s) __hip_atomic_fetch_add(H + b, s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    sh[b] = sh[256 + b] = sh[512 + b] = sh[768 + b] = 0;
     __syncthreads();
 }
 

@@ -83,9 +83,9 @@ __device__ __forceinline__ void run_tile(const DTask &t, int64_t local, int *sh)
 template <int G, uint32_t KINDS>
 __device__ __forceinline__ void drain_loop(const DTask *q, int ntasks, int32_t *ctr, int ticket_idx,
                                            int64_t total, int64_t spin_limit) {
-    __shared__ int sh[4 * 256];
+    __shared__ int sh[HIST_WORDS];
     __shared__ int s_tile, s_task, s_ok;
-    for (int i = threadIdx.x; i < 4 * 256; i += THREADS) sh[i] = 0;
+    for (int i = threadIdx.x; i < HIST_WORDS; i += THREADS) sh[i] = 0;
     int cur = 0;
     int next = 0;
     if (threadIdx.x == 0) next = atomicAdd(&ctr[ticket_idx], 1);

@@ -240,10 +240,10 @@ struct HArgs {
 };
 
 __global__ __launch_bounds__(256) void k_hist256(HArgs a) {
-    __shared__ int sh[4 * 256];
+    __shared__ int sh[HIST_WORDS];
     int ti = find_task(a.begin, a.ntask, blockIdx.x);
     const HTask &t = a.t[ti];
-    for (int i = threadIdx.x; i < 4 * 256; i += 256) sh[i] = 0;
+    for (int i = threadIdx.x; i < HIST_WORDS; i += 256) sh[i] = 0;
     __syncthreads();
     const int64_t end = t.hi < a.n ? t.hi : a.n;
     const int nblk = a.begin[ti + 1] - a.begin[ti];
