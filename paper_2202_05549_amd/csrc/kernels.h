@@ -94,6 +94,12 @@ struct CopyBoxEntry {
 };
 hipError_t launch_copy_boxes(hipStream_t s, const CopyBoxEntry *table, int n, int esz, int64_t max_elems);
 
+// Copies `bytes` bytes (a multiple of 16; both pointers 16-byte aligned)
+// with a kernel: one 16-byte word per thread, one pass per workgroup.  The
+// pointers may be device memory or pinned host memory (which kernels reach
+// over the host link).  Returns hipErrorInvalidValue for other shapes.
+hipError_t launch_copy_linear(hipStream_t s, void *dst, const void *src, int64_t bytes);
+
 // Sets `count` elements of size esz (1, 4 or 8 bytes) at dst to *value.
 hipError_t launch_fill(hipStream_t s, void *dst, int64_t count, int esz,
                        const void *value);

@@ -394,6 +394,22 @@ hipError_t launch_copy_boxes(hipStream_t s, const CopyBoxEntry *table, int n, in
     return hipGetLastError();
 }
 
+// ============================================================ linear copy
+__global__ __launch_bounds__(256) void k_copy16(int4 *dst, const int4 *src, int64_t words) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < words) dst[i] = src[i];
+}
+
+hipError_t launch_copy_linear(hipStream_t s, void *dst, const void *src, int64_t bytes) {
+    if (bytes <= 0) return hipSuccess;
+    if ((bytes & 15) || ((uintptr_t)dst & 15) || ((uintptr_t)src & 15)) return hipErrorInvalidValue;
+    const int64_t words = bytes / 16;
+    const int64_t blocks = (words + 255) / 256;
+    if (blocks > INT32_MAX) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_copy16, dim3((unsigned)blocks), dim3(256), 0, s, (int4 *)dst, (const int4 *)src, words);
+    return hipGetLastError();
+}
+
 // =================================================================== fill
 template <class T>
 __global__ __launch_bounds__(256) void k_fill(T *p, int64_t count, T v) {

@@ -26,6 +26,7 @@
 #include <cstring>
 #include <string>
 
+#include "kernels.h"
 #include "lt_internal.h"
 
 namespace lt {
@@ -567,9 +568,18 @@ lt_status write_back(Ctx *ctx, Chunk *c, uint64_t *seq) {
     if (st) return st;
     const Array *arr = c->arr;
     const Box &part = arr->host_backed ? c->core : c->box;
-    st = copy_sub(ctx, ctx->d2h, c->host_ptr, c->box.lo, c->host_stride, dev_ptr(ctx, c), c->box.lo,
-                  c->dev_stride, part, arr->ndim, arr->esz, hipMemcpyDeviceToHost);
-    if (st) return st;
+    if (c->host_owned && !ctx->dry && c->bytes >= ((int64_t)1 << 20) &&
+        launch_copy_linear(ctx->streams[ctx->d2h].h, c->host_ptr, dev_ptr(ctx, c), c->bytes) == hipSuccess) {
+        // a spill buffer (pinned by the runtime, so kernels can write it)
+        // holds the whole box with the device layout: one linear copy, done
+        // by a copy kernel
+        ctx->stats.bytes_d2h += (uint64_t)c->bytes;
+        ctx->stats.copies_d2h++;
+    } else {
+        st = copy_sub(ctx, ctx->d2h, c->host_ptr, c->box.lo, c->host_stride, dev_ptr(ctx, c), c->box.lo,
+                      c->dev_stride, part, arr->ndim, arr->esz, hipMemcpyDeviceToHost);
+        if (st) return st;
+    }
     *seq = bump(ctx, ctx->d2h);
     c->host_ready = Fence();
     c->host_ready.add(ctx->d2h, *seq);
