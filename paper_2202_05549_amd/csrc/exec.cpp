@@ -1260,7 +1260,7 @@ static lt_status issue_exec(Ctx *ctx, lt_kernel *k, TaskPlan &tp, uint64_t L,
     // and once the budget binds, write-backs and reloads wait for the last
     // users of the chunks they evict.  A mark taken later would also cover
     // every task issued since (the host runs ahead of the device).
-    if (staged_copy || ctx->stats.evictions_clean + ctx->stats.evictions_dirty > 0) {
+    if (staged_copy || ctx->budget_binds) {
         st = mark_tail(ctx, s);
         if (st) {
             unpin();

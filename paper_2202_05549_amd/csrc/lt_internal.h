@@ -405,6 +405,7 @@ struct lt_context {
     char *arena_base = nullptr;
     bool arena_owned = false;
     uint64_t lru_clock = 0;
+    bool budget_binds = false;    // a chunk has been evicted (sticky)
     uint64_t cur_launch = ~0ull;  // launch whose tasks are being issued
     int32_t cur_task = 0;         // index of the task being issued in it
     // disk tier: pinned spill memory in use, the spill file and its next free slot

@@ -646,6 +646,7 @@ lt_status refresh_halo(Ctx *ctx, Chunk *c, const Box &region) {
 
 // Evicts one unpinned chunk: write back if its device copy is newer.
 lt_status evict_chunk(Ctx *ctx, Chunk *c) {
+    ctx->budget_binds = true;
     Fence f = c->last_access;
     if (c->dev_valid && !c->host_valid && c->defined) {
         uint64_t p = 0;
