@@ -394,3 +394,62 @@ def test_empty_grid_launch_is_a_no_op(L):
         ctx.launch("stencil1d_f32", [0], [1], [1], args=[n, y, x])
         ctx.sync()
         assert np.all(y.read() == 7.0)
+
+
+# --------------------------------------------------------------- denormals
+# The oracle never flushes subnormals; the HIP code is built without
+# flush-to-zero, so the stencils stay bit-exact on subnormal data.
+
+def test_stencil1d_subnormal_inputs_bit_exact(L):
+    n = 4099
+    say("stencil1d subnormal")
+    rng = np.random.default_rng(77)
+    x0 = (rng.uniform(-1, 1, n) * 2.0 ** -140).astype(np.float32)
+    assert np.count_nonzero(np.abs(x0) < np.finfo(np.float32).tiny) > n // 2
+    with ctx_of(L) as ctx:
+        x = ctx.array([n], chunk=[1024])
+        y = ctx.array([n], chunk=[1024])
+        x.write(x0)
+        ctx.launch("stencil1d_f32", [n], [1], [1024], args=[n, y, x])
+        ctx.sync()
+        got = y.read()
+    ref = oracle.stencil1d(x0)
+    assert np.count_nonzero(ref) > 0
+    assert np.array_equal(got.view(np.uint32), ref.view(np.uint32))
+
+
+def test_jacobi_subnormal_inputs_bit_exact(L):
+    n, m = 130, 1024
+    say("jacobi subnormal")
+    rng = np.random.default_rng(78)
+    x0 = (rng.uniform(0, 1, (n, m)) * 2.0 ** -138).astype(np.float32)
+    with ctx_of(L) as ctx:
+        a = ctx.array([n, m], chunk=[64, 0])
+        b = ctx.array([n, m], chunk=[64, 0])
+        a.write(x0)
+        ctx.launch("jacobi2d_f32", [n, m], [1, 1], [64, 0], args=[n, m, b, a])
+        ctx.sync()
+        got = b.read()
+    ref = oracle.jacobi2d(x0, 1)
+    assert np.array_equal(got.view(np.uint32), ref.view(np.uint32))
+
+
+def test_gemm_subnormal_products_kept(L):
+    # products of 2^-70 x 2^-70 = 2^-140 are float32 subnormals, and so is
+    # their sum over K = 256 (2^-132); the FP32 matrix cores keep them
+    M = N = K = 256
+    say("gemm subnormal")
+    A = np.full((M, K), 2.0 ** -70, np.float32)
+    B = np.full((K, N), 2.0 ** -70, np.float32)
+    with ctx_of(L) as ctx:
+        a = ctx.array([M, K])
+        b = ctx.array([K, N])
+        c = ctx.array([M, N])
+        a.write(A)
+        b.write(B)
+        ctx.launch("gemm_f32", [M, N], [1, 1], [M, N], args=[M, N, K, c, a, b])
+        ctx.sync()
+        got = c.read()
+    exact = np.float32(K * 2.0 ** -140)   # 2^-132, a subnormal, exactly representable
+    assert exact != 0 and exact < np.finfo(np.float32).tiny
+    assert np.all(got == exact)
