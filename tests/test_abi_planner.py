@@ -500,3 +500,26 @@ def test_scattered_runs_move_on_device_instead_of_reloading():
     assert s["bytes_d2d"] > 0
     assert s["bytes_h2d"] <= 1.15 * sweeps * field, s["bytes_h2d"] / (sweeps * field)
     assert s["bytes_d2h"] <= 1.15 * sweeps * field
+
+
+def test_pinned_pool_recycles_spill_buffers_within_the_host_budget():
+    # repeated demotion and reload cycles through the disk tier reuse pooled
+    # pinned buffers; held spill memory never exceeds the host budget
+    chunk = 1 << 14
+    n = 16 * chunk
+    hb = 4 * chunk * 4
+    ctx = dry(device_budget_bytes=4 * chunk * 4, host_budget_bytes=hb, stage_threshold_bytes=1 << 40)
+    x = ctx.array([n], chunk=[chunk])
+    y = ctx.array([n], chunk=[chunk])
+    x.fill(1.0)
+    y.fill(0.0)
+    peak = 0
+    for _ in range(6):
+        ctx.launch("stencil1d_f32", [n], [256], [chunk], args=[n, y, x])
+        x, y = y, x
+        peak = max(peak, ctx.stats()["host_spill_bytes"])
+    ctx.sync()
+    s = ctx.stats()
+    ctx.close()
+    assert peak <= hb and s["host_spill_bytes"] <= hb
+    assert s["bytes_disk_write"] > 0 and s["bytes_disk_read"] > 0
