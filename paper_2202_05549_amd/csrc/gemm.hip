@@ -1,9 +1,10 @@
 // C = A * B in float32 on the CDNA4 matrix cores (v_mfma_f32_32x32x2f32).
 //
 // One task is one superblock of C (thread (i, j) owns C[i][j]; annotation
-// read A[i, :], read B[:, j], write C[i, j]).  A workgroup of 256 threads
-// computes a 256 x 256 block of C: its four waves each own 128 x 128 as
-// 4 x 4 MFMA blocks of 32 x 32 (256 accumulators per lane).  K advances in
+// read A[i, :], read B[:, j], write C[i, j]).  A workgroup of 512 threads
+// computes a 256 x 256 block of C: its eight waves (two per SIMD, so one
+// hides the other's LDS reads) each own 128 x 64 as 4 x 2 MFMA blocks of
+// 32 x 32 (128 accumulators per lane).  K advances in
 // tiles of 32 staged in LDS: A transposed to [k][m] (odd row stride, so the
 // transposing stores do not collide on banks), B as [k][n].  The LDS tile is
 // double-buffered and the next tile's global loads are in flight while the
@@ -60,13 +61,13 @@ __device__ __forceinline__ void gemm_block(const GReg &t, int64_t m0, int64_t n0
                                            float (*Bs)[BK][LDB], int vec) {
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
-    const int wm = (wave >> 1) * 128, wn = (wave & 1) * 128;
+    const int wm = (wave >> 2) * 128, wn = (wave & 3) * 64;
     const int64_t K = t.K;
 
     // global -> register staging of one K tile
-    // A: thread covers rows tid/8 + 32*j, k4 = tid%8 (8 float4)
-    // B: thread covers k = tid/64 + 4*j, n4 = tid%64 (8 float4)
-    float4 ra[8], rb[8];
+    // A: thread covers rows tid/8 + 64*j, k4 = tid%8 (4 float4)
+    // B: thread covers k = tid/64 + 8*j, n4 = tid%64 (4 float4)
+    float4 ra[4], rb[4];
     const int a_row = tid >> 3, a_k4 = tid & 7;
     const int b_k = tid >> 6, b_n4 = tid & 63;
     const LT_GLOBAL float *Ab = t.A + (m0 + a_row) * t.as + a_k4 * 4;
@@ -75,13 +76,13 @@ __device__ __forceinline__ void gemm_block(const GReg &t, int64_t m0, int64_t n0
     auto load_tile = [&](int64_t k0) {
         if constexpr (FULL) {
 #pragma unroll
-            for (int j = 0; j < 8; ++j) ra[j] = body::ld4<float4>(Ab + 32 * j * t.as + k0);
+            for (int j = 0; j < 4; ++j) ra[j] = body::ld4<float4>(Ab + 64 * j * t.as + k0);
 #pragma unroll
-            for (int j = 0; j < 8; ++j) rb[j] = body::ld4<float4>(Bb + (k0 + 4 * j) * t.bs);
+            for (int j = 0; j < 4; ++j) rb[j] = body::ld4<float4>(Bb + (k0 + 8 * j) * t.bs);
         } else {
 #pragma unroll
-            for (int j = 0; j < 8; ++j) {
-                const int64_t r = m0 + a_row + 32 * j;
+            for (int j = 0; j < 4; ++j) {
+                const int64_t r = m0 + a_row + 64 * j;
                 const int64_t k = k0 + a_k4 * 4;
                 if (vec && r < t.i1 && k + 3 < K) {
                     ra[j] = body::ld4<float4>(t.A + r * t.as + k);
@@ -92,8 +93,8 @@ __device__ __forceinline__ void gemm_block(const GReg &t, int64_t m0, int64_t n0
                 }
             }
 #pragma unroll
-            for (int j = 0; j < 8; ++j) {
-                const int64_t k = k0 + b_k + 4 * j;
+            for (int j = 0; j < 4; ++j) {
+                const int64_t k = k0 + b_k + 8 * j;
                 const int64_t c = n0 + b_n4 * 4;
                 if (vec && k < K && c + 3 < t.j1) {
                     rb[j] = body::ld4<float4>(t.B + k * t.bs + c);
@@ -107,22 +108,22 @@ __device__ __forceinline__ void gemm_block(const GReg &t, int64_t m0, int64_t n0
     };
     auto store_tile = [&](int buf) {
 #pragma unroll
-        for (int j = 0; j < 8; ++j) {
-            const int m = a_row + 32 * j;
+        for (int j = 0; j < 4; ++j) {
+            const int m = a_row + 64 * j;
             As[buf][a_k4 * 4 + 0][m] = ra[j].x;
             As[buf][a_k4 * 4 + 1][m] = ra[j].y;
             As[buf][a_k4 * 4 + 2][m] = ra[j].z;
             As[buf][a_k4 * 4 + 3][m] = ra[j].w;
         }
 #pragma unroll
-        for (int j = 0; j < 8; ++j) *reinterpret_cast<float4 *>(&Bs[buf][b_k + 4 * j][b_n4 * 4]) = rb[j];
+        for (int j = 0; j < 4; ++j) *reinterpret_cast<float4 *>(&Bs[buf][b_k + 8 * j][b_n4 * 4]) = rb[j];
     };
 
-    f32x16 acc[4][4];
+    f32x16 acc[4][2];
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j)
+        for (int j = 0; j < 2; ++j)
 #pragma unroll
             for (int v = 0; v < 16; ++v) acc[i][j][v] = 0.f;
 
@@ -137,11 +138,11 @@ __device__ __forceinline__ void gemm_block(const GReg &t, int64_t m0, int64_t n0
         if (more) load_tile((int64_t)(kt + 1) * BK);
         // fragments of k-step s + 1 are read from LDS before the matrix-core
         // instructions of step s are issued, so their latency is hidden
-        float av[2][4], bv[2][4];
+        float av[2][4], bv[2][2];
 #pragma unroll
         for (int i = 0; i < 4; ++i) av[0][i] = As[buf][half][wm + 32 * i + l32];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) bv[0][j] = Bs[buf][half][wn + 32 * j + l32];
+        for (int j = 0; j < 2; ++j) bv[0][j] = Bs[buf][half][wn + 32 * j + l32];
 #pragma unroll
         for (int s = 0; s < BK / 2; ++s) {
             const int cur = s & 1;
@@ -150,7 +151,7 @@ __device__ __forceinline__ void gemm_block(const GReg &t, int64_t m0, int64_t n0
 #pragma unroll
                 for (int i = 0; i < 4; ++i) av[cur ^ 1][i] = As[buf][k][wm + 32 * i + l32];
 #pragma unroll
-                for (int j = 0; j < 4; ++j) bv[cur ^ 1][j] = Bs[buf][k][wn + 32 * j + l32];
+                for (int j = 0; j < 2; ++j) bv[cur ^ 1][j] = Bs[buf][k][wn + 32 * j + l32];
             }
             // the next tile goes into the other LDS buffer half-way through
             // this one, so its stores overlap the matrix-core work
@@ -158,7 +159,7 @@ __device__ __forceinline__ void gemm_block(const GReg &t, int64_t m0, int64_t n0
 #pragma unroll
             for (int i = 0; i < 4; ++i)
 #pragma unroll
-                for (int j = 0; j < 4; ++j)
+                for (int j = 0; j < 2; ++j)
                     acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[cur][i], bv[cur][j], acc[i][j], 0, 0, 0);
         }
         __syncthreads();
@@ -169,7 +170,7 @@ __device__ __forceinline__ void gemm_block(const GReg &t, int64_t m0, int64_t n0
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
+        for (int j = 0; j < 2; ++j) {
             const int64_t col = n0 + wn + 32 * j + l32;
 #pragma unroll
             for (int v = 0; v < 16; ++v) {
@@ -179,7 +180,7 @@ __device__ __forceinline__ void gemm_block(const GReg &t, int64_t m0, int64_t n0
         }
 }
 
-__global__ __launch_bounds__(256, 1) void k_gemm(GArgs g) {
+__global__ __launch_bounds__(512, 1) void k_gemm(GArgs g) {
     __shared__ float As[2][BK][LDA];
     __shared__ float Bs[2][BK][LDB];
 
@@ -242,7 +243,7 @@ hipError_t launch_gemm_f32(const KLaunch &L) {
     g.begin[L.ntask] = (int)nb;
     g.nblocks = (int)nb;
     if (nb == 0) return hipSuccess;  // K = 0 still runs: C becomes the empty sum, 0
-    hipLaunchKernelGGL(k_gemm, dim3((unsigned)nb), dim3(256), 0, L.stream, g);
+    hipLaunchKernelGGL(k_gemm, dim3((unsigned)nb), dim3(512), 0, L.stream, g);
     return hipGetLastError();
 }
 
