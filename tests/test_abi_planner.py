@@ -355,6 +355,30 @@ def test_halo_refreshes_are_batched_per_launch():
     ctx.close()
 
 
+@pytest.mark.parametrize("M,N,K,sb,ndisp", [
+    (300, 260, 77, (128, 100), 2),   # 9 tasks, 8 per GEMM dispatch
+    (520, 530, 96, (256, 256), 2),
+    (1100, 300, 64, (256, 300), 1),
+])
+def test_gemm_groups_superblocks_without_edges(M, N, K, sb, ndisp):
+    # grouped executor: superblocks with no edges among them share dispatches
+    # of up to 8 tasks; with C in one chunk, every task writes that chunk, so
+    # each depends on the one before and gets a dispatch of its own
+    for chunk_c, want in ((list(sb), ndisp), ([0, 0], 9 if ndisp == 2 else 5)):
+        ctx = dry(exec_mode=1)
+        a = ctx.array([M, K])
+        b = ctx.array([K, N])
+        c = ctx.array([M, N], chunk=chunk_c)
+        a.fill(0.0)
+        b.fill(0.0)
+        c.fill(0.0)
+        ctx.reset_stats()
+        ctx.launch("gemm_f32", [M, N], [1, 1], list(sb), args=[M, N, K, c, a, b])
+        ctx.sync()
+        assert ctx.stats()["dispatches"] == want, (chunk_c, ctx.stats())
+        ctx.close()
+
+
 def test_halo_stores_cores_with_replicas():
     ctx = dry()
     x = ctx.array([100], chunk=[30], halo=[2])

@@ -297,6 +297,37 @@ def test_gemm_small_componentwise(L, M, N, K, chunkA, chunkB, chunkC, sb):
     assert np.all(np.abs(got - ref) <= 1e-5 * scale + 1e-30)
 
 
+@pytest.mark.parametrize("M,N,K,sb,ndisp", [
+    (300, 260, 77, (128, 100), 2),    # 3 x 3 = 9 superblocks: a dispatch of 8 tasks, then 1
+    (520, 530, 96, (256, 256), 2),    # 3 x 3 superblocks, ragged edge blocks in the last row and column
+    (1100, 300, 64, (256, 300), 1),   # 5 superblocks of whole rows, the last one 76 rows
+])
+def test_gemm_grouped_dispatch(L, M, N, K, sb, ndisp):
+    # LT_EXEC_GROUPED: superblocks of one launch without edges among them share
+    # a dispatch and each workgroup finds its task in the table.  C is chunked
+    # like the superblocks, so no two tasks write one chunk.
+    say("gemm grouped", M, N, K, sb)
+    rng = np.random.default_rng(23)
+    A = rng.standard_normal((M, K), dtype=np.float32)
+    B = rng.standard_normal((K, N), dtype=np.float32)
+    with ctx_of(L, exec_mode=1) as ctx:
+        a = ctx.array([M, K])
+        b = ctx.array([K, N])
+        c = ctx.array([M, N], chunk=list(sb))
+        a.write(A)
+        b.write(B)
+        c.fill(np.nan)
+        d0 = ctx.stats()["dispatches"]
+        ctx.launch("gemm_f32", [M, N], [1, 1], list(sb), args=[M, N, K, c, a, b])
+        ctx.sync()
+        assert ctx.stats()["dispatches"] - d0 == ndisp
+        got = c.read()
+    ref = oracle.gemm(A, B)
+    scale = oracle.gemm(np.abs(A), np.abs(B))
+    assert not np.isnan(got).any()
+    assert np.all(np.abs(got - ref) <= 1e-5 * scale + 1e-30)
+
+
 def test_gemm_identity_is_exact(L):
     say("gemm identity")
     A, B, got = _gemm_case(L, 512, 384, 384, (256, 0), (0, 128), (256, 128), (256, 128), ident=True)
