@@ -338,7 +338,12 @@ def bench_gemm_ooc(args, L, torch):
     steps = args.steps if args.steps_given else 1
     warmup = args.warmup if args.warmup_given else 0
     streams = args.compute_streams or 1
-    ctx = L.Context(device_budget_bytes=16 << 30, stage_threshold_bytes=8 << 30, sb_order=L.LT_ORDER_SERPENTINE,
+    band = args.sb_band
+    if band > 0:
+        order, order_name = L.LT_ORDER_BANDS, "bands of %d superblock rows, column by column" % band
+    else:
+        order, order_name = L.LT_ORDER_SERPENTINE, "serpentine order"
+    ctx = L.Context(device_budget_bytes=16 << 30, stage_threshold_bytes=8 << 30, sb_order=order, sb_band=max(band, 0),
                     n_compute_streams=streams)
     try:
         log("allocating 48 GiB of pinned host memory")
@@ -379,7 +384,7 @@ def bench_gemm_ooc(args, L, torch):
     h2d = st["bytes_h2d"] / steps
     d2h = st["bytes_d2h"] / steps
     line = base_line({"workload": "out-of-core GEMM 65536^3 f32 ~N(0,1) seed 2, A/B/C in pinned host memory "
-                                  "(48 GiB), device budget 16 GiB, 4096^2 superblocks in serpentine order",
+                                  "(48 GiB), device budget 16 GiB, 4096^2 superblocks in " + order_name,
                       "executor": "plain", "stage_threshold_bytes": 8 << 30, "compute_streams": streams},
                      steps, warmup)
     line.update({"value": round(compulsory / wall / 1e9, 2), "unit": "GB/s", "ms_per_step": round(wall * 1e3, 2),
@@ -747,6 +752,8 @@ def main():
                                            "jacobi_tiled", "disk"],
                     default="jacobi")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--sb-band", type=int, default=0,
+                    help="gemm_ooc: superblock rows per band of the banded issue order (0 = serpentine order)")
     ap.add_argument("--rows", type=int, default=0,
                     help="Jacobi tile variant (lt_kernel_tune: 8/16/32, 132/164/228, 302/304/308; 0 = default)")
     ap.add_argument("--executor", choices=["all", "grouped", "drain", "plain"], default="all",

@@ -98,11 +98,19 @@ typedef struct lt_config {
                                        allocates its own on first use           */
     uint64_t arena_bytes;           /* size of device_arena                     */
     int32_t trace;                  /* 1: record a per-operation trace          */
-    int32_t sb_order;               /* superblock issue order of 2-D/3-D grids:
-                                       LT_ORDER_ROWMAJOR or LT_ORDER_SERPENTINE
-                                       (odd rows of superblocks reversed, so
-                                       consecutive rows reuse the chunks the
-                                       previous row touched last)            */
+    int32_t sb_order;               /* superblock issue order of 2-D/3-D grids
+                                       (the last two axes; earlier axes
+                                       outermost): LT_ORDER_ROWMAJOR,
+                                       LT_ORDER_SERPENTINE (odd rows of
+                                       superblocks reversed, so consecutive
+                                       rows reuse the chunks the previous row
+                                       touched last) or LT_ORDER_BANDS (bands
+                                       of sb_band rows, issued column by
+                                       column with the rows of a column
+                                       consecutive, odd bands reversed: a chunk
+                                       that spans a column is used by sb_band
+                                       superblocks in a row).  Changes traffic
+                                       only, never results.                   */
     int32_t drain_workgroups;       /* workgroups of the batch drain kernel;
                                        0 = 1024                               */
     int32_t batch_flush_tasks;      /* an open batch issues its queue whenever
@@ -122,7 +130,9 @@ typedef struct lt_config {
                                        or never, then the least recently used;
                                        LT_EVICT_LRU (1) uses recency only.
                                        Changes traffic only, never results.   */
-    int32_t reserved[2];
+    int32_t sb_band;                /* LT_ORDER_BANDS: rows of superblocks per
+                                       band, >= 0; 0 = 2                      */
+    int32_t reserved[1];
     uint64_t host_budget_bytes;     /* cap on the pinned host memory of spill
                                        buffers (chunks of device-home arrays
                                        evicted from the device); beyond it the
@@ -137,6 +147,7 @@ typedef struct lt_config {
 
 #define LT_ORDER_ROWMAJOR 0
 #define LT_ORDER_SERPENTINE 1
+#define LT_ORDER_BANDS 2
 
 /* Fills *cfg with defaults. */
 void lt_config_init(lt_config *cfg);
@@ -150,7 +161,7 @@ lt_status lt_context_create(const lt_config *cfg, lt_context **out);
 lt_status lt_context_destroy(lt_context *ctx);
 
 /* Updates the tunable fields of a live context from *cfg: exec_mode,
- * stage_threshold_bytes, sb_order, drain_workgroups, batch_flush_tasks,
+ * stage_threshold_bytes, sb_order, sb_band, drain_workgroups, batch_flush_tasks,
  * trace.  Other fields are ignored.  Pending grouped work and an open batch's
  * queue are issued first.  Errors: LT_ERR_INVALID. */
 lt_status lt_context_configure(lt_context *ctx, const lt_config *cfg);

@@ -37,7 +37,7 @@ NP2LT = {np.dtype(v): k for k, v in DTYPES.items()}
 LT_EXEC_PLAIN, LT_EXEC_GROUPED = 0, 1
 LT_EVICT_NEXT_USE = 0
 LT_EVICT_LRU = 1
-LT_ORDER_ROWMAJOR, LT_ORDER_SERPENTINE = 0, 1
+LT_ORDER_ROWMAJOR, LT_ORDER_SERPENTINE, LT_ORDER_BANDS = 0, 1, 2
 LT_DIST_BLOCK, LT_DIST_CUSTOM, LT_DIST_STENCIL = 0, 1, 2
 LT_ARG_ARRAY, LT_ARG_INT, LT_ARG_FLOAT = 0, 1, 2
 LT_TASK_EXEC, LT_TASK_COMBINE, LT_TASK_IO = 0, 1, 2
@@ -49,7 +49,8 @@ class lt_config(C.Structure):
                 ("stage_threshold_bytes", C.c_uint64), ("device_arena", C.c_void_p),
                 ("arena_bytes", C.c_uint64), ("trace", C.c_int32), ("sb_order", C.c_int32),
                 ("drain_workgroups", C.c_int32), ("batch_flush_tasks", C.c_int32), ("drain_vectors", C.c_int32),
-                ("evict_policy", C.c_int32), ("reserved", C.c_int32 * 2), ("host_budget_bytes", C.c_uint64),
+                ("evict_policy", C.c_int32), ("sb_band", C.c_int32), ("reserved", C.c_int32 * 1),
+                ("host_budget_bytes", C.c_uint64),
                 ("spill_dir", C.c_char_p)]
 
 
@@ -306,7 +307,7 @@ class Context:
 
     def configure(self, **cfg):
         """Change tunable fields (exec_mode, stage_threshold_bytes, sb_order,
-        drain_workgroups, batch_flush_tasks, drain_vectors, evict_policy,
+        sb_band, drain_workgroups, batch_flush_tasks, drain_vectors, evict_policy,
         trace) of the live context."""
         for k, v in cfg.items():
             setattr(self.cfg, k, v)

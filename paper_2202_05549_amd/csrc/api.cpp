@@ -489,6 +489,10 @@ lt_status lt_context_create(const lt_config *cfg_in, lt_context **out) {
         g_create_err = "evict_policy must be LT_EVICT_NEXT_USE or LT_EVICT_LRU";
         return LT_ERR_INVALID;
     }
+    if (cfg.sb_order < LT_ORDER_ROWMAJOR || cfg.sb_order > LT_ORDER_BANDS || cfg.sb_band < 0) {
+        g_create_err = "sb_order must be LT_ORDER_ROWMAJOR, LT_ORDER_SERPENTINE or LT_ORDER_BANDS, sb_band >= 0";
+        return LT_ERR_INVALID;
+    }
     Ctx *ctx = new Ctx();
     ctx->cfg = cfg;
     if (cfg.spill_dir) ctx->spill_dir = cfg.spill_dir;
@@ -536,11 +540,15 @@ lt_status lt_context_configure(lt_context *ctx, const lt_config *cfg) {
         return set_err(ctx, LT_ERR_INVALID, "drain_vectors must be 0, 2 or 4");
     if (cfg->evict_policy != LT_EVICT_NEXT_USE && cfg->evict_policy != LT_EVICT_LRU)
         return set_err(ctx, LT_ERR_INVALID, "evict_policy must be LT_EVICT_NEXT_USE or LT_EVICT_LRU");
+    if (cfg->sb_order < LT_ORDER_ROWMAJOR || cfg->sb_order > LT_ORDER_BANDS || cfg->sb_band < 0)
+        return set_err(ctx, LT_ERR_INVALID,
+                       "sb_order must be LT_ORDER_ROWMAJOR, LT_ORDER_SERPENTINE or LT_ORDER_BANDS, sb_band >= 0");
     lt_status st = flush_all(ctx);
     if (st) return st;
     ctx->cfg.exec_mode = cfg->exec_mode;
     ctx->cfg.stage_threshold_bytes = cfg->stage_threshold_bytes;
     ctx->cfg.sb_order = cfg->sb_order;
+    ctx->cfg.sb_band = cfg->sb_band;
     ctx->cfg.drain_workgroups = cfg->drain_workgroups;
     ctx->cfg.batch_flush_tasks = cfg->batch_flush_tasks;
     ctx->cfg.drain_vectors = cfg->drain_vectors;

@@ -98,6 +98,38 @@ bool direct_view(Ctx *ctx, const Array *arr, const std::vector<Chunk *> &ch, KVi
     return true;
 }
 
+// Grid index of the t-th superblock issued (row-major numbering of `nsb`
+// superblocks per axis, last axis fastest), in the context's issue order.
+// The orders permute only the last two axes; earlier axes stay outermost.
+static void sb_index(int64_t t, int nd, const int64_t *nsb, int order, int band, int64_t *idx) {
+    int64_t r = t;
+    for (int a = nd - 1; a >= 0; --a) {
+        idx[a] = r % nsb[a];
+        r /= nsb[a];
+    }
+    if (nd < 2 || order == LT_ORDER_ROWMAJOR) return;
+    const int64_t rows = nsb[nd - 2], cols = nsb[nd - 1];
+    if (order == LT_ORDER_SERPENTINE) {
+        // reverse the fastest axis on every other row of superblocks
+        if ((t / cols) & 1) idx[nd - 1] = cols - 1 - idx[nd - 1];
+        return;
+    }
+    // LT_ORDER_BANDS: bands of h rows; within a band column by column, the
+    // rows of a column in turn (reversed on odd columns, so the row a column
+    // ends on starts the next); odd bands run right to left
+    const int64_t h = band > 0 ? band : 2;
+    const int64_t u = t % (rows * cols);
+    const int64_t b = u / (h * cols);       // every band before b is full
+    const int64_t r0 = b * h;
+    const int64_t hb = std::min(h, rows - r0);
+    const int64_t v = u - b * h * cols;
+    const int64_t ci = v / hb;
+    int64_t ri = v % hb;
+    if (ci & 1) ri = hb - 1 - ri;
+    idx[nd - 2] = r0 + ri;
+    idx[nd - 1] = (b & 1) ? cols - 1 - ci : ci;
+}
+
 void add_dep(std::vector<uint64_t> *deps, uint64_t id) {
     if (id && std::find(deps->begin(), deps->end(), id) == deps->end()) deps->push_back(id);
 }
@@ -1518,16 +1550,7 @@ lt_status launch(Ctx *ctx, lt_kernel *k, int nd, const int64_t *grid,
     int64_t idx[MAXD] = {0, 0, 0};
     std::vector<Chunk *> seen;
     for (int64_t t = 0; t < total; ++t) {
-        int64_t r = t;
-        for (int a = nd - 1; a >= 0; --a) {
-            idx[a] = r % nsb[a];
-            r /= nsb[a];
-        }
-        if (ctx->cfg.sb_order == LT_ORDER_SERPENTINE && nd >= 2) {
-            // reverse the fastest axis on every other row of superblocks
-            int64_t outer = t / nsb[nd - 1];
-            if (outer & 1) idx[nd - 1] = nsb[nd - 1] - 1 - idx[nd - 1];
-        }
+        sb_index(t, nd, nsb, ctx->cfg.sb_order, ctx->cfg.sb_band, idx);
         TaskPlan tp;
         int64_t blo[MAXD], bhi[MAXD];
         for (int a = 0; a < nd; ++a) {

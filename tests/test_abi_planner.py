@@ -141,6 +141,57 @@ def test_superblocks_partition_grid(grid, block, sb):
     ctx.close()
 
 
+@pytest.mark.parametrize("grid,sb", [((1000, 700), (100, 100)), ((64, 64), (8, 16)), ((30, 500), (10, 100)),
+                                     ((7, 9), (1, 1))])
+@pytest.mark.parametrize("order,band", [(0, 0), (1, 0), (2, 0), (2, 1), (2, 3), (2, 4), (2, 50)])
+def test_superblock_issue_orders(grid, sb, order, band):
+    # every order issues each superblock of the row-major partition once;
+    # serpentine reverses odd rows; bands visit h rows column by column, the
+    # rows of a column consecutively, snaking, odd bands right to left
+    ctx = dry(sb_order=order, sb_band=band)
+    x = ctx.array(list(grid)); y = ctx.array(list(grid))
+    lid = ctx.launch("jacobi2d_f32", list(grid), [1, 1], list(sb), args=[grid[0], grid[1], y, x])
+    got = [(tuple(t.sb_lo[:2]), tuple(t.sb_hi[:2])) for t in ctx.tasks(lid)]
+    ctx.close()
+    want = P.superblocks(list(grid), [1, 1], list(sb))
+    assert sorted(got) == sorted(want) and len(got) == len(want)
+    rows = -(-grid[0] // sb[0])
+    cols = -(-grid[1] // sb[1])
+    ij = [(lo[0] // sb[0], lo[1] // sb[1]) for lo, _ in got]
+    if order == 0:
+        assert ij == [(i, j) for i in range(rows) for j in range(cols)]
+    elif order == 1:
+        assert ij == [(i, j if i % 2 == 0 else cols - 1 - j) for i in range(rows) for j in range(cols)]
+    else:
+        h = band if band > 0 else 2
+        k = 0
+        for bnd, r0 in enumerate(range(0, rows, h)):
+            hb = min(h, rows - r0)
+            last_row = None
+            col_seq = range(cols) if bnd % 2 == 0 else range(cols - 1, -1, -1)
+            for c in col_seq:
+                col = ij[k:k + hb]
+                k += hb
+                assert all(j == c for _, j in col)
+                assert sorted(i for i, _ in col) == list(range(r0, r0 + hb))
+                if last_row is not None:
+                    assert col[0][0] == last_row        # the snake turns on the row it ended on
+                last_row = col[-1][0]
+        assert k == len(ij)
+
+
+def test_superblock_order_validation():
+    with pytest.raises(L.LtError):
+        dry(sb_order=3)
+    with pytest.raises(L.LtError):
+        dry(sb_order=2, sb_band=-1)
+    ctx = dry()
+    with pytest.raises(L.LtError):
+        ctx.configure(sb_order=-1)
+    ctx.configure(sb_order=L.LT_ORDER_BANDS, sb_band=4)
+    ctx.close()
+
+
 # ------------------------------------------------------------- DAG (T4)
 
 def _launch_seq(ctx, rng, n, arrays, steps):
@@ -487,6 +538,38 @@ def test_next_use_eviction_moves_no_more_than_lru():
     lru, lru_ev = _ooc_gemm_h2d(L.LT_EVICT_LRU)
     assert nu_ev > 0 and lru_ev > 0  # the budget binds under both
     assert nu <= lru, (nu, lru)
+
+
+def test_banded_order_reuses_panels():
+    # out-of-core GEMM with host-home operands, 16 x 16 C tiles and a device
+    # budget smaller than B: bands of h superblock rows use each B panel for h
+    # tiles in a row, so the product loads fewer panels than in serpentine
+    # order (at a budget of 16 panels these are the ratios of the 65536^3
+    # product with 16 GiB: 77, 67, 51 panels of which 32 are compulsory)
+    n, T = 4096, 256
+    panel = (n // T) * T * T * 4
+    A = np.zeros((n, n), np.float32)
+    B = np.zeros((n, n), np.float32)
+    Cm = np.zeros((n, n), np.float32)
+
+    def h2d(budget, order, band):
+        ctx = dry(device_budget_bytes=budget * panel, stage_threshold_bytes=1 << 40, sb_order=order, sb_band=band)
+        a = ctx.array_host(A, chunk=[T, 0])
+        b = ctx.array_host(B, chunk=[0, T])
+        c = ctx.array_host(Cm, chunk=[T, T])
+        ctx.launch("gemm_f32", [n, n], [1, 1], [T, T], args=[n, n, n, c, a, b])
+        ctx.sync()
+        s = ctx.stats()
+        ctx.close()
+        assert s["bytes_d2h"] == n * n * 4          # C written back once
+        return s["bytes_h2d"] / panel
+
+    for budget in (10, 16):
+        serp = h2d(budget, L.LT_ORDER_SERPENTINE, 0)
+        b2 = h2d(budget, L.LT_ORDER_BANDS, 2)
+        b4 = h2d(budget, L.LT_ORDER_BANDS, 4)
+        assert 32 <= b4 < b2 < serp, (budget, serp, b2, b4)
+    assert b4 <= 0.7 * serp
 
 
 def test_evict_policy_validated():
