@@ -95,12 +95,20 @@ JACOBI_SOURCES = [
     ("kernels.hip", "// Stacked tiles of 4 RB rows", "// ================================================================ hist256"),
 ]
 
+# the code of k_gemm: the whole file (kernel, block order and launcher)
+GEMM_SOURCES = [("gemm.hip", "#include <hip/hip_runtime.h>", "}  // namespace lt")]
+
 TRAFFIC = {
     # k_jacobi2d_stack<4>, one 16384 x 16384 sweep per dispatch: FETCH_SIZE
     # 528,412 KiB x 2.000 (the 1 GiB copy reads 524,309 KiB) + WRITE_SIZE
     # 1,048,826 KiB x 1.000 (the copy writes 1,048,576 KiB)
     "k_jacobi2d_stack": {"sources": JACOBI_SOURCES, "digest": "e7b9d79b7799ba4e",
                          "bytes_per_dispatch": 528412 * 1024 * 2.000 + 1048826 * 1024},
+    # k_gemm, one 4096^2 C tile with K = 65536 per dispatch (out-of-core GEMM
+    # 65536^3, 256 dispatches): FETCH_SIZE 4,366,023 KiB x 2.000 (the 1 GiB
+    # copy reads 524,309 KiB) + WRITE_SIZE 67,935 KiB x 1.000
+    "k_gemm": {"sources": GEMM_SOURCES, "digest": "3aa440b270bd49e5",
+               "bytes_per_dispatch": 4366023 * 1024 * 2.000 + 67935 * 1024},
 }
 
 
@@ -396,7 +404,7 @@ def bench_gemm_ooc(args, L, torch):
                  "kernel_busy_frac": round(prof["total_ms"] / steps * 1e-3 / wall, 4),
                  "p50_ms": round(pct(times, 50), 2), "p99_ms": round(pct(times, 99), 2),
                  "roofline": {"bound": "mfma", "achieved": round(kernel_tflops, 2), "peak": MFMA_FP32_PEAK,
-                              "unit": "TFLOP/s", "frac": round(kernel_tflops / MFMA_FP32_PEAK, 4), "traffic": None,
+                              "unit": "TFLOP/s", "frac": round(kernel_tflops / MFMA_FP32_PEAK, 4), "traffic": traffic_for("k_gemm"),
                               "kernel": "k_gemm", "kernel_avg_ms": round(prof["total_ms"] / prof["dispatches"], 3)}})
     return line
 

@@ -25,6 +25,7 @@ constexpr int BM = 256, BN = 256, BK = 32;
 constexpr int LDA = BM + 1;   // As[k][m]
 constexpr int LDB = BN + 4;   // Bs[k][n]
 constexpr int GMAX = 8;       // tasks per dispatch
+constexpr int GM = 4;         // block rows per group of the block order
 
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
@@ -187,8 +188,18 @@ __global__ __launch_bounds__(512, 1) void k_gemm(GArgs g) {
     const int b = body::xcd_remap(blockIdx.x, g.nblocks);
     const int ti = body::find_task(g.begin, g.ntask, b);
     const GTask &tk = g.t[ti];
+    // Blocks of a task go in groups of GM block rows, column by column within
+    // a group, so that a run of 32 consecutive blocks (one XCD's share of a
+    // 16 x 16 task after xcd_remap) covers 4 x 8 blocks: the XCD's L2 then
+    // serves 12 operand strips instead of the 18 of two whole block rows.
+    // A bijection onto the task's blocks for any shape.
     const int local = b - g.begin[ti];
-    const int tmi = local / tk.tn, tni = local - tmi * tk.tn;
+    const int tm = (g.begin[ti + 1] - g.begin[ti]) / tk.tn;
+    const int grp = local / (GM * tk.tn);
+    const int first = grp * GM;
+    const int gsz = tm - first < GM ? tm - first : GM;
+    const int r = local - grp * GM * tk.tn;
+    const int tmi = first + r % gsz, tni = r / gsz;
     const int64_t m0 = tk.i0 + (int64_t)tmi * BM;
     const int64_t n0 = tk.j0 + (int64_t)tni * BN;
     // global-address-space pointers: global (not flat) loads do not hold up
