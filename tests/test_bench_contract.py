@@ -1,0 +1,48 @@
+"""Host-side checks of bench.py: the one-GPU contract, and the HBM traffic
+table that feeds ``roofline.traffic`` (no GPU needed)."""
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _bench_module():
+    import importlib.util
+
+    spec = importlib.util.spec_from_file_location("bench_contract_probe", os.path.join(ROOT, "bench.py"))
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    return mod
+
+
+@pytest.mark.parametrize("n", [2, 8])
+def test_multi_gpu_request_exits_with_message(n):
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", str(n)],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr and r.stdout == ""
+
+
+def test_traffic_table_entries_are_well_formed():
+    b = _bench_module()
+    for name, t in b.TRAFFIC.items():
+        assert t["bytes_per_dispatch"] > 0
+        # the digest is taken over existing source sections: a marker that no
+        # longer matches raises instead of silently nulling the figure
+        d = b.kernel_digest(t["sources"])
+        assert len(d) == 16
+        got = b.traffic_for(name)
+        assert got is None or got == int(round(t["bytes_per_dispatch"]))
+    assert b.traffic_for("no_such_kernel") is None
+
+
+def test_traffic_at_least_algorithmic():
+    # measured HBM bytes per dispatch can exceed the algorithmic bytes (re-reads)
+    # but never undercut them: 16384^2 x 8 B per Jacobi sweep, and one 1 GiB A
+    # panel, one 1 GiB B panel and a 64 MiB C tile per GEMM dispatch
+    b = _bench_module()
+    assert b.TRAFFIC["k_jacobi2d_stack"]["bytes_per_dispatch"] >= 16384 * 16384 * 8
+    assert b.TRAFFIC["k_gemm"]["bytes_per_dispatch"] >= 2 * 4096 * 65536 * 4 + 4096 * 4096 * 4
