@@ -105,10 +105,10 @@ TRAFFIC = {
     "k_jacobi2d_stack": {"sources": JACOBI_SOURCES, "digest": "e7b9d79b7799ba4e",
                          "bytes_per_dispatch": 528412 * 1024 * 2.000 + 1048826 * 1024},
     # k_gemm, one 4096^2 C tile with K = 65536 per dispatch (out-of-core GEMM
-    # 65536^3, 256 dispatches): FETCH_SIZE 4,366,023 KiB x 2.000 (the 1 GiB
-    # copy reads 524,309 KiB) + WRITE_SIZE 67,935 KiB x 1.000
-    "k_gemm": {"sources": GEMM_SOURCES, "digest": "3aa440b270bd49e5",
-               "bytes_per_dispatch": 4366023 * 1024 * 2.000 + 67935 * 1024},
+    # 65536^3, 256 dispatches): FETCH_SIZE 4,046,964 KiB x 2.000 (the 1 GiB
+    # copy reads 524,309 KiB) + WRITE_SIZE 68,518 KiB x 1.000
+    "k_gemm": {"sources": GEMM_SOURCES, "digest": "09089ee7a4180e74",
+               "bytes_per_dispatch": 4046964 * 1024 * 2.000 + 68518 * 1024},
 }
 
 

@@ -25,7 +25,7 @@ constexpr int BM = 256, BN = 256, BK = 32;
 constexpr int LDA = BM + 1;   // As[k][m]
 constexpr int LDB = BN + 4;   // Bs[k][n]
 constexpr int GMAX = 8;       // tasks per dispatch
-constexpr int GM = 4;         // block rows per group of the block order
+constexpr int GM = 8;         // block rows per group of the block order
 
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
@@ -190,7 +190,7 @@ __global__ __launch_bounds__(512, 1) void k_gemm(GArgs g) {
     const GTask &tk = g.t[ti];
     // Blocks of a task go in groups of GM block rows, column by column within
     // a group, so that a run of 32 consecutive blocks (one XCD's share of a
-    // 16 x 16 task after xcd_remap) covers 4 x 8 blocks: the XCD's L2 then
+    // 16 x 16 task after xcd_remap) covers 8 x 4 blocks: the XCD's L2 then
     // serves 12 operand strips instead of the 18 of two whole block rows.
     // A bijection onto the task's blocks for any shape.
     const int local = b - g.begin[ti];
