@@ -180,6 +180,16 @@ def test_superblock_issue_orders(grid, sb, order, band):
         assert k == len(ij)
 
 
+@pytest.mark.parametrize("shape", [[0], [64, 0], [0, 64], [4, 4, 0]])
+def test_zero_extent_arrays_are_rejected(shape):
+    # an array has at least one element along every axis; an empty launch grid
+    # is the way to express no work
+    ctx = dry()
+    with pytest.raises(L.LtError, match="must be > 0"):
+        ctx.array(shape)
+    ctx.close()
+
+
 def test_superblock_order_validation():
     with pytest.raises(L.LtError):
         dry(sb_order=3)
