@@ -98,6 +98,14 @@ JACOBI_SOURCES = [
 # the code of k_gemm: the whole file (kernel, block order and launcher)
 GEMM_SOURCES = [("gemm.hip", "#include <hip/hip_runtime.h>", "}  // namespace lt")]
 
+# the code of k_kmeans (assignment): its section of kernels.hip
+KMEANS_SOURCES = [("kernels.hip", "// ========================================================== kmeans assign",
+                   "// ============================================================== copy boxes")]
+# the code of k_kmeans_update_v: its section of reduce.hip and the slot rule
+KMU_SOURCES = [("reduce.hip", "// ======================================================== k-means update",
+                "// ========================================================= k-means centres"),
+               ("kernels.h", "// k-means update: points per workgroup tile", "// Runtime helpers.")]
+
 TRAFFIC = {
     # k_jacobi2d_stack<4>, one 16384 x 16384 sweep per dispatch: FETCH_SIZE
     # 528,412 KiB x 2.000 (the 1 GiB copy reads 524,309 KiB) + WRITE_SIZE
@@ -109,6 +117,16 @@ TRAFFIC = {
     # copy reads 524,309 KiB) + WRITE_SIZE 68,518 KiB x 1.000
     "k_gemm": {"sources": GEMM_SOURCES, "digest": "09089ee7a4180e74",
                "bytes_per_dispatch": 4046964 * 1024 * 2.000 + 68518 * 1024},
+    # k_kmeans<16>, one dispatch per assignment launch of 2^26 points (d = 16,
+    # K = 64): FETCH_SIZE 2,097,210 KiB x 2.000 + WRITE_SIZE 262,144 KiB x
+    # 1.000, the 64 B of each point and its 4 B label
+    "k_kmeans": {"sources": KMEANS_SOURCES, "digest": "9c654699cb5049b5",
+                 "bytes_per_dispatch": 2097210 * 1024 * 2.000 + 262144 * 1024},
+    # k_kmeans_update_v<16, 4>, one dispatch per 2^22-point superblock:
+    # FETCH_SIZE 139,300 KiB x 2.000 + WRITE_SIZE 8,448 KiB x 1.000 (1024
+    # partial slots of 64 x 16 float64 sums and 64 counts)
+    "k_kmeans_update": {"sources": KMU_SOURCES, "digest": "d98381726987eb27",
+                        "bytes_per_dispatch": 139300 * 1024 * 2.000 + 8448 * 1024},
 }
 
 
@@ -726,10 +744,11 @@ def bench_kmeans(args, L, torch):
     line.update({"value": round(gbs, 2), "unit": "GB/s", "ms_per_step": round(ms, 3), "dtype": "f32+f64",
                  "p50_ms": round(pct(times, 50), 3), "p99_ms": round(pct(times, 99), 3),
                  "roofline": {"bound": "alu", "achieved": round(a_tflops, 2), "peak": 78.6, "unit": "TFLOP/s",
-                              "frac": round(a_tflops / 78.6, 4), "traffic": None, "kernel": "k_kmeans",
+                              "frac": round(a_tflops / 78.6, 4), "traffic": traffic_for("k_kmeans"), "kernel": "k_kmeans",
                               "kernel_avg_ms": round(a_avg, 4), "time_share": round(a_share, 3)},
                  "update": {"kernel": "k_kmeans_update", "bound": "hbm", "achieved_gbs": round(u_gbs, 1),
-                            "frac": round(u_gbs / HBM_PEAK_GBS, 4), "kernel_avg_ms": round(u_avg, 4)}})
+                            "frac": round(u_gbs / HBM_PEAK_GBS, 4), "kernel_avg_ms": round(u_avg, 4),
+                            "traffic": traffic_for("k_kmeans_update")}})
     if not args.no_cpu:
         import oracle
 
