@@ -85,6 +85,23 @@ def test_jacobi_halo_out_of_core(L, host):
     assert st["evictions_dirty"] > 0 and (host or st["halo_copies"] > 0)
 
 
+@pytest.mark.parametrize("order,band", [(1, 0), (2, 2), (2, 3)])
+def test_jacobi_halo_out_of_core_issue_orders(L, order, band):
+    # the out-of-core halo tiles under the serpentine and banded issue orders:
+    # replica refreshes and reloads follow the order of the superblocks, and
+    # the result is the oracle's bit for bit under every order
+    n, m = 1024, 1280
+    say("jacobi halo spill order", order, band)
+    x0 = synthetic.jacobi2d_input(n, m, seed=23)
+    tile = 256 * 256 * 4
+    with L.Context(device_budget_bytes=14 * tile, stage_threshold_bytes=1 << 40, sb_order=order,
+                   sb_band=band) as ctx:
+        got = _jacobi(ctx, x0, [256, 256], [1, 1], 4, [256, 256])
+        st = ctx.stats()
+    assert np.array_equal(got, oracle.jacobi2d(x0, 4))
+    assert st["evictions_dirty"] > 0
+
+
 @pytest.mark.parametrize("halo", [1, 3])
 def test_stencil1d_halo_bit_exact(L, halo):
     n = 100003
