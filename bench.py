@@ -232,7 +232,8 @@ def jacobi_cpu_baseline(x0, budget_s=24.0):
     t0 = time.perf_counter()
     oracle.lib().or_jacobi2d_sweep_f32(N, N, a.ctypes.data, b.ctypes.data)
     one = time.perf_counter() - t0
-    # about budget_s of CPU work: whole steps of SWEEPS sweeps where they fit
+    # about budget_s of CPU work (the estimate from one sweep runs high, so 10-25 s
+    # in practice): whole steps of SWEEPS sweeps where they fit
     # (up to 20), else the sweeps of one step that fit
     sweeps = int(max(1, min(20 * SWEEPS, budget_s / max(one, 1e-3))))
     if sweeps > SWEEPS:
