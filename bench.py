@@ -278,7 +278,8 @@ def bench_jacobi(args, L, torch):
                  "p99_ms": round(m["p99_ms"], 3),
                  "roofline": {"bound": "hbm", "achieved": round(m["kernel_gbs"], 2), "peak": HBM_PEAK_GBS,
                               "unit": "GB/s", "frac": round(m["kernel_gbs"] / HBM_PEAK_GBS, 4),
-                              "traffic": traffic_for(jk) if best == "grouped" else None,
+                              # measured on the default variant (k_jacobi2d_stack<4>) only
+                              "traffic": traffic_for(jk) if best == "grouped" and args.rows in (0, 304) else None,
                               "kernel": "k_drain" if best == "drain" else jk,
                               "kernel_avg_ms": round(m["kernel_avg_ms"], 4)}})
     for ex in execs:
