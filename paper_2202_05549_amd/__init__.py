@@ -288,7 +288,20 @@ class Array:
 class Context:
     """An lt_context with keyword configuration (see lt_config in lt.h)."""
 
+    _FIELDS = None
+
+    @classmethod
+    def _check_keys(cls, cfg):
+        # ctypes would store an unknown (e.g. misspelt) key as a plain Python
+        # attribute and the library would never see it
+        if cls._FIELDS is None:
+            cls._FIELDS = {f[0] for f in lt_config._fields_} - {"reserved"}
+        bad = sorted(set(cfg) - cls._FIELDS)
+        if bad:
+            raise TypeError("unknown lt_config field(s): %s" % ", ".join(bad))
+
     def __init__(self, **cfg):
+        self._check_keys(cfg)
         c = lt_config()
         lt_config_init(C.byref(c))
         for k, v in cfg.items():
@@ -309,6 +322,7 @@ class Context:
         """Change tunable fields (exec_mode, stage_threshold_bytes, sb_order,
         sb_band, drain_workgroups, batch_flush_tasks, drain_vectors, evict_policy,
         trace) of the live context."""
+        self._check_keys(cfg)
         for k, v in cfg.items():
             setattr(self.cfg, k, v)
         check(self.h, lt_context_configure(self.h, C.byref(self.cfg)))

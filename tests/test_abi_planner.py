@@ -190,6 +190,15 @@ def test_zero_extent_arrays_are_rejected(shape):
     ctx.close()
 
 
+def test_unknown_config_keys_are_rejected():
+    with pytest.raises(TypeError, match="sb_bnd"):
+        dry(sb_bnd=2)
+    ctx = dry()
+    with pytest.raises(TypeError, match="evict_polcy"):
+        ctx.configure(evict_polcy=1)
+    ctx.close()
+
+
 def test_superblock_order_validation():
     with pytest.raises(L.LtError):
         dry(sb_order=3)
