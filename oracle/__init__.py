@@ -47,6 +47,7 @@ def lib():
         L.or_gemm_f64.argtypes = [i64, i64, i64, p, i64, p, i64, p, i64]
         L.or_gemm_entries_f64.argtypes = [i64, p, i64, p, i64, i64, p, p, p, p]
         L.or_matvec_f64.argtypes = [i64, i64, p, i64, p, p, i32]
+        L.or_matmul_thin_f64.argtypes = [i64, i64, p, i64, i64, p, p, i32]
         L.or_hist256_i32.argtypes = [i64, p, p]
         L.or_kmeans_assign_f32.argtypes = [i64, i64, i64, p, p, p]
         L.or_kmeans_dist_f64.argtypes = [i64, p, p]
@@ -140,24 +141,51 @@ def matvec(A: np.ndarray, x: np.ndarray, absval: bool = False) -> np.ndarray:
     return y
 
 
-def freivalds(A, B, Cm, trials: int = 3, seed: int = 12345):
-    """Randomized check of Cm = A B in float64.
+def matmul_thin(A: np.ndarray, X: np.ndarray, absval: bool = False) -> np.ndarray:
+    """op(A) X in float64 for float32 A (unit column stride) and a float64
+    X with few columns; op takes |a| when ``absval``."""
+    assert A.dtype == np.float32 and A.strides[1] == 4
+    X = np.ascontiguousarray(X, dtype=np.float64)
+    assert X.shape[0] == A.shape[1]
+    Y = np.empty((A.shape[0], X.shape[1]), dtype=np.float64)
+    lib().or_matmul_thin_f64(A.shape[0], A.shape[1], C.c_void_p(A.ctypes.data), A.strides[0] // 4,
+                             X.shape[1], _ptr(X), _ptr(Y), int(absval))
+    return Y
 
-    For each trial draws r in {-1, +1}^n and returns, per row i, the residual
-    |(Cm r - A (B r))_i| and the scale (|A| (|B| 1))_i; a correct float32
-    product has residual / scale of the order of the float32 unit roundoff
-    times sqrt(K).  Returns the worst ratio over rows and trials.
+
+def freivalds(A, B, Cm, trials: int = 3, seed: int = 12345, panel: int = 0):
+    """Randomized check of Cm = A B in float64 (Freivalds' algorithm).
+
+    Each trial draws r in {-1, +1}^n and compares, row by row, Cm r with
+    A (B r); the residual |(Cm r - A (B r))_i| is divided by the scale
+    (|A| (|B| 1))_i, so a correct float32 product scores of the order of the
+    float32 unit roundoff times sqrt(K).  With ``panel`` > 0 the columns are
+    checked in panels of that width, each with its own r supported on the
+    panel only: the scale then covers one panel instead of all n columns, so
+    an error confined to a small block of C is not diluted by the whole row.
+    Returns the worst ratio over rows, panels and trials.  A non-finite
+    entry of Cm makes its row of Cm R non-finite (NaN times the zero of
+    another panel is still NaN), and any non-finite ratio returns +inf, so a
+    NaN-filled or unwritten part of C can never pass.
     """
     rng = np.random.default_rng(seed)
     n = B.shape[1]
-    ones = np.ones(n, dtype=np.float64)
-    scale = matvec(A, matvec(B, ones, absval=True), absval=True)
+    w = n if panel <= 0 else min(panel, n)
+    starts = list(range(0, n, w))
+    # column c of R is the indicator of panel c (for the scale) or the random
+    # signs on panel c (for a trial): one pass over each matrix per trial
+    ind = np.zeros((n, len(starts)), dtype=np.float64)
+    for c, j0 in enumerate(starts):
+        ind[j0:j0 + w, c] = 1.0
+    scale = matmul_thin(A, matmul_thin(B, ind, absval=True), absval=True)
     worst = 0.0
     for _ in range(trials):
-        r = rng.choice(np.array([-1.0, 1.0]), n)
-        lhs = matvec(Cm, r)
-        rhs = matvec(A, matvec(B, r))
+        R = ind * rng.choice(np.array([-1.0, 1.0]), (n, 1))
+        lhs = matmul_thin(Cm, R)
+        rhs = matmul_thin(A, matmul_thin(B, R))
         ratio = np.abs(lhs - rhs) / np.maximum(scale, np.finfo(np.float64).tiny)
+        if not np.isfinite(ratio).all():
+            return float("inf")
         worst = max(worst, float(ratio.max()))
     return worst
 

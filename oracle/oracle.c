@@ -148,6 +148,31 @@ void or_matvec_f64(int64_t M, int64_t K, const float *A, int64_t lda,
     }
 }
 
+/* Y = op(A) X in float64 for a row-major float32 M x K matrix A and a
+ * row-major float64 K x m matrix X with few columns (m of about 16): the
+ * matvec above for m right-hand sides at once, so a randomized check with
+ * one probe vector per column panel reads A once.
+ */
+void or_matmul_thin_f64(int64_t M, int64_t K, const float *A, int64_t lda,
+                        int64_t m, const double *X, double *Y, int absval)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < M; ++i) {
+        const float *ai = A + i * lda;
+        double *yi = Y + i * m;
+        for (int64_t c = 0; c < m; ++c)
+            yi[c] = 0.0;
+        for (int64_t k = 0; k < K; ++k) {
+            double a = (double)ai[k];
+            if (absval)
+                a = fabs(a);
+            const double *xk = X + k * m;
+            for (int64_t c = 0; c < m; ++c)
+                yi[c] += a * xk[c];
+        }
+    }
+}
+
 /* ---------------------------------------------------------------- histogram
  * 256-bin integer histogram: h[b] = #{ i : v[i] == b }.  The annotation's
  * reduce(+) mode (Sec. 2.3) makes the target the sum of all contributions,

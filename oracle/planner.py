@@ -297,15 +297,52 @@ def superblocks(grid, block, sb):
     return out
 
 
-def conflicting(mode_a, op_a, mode_b, op_b):
+def conflicting(mode_a, op_a, mode_b, op_b, same_launch=False):
     """Do two accesses to overlapping elements need an ordering (Sec. 2.4:
-    read-write, write-write and write-read conflicts)?  Two reads never do;
-    two reductions with the same operator commute."""
+    read-write, write-write and write-read conflicts)?  Two reads never do.
+    Two reductions with the same operator commute only inside one launch:
+    a launch's fold overwrites its target (reduce(f) is write-like, Sec. 2.3,
+    and the target is the fold of that launch's contributions alone), so
+    reductions from different launches into one element keep program
+    order."""
     if mode_a == "read" and mode_b == "read":
         return False
-    if mode_a == "reduce" and mode_b == "reduce" and op_a == op_b:
+    if mode_a == "reduce" and mode_b == "reduce" and op_a == op_b and same_launch:
         return False
     return True
+
+
+def launch_tasks(launch, sb_accesses):
+    """Tasks of one launch as the planner of Sec. 2.4 lays them out.
+
+    ``sb_accesses`` holds, per superblock in issue order, its accesses
+    (array, mode, op, inclusive box).  Each superblock is one task.  A
+    reduce access does not touch the target: the superblock writes a private
+    temporary ("partial", launch, array, superblock) instead, and one
+    reduction task per reduced array, after the superblock tasks, reads all
+    of that array's partials and writes the union of their boxes in the
+    target (the fold overwrites it).  Returns task dicts for
+    ``required_orderings``.
+    """
+    tasks = []
+    reduced = {}
+    for k, acc in enumerate(sb_accesses):
+        mine = []
+        for (ar, mode, op, box) in acc:
+            if mode == "reduce":
+                part = ("partial", launch, ar, k)
+                mine.append((part, "write", None, ((0, 0),)))
+                reduced.setdefault(ar, []).append((part, box))
+            else:
+                mine.append((ar, mode, op, box))
+        tasks.append({"launch": launch, "accesses": mine})
+    for ar, parts in reduced.items():
+        lo = [min(b[a][0] for _, b in parts) for a in range(len(parts[0][1]))]
+        hi = [max(b[a][1] for _, b in parts) for a in range(len(parts[0][1]))]
+        acc = [(p, "read", None, ((0, 0),)) for p, _ in parts]
+        acc.append((ar, "write", None, tuple(zip(lo, hi))))
+        tasks.append({"launch": launch, "accesses": acc})
+    return tasks
 
 
 def boxes_overlap(a, b):
@@ -316,16 +353,19 @@ def required_orderings(tasks):
     """Pairs (p, q), p < q, of tasks in program order that must stay ordered.
 
     ``tasks`` is a list of dicts {"accesses": [(array, mode, op, box)]} with
-    inclusive boxes.  Two tasks must be ordered when they touch overlapping
-    parts of one array and at least one of the accesses conflicts.
+    inclusive boxes and an optional "launch" key.  Two tasks must be ordered
+    when they touch overlapping parts of one array and the two accesses
+    conflict (tasks without a launch key count as different launches).
     """
     out = []
     for q in range(len(tasks)):
         for p in range(q):
             need = False
+            lp, lq = tasks[p].get("launch"), tasks[q].get("launch")
+            same = lp is not None and lp == lq
             for (ar, ma, oa, ba) in tasks[p]["accesses"]:
                 for (br, mb, ob, bb) in tasks[q]["accesses"]:
-                    if ar == br and conflicting(ma, oa, mb, ob) and boxes_overlap(ba, bb):
+                    if ar == br and conflicting(ma, oa, mb, ob, same) and boxes_overlap(ba, bb):
                         need = True
             if need:
                 out.append((p, q))

@@ -213,51 +213,67 @@ def test_superblock_order_validation():
 
 # ------------------------------------------------------------- DAG (T4)
 
-def _launch_seq(ctx, rng, n, arrays, steps):
-    """Random stencil/touch launches on tiny arrays; returns the oracle task
-    list with inclusive boxes, in program order, plus task ids."""
+def _launch_seq(ctx, rng, n, arrays, steps, hist=None, first=()):
+    """Random stencil/touch launches on tiny arrays, and with ``hist`` =
+    (h, values, h2) also histogram reductions into the shared target h,
+    read-modify-writes of h, and plain reads of h (a histogram of h's bins
+    into h2).  ``first`` fixes the kinds of the first launches.  Returns the oracle task list in program order
+    (each launch expanded as the planner lays it out, reductions folded by a
+    task of their own) and the planner's task ids in the same order."""
     tasks, ids = [], []
     annots = ["global i => read x[i-1:i+1], write y[i]", "global i => read x[i], write y[i]",
               "global i => read x[:], write y[i]", "global i => read x[i+2:i+3], write y[i]"]
-    for _ in range(steps):
-        kind = rng.integers(3)
+    modes = {0: "read", 1: "write", 2: "readwrite", 3: "reduce"}
+    ops = {0: "+", 1: "*", 2: "min", 3: "max"}
+
+    def record(lid, arr_of):
+        sbs, sb_ids, tail = [], [], []
+        for t in ctx.tasks(lid):
+            acc = [(arr_of(r).id, modes[r.mode], ops[r.op] if r.mode == 3 else None, _box(r, 1))
+                   for r in ctx.regions(t.id)]
+            if t.kind == L.LT_TASK_COMBINE:
+                tail.append(t.id)
+            else:
+                sbs.append(acc)
+                sb_ids.append(t.id)
+        expanded = P.launch_tasks(lid, sbs)
+        assert len(expanded) == len(sb_ids) + len(tail)
+        tasks.extend(expanded)
+        ids.extend(sb_ids + tail)
+
+    nkinds = 6 if hist is not None else 3
+    for step in range(steps):
+        kind = first[step] if step < len(first) else rng.integers(nkinds)
         sb = int(rng.choice([4, 8, 12]))
         if kind < 2:
             a, b = rng.choice(len(arrays), 2, replace=False)
             annot = annots[rng.integers(len(annots))]
             lid = ctx.launch("stencil1d_f32", [n], [4], [sb], args=[n, arrays[b], arrays[a]],
                              kernel_annotation=annot)
-            for t in ctx.tasks(lid):
-                acc = []
-                for r in ctx.regions(t.id):
-                    arr = arrays[a] if r.arg == 2 else arrays[b]
-                    mode = "read" if r.mode == 0 else "write"
-                    acc.append((arr.id, mode, None, _box(r, 1)))
-                tasks.append({"accesses": acc}); ids.append(t.id)
-        else:
+            record(lid, lambda r, a=a, b=b: arrays[a] if r.arg == 2 else arrays[b])
+        elif kind == 2:
             a = rng.integers(len(arrays))
-            arr_i = ctx.array([n], np.int32) if False else None
             lid = ctx.launch("stencil1d_f32", [n], [4], [sb], args=[n, arrays[a], arrays[a]],
                              kernel_annotation="global i => readwrite y[i], read x[i]")
-            for t in ctx.tasks(lid):
-                acc = []
-                for r in ctx.regions(t.id):
-                    mode = {0: "read", 1: "write", 2: "readwrite"}[r.mode]
-                    acc.append((arrays[a].id, mode, None, _box(r, 1)))
-                tasks.append({"accesses": acc}); ids.append(t.id)
+            record(lid, lambda r, a=a: arrays[a])
+        elif kind == 3:
+            h, vals, _ = hist
+            v = vals[rng.integers(len(vals))]
+            lid = ctx.launch("hist256_i32", [n], [4], [sb], args=[n, h, v])
+            record(lid, lambda r, h=h, v=v: h if r.arg == 1 else v)
+        elif kind == 4:
+            h, _, _ = hist
+            lid = ctx.launch("touch_i32", [256], [4], [int(rng.choice([64, 256]))], args=[256, h])
+            record(lid, lambda r, h=h: h)
+        else:
+            # a plain read of h: its bins are the values of another histogram
+            h, _, h2 = hist
+            lid = ctx.launch("hist256_i32", [256], [4], [int(rng.choice([64, 256]))], args=[256, h2, h])
+            record(lid, lambda r, h=h, h2=h2: h2 if r.arg == 1 else h)
     return tasks, ids
 
 
-@pytest.mark.parametrize("halo", [None, 1, 3])
-@pytest.mark.parametrize("seed", range(6))
-def test_dag_contains_every_required_ordering(seed, halo):
-    rng = np.random.default_rng(seed)
-    ctx = dry()
-    n = 40
-    arrays = [ctx.array([n], chunk=[int(rng.choice([5, 8, 40]))], halo=None if halo is None else [halo])
-              for _ in range(3)]
-    tasks, ids = _launch_seq(ctx, rng, n, arrays, 6)
-    # transitive closure of the planner's edges
+def _closure_contains_required(ctx, tasks, ids):
     pos = {tid: k for k, tid in enumerate(ids)}
     preds = {k: set() for k in range(len(ids))}
     for k, tid in enumerate(ids):
@@ -273,6 +289,38 @@ def test_dag_contains_every_required_ordering(seed, halo):
         reach[k] = r
     for p, q in P.required_orderings(tasks):
         assert p in reach[q], (p, q)
+
+
+@pytest.mark.parametrize("halo", [None, 1, 3])
+@pytest.mark.parametrize("seed", range(6))
+def test_dag_contains_every_required_ordering(seed, halo):
+    rng = np.random.default_rng(seed)
+    ctx = dry()
+    n = 40
+    arrays = [ctx.array([n], chunk=[int(rng.choice([5, 8, 40]))], halo=None if halo is None else [halo])
+              for _ in range(3)]
+    tasks, ids = _launch_seq(ctx, rng, n, arrays, 6)
+    _closure_contains_required(ctx, tasks, ids)
+    ctx.close()
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_dag_orders_reductions_into_one_target(seed):
+    # histogram launches into one target h, mixed with read-modify-writes of
+    # h and stencil launches: a later fold must follow every earlier fold,
+    # read and write of h (the target is overwritten per launch)
+    rng = np.random.default_rng(100 + seed)
+    ctx = dry()
+    n = 40
+    arrays = [ctx.array([n], chunk=[int(rng.choice([5, 8, 40]))]) for _ in range(3)]
+    h = ctx.array([256], np.int32, chunk=[int(rng.choice([64, 256]))])
+    vals = [ctx.array([n], np.int32, chunk=[int(rng.choice([8, 40]))]) for _ in range(2)]
+    h2 = ctx.array([256], np.int32)
+    # fold, read of h, read-modify-write, fold again; then random launches
+    tasks, ids = _launch_seq(ctx, rng, n, arrays, 12, hist=(h, vals, h2), first=(3, 5, 3, 4, 3))
+    assert any(len(t["accesses"]) and t["accesses"][-1][0] == h.id and t["accesses"][-1][1] == "write"
+               for t in tasks)
+    _closure_contains_required(ctx, tasks, ids)
     ctx.close()
 
 

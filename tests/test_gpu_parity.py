@@ -242,6 +242,43 @@ def test_hist256_bit_exact_and_overwrites_target(L, n, chunk, sb):
     assert np.array_equal(got, oracle.hist256(v))
 
 
+@pytest.mark.parametrize("batched", [False, True])
+@pytest.mark.parametrize("hchunk", [0, 64])
+def test_hist256_reductions_into_one_target_keep_program_order(L, batched, hchunk):
+    # three histogram launches into one h, with a plain read of h (its bins
+    # are the values of a histogram into g) and a read-modify-write of h
+    # between them, all issued without a sync.  Each fold overwrites h, so
+    # only program order gives g = hist(H1) and h = H3.
+    say("hist ordering", batched, hchunk)
+    rng = np.random.default_rng(41)
+    sizes = (1000, 5003, 300_001)
+    vs = [synthetic.zipf_values(n, rng) for n in sizes]
+    with ctx_of(L) as ctx:
+        va = [ctx.array([n], np.int32, chunk=[4096]) for n in sizes]
+        for a, v in zip(va, vs):
+            a.write(v)
+        h = ctx.array([256], np.int32, chunk=[hchunk])
+        g = ctx.array([256], np.int32)
+        h.fill(-1)
+        g.fill(-1)
+        ctx.sync()
+        if batched:
+            ctx.batch_begin()
+        ctx.launch("hist256_i32", [sizes[0]], [1], [512], args=[sizes[0], h, va[0]])
+        ctx.launch("hist256_i32", [256], [1], [64], args=[256, g, h])
+        ctx.launch("hist256_i32", [sizes[1]], [1], [2048], args=[sizes[1], h, va[1]])
+        ctx.launch("touch_i32", [256], [1], [128], args=[256, h])
+        ctx.launch("hist256_i32", [sizes[2]], [1], [65536], args=[sizes[2], h, va[2]])
+        if batched:
+            ctx.batch_end()
+        ctx.sync()
+        got_g, got_h = g.read(), h.read()
+    h1 = oracle.hist256(vs[0])
+    assert h1.max() < 256  # the bins of H1 are valid histogram values
+    assert np.array_equal(got_g, oracle.hist256(h1))
+    assert np.array_equal(got_h, oracle.hist256(vs[2]))
+
+
 # ----------------------------------------------------------------- k-means
 
 @pytest.mark.parametrize("N,d,K,chunk", [(100_003, 16, 64, 1 << 14), (5000, 3, 7, 999), (4096, 32, 256, 0)])
@@ -344,14 +381,32 @@ def test_gemm_one_4096_tile_sampled(L):
     jj = rng.integers(0, N, 2048)
     val, av = oracle.gemm_entries(A, B, ii, jj)
     assert np.all(np.abs(got[ii, jj] - val) <= 1e-5 * av)
-    assert oracle.freivalds(A, B, got) < 1e-5
+    assert oracle.freivalds(A, B, got, panel=256) < 1e-5
+
+
+def test_gemm_whole_4096_tile_elementwise(L):
+    # one 4096^2 superblock with K = 4096: the shape of one out-of-core tile
+    # dispatch, which runs the full block grid (groups of 8 block rows, each
+    # XCD's blocks an 8 x 4 patch); every element against the float64 product
+    M = N = K = 4096
+    say("gemm whole 4096 tile")
+    A, B, got = _gemm_case(L, M, N, K, (4096, 0), (0, 4096), (4096, 4096), (4096, 4096), seed=31)
+    assert not np.isnan(got).any()
+    ref = oracle.gemm(A, B)
+    scale = oracle.gemm(np.abs(A), np.abs(B))
+    err = np.abs(got - ref) / scale
+    say("gemm whole 4096 tile: worst componentwise error %.3g" % err.max())
+    assert err.max() <= 1e-5
 
 
 def test_gemm_config3_out_of_core(L):
     # C = A B, FP32, 65536^2 operands (16 GiB each) in pinned host memory,
     # device budget 16 GiB, 4096^2 superblocks in serpentine order: A is split
-    # in 4096-row panels, B in 4096-column panels, C in 4096^2 tiles.  Checked
-    # by Freivalds at full size and 4096 sampled entries against float64.
+    # in 4096-row panels, B in 4096-column panels, C in 4096^2 tiles.  C
+    # starts as NaN, so a tile that is never written cannot pass.  Checked by
+    # Freivalds at full size per 4096-column panel (each panel its own probe
+    # vector, so the scale is one panel's, not a whole row's) and 4096 sampled
+    # entries against float64.
     n, T = 65536, 4096
     say("gemm config3: allocating 48 GiB pinned host memory")
     with ctx_of(L, device_budget_bytes=16 << 30, stage_threshold_bytes=8 << 30,
@@ -362,6 +417,8 @@ def test_gemm_config3_out_of_core(L):
         say("gemm config3: generating operands")
         synthetic.gemm_operand(0, n, T, out=A, workers=16)
         synthetic.gemm_operand(1, n, T, out=B, workers=16)
+        for r0 in range(0, n, T):
+            Cm[r0:r0 + T].fill(np.nan)
         a = ctx.array_host(A, chunk=[T, 0])
         b = ctx.array_host(B, chunk=[0, T])
         c = ctx.array_host(Cm, chunk=[T, T])
@@ -375,10 +432,14 @@ def test_gemm_config3_out_of_core(L):
         rng = np.random.default_rng(7)
         ii = rng.integers(0, n, 4096)
         jj = rng.integers(0, n, 4096)
+        for r0 in range(0, n, T):
+            assert not np.isnan(Cm[r0:r0 + T]).any(), r0
         val, av = oracle.gemm_entries(A, B, ii, jj)
         assert np.all(np.abs(Cm[ii, jj] - val) <= 1e-5 * av)
-        say("gemm config3: Freivalds")
-        assert oracle.freivalds(A, B, Cm, trials=2) < 1e-5
+        say("gemm config3: Freivalds per 4096-column panel")
+        worst = oracle.freivalds(A, B, Cm, trials=2, panel=T)
+        say("gemm config3: Freivalds worst ratio %.3g" % worst)
+        assert worst < 1e-5
 
 
 def test_gemm_out_of_core_issue_orders(L):

@@ -164,6 +164,63 @@ def test_gemm_entries_and_freivalds_detect_error():
     assert oracle.freivalds(A, B, bad) > 1e-5
 
 
+@pytest.mark.parametrize("bad", [np.nan, np.inf, -np.inf])
+def test_freivalds_fails_on_non_finite_entries(bad):
+    # one non-finite entry anywhere (here in the last row and column) must
+    # fail the check, with or without column panels
+    rng = np.random.default_rng(15)
+    A = rng.standard_normal((64, 48), dtype=np.float32)
+    B = rng.standard_normal((48, 80), dtype=np.float32)
+    C32 = oracle.gemm(A, B).astype(np.float32)
+    assert oracle.freivalds(A, B, C32, panel=16) < 1e-6
+    C32[63, 79] = bad
+    assert oracle.freivalds(A, B, C32) == np.inf
+    assert oracle.freivalds(A, B, C32, panel=16) == np.inf
+
+
+def test_freivalds_matches_a_direct_residual_on_one_panel():
+    # with a single trial and one panel the ratio is exactly
+    # |(C - A B)[:, panel] r| / (|A| |B|)[:, panel] 1 for the drawn signs:
+    # recomputed here from the full float64 product, independent of the
+    # thin products the check uses
+    rng = np.random.default_rng(16)
+    A = rng.standard_normal((40, 30), dtype=np.float32)
+    B = rng.standard_normal((30, 24), dtype=np.float32)
+    E = np.zeros((40, 24), dtype=np.float64)
+    E[7, 13] = 0.5
+    Cm = (oracle.gemm(A, B) + E).astype(np.float32)
+    got = oracle.freivalds(A, B, Cm, trials=1, seed=99, panel=8)
+    r_all = np.random.default_rng(99).choice(np.array([-1.0, 1.0]), (24, 1))[:, 0]
+    resid = np.zeros((40, 3))
+    scale = np.zeros((40, 3))
+    ref = oracle.gemm(A, B)
+    absref = oracle.gemm(np.abs(A), np.abs(B))
+    for c in range(3):
+        sl = slice(8 * c, 8 * c + 8)
+        resid[:, c] = np.abs((Cm.astype(np.float64)[:, sl] - ref[:, sl]) @ r_all[sl])
+        scale[:, c] = absref[:, sl].sum(axis=1)
+    assert got == pytest.approx((resid / scale).max(), rel=1e-6)
+
+
+def test_freivalds_panels_see_a_wrong_block_that_whole_rows_miss():
+    # a 32 x 32 block of C off by 1e-2 of |C| per entry: against the scale of
+    # a whole 2048-column row the residual stays under the 1e-5 threshold;
+    # against one 128-column panel it is far above it
+    rng = np.random.default_rng(17)
+    n = 2048
+    A = rng.standard_normal((n, n), dtype=np.float32)
+    B = rng.standard_normal((n, n), dtype=np.float32)
+    Cm = oracle.gemm(A, B).astype(np.float32)
+    assert oracle.freivalds(A, B, Cm, trials=1, panel=128) < 1e-6
+    blk = Cm[512:544, 1024:1056]
+    blk += np.float32(1e-2) * np.abs(blk) + np.float32(0.1)
+    whole = oracle.freivalds(A, B, Cm, trials=2)
+    panels = oracle.freivalds(A, B, Cm, trials=2, panel=128)
+    assert panels > 1e-5
+    assert whole < 1e-5
+    assert panels > 8 * whole
+
+
 # ----------------------------------------------------------------- histogram
 
 def test_hist_counts_sum_and_bincount():

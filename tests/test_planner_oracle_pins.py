@@ -125,8 +125,12 @@ def test_conflict_table():
     assert P.conflicting("write", None, "read", None)
     assert P.conflicting("write", None, "write", None)
     assert P.conflicting("readwrite", None, "read", None)
-    assert not P.conflicting("reduce", "+", "reduce", "+")
-    assert P.conflicting("reduce", "+", "reduce", "max")
+    # same-operator reductions commute inside one launch only: a later
+    # launch's fold overwrites the target
+    assert not P.conflicting("reduce", "+", "reduce", "+", same_launch=True)
+    assert P.conflicting("reduce", "+", "reduce", "+")
+    assert P.conflicting("reduce", "+", "reduce", "+", same_launch=False)
+    assert P.conflicting("reduce", "+", "reduce", "max", same_launch=True)
     assert P.conflicting("reduce", "+", "read", None)
 
 
@@ -144,3 +148,36 @@ def test_required_orderings_stencil_pingpong():
             tasks.append({"accesses": [(src, "read", None, rx), (dst, "write", None, ry)]})
     req = P.required_orderings(tasks)
     assert set(req) == {(0, 2), (1, 2), (0, 3), (1, 3)}
+
+
+def test_required_orderings_two_reductions_into_one_target():
+    # two histogram launches into one h (two superblocks each), with a read
+    # of h between them: under the overwrite reading the second launch's fold
+    # must follow the first one's and the read, and the read must follow the
+    # first fold; superblocks of one launch stay unordered
+    n = 8
+    t = "global i => read v[i], reduce(+) h[:]"
+    shape_h = [256]
+    tasks = []
+    for L, src in ((1, "v1"), (3, "v2")):
+        sbs = []
+        for lo, hi in P.superblocks([n], [1], [4]):
+            rv = P.region(t, "v", [n], lo, hi, [1])
+            rh = P.region(t, "h", shape_h, lo, hi, [1])
+            sbs.append([(src, "read", None, rv), ("h", "reduce", "+", rh)])
+        tasks += P.launch_tasks(L, sbs)
+        if L == 1:
+            tasks.append({"launch": 2, "accesses": [("h", "read", None, ((0, 255),))]})
+    # tasks: 0, 1 = launch 1 superblocks; 2 = its fold; 3 = the read;
+    # 4, 5 = launch 3 superblocks; 6 = its fold
+    req = set(P.required_orderings(tasks))
+    assert {(0, 2), (1, 2), (2, 3), (2, 6), (3, 6), (4, 6), (5, 6)} <= req
+    assert (0, 1) not in req and (4, 5) not in req
+    # the superblocks of launch 3 write private partials: nothing orders them
+    # after launch 1 or the read
+    assert not any(q in (4, 5) for _, q in req)
+    # flat (unexpanded) superblock accesses from different launches conflict
+    flat = [{"launch": 1, "accesses": [("h", "reduce", "+", ((0, 255),))]},
+            {"launch": 2, "accesses": [("h", "reduce", "+", ((0, 255),))]},
+            {"launch": 2, "accesses": [("h", "reduce", "+", ((0, 255),))]}]
+    assert set(P.required_orderings(flat)) == {(0, 1), (0, 2)}
