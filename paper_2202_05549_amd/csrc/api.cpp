@@ -427,10 +427,12 @@ lt_status array_fill(Ctx *ctx, Array *arr, const void *scalar) {
 }
 
 lt_status array_destroy(Ctx *ctx, Array *arr) {
-    for (Chunk *c : arr->chunks)
-        if (c->pin > 0) return set_err(ctx, LT_ERR_INVALID, "array is in use by a graph");
+    // an open batch is issued first (its queued tasks pin their chunks); a
+    // graph, or one being recorded, keeps its pins
     lt_status st = flush_all(ctx);
     if (st) return st;
+    for (Chunk *c : arr->chunks)
+        if (c->pin > 0) return set_err(ctx, LT_ERR_INVALID, "array is in use by a graph");
     arr->dead = true;
     for (Chunk *c : arr->chunks) {
         if (c->dev_off >= 0) {
@@ -757,7 +759,9 @@ lt_status lt_graph_end(lt_context *ctx, lt_graph **out) {
     *out = nullptr;
     lt_status st = graph_end(ctx, out);
     if (st) {
-        ctx->batch = Batch();
+        batch_drop(ctx);
+        ctx->batch.open = false;
+        ctx->batch.capture = false;
     }
     return st;
 }

@@ -597,7 +597,11 @@ static lt_status batch_add_exec(Ctx *ctx, const KernelDef *def, TaskPlan &tp, Ta
         d.flags |= DF_ATOMIC;  // its partial is built with device-scope atomics
     }
     batch_push(ctx, d, tp.id);
-    B.uses.insert(B.uses.end(), uses.begin(), uses.end());
+    for (const ChunkUse &u : uses) {
+        u.c->pin++;
+        B.uses.push_back(u);
+        if (u.write) B.written.insert(u.c);
+    }
     if (B.launches.empty() || B.launches.back() != rec.launch) B.launches.push_back(rec.launch);
     ctx->tasks.at(tp.id) = std::move(rec);
     return LT_OK;
@@ -649,7 +653,9 @@ static lt_status batch_add_combine(Ctx *ctx, Partials &P, Array *arr, uint64_t L
     for (Chunk *c : ch) {
         record_access(c, M_WRITE, R_ADD, rec.id);
         c->lru = ++ctx->lru_clock;
+        c->pin++;
         B.uses.push_back({c, true});
+        B.written.insert(c);
     }
     rec.regions.push_back(lt_region_info{P.param, (int)M_REDUCE, (int)P.op, 0, arr->id,
                                          {U.lo[0], U.lo[1], U.lo[2]}, {U.hi[0], U.hi[1], U.hi[2]}});
@@ -683,6 +689,32 @@ static void *staging_get(Ctx *ctx, uint64_t bytes, lt_status *st) {
     ctx->staging_used.push_back(p);
     ctx->staging_size_used.push_back(sz);
     return p;
+}
+
+// Reads of halo replicas while a batch is open.  Versions move only when a
+// batch is issued, so a replica whose owner a queued task writes still looks
+// current: it can be refreshed only after the batch has run, so the batch is
+// issued first (*flush).  A graph cannot refresh replicas between or inside
+// its replays, so a graph that reads replicas is refused.
+static lt_status batch_halo_reads(Ctx *ctx, std::vector<TaskPlan> &plans, Array **arrs, int nparam,
+                                  bool *flush) {
+    Batch &B = ctx->batch;
+    *flush = false;
+    for (auto &tp : plans)
+        for (int p = 0; p < nparam; ++p) {
+            ArgPlan &a = tp.arg[p];
+            if (!a.used || a.mode == M_WRITE || a.mode == M_REDUCE || !arrs[p]->has_halo) continue;
+            const int nd = arrs[p]->ndim;
+            for (Chunk *c : a.chunks)
+                for (const HaloSrc &h : c->halo) {
+                    if (intersect(h.box, a.region, nd).empty(nd)) continue;
+                    if (B.capture)
+                        return set_err(ctx, LT_ERR_UNSUPPORTED,
+                                       "a graph cannot read halo replicas: a replay could not refresh them");
+                    if (B.written.count(h.k)) *flush = true;
+                }
+        }
+    return LT_OK;
 }
 
 // Halo replicas that the reads of a launch will use, refreshed up front from
@@ -805,11 +837,40 @@ static lt_status refresh_launch_halos(Ctx *ctx, std::vector<TaskPlan> &plans, Ar
     return LT_OK;
 }
 
+void batch_drop(Ctx *ctx) {
+    Batch &B = ctx->batch;
+    for (const ChunkUse &u : B.uses) u.c->pin--;
+    const bool open = B.open;
+    B = Batch();
+    B.open = open;
+}
+
+static lt_status batch_issue(Ctx *ctx);
+
 lt_status batch_flush(Ctx *ctx) {
     Batch &B = ctx->batch;
     if (B.q.empty() || B.capture) return LT_OK;
     lt_status st = flush_group(ctx);
     if (st) return st;
+    st = batch_issue(ctx);
+    if (st) {
+        // the queued tasks are in the DAG but will never run: every later
+        // result could be wrong, so the failure is sticky until lt_sync
+        if (ctx->sticky == LT_OK) {
+            ctx->sticky = st;
+            ctx->sticky_msg = "a batch could not be issued: " + ctx->err;
+        }
+        batch_drop(ctx);
+    }
+    return st;
+}
+
+// Uploads the queue of the open batch and issues its drain.  The queue,
+// counters and partials take one arena range; the batch's chunks are pinned,
+// so making room for it never evicts them (LT_ERR_BUDGET when it cannot fit).
+static lt_status batch_issue(Ctx *ctx) {
+    Batch &B = ctx->batch;
+    lt_status st;
     const int ntasks = (int)B.q.size();
     const int nctr = ntasks + B.nsignals + 2;
     const int64_t qbytes = (int64_t)ntasks * (int64_t)sizeof(DTask);
@@ -830,7 +891,10 @@ lt_status batch_flush(Ctx *ctx) {
             if (d.dep_ctr[i] <= -2) d.dep_ctr[i] = ntasks + (-2 - d.dep_ctr[i]);
     }
     void *stage = staging_get(ctx, (uint64_t)qbytes, &st);
-    if (!stage) return st;
+    if (!stage) {
+        ctx->arena.release(off, mem);
+        return st;
+    }
     memcpy(stage, B.q.data(), (size_t)qbytes);
     const int s = 0;
     B.wait.merge(mem);
@@ -887,9 +951,7 @@ lt_status batch_flush(Ctx *ctx) {
     done.add(s, p);
     ctx->arena.release(off, done);
     for (uint64_t L : B.launches) ctx->launches.at(L).done.add(s, p);  // they complete with the drain
-    bool open = B.open;
-    B = Batch();
-    B.open = open;
+    batch_drop(ctx);
     return LT_OK;
 }
 
@@ -919,20 +981,42 @@ lt_status graph_end(Ctx *ctx, lt_graph **out) {
         for (int i = 0; i < d.ndeps; ++i)
             if (d.dep_ctr[i] <= -2) d.dep_ctr[i] = ntasks + (-2 - d.dep_ctr[i]);
     }
+    // on failure below, the arena range and host buffers go back
+    auto undo = [&]() {
+        ctx->arena.release(g->off, mem);
+        if (g->exec) (void)hipGraphExecDestroy(g->exec);
+        if (g->graph) (void)hipGraphDestroy(g->graph);
+        if (g->staging) (void)hipHostFree(g->staging);
+        if (g->status) (void)hipHostFree(g->status);
+    };
     hipError_t r = hipHostMalloc(&g->staging, (size_t)qbytes, hipHostMallocDefault);
-    if (r != hipSuccess) return hip_fail(ctx, r, "graph staging");
+    if (r != hipSuccess) {
+        g->staging = nullptr;
+        undo();
+        return hip_fail(ctx, r, "graph staging");
+    }
     r = hipHostMalloc((void **)&g->status, 4, hipHostMallocDefault);
-    if (r != hipSuccess) return hip_fail(ctx, r, "graph status");
+    if (r != hipSuccess) {
+        g->status = nullptr;
+        undo();
+        return hip_fail(ctx, r, "graph status");
+    }
     *g->status = 0;
     memcpy(g->staging, B.q.data(), (size_t)qbytes);
     const int s = 0;
     g->stream = s;
     st = stream_wait(ctx, s, mem);
-    if (st) return st;
+    if (st) {
+        undo();
+        return st;
+    }
     hipStream_t h = ctx->streams[s].h;
     int nwg = ctx->cfg.drain_workgroups > 0 ? ctx->cfg.drain_workgroups : 1024;
     r = hipStreamBeginCapture(h, hipStreamCaptureModeThreadLocal);
-    if (r != hipSuccess) return hip_fail(ctx, r, "hipStreamBeginCapture");
+    if (r != hipSuccess) {
+        undo();
+        return hip_fail(ctx, r, "hipStreamBeginCapture");
+    }
     hipError_t r1 = hipMemcpyAsync(base, g->staging, (size_t)qbytes, hipMemcpyHostToDevice, h);
     uint32_t zero = 0;
     hipError_t r2 = launch_fill(h, base + qalloc, (calloc_ + B.part_bytes) / 4, 4, &zero);
@@ -942,11 +1026,17 @@ lt_status graph_end(Ctx *ctx, lt_graph **out) {
     hipError_t r4 = hipMemcpyAsync(g->status, base + qalloc + (int64_t)(ntasks + B.nsignals + 1) * 4, 4,
                                    hipMemcpyDeviceToHost, h);
     r = hipStreamEndCapture(h, &g->graph);
-    if (r1 != hipSuccess || r2 != hipSuccess || r3 != hipSuccess || r4 != hipSuccess || r != hipSuccess)
+    if (r1 != hipSuccess || r2 != hipSuccess || r3 != hipSuccess || r4 != hipSuccess || r != hipSuccess) {
+        undo();
         return hip_fail(ctx, r != hipSuccess ? r : (r1 != hipSuccess ? r1 : (r2 != hipSuccess ? r2 : (r3 != hipSuccess ? r3 : r4))),
                         "graph capture");
+    }
     r = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
-    if (r != hipSuccess) return hip_fail(ctx, r, "hipGraphInstantiate");
+    if (r != hipSuccess) {
+        g->exec = nullptr;
+        undo();
+        return hip_fail(ctx, r, "hipGraphInstantiate");
+    }
     // chunks the graph touches stay where they are while it lives; the
     // capture recorded no work, so their histories go back to empty
     for (const ChunkUse &u : B.uses) {
@@ -967,7 +1057,8 @@ lt_status graph_end(Ctx *ctx, lt_graph **out) {
     }
     g->ntasks = ntasks;
     ctx->graph_status.push_back(g->status);
-    B = Batch();
+    batch_drop(ctx);  // the graph holds its own pins
+    ctx->batch.open = false;
     *out = g.release();
     return LT_OK;
 }
@@ -1600,7 +1691,17 @@ lt_status launch(Ctx *ctx, lt_kernel *k, int nd, const int64_t *grid,
         }
         plans.push_back(std::move(tp));
     }
-    lt_status st = ensure_arena(ctx);
+    lt_status st;
+    if (ctx->batch.open) {
+        bool flush = false;
+        st = batch_halo_reads(ctx, plans, arrs, def->nparam, &flush);
+        if (st) return st;
+        if (flush) {
+            st = batch_flush(ctx);
+            if (st) return st;
+        }
+    }
+    st = ensure_arena(ctx);
     if (st) return st;
     // partial blocks for reduce arguments
     std::vector<Partials> parts;

@@ -15,6 +15,7 @@
 #include <memory>
 #include <string>
 #include <unordered_map>
+#include <unordered_set>
 #include <vector>
 
 #include "lt.h"
@@ -372,7 +373,12 @@ struct Batch {
     int nsignals = 0;
     int64_t tiles = 0;
     uint32_t kinds = 0;                // bit k set: a task of body DK k is queued
+    // every chunk a queued task touches, one entry per use; each entry holds
+    // a pin on its chunk until the batch is issued or dropped, so that no
+    // allocation made meanwhile (the batch's own queue area, halo tables)
+    // evicts memory that a queued task addresses directly
     std::vector<ChunkUse> uses;
+    std::unordered_set<Chunk *> written;  // chunks a queued task writes
     Fence wait;                        // dependencies issued before the batch
 };
 
@@ -490,6 +496,9 @@ lt_status launch(Ctx *ctx, lt_kernel *k, int nd, const int64_t *grid,
 lt_status sync_all(Ctx *ctx);
 lt_status flush_group(Ctx *ctx);
 lt_status batch_flush(Ctx *ctx);
+// Releases the pins of the queued tasks and empties the batch (it stays
+// open if it was).
+void batch_drop(Ctx *ctx);
 lt_status graph_end(Ctx *ctx, lt_graph **out);
 lt_status graph_launch(Ctx *ctx, lt_graph *g);
 lt_status graph_destroy(Ctx *ctx, lt_graph *g);

@@ -697,3 +697,90 @@ def test_pinned_pool_recycles_spill_buffers_within_the_host_budget():
     ctx.close()
     assert peak <= hb and s["host_spill_bytes"] <= hb
     assert s["bytes_disk_write"] > 0 and s["bytes_disk_read"] > 0
+
+
+@pytest.mark.parametrize("chunk,halo", [([64, 0], [1, 0]), ([64, 128], [1, 1])])
+def test_batched_halo_pingpong_refreshes_like_the_plain_path(chunk, halo):
+    # a sweep reads replicas whose owners the previous sweep, queued in the
+    # same open batch, writes: the batch is issued first, so every replica is
+    # refreshed exactly as on the plain path
+    n, m = 256, 512
+
+    def run(batched):
+        ctx = dry()
+        a = ctx.array([n, m], chunk=chunk, halo=halo)
+        b = ctx.array([n, m], chunk=chunk, halo=halo)
+        a.fill(1.0)
+        b.fill(0.0)
+        ctx.sync()
+        ctx.reset_stats()
+        if batched:
+            ctx.batch_begin()
+        inp, out = a, b
+        for _ in range(4):
+            ctx.launch("jacobi2d_f32", [n, m], [1, 64], chunk[:1] + [chunk[1] or m], args=[n, m, out, inp])
+            inp, out = out, inp
+        if batched:
+            ctx.batch_end()
+        ctx.sync()
+        s = ctx.stats()
+        ctx.close()
+        return s
+
+    plain, batched = run(False), run(True)
+    assert plain["halo_copies"] > 0
+    if chunk[1] == 0:
+        assert plain["halo_copies"] == 18  # 3 sweeps x 6 row pieces of 4 slabs
+    assert batched["halo_copies"] == plain["halo_copies"]
+    assert batched["assembled_regions"] == 0
+
+
+def test_graph_refuses_halo_replica_reads():
+    ctx = dry()
+    a = ctx.array([256, 512], chunk=[64, 0], halo=[1, 0])
+    b = ctx.array([256, 512], chunk=[64, 0], halo=[1, 0])
+    a.fill(1.0)
+    ctx.graph_begin()
+    with pytest.raises(L.LtError, match="halo replicas") as e:
+        ctx.launch("jacobi2d_f32", [256, 512], [1, 64], [64, 512], args=[256, 512, b, a])
+    assert e.value.status == L.LT_ERR_UNSUPPORTED
+    ctx.close()
+
+
+def test_batch_queue_never_evicts_a_queued_chunk():
+    # four resident 4 MiB arrays fill the budget exactly; a batch of two
+    # stencil launches over them needs room for its queue.  The chunks the
+    # queued tasks address are pinned, so nothing is evicted and the batch
+    # fails cleanly with LT_ERR_BUDGET (reported again, sticky, at lt_sync).
+    n = 1 << 20
+    ctx = dry(device_budget_bytes=4 * n * 4)
+    xs = [ctx.array([n], chunk=[1 << 18]) for _ in range(4)]
+    for x in xs:
+        x.fill(0.5)
+    ctx.sync()
+    ctx.reset_stats()
+    ctx.batch_begin()
+    ctx.launch("stencil1d_f32", [n], [256], [1 << 18], args=[n, xs[1], xs[0]])
+    ctx.launch("stencil1d_f32", [n], [256], [1 << 18], args=[n, xs[3], xs[2]])
+    with pytest.raises(L.LtError) as e:
+        ctx.batch_end()
+    assert e.value.status == L.LT_ERR_BUDGET
+    s = ctx.stats()
+    assert s["evictions_dirty"] == 0 and s["evictions_clean"] == 0
+    with pytest.raises(L.LtError) as e:
+        ctx.sync()
+    assert e.value.status == L.LT_ERR_BUDGET
+    # with one spare megabyte the same batch is issued
+    ctx.close()
+    ctx = dry(device_budget_bytes=4 * n * 4 + (1 << 20))
+    xs = [ctx.array([n], chunk=[1 << 18]) for _ in range(4)]
+    for x in xs:
+        x.fill(0.5)
+    ctx.batch_begin()
+    ctx.launch("stencil1d_f32", [n], [256], [1 << 18], args=[n, xs[1], xs[0]])
+    ctx.launch("stencil1d_f32", [n], [256], [1 << 18], args=[n, xs[3], xs[2]])
+    ctx.batch_end()
+    ctx.sync()
+    s = ctx.stats()
+    assert s["evictions_dirty"] == 0 and s["evictions_clean"] == 0
+    ctx.close()

@@ -191,3 +191,94 @@ def test_graph_replays_with_eager_work_between(L):
         assert np.all(z.read() == 4)
         ctx.graph_destroy(g)
         ctx.sync()
+
+
+def test_batch_near_the_budget_matches_oracle(L):
+    # the arrays take the whole budget but 1 MiB: the batch's queue area fits
+    # beside them, and no chunk a queued task addresses may be evicted for it
+    n = 1 << 20
+    say("batch near budget")
+    x0 = [synthetic.stencil1d_input(n, 60 + i) for i in range(2)]
+    with L.Context(device_budget_bytes=4 * n * 4 + (1 << 20)) as ctx:
+        xs = [ctx.array([n], chunk=[1 << 18]) for _ in range(4)]
+        xs[0].write(x0[0])
+        xs[2].write(x0[1])
+        ctx.sync()
+        ctx.batch_begin()
+        ctx.launch("stencil1d_f32", [n], [256], [1 << 18], args=[n, xs[1], xs[0]])
+        ctx.launch("stencil1d_f32", [n], [256], [1 << 18], args=[n, xs[3], xs[2]])
+        ctx.launch("stencil1d_f32", [n], [256], [1 << 18], args=[n, xs[0], xs[1]])
+        ctx.batch_end()
+        ctx.sync()
+        s = ctx.stats()
+        assert s["evictions_dirty"] == 0 and s["evictions_clean"] == 0
+        got0, got3 = xs[0].read(), xs[3].read()
+    assert np.array_equal(got0, oracle.stencil1d_iter(x0[0], 2))
+    assert np.array_equal(got3, oracle.stencil1d(x0[1]))
+
+
+def _c4_subset(count=8192, take=112, big=8, seed=3):
+    """Launch indices of the 8192-launch batching mix (sizes 2^10..2^24):
+    ``big`` launches above 2^22 elements and ``take`` others, drawn with a
+    fixed seed, in program order."""
+    plan = synthetic.batch_plan(count, seed=seed)
+    pick = np.random.default_rng(77)
+    large = [i for i, (_, n) in enumerate(plan) if n > (1 << 22)]
+    rest = [i for i, (_, n) in enumerate(plan) if n <= (1 << 22)]
+    idx = sorted(set(pick.choice(large, big, replace=False).tolist()) |
+                 set(pick.choice(rest, take, replace=False).tolist()))
+    return [(i, plan[i][0], plan[i][1]) for i in idx]
+
+
+@pytest.mark.parametrize("sb", [1 << 24, 1 << 22])
+def test_c4_mix_at_benchmark_superblocks_batched_and_replayed(L, sb):
+    # launches of the 8192-launch mix at the superblocks the benchmark runs
+    # (2^24: one task per launch, up to 256 drain tiles of 65536 elements, so
+    # a histogram task flushes many tiles into one partial; 2^22: several
+    # tasks and partials per launch), inputs from the seeded recipe.  Every
+    # launch matches the oracle batched, and on each of two graph replays.
+    sub = _c4_subset()
+    assert sum(1 for _, _, n in sub if n > (1 << 22)) >= 8
+    say("c4 subset", len(sub), "launches, sb", sb, "elements", sum(n for _, _, n in sub))
+    data = [synthetic.batch_data(k, n, i, seed=3) for i, k, n in sub]
+    refs = [oracle.stencil1d(v) if k == 0 else oracle.hist256(v) for (_, k, _), v in zip(sub, data)]
+    with L.Context(device_budget_bytes=8 << 30) as ctx:
+        arrs = []
+        for (_, k, n), v in zip(sub, data):
+            if k == 0:
+                x = ctx.array([n], chunk=[sb])
+                y = ctx.array([n], chunk=[sb])
+            else:
+                x = ctx.array([n], np.int32, chunk=[sb])
+                y = ctx.array([256], np.int32)
+            x.write(v)
+            arrs.append((y, x))
+        names = ["stencil1d_f32" if k == 0 else "hist256_i32" for _, k, _ in sub]
+        args = L.Context.arg_table(len(sub), [[n for _, _, n in sub], [a[0] for a in arrs], [a[1] for a in arrs]])
+        grids = np.array([[n] for _, _, n in sub], dtype=np.int64)
+
+        def clear():
+            for (_, k, _), (y, _) in zip(sub, arrs):
+                y.fill(np.float32(np.nan) if k == 0 else np.int32(-5))
+            ctx.sync()
+
+        def check(tag):
+            for (i, k, n), (y, _), ref in zip(sub, arrs, refs):
+                assert np.array_equal(y.read(), ref), (tag, i, k, n)
+
+        clear()
+        ctx.batch_begin()
+        ctx.launch_many(names, grids, [256], [sb], args)
+        ctx.batch_end()
+        ctx.sync()
+        check("batched")
+        ctx.graph_begin()
+        ctx.launch_many(names, grids, [256], [sb], args)
+        g = ctx.graph_end()
+        for rep in range(2):
+            clear()
+            ctx.graph_launch(g)
+            ctx.sync()
+            check("replay %d" % rep)
+        ctx.graph_destroy(g)
+        ctx.sync()
