@@ -57,6 +57,19 @@ def pct(times, q):
     return float(np.percentile(np.asarray(times) * 1e3, q))
 
 
+def cpu_model():
+    """Model name of this host's CPU (from /proc/cpuinfo), for the CPU
+    baselines."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for ln in f:
+                if ln.startswith("model name"):
+                    return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def base_line(workload_cfg, steps, warmup):
     return {"metric": METRIC, "n_gpus": 1, "steps": steps, "warmup": warmup, "higher_is_better": True,
             "scaling": "weak", "vs_baseline": None, "data": "synthetic", "config": workload_cfg}
@@ -194,9 +207,11 @@ def jacobi_run(L, torch, x0, executor, steps, warmup, rows=None):
 
         for _ in range(warmup):
             step()
-        # HIP events on every 10th dispatch (grouped: one per sweep) during the
-        # timed steps; plain: per-task events would slow its host path
-        ctx.profile(executor != "plain", every=10 if executor == "grouped" else 1)
+        # HIP events around every dispatch during the timed steps (grouped:
+        # one per sweep), so the summed kernel time can never exceed the
+        # wall; plain: per-task events would slow its host path, so its
+        # kernel time comes from a separate profiled step
+        ctx.profile(executor != "plain", every=1)
         ctx.profile_reset()
         ctx.reset_stats()
         torch.cuda.synchronize()
@@ -242,7 +257,7 @@ def jacobi_cpu_baseline(x0, budget_s=24.0):
     oracle.jacobi2d(a, sweeps, inplace=True)
     dt = time.perf_counter() - t0
     return {"value": round(sweeps * N * N * 8 / dt / 1e9, 3), "unit": "GB/s", "cores": oracle.num_threads(),
-            "kind": "oracle",
+            "cpu_model": cpu_model(), "kind": "oracle",
             "sample": "%d sweeps of the 16384x16384 float32 field (%d per step), %.2f s" % (sweeps, SWEEPS, dt)}
 
 
@@ -369,8 +384,8 @@ def bench_gemm_ooc(args, L, torch):
     import synthetic
 
     n, T = 65536, 4096
-    steps = args.steps if args.steps_given else 1
-    warmup = args.warmup if args.warmup_given else 0
+    steps = args.steps if args.steps_given else 3
+    warmup = args.warmup if args.warmup_given else 1
     streams = args.compute_streams or 1
     band = args.sb_band
     if band > 0:
@@ -409,6 +424,9 @@ def bench_gemm_ooc(args, L, torch):
         total = sum(times)
         prof = ctx.profile_get()["gemm_f32"]
         st = ctx.stats()
+        cpu = None
+        if not args.no_cpu:
+            cpu = gemm_cpu_baseline(A, B, n)
     finally:
         ctx.close()
     flops = 2.0 * n ** 3
@@ -432,7 +450,25 @@ def bench_gemm_ooc(args, L, torch):
                  "roofline": {"bound": "mfma", "achieved": round(kernel_tflops, 2), "peak": MFMA_FP32_PEAK,
                               "unit": "TFLOP/s", "frac": round(kernel_tflops / MFMA_FP32_PEAK, 4), "traffic": traffic_for("k_gemm"),
                               "kernel": "k_gemm", "kernel_avg_ms": round(prof["total_ms"] / prof["dispatches"], 3)}})
+    if cpu:
+        line["cpu_baseline"] = cpu
     return line
+
+
+def gemm_cpu_baseline(A, B, n, rows=64):
+    """The oracle's float64-accumulated product timed on the first ``rows``
+    rows of C (a panel of A times all of B), extrapolated to the whole
+    product by FLOP count."""
+    import oracle
+
+    t0 = time.perf_counter()
+    oracle.gemm(A[:rows], B)
+    dt = time.perf_counter() - t0
+    rate = 2.0 * rows * n * n / dt
+    return {"value": round(rate / 1e12, 4), "unit": "TFLOP/s", "cores": oracle.num_threads(),
+            "cpu_model": cpu_model(), "kind": "oracle",
+            "sample": "%d rows of C (A panel %d x %d times B %d x %d), %.2f s; extrapolated to the whole "
+                      "65536^3 product: %.0f s" % (rows, rows, n, n, n, dt, 2.0 * n ** 3 / rate)}
 
 
 # ==================================================================== batch
@@ -449,27 +485,39 @@ def bench_batch(args, L, torch):
     budget = int(algo_bytes * 1.05) + (8 << 30)
     arena = torch_arena(torch, budget)
     ctx = L.Context(device_budget_bytes=budget, device_arena=arena.data_ptr(), arena_bytes=budget)
-    g = torch.Generator(device="cuda:0")
-    g.manual_seed(3)
-    cdf = torch.tensor(synthetic.zipf_cdf(), dtype=torch.float64, device="cuda:0")
-    log("creating %d arrays (%.1f GB of inputs and outputs), inputs drawn on the GPU" % (len(plan), algo_bytes / 1e9))
+    log("creating %d arrays (%.1f GB of inputs and outputs), inputs from the seeded recipe" %
+        (len(plan), algo_bytes / 1e9))
+    from concurrent.futures import ThreadPoolExecutor
+
+    # launch l's input is synthetic.batch_data(kind, n, l, seed 3), as in the
+    # tests; drawn by a pool of threads, written in launch order
     arrs = []
-    for k, n in plan:
-        if k == 0:
-            x = ctx.array([n])
-            y = ctx.array([n])
-            t = torch.rand(n, generator=g, device="cuda:0", dtype=torch.float32) * 2 - 1
-        else:
-            x = ctx.array([n], np.int32)
-            y = ctx.array([256], np.int32)
-            u = torch.rand(n, generator=g, device="cuda:0", dtype=torch.float64)
-            t = torch.clamp(torch.searchsorted(cdf, u, right=True), max=255).to(torch.int32)
-        x.write_device(t.data_ptr())
-        arrs.append((y, x))
-    del t
+    with ThreadPoolExecutor(16) as ex:
+        futs = [ex.submit(synthetic.batch_data, k, n, l, 3) for l, (k, n) in enumerate(plan[:64])]
+        for l, (k, n) in enumerate(plan):
+            v = futs[l].result()
+            futs[l] = None
+            if l + 64 < len(plan):
+                kk, nn = plan[l + 64]
+                futs.append(ex.submit(synthetic.batch_data, kk, nn, l + 64, 3))
+            if k == 0:
+                x = ctx.array([n])
+                y = ctx.array([n])
+            else:
+                x = ctx.array([n], np.int32)
+                y = ctx.array([256], np.int32)
+            x.write(v)
+            arrs.append((y, x))
     torch.cuda.synchronize()
     grids = ns[:, None]
     res = {}
+    # outputs of a fixed sample of launches (the largest, the smallest and a
+    # seeded draw) after each executor: every executor must give the plain
+    # path's results bit for bit
+    order = np.argsort(ns)
+    sample = sorted(set(np.random.default_rng(17).choice(len(plan), 48, replace=False).tolist())
+                    | set(order[-6:].tolist()) | set(order[:2].tolist()))
+    sample_out = {}
 
     def run(mode, sb, wg=1024, flush=0, steps=None, times=None, graph=None, vec=0):
         ctx.configure(drain_workgroups=wg, batch_flush_tasks=flush, drain_vectors=vec)
@@ -522,6 +570,13 @@ def bench_batch(args, L, torch):
         ctx.profile(False)
         if graph is not None:
             ctx.graph_destroy(graph)
+        outs = [arrs[i][0].read() for i in sample]
+        if mode == "plain":
+            sample_out["plain"] = outs
+        else:
+            same = all(np.array_equal(a, b) for a, b in zip(outs, sample_out["plain"]))
+            sample_out[mode] = same
+            log("%s: %d sampled launches identical to plain: %s" % (mode, len(sample), same))
         wall = float(np.mean(times))
         r = {"gbs": algo_bytes / wall / 1e9, "ms_per_step": wall * 1e3, "p50_ms": pct(times, 50),
              "p99_ms": pct(times, 99), "dispatches_per_step": stats["dispatches"] / args.steps,
@@ -556,10 +611,38 @@ def bench_batch(args, L, torch):
                  "batched": {k: round(v, 3) for k, v in res["batched"].items()},
                  "graph": {k: round(v, 3) for k, v in res["graph"].items()},
                  "batched_over_plain": round(res["batched"]["gbs"] / res["plain"]["gbs"], 3),
-                 "graph_over_plain": round(res["graph"]["gbs"] / res["plain"]["gbs"], 3)})
+                 "graph_over_plain": round(res["graph"]["gbs"] / res["plain"]["gbs"], 3),
+                 "sample_check": {"launches": len(sample),
+                                  "elements": int(ns[sample].sum()),
+                                  "batched_equals_plain": sample_out["batched"],
+                                  "graph_equals_plain": sample_out["graph"]}})
+    if not args.no_cpu:
+        line["cpu_baseline"] = batch_cpu_baseline(plan, sample)
     ctx.close()
     del arena
     return line
+
+
+def batch_cpu_baseline(plan, sample, budget_s=12.0):
+    """The oracle's stencil and histogram over the inputs of a sample of the
+    mix's launches (the same seeded recipe), repeated to about budget_s of
+    CPU work; GB/s of algorithmic bytes."""
+    import oracle
+    import synthetic
+
+    data = [(plan[i][0], synthetic.batch_data(plan[i][0], plan[i][1], i, 3)) for i in sample]
+    nbytes = sum(v.size * (8 if k == 0 else 4) + (0 if k == 0 else 1024) for k, v in data)
+    reps, dt = 0, 0.0
+    t0 = time.perf_counter()
+    while dt < budget_s and reps < 100:
+        for k, v in data:
+            oracle.stencil1d(v) if k == 0 else oracle.hist256(v)
+        reps += 1
+        dt = time.perf_counter() - t0
+    return {"value": round(reps * nbytes / dt / 1e9, 3), "unit": "GB/s", "cores": oracle.num_threads(),
+            "cpu_model": cpu_model(), "kind": "oracle",
+            "sample": "%d launches of the mix (%d elements) x %d repetitions, %.2f s" %
+                      (len(data), sum(v.size for _, v in data), reps, dt)}
 
 
 # ==================================================================== serve
@@ -767,8 +850,113 @@ def bench_kmeans(args, L, torch):
         oracle.kmeans_lloyd(Xs, c0, 1)
         dt = time.perf_counter() - t0
         line["cpu_baseline"] = {"value": round(ns * 2 * (d * 4 + 4) / dt / 1e9, 3), "unit": "GB/s",
-                                "cores": oracle.num_threads(), "kind": "oracle",
+                                "cores": oracle.num_threads(), "cpu_model": cpu_model(), "kind": "oracle",
                                 "sample": "one round of %d points (of %d x 5 per step), %.2f s" % (ns, N, dt)}
+    return line
+
+
+def link_peak(torch, nbytes=1 << 30, reps=5):
+    """Pinned host <-> device copy rates (GB/s) of 1 GiB copies through the
+    copy engines (torch's copy_, i.e. hipMemcpyAsync), measured here: the
+    host-link roofline of the out-of-core legs."""
+    h = torch.empty(nbytes, dtype=torch.uint8, pin_memory=True)
+    d = torch.empty(nbytes, dtype=torch.uint8, device="cuda:0")
+    out = {}
+    for name, dst, src in (("h2d", d, h), ("d2h", h, d)):
+        dst.copy_(src, non_blocking=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            dst.copy_(src, non_blocking=True)
+        torch.cuda.synchronize()
+        out[name] = reps * nbytes / (time.perf_counter() - t0) / 1e9
+    del h, d
+    return out
+
+
+def bench_kmeans_ooc(args, L, torch):
+    """Out-of-core k-means assignment (the paper's single-GPU K-Means study,
+    Sec. 4.3): 10^9 points of d = 16 (64 GB) and their labels in pinned host
+    memory, device budget 64 GiB, K = 64.  A step is one assignment pass from
+    a cold device (the arrays are created over the host buffers before the
+    step and destroyed after it): every chunk of points crosses the host
+    link once, every chunk of labels comes back.  Chunk sizes are swept as in
+    the paper (64 MiB to 4 GiB of points per chunk); the best one is
+    ``value``.  Bound: the host link."""
+    import synthetic
+
+    N, d, K = args.kmeans_points, 16, 64
+    budget = 64 << 30
+    steps = args.steps if args.steps_given else 3
+    warmup = args.warmup if args.warmup_given else 1
+    link = link_peak(torch)
+    log("host link (pinned 1 GiB copies): H2D %.1f GB/s, D2H %.1f GB/s" % (link["h2d"], link["d2h"]))
+    arena = torch_arena(torch, budget)
+    ctx = L.Context(device_budget_bytes=budget, device_arena=arena.data_ptr(), arena_bytes=budget,
+                    stage_threshold_bytes=16 << 30, exec_mode=L.LT_EXEC_GROUPED)
+    sweep = [1 << 20, 1 << 22, 1 << 24, 1 << 26]
+    res = {}
+    try:
+        log("allocating %.1f GB of pinned host memory" % (N * (d * 4 + 4) / 1e9))
+        X = ctx.pinned((N, d))
+        lab = ctx.pinned((N,), np.int32)
+        log("generating %d points (d=%d, K=%d) in bands" % (N, d, K))
+        _, mu = synthetic.kmeans_blobs_banded(N, d, K, seed=4, out=X)
+        cen0 = (mu + np.random.default_rng(5).normal(0, 1.5, mu.shape)).astype(np.float32)
+        cen = ctx.array([K, d])
+        cen.write(cen0)
+        ctx.sync()
+        for c in sweep:
+            times, h2d, d2h, kms = [], [], [], []
+            for it in range(warmup + steps):
+                x = ctx.array_host(X, chunk=[c, 0])
+                lb = ctx.array_host(lab, chunk=[c])
+                ctx.sync()
+                ctx.reset_stats()
+                ctx.profile(True)
+                ctx.profile_reset()
+                s0 = time.perf_counter()
+                ctx.launch("kmeans_assign_f32", [N], [256], [c], args=[N, d, K, lb, x, cen])
+                ctx.sync()
+                dt = time.perf_counter() - s0
+                st = ctx.stats()
+                prof = ctx.profile_get().get("kmeans_assign_f32", {"total_ms": float("nan")})
+                ctx.profile(False)
+                x.destroy()
+                lb.destroy()
+                ctx.sync()
+                if it >= warmup:
+                    times.append(dt)
+                    h2d.append(st["bytes_h2d"])
+                    d2h.append(st["bytes_d2h"])
+                    kms.append(prof["total_ms"])
+            wall = float(np.median(times))
+            r = {"chunk_points": c, "chunk_mib": c * d * 4 / 2**20, "wall_ms": wall * 1e3,
+                 "p50_ms": pct(times, 50), "p99_ms": pct(times, 99),
+                 "gbs": N * (d * 4 + 4) / wall / 1e9,
+                 "h2d_gb": float(np.median(h2d)) / 1e9, "d2h_gb": float(np.median(d2h)) / 1e9,
+                 "h2d_gbs": float(np.median(h2d)) / wall / 1e9,
+                 "kernel_busy_frac": float(np.median(kms)) * 1e-3 / wall}
+            r["link_frac"] = r["h2d_gbs"] / link["h2d"]
+            res[c] = r
+            log("chunk %d points (%.0f MiB): %s" % (c, r["chunk_mib"], json.dumps(r)))
+    finally:
+        ctx.close()
+        del arena
+    best = max(res, key=lambda c: res[c]["gbs"])
+    m = res[best]
+    line = base_line({"workload": "out-of-core k-means assignment: %d points d=%d (Gaussian blobs, banded seed 4) "
+                                  "and labels in pinned host memory (%.1f GB), K=%d, device budget 64 GiB, "
+                                  "one cold pass per step" % (N, d, N * (d * 4 + 4) / 1e9, K),
+                      "executor": "grouped", "chunk_points": best}, steps, warmup)
+    line.update({"value": round(m["gbs"], 2), "unit": "GB/s", "ms_per_step": round(m["wall_ms"], 2),
+                 "dtype": "f32", "p50_ms": round(m["p50_ms"], 2), "p99_ms": round(m["p99_ms"], 2),
+                 "roofline": {"bound": "host_link", "achieved": round(m["h2d_gbs"], 2),
+                              "peak": round(link["h2d"], 2), "unit": "GB/s", "frac": round(m["link_frac"], 4),
+                              "peak_nominal": PCIE_NOMINAL_GBS, "peak_d2h": round(link["d2h"], 2),
+                              "traffic": None, "kernel": "k_kmeans (H2D copies bound the pass)"},
+                 "chunk_sweep": [{k: (round(v, 4) if isinstance(v, float) else v) for k, v in res[c].items()}
+                                 for c in sweep]})
     return line
 
 
@@ -784,8 +972,10 @@ def main():
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=None)
     ap.add_argument("--workload", choices=["jacobi", "stencil1d", "gemm_ooc", "batch", "serve", "kmeans",
-                                           "jacobi_tiled", "disk"],
+                                           "kmeans_ooc", "jacobi_tiled", "disk"],
                     default="jacobi")
+    ap.add_argument("--kmeans-points", type=int, default=1_000_000_000,
+                    help="kmeans_ooc: points in host memory (default 10^9)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--sb-band", type=int, default=0,
                     help="gemm_ooc: superblock rows per band of the banded issue order (0 = serpentine order)")
@@ -820,7 +1010,8 @@ def main():
     if args.calibrate_copy:
         calibration_copy(torch)
     fn = {"jacobi": bench_jacobi, "stencil1d": bench_stencil1d, "gemm_ooc": bench_gemm_ooc, "batch": bench_batch,
-          "serve": bench_serve, "kmeans": bench_kmeans, "jacobi_tiled": bench_jacobi_tiled,
+          "serve": bench_serve, "kmeans": bench_kmeans, "kmeans_ooc": bench_kmeans_ooc,
+          "jacobi_tiled": bench_jacobi_tiled,
           "disk": bench_disk}[args.workload]
     line = fn(args, L, torch)
     print(json.dumps(line), flush=True)

@@ -79,10 +79,11 @@ class Server:
                 raise LtError(st, "server destroy")
 
 
-def replay(server, trace, submit_fn, realtime=True, poll_interval=2e-4):
+def replay(server, trace, submit_fn, realtime=True, poll_interval=2e-4, progress=None):
     """Submits trace requests at their arrival times (seconds from start) and
-    polls until all complete.  ``submit_fn(server, req) -> id``.  Returns
-    (completions by request index, start time on lt_now's clock)."""
+    polls until all complete.  ``submit_fn(server, req) -> id``;
+    ``progress(done, total)`` (optional) is called after each completion.
+    Returns (completions by request index, start time on lt_now's clock)."""
     start = lt_now()
     pending = {}
     done = {}
@@ -94,6 +95,8 @@ def replay(server, trace, submit_fn, realtime=True, poll_interval=2e-4):
             i += 1
         for c in server.poll():
             done[pending.pop(c["id"])] = c
+            if progress:
+                progress(len(done), len(trace))
         if i < len(trace) and realtime:
             wait = trace[i]["t"] - (lt_now() - start)
             if wait > 0 and not pending:
@@ -137,9 +140,9 @@ def make_datasets(ctx, trace, seed=4):
             synthetic.jacobi2d_input(n, seed=seed * 1000 + r["dataset"], out=f)
             data[key] = (f, None)
         elif r["kind"] == "kmeans":
-            X, mu, _ = synthetic.kmeans_blobs(n, 16, 64, seed=seed * 1000 + r["dataset"])
-            xp = ctx.pinned(X.shape)
-            xp[...] = X
+            # drawn in bands straight into pinned memory (up to 1e9 points)
+            xp = ctx.pinned((n, 16))
+            _, mu = synthetic.kmeans_blobs_banded(n, 16, 64, seed=seed * 1000 + r["dataset"], out=xp)
             cp = ctx.pinned(mu.shape)
             cp[...] = mu
             data[key] = (xp, cp)
@@ -204,10 +207,13 @@ def bench(args, L, torch, log):
     import synthetic
 
     full = getattr(args, "serve_full", False)
-    count = 64
+    # the full size ranges with 8 datasets per kind; the default run keeps
+    # the ranges below 16384 / 1e8 / 16384 and 4 datasets per kind so that it
+    # ends in a minute
+    count, pool = (128, 8) if full else (64, 4)
     ranges = dict(jacobi_range=(1024, 32768 if full else 16384), kmeans_range=(1e5, 1e9 if full else 1e8),
                   gemm_range=(1024, 65536 if full else 16384))
-    trace = synthetic.serving_trace(count=count, rate=200.0, seed=4, pool=4, **ranges)
+    trace = synthetic.serving_trace(count=count, rate=200.0, seed=4, pool=pool, **ranges)
     for r in trace:
         r["sweeps"] = 10
     budget = 64 << 30
@@ -222,6 +228,9 @@ def bench(args, L, torch, log):
         log("serving: generating %d datasets in pinned host memory" % len({(r["kind"], r["dataset"]) for r in trace}))
         data = make_datasets(ctx, trace)
         outs = output_buffers(ctx, trace)
+        host_gb = sum(a.nbytes + (b.nbytes if b is not None else 0) for a, b in data.values()) / 1e9
+        host_gb += sum(o.nbytes for o in outs.values()) / 1e9
+        log("serving: %.1f GB of pinned inputs and outputs" % host_gb)
         # warm-up outside the timed traces: one small request of each kind on
         # datasets the trace never uses (device arena, code objects, streams)
         warm = [{"id": i, "t": 0.0, "kind": k, "dataset": 1000 + i, "size": n, "sweeps": 2}
@@ -237,8 +246,12 @@ def bench(args, L, torch, log):
             log("serving %s: %d requests, Poisson 200/s" % (mode, count))
             srv = Server(ctx, max_active=act, keep_resident=keep, admit_bytes=budget)
             ctx.reset_stats()
+            def progress(k, total):
+                if k % 16 == 0 or k == total:
+                    log("%s: %d of %d requests done" % (mode, k, total))
+
             try:
-                done, start = replay(srv, trace, submit_with(data, outs))
+                done, start = replay(srv, trace, submit_with(data, outs), progress=progress)
             finally:
                 srv.close()
             ctx.sync()
@@ -255,11 +268,11 @@ def bench(args, L, torch, log):
             "vs_baseline": None, "data": "synthetic",
             "config": {"workload": "serving: %d requests, Poisson 200/s seed 4, kinds uniform over Jacobi "
                                    "(n %d..%d, 10 sweeps), k-means assignment (N %.0e..%.0e, d=16, K=64) and GEMM "
-                                   "(n %d..%d), 4 datasets per kind with Zipf(1.1) popularity, device budget "
-                                   "64 GiB, inputs in pinned host memory"
+                                   "(n %d..%d), %d datasets per kind with Zipf(1.1) popularity, device budget "
+                                   "64 GiB, inputs in pinned host memory (%.1f GB)"
                                    % (count, ranges["jacobi_range"][0], ranges["jacobi_range"][1],
                                       ranges["kmeans_range"][0], ranges["kmeans_range"][1],
-                                      ranges["gemm_range"][0], ranges["gemm_range"][1]),
+                                      ranges["gemm_range"][0], ranges["gemm_range"][1], pool, host_gb),
                        "executor": "continuous batching, %d slots, resident datasets" % slots},
             "value": round(m["gbs"], 2), "unit": "GB/s", "ms_per_step": round(m["makespan_s"] * 1e3, 2),
             "dtype": "f32+i32", "p50_ms": round(m["p50_ms"], 2), "p99_ms": round(m["p99_ms"], 2),

@@ -112,12 +112,33 @@ def zipf_cdf(s: float = ZIPF_S, nbins: int = HIST_BINS) -> np.ndarray:
     return c / c[-1]
 
 
+_ZIPF_TABLES = {}
+
+
+def _zipf_table(s: float, nbins: int, cells: int = 1 << 16):
+    """Per cell [j / cells, (j + 1) / cells) of the unit interval: the number
+    of CDF entries <= j / cells, and the most entries any cell spans."""
+    key = (s, nbins, cells)
+    if key not in _ZIPF_TABLES:
+        cdf = zipf_cdf(s, nbins)
+        lo = np.searchsorted(cdf, np.arange(cells, dtype=np.float64) / cells, side="right")
+        hi = np.searchsorted(cdf, np.arange(1, cells + 1, dtype=np.float64) / cells, side="right")
+        _ZIPF_TABLES[key] = (cdf, lo.astype(np.int32), int((hi - lo).max()), cells)
+    return _ZIPF_TABLES[key]
+
+
 def zipf_values(n: int, rng: np.random.Generator, s: float = ZIPF_S,
                 nbins: int = HIST_BINS) -> np.ndarray:
-    """n int32 values in [0, nbins) drawn by inverse CDF from bounded Zipf(s)."""
-    cdf = zipf_cdf(s, nbins)
+    """n int32 values in [0, nbins) drawn by inverse CDF from bounded Zipf(s):
+    value = the number of CDF entries <= u for u ~ U[0, 1) (searchsorted with
+    side "right", clipped to nbins - 1), found through a cell table and at
+    most `span` exact comparisons against the CDF."""
+    cdf, lo, span, cells = _zipf_table(s, nbins)
     u = rng.random(n)
-    v = np.searchsorted(cdf, u, side="right")
+    v = lo[(u * cells).astype(np.int64)]
+    cdf_ext = np.append(cdf, np.inf)
+    for _ in range(span):
+        v += cdf_ext[v] <= u
     np.minimum(v, nbins - 1, out=v)
     return v.astype(np.int32)
 
@@ -162,6 +183,34 @@ def kmeans_blobs(N: int, d: int = 16, K: int = 64, seed: int = 4,
     z = rng.integers(0, K, N).astype(np.int32)
     X = (mu[z] + rng.standard_normal((N, d), dtype=np.float32)).astype(np.float32)
     return X, mu, z
+
+
+def kmeans_blobs_banded(N: int, d: int = 16, K: int = 64, seed: int = 4, spread: float = 10.0,
+                        out: np.ndarray | None = None, band: int = 1 << 22, workers: int = 16):
+    """Gaussian blobs for large N, drawn in bands of ``band`` points by a pool
+    of threads straight into ``out`` (e.g. pinned host memory): K means
+    ~ U(-spread, spread)^d from sub-stream [seed, N, d, K]; band b's labels z
+    (uniform over K) and N(0, I) offsets from sub-stream [seed, N, d, K, b].
+    The same law as ``kmeans_blobs``, other streams.  Returns (X, means)."""
+    mu = np.random.default_rng([seed, N, d, K]).uniform(-spread, spread, (K, d)).astype(np.float32)
+    if out is None:
+        out = np.empty((N, d), dtype=np.float32)
+
+    def fill(b):
+        r0 = b * band
+        r1 = min(N, r0 + band)
+        rng = np.random.default_rng([seed, N, d, K, b])
+        z = rng.integers(0, K, r1 - r0)
+        rng.standard_normal((r1 - r0, d), dtype=np.float32, out=out[r0:r1])
+        out[r0:r1] += mu[z]
+
+    nb = (N + band - 1) // band
+    if nb == 1:
+        fill(0)
+    else:
+        with ThreadPoolExecutor(max_workers=workers) as ex:
+            list(ex.map(fill, range(nb)))
+    return out, mu
 
 
 # ------------------------------------------------------------------- serving

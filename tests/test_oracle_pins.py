@@ -398,3 +398,13 @@ def test_batch_plan_sizes_log_uniform():
     kinds = np.array([k for k, _ in plan])
     assert 0.45 < kinds.mean() < 0.55
     assert abs(np.median(np.log2(ns)) - 17) < 0.3
+
+
+def test_zipf_sampler_is_the_inverse_cdf():
+    # the generator's cell table gives exactly searchsorted(cdf, u, "right")
+    # (clipped to 255) for the uniform draws of the same generator
+    cdf = synthetic.zipf_cdf()
+    for seed in (0, 3, 11):
+        u = np.random.default_rng(seed).random(2_000_000)
+        ref = np.minimum(np.searchsorted(cdf, u, side="right"), 255).astype(np.int32)
+        assert np.array_equal(synthetic.zipf_values(2_000_000, np.random.default_rng(seed)), ref)
