@@ -378,6 +378,31 @@ lt_status lt_wait(lt_context *ctx, uint64_t launch_id);
 lt_status lt_batch_begin(lt_context *ctx);
 lt_status lt_batch_end(lt_context *ctx);
 
+/* lt_batch_end without allocating, for callers that cannot allocate device
+ * or pinned memory at this point (tight serving loops, code that runs
+ * between allocation-free checkpoints).  It issues the open batch like
+ * lt_batch_end, but the queue, counters and partials go to a fixed device
+ * scratch of 32 MiB (one per GPU, held until the process ends) instead of an
+ * arena range, so nothing is evicted; the queue is uploaded from the
+ * planner's host copy instead of a pinned staging buffer; and the drain's
+ * error flag reuses one of the context's preallocated slots (when all are
+ * pending, the call first waits for compute stream 0).  No hipMalloc,
+ * hipFree or hipHostMalloc is called.  Tasks that lt_launch issued before
+ * (a batch that filled up, or launches that needed an earlier issue) went
+ * through the usual path.  Errors, each leaving the batch open and
+ * unissued (lt_batch_end can still issue it): LT_ERR_BUDGET if the batch
+ * needs more than 32 MiB of scratch (192 bytes per task, 4 per counter, the
+ * partials: about 160k tasks without partials), LT_ERR_DEVICE if the
+ * scratch could not be found on the context's device, LT_ERR_UNSUPPORTED
+ * for dry-run contexts; LT_ERR_INVALID while a graph is recorded.  A failure
+ * of the issue itself is sticky until lt_sync, as for lt_batch_end.  Every
+ * call on one GPU shares
+ * that GPU's scratch and keeps its last contents (the counters are cleared
+ * per call): calls from one context are ordered on its compute stream 0,
+ * but calls from different contexts or processes on one GPU that overlap
+ * in time race and give wrong results. */
+lt_status lt_batch_end_noalloc(lt_context *ctx);
+
 /* Graphs: a batch planned once and replayed.  lt_graph_begin opens a batch
  * whose queue is not issued; lt_graph_end turns it into a HIP graph (queue
  * upload, counter clear, drain) that owns its device queue and keeps every

@@ -167,6 +167,7 @@ _SIGS = [
     ("lt_sync", C.c_int32, [_P]),
     ("lt_batch_begin", C.c_int32, [_P]),
     ("lt_batch_end", C.c_int32, [_P]),
+    ("lt_batch_end_noalloc", C.c_int32, [_P]),
     ("lt_graph_begin", C.c_int32, [_P]),
     ("lt_graph_end", C.c_int32, [_P, C.POINTER(_P)]),
     ("lt_graph_launch", C.c_int32, [_P, _P]),
@@ -419,6 +420,11 @@ class Context:
 
     def batch_end(self):
         check(self.h, lt_batch_end(self.h))
+
+    def batch_end_noalloc(self):
+        """lt_batch_end_noalloc: issue the open batch from the library's fixed
+        device scratch, allocating nothing."""
+        check(self.h, lt_batch_end_noalloc(self.h))
 
     def launch_many(self, names, grids, blocks, superblocks, args, annotation=None):
         """Many launches in one call.  ``names``: kernel name per launch (or

@@ -103,12 +103,7 @@ lt_status sync_all(Ctx *ctx) {
             if (r != hipSuccess && !st) st = hip_fail(ctx, r, "hipStreamSynchronize");
         }
         prof_collect(ctx);
-        for (int i = 0; i < ctx->status_next; ++i)
-            if (ctx->status_host[i] && ctx->sticky == LT_OK) {
-                ctx->sticky = LT_ERR_TIMEOUT;
-                ctx->sticky_msg = "a dependency wait inside the batch drain exceeded its poll limit";
-            }
-        ctx->status_next = 0;
+        fold_drain_status(ctx);
         for (int32_t *gs : ctx->graph_status)
             if (*gs && ctx->sticky == LT_OK) {
                 ctx->sticky = LT_ERR_TIMEOUT;
@@ -521,6 +516,18 @@ lt_status lt_context_create(const lt_config *cfg_in, lt_context **out) {
                 return LT_ERR_DEVICE;
             }
         }
+        // set-up for lt_batch_end_noalloc: the device scratch's address on
+        // this device (a failure only disables that call) and the drain
+        // error-flag slots it reuses
+        ctx->scratch_err = drain_scratch_address(cfg.device, &ctx->scratch);
+        r = hipHostMalloc((void **)&ctx->status_host, 64 * 4, hipHostMallocDefault);
+        if (r != hipSuccess) {
+            g_create_err = std::string("hipHostMalloc(status slots): ") + hipGetErrorString(r);
+            for (int q = 0; q < ctx->nstreams; ++q) (void)hipStreamDestroy(ctx->streams[q].h);
+            delete ctx;
+            return LT_ERR_DEVICE;
+        }
+        ctx->status_slots = 64;
     }
     *out = ctx;
     return LT_OK;
@@ -740,6 +747,17 @@ lt_status lt_batch_end(lt_context *ctx) {
     if (ctx->batch.capture) return set_err(ctx, LT_ERR_INVALID, "a graph is being recorded (lt_graph_end)");
     lt_status st = batch_flush(ctx);
     ctx->batch.open = false;
+    return st;
+}
+
+lt_status lt_batch_end_noalloc(lt_context *ctx) {
+    if (!ctx) return LT_ERR_INVALID;
+    if (ctx->batch.capture) return set_err(ctx, LT_ERR_INVALID, "a graph is being recorded (lt_graph_end)");
+    lt_status st = batch_flush_noalloc(ctx);
+    // a batch rejected before its issue (too large for the scratch, no
+    // scratch, dry run) stays open and unissued; an issued or dropped one
+    // leaves an empty queue
+    if (ctx->batch.q.empty()) ctx->batch.open = false;
     return st;
 }
 

@@ -10,6 +10,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <mutex>
 
 #include "bodies.h"
 #include "kernels.h"
@@ -169,6 +170,33 @@ hipError_t launch_drain(hipStream_t s, const DTask *q, int ntasks, int32_t *coun
     hipLaunchKernelGGL(k, dim3((unsigned)nwg), dim3(256), 0, s, q, ntasks, counters, ticket_idx, total_tiles,
                        spin_limit);
     return hipGetLastError();
+}
+
+// Device scratch of the no-allocation batch issue: one copy per GPU, held
+// until the process ends.  Host code never passes this name to a kernel or a
+// copy (on the host it is only a stand-in for the symbol); it uses the
+// address drain_scratch_address() looks up on each device.
+static __device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
+
+hipError_t drain_scratch_address(int device, void **out) {
+    static std::mutex mu;
+    static void *addr[64] = {};
+    *out = nullptr;
+    if (device < 0 || device >= 64) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[device]) {
+        int cur = -1;
+        hipError_t r = hipGetDevice(&cur);
+        if (r != hipSuccess) return r;
+        if (cur != device && (r = hipSetDevice(device)) != hipSuccess) return r;
+        void *p = nullptr;
+        r = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (cur != device) (void)hipSetDevice(cur);
+        if (r != hipSuccess) return r;
+        addr[device] = p;
+    }
+    *out = addr[device];
+    return hipSuccess;
 }
 
 }  // namespace lt

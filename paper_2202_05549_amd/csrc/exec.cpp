@@ -845,7 +845,18 @@ void batch_drop(Ctx *ctx) {
     B.open = open;
 }
 
-static lt_status batch_issue(Ctx *ctx);
+static lt_status batch_issue(Ctx *ctx, bool noalloc = false);
+
+// Bytes of device memory the open batch needs at issue: queue, counters
+// (one per task and signal, the ticket and the error flag), partials.
+static void batch_layout(const Batch &B, int64_t *qbytes, int64_t *qalloc, int64_t *calloc_, int64_t *total) {
+    const int ntasks = (int)B.q.size();
+    const int nctr = ntasks + B.nsignals + 2;
+    *qbytes = (int64_t)ntasks * (int64_t)sizeof(DTask);
+    *qalloc = (*qbytes + 255) / 256 * 256;
+    *calloc_ = ((int64_t)nctr * 4 + 255) / 256 * 256;
+    *total = *qalloc + *calloc_ + B.part_bytes;
+}
 
 lt_status batch_flush(Ctx *ctx) {
     Batch &B = ctx->batch;
@@ -865,23 +876,74 @@ lt_status batch_flush(Ctx *ctx) {
     return st;
 }
 
+// Issues the open batch from the fixed device scratch instead of an arena
+// range, with no allocation: no arena range (so no eviction), no pinned
+// staging buffer (the queue is uploaded from the planner's own host copy)
+// and no new status slot (when the preallocated slots are used up, the drain
+// stream is synchronized and their flags folded first).  A batch too large
+// for the scratch is left open and unissued (LT_ERR_BUDGET).
+lt_status batch_flush_noalloc(Ctx *ctx) {
+    Batch &B = ctx->batch;
+    if (B.capture) return set_err(ctx, LT_ERR_INVALID, "a graph is being recorded");
+    if (B.q.empty()) return LT_OK;
+    int64_t qbytes, qalloc, calloc_, total;
+    batch_layout(B, &qbytes, &qalloc, &calloc_, &total);
+    if (total > NOALLOC_SCRATCH_BYTES)
+        return set_err(ctx, LT_ERR_BUDGET,
+                       "the batch needs %lld bytes of device scratch (%d tasks, %lld bytes of partials); "
+                       "the no-allocation issue holds at most %lld: issue it with lt_batch_end",
+                       (long long)total, (int)B.q.size(), (long long)B.part_bytes,
+                       (long long)NOALLOC_SCRATCH_BYTES);
+    if (ctx->dry) return set_err(ctx, LT_ERR_UNSUPPORTED, "the no-allocation batch issue needs a device");
+    if (!ctx->scratch)
+        return set_err(ctx, LT_ERR_DEVICE, "device scratch lookup failed at context creation: %s",
+                       hipGetErrorString(ctx->scratch_err));
+    lt_status st = flush_group(ctx);
+    if (st) return st;
+    st = batch_issue(ctx, true);
+    if (st) {
+        if (ctx->sticky == LT_OK) {
+            ctx->sticky = st;
+            ctx->sticky_msg = "a batch could not be issued: " + ctx->err;
+        }
+        batch_drop(ctx);
+    }
+    return st;
+}
+
+// Folds the drain error flags copied back so far into the sticky error
+// (every status copy is on compute stream 0, which must have completed).
+void fold_drain_status(Ctx *ctx) {
+    for (int i = 0; i < ctx->status_next; ++i)
+        if (ctx->status_host[i] && ctx->sticky == LT_OK) {
+            ctx->sticky = LT_ERR_TIMEOUT;
+            ctx->sticky_msg = "a dependency wait inside the batch drain exceeded its poll limit";
+        }
+    ctx->status_next = 0;
+}
+
 // Uploads the queue of the open batch and issues its drain.  The queue,
 // counters and partials take one arena range; the batch's chunks are pinned,
 // so making room for it never evicts them (LT_ERR_BUDGET when it cannot fit).
-static lt_status batch_issue(Ctx *ctx) {
+// With `noalloc` they take the fixed device scratch instead.
+static lt_status batch_issue(Ctx *ctx, bool noalloc) {
     Batch &B = ctx->batch;
     lt_status st;
     const int ntasks = (int)B.q.size();
-    const int nctr = ntasks + B.nsignals + 2;
-    const int64_t qbytes = (int64_t)ntasks * (int64_t)sizeof(DTask);
-    const int64_t qalloc = (qbytes + 255) / 256 * 256;
-    const int64_t calloc_ = ((int64_t)nctr * 4 + 255) / 256 * 256;
-    const int64_t total = qalloc + calloc_ + B.part_bytes;
-    int64_t off;
+    int64_t qbytes, qalloc, calloc_, total;
+    batch_layout(B, &qbytes, &qalloc, &calloc_, &total);
+    int64_t off = -1;
     Fence mem;
-    st = alloc_range(ctx, total, 2, nullptr, &off, &mem);
-    if (st) return st;
-    char *base = ctx->arena_base + off;
+    char *base;
+    if (noalloc) {
+        base = static_cast<char *>(ctx->scratch);
+        // the previous user of the scratch on this context is a drain on
+        // compute stream 0, where this batch is issued too
+    } else {
+        st = alloc_range(ctx, total, 2, nullptr, &off, &mem);
+        if (st) return st;
+        base = ctx->arena_base + off;
+    }
     int64_t part_base = (int64_t)(intptr_t)(base + qalloc + calloc_);
     for (auto &pr : B.patch_y) B.q[pr.first].y += part_base;
     for (auto &pr : B.patch_x) B.q[pr.first].x += part_base;
@@ -890,12 +952,16 @@ static lt_status batch_issue(Ctx *ctx) {
         for (int i = 0; i < d.ndeps; ++i)
             if (d.dep_ctr[i] <= -2) d.dep_ctr[i] = ntasks + (-2 - d.dep_ctr[i]);
     }
-    void *stage = staging_get(ctx, (uint64_t)qbytes, &st);
-    if (!stage) {
-        ctx->arena.release(off, mem);
-        return st;
+    const void *stage = B.q.data();
+    if (!noalloc) {
+        void *p = staging_get(ctx, (uint64_t)qbytes, &st);
+        if (!p) {
+            ctx->arena.release(off, mem);
+            return st;
+        }
+        memcpy(p, B.q.data(), (size_t)qbytes);
+        stage = p;
     }
-    memcpy(stage, B.q.data(), (size_t)qbytes);
     const int s = 0;
     B.wait.merge(mem);
     st = stream_wait(ctx, s, B.wait);
@@ -903,6 +969,8 @@ static lt_status batch_issue(Ctx *ctx) {
     int nwg = ctx->cfg.drain_workgroups > 0 ? ctx->cfg.drain_workgroups : 1024;
     if (!ctx->dry) {
         hipStream_t h = ctx->streams[s].h;
+        // from pageable memory (no-allocation issue) the copy has read its
+        // source when the call returns, so the queue can be dropped below
         hipError_t r = hipMemcpyAsync(base, stage, (size_t)qbytes, hipMemcpyHostToDevice, h);
         if (r != hipSuccess) return hip_fail(ctx, r, "batch queue upload");
         uint32_t zero = 0;
@@ -918,6 +986,12 @@ static lt_status batch_issue(Ctx *ctx) {
         st = prof_end(ctx, s, "drain", pa);
         if (st) return st;
         // error flag back to pinned host memory, checked at lt_sync
+        if (noalloc && ctx->status_next >= ctx->status_slots) {
+            // every slot's copy is on this stream: wait for them and reuse
+            r = hipStreamSynchronize(h);
+            if (r != hipSuccess) return hip_fail(ctx, r, "hipStreamSynchronize");
+            fold_drain_status(ctx);
+        }
         if (ctx->status_next >= ctx->status_slots) {
             int ns = std::max(64, ctx->status_slots * 2);
             int32_t *p = nullptr;
@@ -949,7 +1023,7 @@ static lt_status batch_issue(Ctx *ctx) {
     apply_uses(ctx, B.uses, s, p);
     Fence done;
     done.add(s, p);
-    ctx->arena.release(off, done);
+    if (off >= 0) ctx->arena.release(off, done);
     for (uint64_t L : B.launches) ctx->launches.at(L).done.add(s, p);  // they complete with the drain
     batch_drop(ctx);
     return LT_OK;

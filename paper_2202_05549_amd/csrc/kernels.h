@@ -181,4 +181,11 @@ constexpr int32_t DF_ATOMIC = 2;
 hipError_t launch_drain(hipStream_t s, const DTask *q, int ntasks, int32_t *counters, int ticket_idx,
                         int64_t total_tiles, int nwg, int64_t spin_limit, uint32_t kinds, int vectors);
 
+// Fixed device scratch for issuing a batch without allocating: queue,
+// counters and partials of one batch at a time.  drain_scratch_address
+// returns its address on `device` (looked up once per device, with that
+// device current; later calls return the kept address).
+constexpr int64_t NOALLOC_SCRATCH_BYTES = (int64_t)32 << 20;
+hipError_t drain_scratch_address(int device, void **out);
+
 }  // namespace lt

@@ -451,6 +451,10 @@ struct lt_context {
     int32_t *status_host = nullptr;    // drain error flags copied back
     std::vector<int32_t *> graph_status;  // error flags of live graphs
     int status_slots = 0, status_next = 0;
+    // the device scratch of lt_batch_end_noalloc on this context's device
+    // (looked up at creation; null with scratch_err set if that failed)
+    void *scratch = nullptr;
+    hipError_t scratch_err = hipSuccess;
 
     // profiling: (kernel name, start, end) awaiting resolution
     int prof = 0;                      // 0 off; k: every k-th dispatch of each body is timed
@@ -496,6 +500,8 @@ lt_status launch(Ctx *ctx, lt_kernel *k, int nd, const int64_t *grid,
 lt_status sync_all(Ctx *ctx);
 lt_status flush_group(Ctx *ctx);
 lt_status batch_flush(Ctx *ctx);
+lt_status batch_flush_noalloc(Ctx *ctx);
+void fold_drain_status(Ctx *ctx);
 // Releases the pins of the queued tasks and empties the batch (it stays
 // open if it was).
 void batch_drop(Ctx *ctx);
