@@ -143,6 +143,52 @@ TRAFFIC = {
 }
 
 
+def _union(iv):
+    """Merged, sorted intervals of an (k, 2) array."""
+    if len(iv) == 0:
+        return np.zeros((0, 2))
+    iv = iv[np.argsort(iv[:, 0])]
+    out = [list(iv[0])]
+    for a, b in iv[1:]:
+        if a <= out[-1][1]:
+            out[-1][1] = max(out[-1][1], b)
+        else:
+            out.append([a, b])
+    return np.array(out)
+
+
+def _meet(u, v):
+    """Total length of the intersection of two merged interval lists."""
+    i = j = 0
+    tot = 0.0
+    while i < len(u) and j < len(v):
+        lo, hi = max(u[i][0], v[j][0]), min(u[i][1], v[j][1])
+        if hi > lo:
+            tot += hi - lo
+        if u[i][1] < v[j][1]:
+            i += 1
+        else:
+            j += 1
+    return tot
+
+
+def copy_overlap(spans):
+    """Copy/compute overlap from the library's device-clock spans: per
+    direction, the time some copy of that direction is in flight (union of
+    its spans), and the share of it during which some kernel also runs,
+    (copy time AND kernel time) / copy time."""
+    names = spans["name"]
+    iv = np.stack([spans["start_ms"], spans["end_ms"]], axis=1) if len(spans) else np.zeros((0, 2))
+    kern = _union(iv[(names != b"copy_h2d") & (names != b"copy_d2h")])
+    out = {"kernel_busy_ms": round(float((kern[:, 1] - kern[:, 0]).sum()) if len(kern) else 0.0, 3)}
+    for d in ("h2d", "d2h"):
+        u = _union(iv[names == ("copy_" + d).encode()])
+        busy = float((u[:, 1] - u[:, 0]).sum()) if len(u) else 0.0
+        out[d] = {"copies": int((names == ("copy_" + d).encode()).sum()), "busy_ms": round(busy, 3),
+                  "overlap_frac": round(_meet(u, kern) / busy, 4) if busy > 0 else None}
+    return out
+
+
 def jacobi_kernel_name(variant):
     if variant in (8, 16, 32):
         return "k_jacobi2d"
@@ -379,6 +425,140 @@ def bench_stencil1d(args, L, torch):
     return line
 
 
+# ====================================================== runtime-compiled body
+# The paper's example stencil as a user __device__ function (Sec. 3.5), with
+# the 1-D stencil workload's weights; compiled at run time by the library.
+USER_STENCIL = r"""
+__device__ void stencil(dim3 virtBlockIdx, int n, lt::Vector<float> output, const lt::Vector<float> input) {
+    int i = blockDim.x * virtBlockIdx.x + threadIdx.x;
+    if (i >= n) return;
+    float left = i - 1 >= 0 ? input[i - 1] : 0.0f;
+    float mid = input[i];
+    float right = i + 1 < n ? input[i + 1] : 0.0f;
+    output[i] = 0.25f * (left + right) + 0.5f * mid;
+}
+"""
+# The same arithmetic written for bandwidth: four elements per thread with
+# 16-byte accesses through the views (the rows are 16-byte aligned in the
+# chunks this benchmark uses), scalar halo reads at the ends.
+USER_STENCIL4 = r"""
+__device__ void stencil4(dim3 virtBlockIdx, long long n, lt::Vector<float> output, const lt::Vector<float> input) {
+    const long long i0 = ((long long)virtBlockIdx.x * blockDim.x + threadIdx.x) * 4;
+    if (i0 >= n) return;
+    if (i0 + 4 <= n) {
+        const float4 c = *reinterpret_cast<const float4 *>(&input[i0]);
+        const float l = i0 > 0 ? input[i0 - 1] : 0.0f;
+        const float r = i0 + 4 < n ? input[i0 + 4] : 0.0f;
+        float4 o;
+        o.x = 0.25f * (l + c.y) + 0.5f * c.x;
+        o.y = 0.25f * (c.x + c.z) + 0.5f * c.y;
+        o.z = 0.25f * (c.y + c.w) + 0.5f * c.z;
+        o.w = 0.25f * (c.z + r) + 0.5f * c.w;
+        typedef float v4 __attribute__((ext_vector_type(4)));
+        const v4 ov = {o.x, o.y, o.z, o.w};
+        __builtin_nontemporal_store(ov, reinterpret_cast<v4 *>(&output[i0]));
+    } else {
+        for (long long i = i0; i < n; ++i) {
+            const float l = i > 0 ? input[i - 1] : 0.0f;
+            const float r = i + 1 < n ? input[i + 1] : 0.0f;
+            output[i] = 0.25f * (l + r) + 0.5f * input[i];
+        }
+    }
+}
+"""
+
+
+def bench_rtc(args, L, torch):
+    """Runtime-compiled user bodies beside the built-in body on the same
+    launches: the 1-D stencil workload (2^20, 8 chunks, plain and grouped:
+    launch-bound) and a 2^28-element field in 8 chunks (grouped, HBM-bound).
+    Two user bodies: the paper's example (one element per thread) and the
+    same arithmetic with four elements per thread and 16-byte accesses.
+    Reports wall time per launch, device time per dispatch (HIP events) and
+    the compile time of the user bodies' versions."""
+    import synthetic
+
+    cases = [("c1_plain", 1 << 20, 1 << 17, 0, 200), ("c1_grouped", 1 << 20, 1 << 17, 1, 200),
+             ("large_grouped", 1 << 28, 1 << 25, 1, 20)]
+    res = {}
+    for tag, n, chunk, mode, steps in cases:
+        x0 = synthetic.stencil1d_input(n, 0)
+        ref = None
+        for body in ("builtin", "user", "user4"):
+            nbytes = 2 * n * 4 + (64 << 20)
+            arena = torch_arena(torch, nbytes)
+            ctx = L.Context(device_budget_bytes=nbytes, device_arena=arena.data_ptr(), arena_bytes=nbytes,
+                            exec_mode=mode)
+            name, grid, sbk = "stencil1d_f32", n, chunk
+            before = L.Context.rtc_stats()
+            if body == "user":
+                ctx.define_source("user_stencil", USER_STENCIL, "stencil",
+                                  [("n", "int"), ("output", np.float32, 1), ("input", np.float32, 1)],
+                                  "global i => read input[i-1:i+1], write output[i]")
+                name = "user_stencil"
+            elif body == "user4":
+                ctx.define_source("user_stencil4", USER_STENCIL4, "stencil4",
+                                  [("n", "int"), ("output", np.float32, 1), ("input", np.float32, 1)],
+                                  "global i => read input[4*i-1:4*i+4], write output[4*i:4*i+3]")
+                name, grid, sbk = "user_stencil4", (n + 3) // 4, chunk // 4
+            x = ctx.array([n], chunk=[chunk])
+            y = ctx.array([n], chunk=[chunk])
+            x.write(x0)
+            ctx.sync()
+
+            def step():
+                ctx.launch(name, [grid], [256], [sbk], args=[n, y, x])
+                ctx.sync()
+
+            for _ in range(max(args.warmup, 5)):
+                step()
+            out = y.read()
+            if ref is None:
+                ref = out
+            ctx.profile(True)
+            ctx.profile_reset()
+            times = []
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                s0 = time.perf_counter()
+                step()
+                times.append(time.perf_counter() - s0)
+            total = time.perf_counter() - t0
+            prof = ctx.profile_get()
+            ctx.close()
+            del arena
+            k = prof[{"builtin": "stencil1d_f32", "user": "stencil", "user4": "stencil4"}[body]]
+            avg_ms = k["total_ms"] / k["dispatches"]
+            per_dispatch = n * 8 / k["dispatches"] * steps
+            r = {"us_per_launch": total / steps * 1e6, "gbs": n * 8 / (total / steps) / 1e9,
+                 "p50_us": pct(times, 50) * 1e3, "p99_us": pct(times, 99) * 1e3,
+                 "kernel_avg_us": avg_ms * 1e3, "kernel_gbs": per_dispatch / (avg_ms * 1e-3) / 1e9,
+                 "dispatches_per_launch": k["dispatches"] / steps, "same_result": bool(np.array_equal(out, ref))}
+            if body != "builtin":
+                after = L.Context.rtc_stats()
+                r["versions_compiled"] = after["compiles"] - before["compiles"]
+                r["compile_s"] = after["compile_seconds"] - before["compile_seconds"]
+            res.setdefault(tag, {})[body] = r
+            log("%s %s: %s" % (tag, body, json.dumps(r)))
+        for body in ("user", "user4"):
+            res[tag][body + "_over_builtin_wall"] = (res[tag][body]["us_per_launch"] /
+                                                     res[tag]["builtin"]["us_per_launch"])
+    m = res["large_grouped"]["user4"]
+    line = base_line({"workload": "runtime-compiled user stencil body (the paper's example kernel with "
+                                  "0.25/0.5/0.25 weights, four elements per thread) on a 2^28 f32 field "
+                                  "~U(-1,1) seed 0, 8 chunks of 2^25, grouped dispatch, beside the built-in body",
+                      "executor": "grouped"}, cases[-1][4], max(args.warmup, 5))
+    line.update({"value": round(m["gbs"], 2), "unit": "GB/s", "ms_per_step": round(m["us_per_launch"] / 1e3, 4),
+                 "dtype": "f32", "p50_ms": round(m["p50_us"] / 1e3, 4), "p99_ms": round(m["p99_us"] / 1e3, 4),
+                 "roofline": {"bound": "hbm", "achieved": round(m["kernel_gbs"], 2), "peak": HBM_PEAK_GBS,
+                              "unit": "GB/s", "frac": round(m["kernel_gbs"] / HBM_PEAK_GBS, 4), "traffic": None,
+                              "kernel": "lt_rtc_* (user stencil4)", "kernel_avg_us": round(m["kernel_avg_us"], 2)},
+                 "cases": {t: {b: ({k: (round(v, 4) if isinstance(v, float) else v) for k, v in res[t][b].items()}
+                                   if isinstance(res[t][b], dict) else round(res[t][b], 4)) for b in res[t]}
+                           for t in res}})
+    return line
+
+
 # ================================================================= gemm_ooc
 def bench_gemm_ooc(args, L, torch):
     import synthetic
@@ -423,6 +603,8 @@ def bench_gemm_ooc(args, L, torch):
             times.append(time.perf_counter() - s0)
         total = sum(times)
         prof = ctx.profile_get()["gemm_f32"]
+        overlap = copy_overlap(ctx.profile_spans())
+        log("copy/compute overlap over the timed steps: %s" % json.dumps(overlap))
         st = ctx.stats()
         cpu = None
         if not args.no_cpu:
@@ -446,6 +628,7 @@ def bench_gemm_ooc(args, L, torch):
                           "compulsory_gib": 48.0, "h2d_gbs_avg": round(h2d / wall / 1e9, 2),
                           "link_busy_frac_at_57gbs": round((h2d + d2h) / 57e9 / wall, 3)},
                  "kernel_busy_frac": round(prof["total_ms"] / steps * 1e-3 / wall, 4),
+                 "overlap": overlap,
                  "p50_ms": round(pct(times, 50), 2), "p99_ms": round(pct(times, 99), 2),
                  "roofline": {"bound": "mfma", "achieved": round(kernel_tflops, 2), "peak": MFMA_FP32_PEAK,
                               "unit": "TFLOP/s", "frac": round(kernel_tflops / MFMA_FP32_PEAK, 4), "traffic": traffic_for("k_gemm"),
@@ -907,7 +1090,7 @@ def bench_kmeans_ooc(args, L, torch):
         cen.write(cen0)
         ctx.sync()
         for c in sweep:
-            times, h2d, d2h, kms = [], [], [], []
+            times, h2d, d2h, kms, ovl = [], [], [], [], []
             for it in range(warmup + steps):
                 x = ctx.array_host(X, chunk=[c, 0])
                 lb = ctx.array_host(lab, chunk=[c])
@@ -921,6 +1104,7 @@ def bench_kmeans_ooc(args, L, torch):
                 dt = time.perf_counter() - s0
                 st = ctx.stats()
                 prof = ctx.profile_get().get("kmeans_assign_f32", {"total_ms": float("nan")})
+                spans = ctx.profile_spans()
                 ctx.profile(False)
                 x.destroy()
                 lb.destroy()
@@ -930,13 +1114,15 @@ def bench_kmeans_ooc(args, L, torch):
                     h2d.append(st["bytes_h2d"])
                     d2h.append(st["bytes_d2h"])
                     kms.append(prof["total_ms"])
+                    ovl.append(copy_overlap(spans))
             wall = float(np.median(times))
             r = {"chunk_points": c, "chunk_mib": c * d * 4 / 2**20, "wall_ms": wall * 1e3,
                  "p50_ms": pct(times, 50), "p99_ms": pct(times, 99),
                  "gbs": N * (d * 4 + 4) / wall / 1e9,
                  "h2d_gb": float(np.median(h2d)) / 1e9, "d2h_gb": float(np.median(d2h)) / 1e9,
                  "h2d_gbs": float(np.median(h2d)) / wall / 1e9,
-                 "kernel_busy_frac": float(np.median(kms)) * 1e-3 / wall}
+                 "kernel_busy_frac": float(np.median(kms)) * 1e-3 / wall,
+                 "overlap": ovl[len(ovl) // 2]}
             r["link_frac"] = r["h2d_gbs"] / link["h2d"]
             res[c] = r
             log("chunk %d points (%.0f MiB): %s" % (c, r["chunk_mib"], json.dumps(r)))
@@ -955,6 +1141,7 @@ def bench_kmeans_ooc(args, L, torch):
                               "peak": round(link["h2d"], 2), "unit": "GB/s", "frac": round(m["link_frac"], 4),
                               "peak_nominal": PCIE_NOMINAL_GBS, "peak_d2h": round(link["d2h"], 2),
                               "traffic": None, "kernel": "k_kmeans (H2D copies bound the pass)"},
+                 "overlap": m["overlap"],
                  "chunk_sweep": [{k: (round(v, 4) if isinstance(v, float) else v) for k, v in res[c].items()}
                                  for c in sweep]})
     return line
@@ -972,7 +1159,7 @@ def main():
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=None)
     ap.add_argument("--workload", choices=["jacobi", "stencil1d", "gemm_ooc", "batch", "serve", "kmeans",
-                                           "kmeans_ooc", "jacobi_tiled", "disk"],
+                                           "kmeans_ooc", "jacobi_tiled", "disk", "rtc"],
                     default="jacobi")
     ap.add_argument("--kmeans-points", type=int, default=1_000_000_000,
                     help="kmeans_ooc: points in host memory (default 10^9)")
@@ -1011,7 +1198,7 @@ def main():
         calibration_copy(torch)
     fn = {"jacobi": bench_jacobi, "stencil1d": bench_stencil1d, "gemm_ooc": bench_gemm_ooc, "batch": bench_batch,
           "serve": bench_serve, "kmeans": bench_kmeans, "kmeans_ooc": bench_kmeans_ooc,
-          "jacobi_tiled": bench_jacobi_tiled,
+          "jacobi_tiled": bench_jacobi_tiled, "rtc": bench_rtc,
           "disk": bench_disk}[args.workload]
     line = fn(args, L, torch)
     print(json.dumps(line), flush=True)

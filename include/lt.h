@@ -53,6 +53,8 @@ typedef int32_t lt_status;
 #define LT_ERR_DEVICE (-5)      /* a HIP call failed (message carries the text) */
 #define LT_ERR_TIMEOUT (-6)     /* a bounded device wait gave up               */
 #define LT_ERR_UNSUPPORTED (-7) /* valid request this build does not implement */
+#define LT_ERR_COMPILE (-8)     /* runtime compilation of a user kernel failed
+                                   (the compiler's log is in lt_last_error) */
 
 typedef enum lt_dtype {
     LT_F32 = 0,
@@ -301,6 +303,71 @@ lt_status lt_host_free(lt_context *ctx, void *ptr);
 lt_status lt_kernel_get(lt_context *ctx, const char *name, lt_kernel **out);
 lt_status lt_kernel_define(lt_context *ctx, const char *base,
                            const char *annotation, lt_kernel **out);
+
+/* ------------------------------------------------------------ user kernels
+ * Runtime kernel compilation (Sec. 3.5 "Runtime Kernel Compilation").  The
+ * caller supplies HIP source holding a __device__ function `function` whose
+ * arguments are, in order: the virtual block index (a dim3), then one
+ * argument per entry of params[]:
+ *   LT_ARG_INT   an integer (passed as long long; declare any integer type)
+ *   LT_ARG_FLOAT a number (passed as double; declare float or double)
+ *   LT_ARG_ARRAY a view of an array of `dtype` with `ndim` axes:
+ *                lt::Vector<T>, lt::Matrix<T> or lt::Tensor<T> for 1, 2, 3
+ *                axes (T = float, int, double, long long, unsigned char),
+ *                indexed with GLOBAL array indices: v[i], m(i, j) or m[i][j],
+ *                t(i, j, k) or t[i][j][k]
+ * This is the paper's porting recipe: a __global__ kernel becomes a
+ * __device__ function, takes the block index as an argument (use it in
+ * place of blockIdx; blockDim and threadIdx keep their meaning) and takes
+ * views in place of raw pointers.  The grid's axes map to hardware axes
+ * fastest first: a 1-D grid runs along x, the axes [i, j] of a 2-D grid
+ * along (y, x), [i, j, k] along (z, y, x); block[] is given in the same
+ * order as the grid.
+ *
+ * The runtime generates a wrapper kernel that finds the workgroup's
+ * superblock, forms the virtual block index (the superblock's first block
+ * plus the workgroup's block within it) and builds the views from base
+ * addresses already moved by each region's origin, then calls the function.
+ * The wrapper and the function are compiled together with hipRTC for gfx950
+ * (-O3, no contraction of multiply-add, no packed FP32), with the block
+ * shape, every view's strides and the values of scalars flagged
+ * LT_PARAM_CONST baked in as constants: one compiled version per
+ * combination, cached for the process, compiled at the first dispatch that
+ * needs it.  Up to 16 superblocks share a dispatch in LT_EXEC_GROUPED mode.
+ *
+ * annotation: required; it names params[] entries and its bound index names
+ * fix the rank of the launch grid (1..3).  The source is compiled once here
+ * (block of 64, unit strides) so that its errors are reported now.
+ * Planning, staging, spilling and reductions are those of built-in bodies;
+ * a reduce(f) argument is a view of the superblock's partial, filled with
+ * f's identity before the function runs.  User kernels cannot run inside a
+ * batch (LT_ERR_UNSUPPORTED).  Blocks hold at most 1024 threads.
+ * Errors: LT_ERR_INVALID (parameter list, function name), LT_ERR_PARSE
+ * (annotation), LT_ERR_COMPILE (with the compiler's log).  A failure to
+ * compile or load a later version is reported by the launch that needs it
+ * (LT_ERR_DEVICE).  With the environment variable LT_RTC_DUMP=1 each
+ * generated translation unit is printed to stderr before it is compiled. */
+#define LT_PARAM_CONST 1
+typedef struct lt_param {
+    const char *name;   /* the name annotations use                    */
+    int32_t kind;       /* LT_ARG_ARRAY / LT_ARG_INT / LT_ARG_FLOAT     */
+    int32_t dtype;      /* arrays: element type (lt_dtype)              */
+    int32_t ndim;       /* arrays: number of axes, 1..3                 */
+    int32_t flags;      /* scalars: LT_PARAM_CONST bakes the value in   */
+} lt_param;
+lt_status lt_kernel_define_source(lt_context *ctx, const char *source, const char *function,
+                                  const lt_param *params, int32_t nparams, const char *annotation,
+                                  lt_kernel **out);
+
+/* Process-wide counts of user-kernel versions compiled (including the check
+ * build of each definition) and loaded onto a device, and the seconds spent
+ * compiling. */
+typedef struct lt_rtc_stats {
+    uint64_t compiles;
+    uint64_t loads;
+    double compile_seconds;
+} lt_rtc_stats;
+lt_status lt_rtc_stats_get(lt_rtc_stats *out);
 
 /* Selects a tuning variant of a built-in body for later launches through
  * this handle (0 = default).  Variants change only the work mapping, never
@@ -571,7 +638,16 @@ lt_status lt_trace_clear(lt_context *ctx);
  * "graph" (the whole replay).  Meant for measurement runs (the events add a
  * little overhead).  lt_profile_enable(ctx, k): 0 off, 1 every dispatch, k > 1
  * every k-th dispatch of each body (a sample with 1/k of the overhead; the
- * returned counts and totals cover the sampled dispatches).
+ * returned counts and totals cover the sampled dispatches).  Copies between
+ * host and device memory are timed the same way, as "copy_h2d" and
+ * "copy_d2h" (copy-engine copies and copy kernels alike).
+ *
+ * lt_profile_spans returns every timed operation since profiling was
+ * enabled or reset, as (name, stream, start, end) on the device clock in
+ * milliseconds from an event recorded then on compute stream 0 (starts
+ * before it are negative): copy/compute overlap is measured from these
+ * (Sec. 3.4 overlaps staging with execution).  Spans become available at
+ * lt_sync; at most 2^22 are kept.
  */
 typedef struct lt_kernel_prof {
     char name[32];
@@ -580,7 +656,15 @@ typedef struct lt_kernel_prof {
     double max_ms;
 } lt_kernel_prof;
 
+typedef struct lt_span {
+    char name[32];
+    int32_t stream;       /* stream index: compute 0..n-1, then H2D, then D2H */
+    int32_t pad;
+    double start_ms, end_ms;
+} lt_span;
+
 lt_status lt_profile_enable(lt_context *ctx, int32_t on);
+lt_status lt_profile_spans(lt_context *ctx, lt_span *out, uint64_t cap, uint64_t *n);
 lt_status lt_profile_get(lt_context *ctx, lt_kernel_prof *out, int32_t cap,
                          int32_t *n);
 lt_status lt_profile_reset(lt_context *ctx);

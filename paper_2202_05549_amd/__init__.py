@@ -27,8 +27,10 @@ LT_ERR_OOM = -4
 LT_ERR_DEVICE = -5
 LT_ERR_TIMEOUT = -6
 LT_ERR_UNSUPPORTED = -7
+LT_ERR_COMPILE = -8
 _ERRNAMES = {-1: "LT_ERR_INVALID", -2: "LT_ERR_PARSE", -3: "LT_ERR_BUDGET", -4: "LT_ERR_OOM",
-             -5: "LT_ERR_DEVICE", -6: "LT_ERR_TIMEOUT", -7: "LT_ERR_UNSUPPORTED"}
+             -5: "LT_ERR_DEVICE", -6: "LT_ERR_TIMEOUT", -7: "LT_ERR_UNSUPPORTED", -8: "LT_ERR_COMPILE"}
+LT_PARAM_CONST = 1
 
 LT_F32, LT_I32, LT_F64, LT_I64, LT_U8 = 0, 1, 2, 3, 4
 DTYPES = {LT_F32: np.float32, LT_I32: np.int32, LT_F64: np.float64, LT_I64: np.int64, LT_U8: np.uint8}
@@ -72,6 +74,20 @@ class lt_task_info(C.Structure):
     _fields_ = [("id", C.c_uint64), ("launch", C.c_uint64), ("kind", C.c_int32), ("stream", C.c_int32),
                 ("ndeps", C.c_int32), ("nregions", C.c_int32), ("sb_lo", C.c_int64 * 3),
                 ("sb_hi", C.c_int64 * 3)]
+
+
+class lt_param(C.Structure):
+    _fields_ = [("name", C.c_char_p), ("kind", C.c_int32), ("dtype", C.c_int32), ("ndim", C.c_int32),
+                ("flags", C.c_int32)]
+
+
+class lt_rtc_stats(C.Structure):
+    _fields_ = [("compiles", C.c_uint64), ("loads", C.c_uint64), ("compile_seconds", C.c_double)]
+
+
+class lt_span(C.Structure):
+    _fields_ = [("name", C.c_char * 32), ("stream", C.c_int32), ("pad", C.c_int32), ("start_ms", C.c_double),
+                ("end_ms", C.c_double)]
 
 
 class lt_region_info(C.Structure):
@@ -159,6 +175,9 @@ _SIGS = [
     ("lt_kernel_get", C.c_int32, [_P, C.c_char_p, C.POINTER(_P)]),
     ("lt_kernel_define", C.c_int32, [_P, C.c_char_p, C.c_char_p, C.POINTER(_P)]),
     ("lt_kernel_tune", C.c_int32, [_P, _P, C.c_int32]),
+    ("lt_kernel_define_source", C.c_int32, [_P, C.c_char_p, C.c_char_p, C.POINTER(lt_param), C.c_int32,
+                                            C.c_char_p, C.POINTER(_P)]),
+    ("lt_rtc_stats_get", C.c_int32, [C.POINTER(lt_rtc_stats)]),
     ("lt_launch", C.c_int32, [_P, _P, C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_int64),
                               C.POINTER(C.c_int64), C.c_char_p, C.POINTER(lt_arg), C.c_int32,
                               C.POINTER(C.c_uint64)]),
@@ -190,6 +209,7 @@ _SIGS = [
     ("lt_profile_enable", C.c_int32, [_P, C.c_int32]),
     ("lt_profile_get", C.c_int32, [_P, C.POINTER(lt_kernel_prof), C.c_int32, C.POINTER(C.c_int32)]),
     ("lt_profile_reset", C.c_int32, [_P]),
+    ("lt_profile_spans", C.c_int32, [_P, C.POINTER(lt_span), C.c_uint64, C.POINTER(C.c_uint64)]),
 ]
 
 for _name, _res, _args in _SIGS:
@@ -386,6 +406,40 @@ class Context:
             self._kernels[key] = k
         return self._kernels[key]
 
+    def define_source(self, name, source, function, params, annotation):
+        """lt_kernel_define_source: a user __device__ function compiled at run
+        time, registered under ``name`` for ``launch``.  ``params``: in order,
+        ``(name, "int")``, ``(name, "float")`` (prefix ``"const "`` to bake
+        the value into the code), or ``(name, numpy dtype, ndim)`` for an
+        array (an optional fourth entry ``"const"`` is rejected by the
+        runtime, as for any array)."""
+        P = (lt_param * max(1, len(params)))()
+        keep = []
+        for i, p in enumerate(params):
+            nm = p[0].encode()
+            keep.append(nm)
+            P[i].name = nm
+            if isinstance(p[1], str):
+                kind = p[1].split()
+                P[i].kind = {"int": LT_ARG_INT, "float": LT_ARG_FLOAT}[kind[-1]]
+                P[i].flags = LT_PARAM_CONST if kind[0] == "const" else 0
+            else:
+                P[i].kind = LT_ARG_ARRAY
+                P[i].dtype = NP2LT[np.dtype(p[1])]
+                P[i].ndim = int(p[2])
+                P[i].flags = LT_PARAM_CONST if len(p) > 3 and p[3] == "const" else 0
+        k = _P()
+        check(self.h, lt_kernel_define_source(self.h, source.encode(), function.encode(), P, len(params),
+                                              annotation.encode(), C.byref(k)))
+        self._kernels[(name, None)] = k
+        return k
+
+    @staticmethod
+    def rtc_stats():
+        s = lt_rtc_stats()
+        check(None, lt_rtc_stats_get(C.byref(s)))
+        return {"compiles": int(s.compiles), "loads": int(s.loads), "compile_seconds": float(s.compile_seconds)}
+
     def tune(self, name, variant, kernel_annotation=None):
         check(self.h, lt_kernel_tune(self.h, self.kernel(name, kernel_annotation), int(variant)))
 
@@ -537,6 +591,17 @@ class Context:
         check(self.h, lt_profile_get(self.h, buf, n.value, C.byref(n)))
         return {buf[i].name.decode(): {"dispatches": int(buf[i].dispatches), "total_ms": buf[i].total_ms,
                                        "max_ms": buf[i].max_ms} for i in range(n.value)}
+
+    def profile_spans(self):
+        """Timed operations since profiling was enabled or reset: a structured
+        array of (name, stream, start_ms, end_ms) on the device clock."""
+        n = C.c_uint64()
+        check(self.h, lt_profile_spans(self.h, None, 0, C.byref(n)))
+        buf = (lt_span * max(1, n.value))()
+        check(self.h, lt_profile_spans(self.h, buf, n.value, C.byref(n)))
+        raw = np.frombuffer(buf, dtype=np.dtype([("name", "S32"), ("stream", np.int32), ("pad", np.int32),
+                                                  ("start_ms", np.float64), ("end_ms", np.float64)]))[:n.value]
+        return raw[["name", "stream", "start_ms", "end_ms"]].copy()
 
     def clear_trace(self):
         check(self.h, lt_trace_clear(self.h))

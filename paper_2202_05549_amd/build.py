@@ -20,7 +20,7 @@ OUT = os.path.join(HERE, "liblt.so")
 BUILD = os.path.join(HERE, "_build")
 ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 
-HOST_SRC = ["annot.cpp", "plan.cpp", "memory.cpp", "exec.cpp", "api.cpp", "serve.cpp"]
+HOST_SRC = ["annot.cpp", "plan.cpp", "memory.cpp", "exec.cpp", "api.cpp", "serve.cpp", "rtc.cpp"]
 HIP_SRC = ["kernels.hip", "gemm.hip", "drain.hip", "reduce.hip"]
 
 HOST_FLAGS = ["-O2", "-g", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",
@@ -60,7 +60,7 @@ def build(verbose: bool = False) -> str:
                 print(o)
     tmp = OUT + ".tmp%d" % os.getpid()
     _run([os.path.join(ROCM, "bin", "hipcc"), "-shared", "-fPIC", "--offload-arch=gfx950", "-o", tmp]
-         + [j[1] for j in jobs] + ["-L" + os.path.join(ROCM, "lib"), "-lamdhip64",
+         + [j[1] for j in jobs] + ["-L" + os.path.join(ROCM, "lib"), "-lamdhip64", "-lhiprtc",
                                    "-Wl,-rpath," + os.path.join(ROCM, "lib")])
     os.replace(tmp, OUT)
     return OUT

@@ -363,7 +363,10 @@ struct Parser {
 lt_status compile_annotation(Ctx *ctx, const KernelDef *def, const char *text,
                              std::shared_ptr<Annotation> *out) {
     if (!text) return set_err(ctx, LT_ERR_INVALID, "annotation is NULL");
-    std::string key = std::string(def->name) + "\x1f" + text;
+    // definitions are told apart by address (user kernels may share names)
+    char tag[32];
+    snprintf(tag, sizeof tag, "%p\x1f", (const void *)def);
+    std::string key = std::string(tag) + text;
     auto it = ctx->annot_cache.find(key);
     if (it != ctx->annot_cache.end()) {
         *out = it->second;

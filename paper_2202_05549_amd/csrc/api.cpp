@@ -199,6 +199,7 @@ void ctx_release_all(Ctx *ctx) {
             if (ctx->streams[s].h) (void)hipStreamDestroy(ctx->streams[s].h);
         for (hipEvent_t e : ctx->event_pool) (void)hipEventDestroy(e);
         for (hipEvent_t e : ctx->prof_pool) (void)hipEventDestroy(e);
+        if (ctx->prof_base) (void)hipEventDestroy(ctx->prof_base);
         if (ctx->arena_owned && ctx->arena_base) (void)hipFree(ctx->arena_base);
         for (void *p : ctx->host_allocs) (void)hipHostFree(p);
         for (void *p : ctx->staging_free) (void)hipHostFree(p);
@@ -696,6 +697,19 @@ lt_status lt_kernel_define(lt_context *ctx, const char *base, const char *annota
     return LT_OK;
 }
 
+lt_status lt_kernel_define_source(lt_context *ctx, const char *source, const char *function,
+                                  const lt_param *params, int32_t nparams, const char *annotation,
+                                  lt_kernel **out) {
+    if (!ctx || !out) return LT_ERR_INVALID;
+    return rtc_define(ctx, source, function, params, nparams, annotation, out);
+}
+
+lt_status lt_rtc_stats_get(lt_rtc_stats *out) {
+    if (!out) return LT_ERR_INVALID;
+    rtc_counters(&out->compiles, &out->loads, &out->compile_seconds);
+    return LT_OK;
+}
+
 lt_status lt_kernel_tune(lt_context *ctx, lt_kernel *k, int32_t variant) {
     if (!ctx || !k) return LT_ERR_INVALID;
     k->variant = variant;
@@ -884,10 +898,36 @@ lt_status lt_trace_get(lt_context *ctx, lt_trace_rec *out, uint64_t cap, uint64_
     return LT_OK;
 }
 
+// The origin of the spans: an event recorded now on compute stream 0.
+static lt_status prof_mark_base(Ctx *ctx) {
+    ctx->prof_spans.clear();
+    if (ctx->dry || !ctx->prof) return LT_OK;
+    if (!ctx->prof_base) {
+        hipError_t r = hipEventCreate(&ctx->prof_base);
+        if (r != hipSuccess) {
+            ctx->prof_base = nullptr;
+            return hip_fail(ctx, r, "hipEventCreate(profile base)");
+        }
+    }
+    hipError_t r = hipEventRecord(ctx->prof_base, ctx->streams[0].h);
+    if (r != hipSuccess) return hip_fail(ctx, r, "hipEventRecord(profile base)");
+    return LT_OK;
+}
+
 lt_status lt_profile_enable(lt_context *ctx, int32_t on) {
     if (!ctx || on < 0) return LT_ERR_INVALID;
+    const bool was = ctx->prof != 0;
     ctx->prof = on;
     ctx->prof_seen.clear();
+    if (on && !was) return prof_mark_base(ctx);
+    return LT_OK;
+}
+
+lt_status lt_profile_spans(lt_context *ctx, lt_span *out, uint64_t cap, uint64_t *n) {
+    if (!ctx || !n) return LT_ERR_INVALID;
+    *n = ctx->prof_spans.size();
+    if (out)
+        for (uint64_t i = 0; i < *n && i < cap; ++i) out[i] = ctx->prof_spans[i];
     return LT_OK;
 }
 
@@ -906,7 +946,7 @@ lt_status lt_profile_reset(lt_context *ctx) {
     if (!ctx) return LT_ERR_INVALID;
     ctx->prof_acc.clear();
     ctx->prof_seen.clear();
-    return LT_OK;
+    return prof_mark_base(ctx);
 }
 
 lt_status lt_trace_clear(lt_context *ctx) {

@@ -220,7 +220,7 @@ lt_status prof_end(Ctx *ctx, int s, const char *name, hipEvent_t a) {
     hipEvent_t b = prof_event(ctx);
     hipError_t r = hipEventRecord(b, ctx->streams[s].h);
     if (r != hipSuccess) return hip_fail(ctx, r, "hipEventRecord(profile)");
-    ctx->prof_pending.push_back({name, a, b});
+    ctx->prof_pending.push_back({name, a, b, s});
     return LT_OK;
 }
 
@@ -233,6 +233,17 @@ void prof_collect(Ctx *ctx) {
             k.dispatches++;
             k.total_ms += ms;
             if (ms > k.max_ms) k.max_ms = ms;
+            float t0 = 0.f;
+            if (ctx->prof_base && ctx->prof_spans.size() < ((size_t)1 << 22) &&
+                hipEventElapsedTime(&t0, ctx->prof_base, p.a) == hipSuccess) {
+                lt_span sp;
+                memset(&sp, 0, sizeof sp);
+                snprintf(sp.name, sizeof sp.name, "%s", p.name);
+                sp.stream = p.stream;
+                sp.start_ms = t0;
+                sp.end_ms = (double)t0 + ms;
+                ctx->prof_spans.push_back(sp);
+            }
         }
         ctx->prof_pool.push_back(p.a);
         ctx->prof_pool.push_back(p.b);
@@ -249,7 +260,10 @@ static lt_status dispatch(Ctx *ctx, const KernelDef *def, KLaunch &kl, int s) {
     lt_status st = prof_begin(ctx, s, def->name, &pa);
     if (st) return st;
     hipError_t r = def->fn(kl);
-    if (r != hipSuccess) return hip_fail(ctx, r, def->name);
+    if (r != hipSuccess) {
+        if (const char *m = rtc_last_error(def)) return set_err(ctx, LT_ERR_DEVICE, "%s", m);
+        return hip_fail(ctx, r, def->name);
+    }
     return prof_end(ctx, s, def->name, pa);
 }
 
@@ -1692,6 +1706,9 @@ lt_status launch(Ctx *ctx, lt_kernel *k, int nd, const int64_t *grid,
         total *= nsb[a];
     }
     if (total > ((int64_t)1 << 22)) return set_err(ctx, LT_ERR_INVALID, "too many superblocks (%lld)", (long long)total);
+    if (def->user && B[0] * B[1] * B[2] > 1024)
+        return set_err(ctx, LT_ERR_INVALID, "%s: a block of %lld threads is more than 1024", def->name,
+                       (long long)(B[0] * B[1] * B[2]));
     // combined access per array parameter
     Mode pmode[MAXPARAM];
     ROp pop[MAXPARAM];
@@ -1808,6 +1825,7 @@ lt_status launch(Ctx *ctx, lt_kernel *k, int nd, const int64_t *grid,
     }
     for (int a = 0; a < MAXD; ++a) proto.block[a] = B[a];
     proto.variant = k->variant;
+    proto.user = def->user;
     for (int p = 0; p < def->nparam && p < KMAXP; ++p)
         if (pany[p] && pmode[p] == M_REDUCE) proto.rop[p] = (int32_t)pop[p];
     for (auto &P : parts) {

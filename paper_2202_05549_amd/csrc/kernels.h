@@ -48,6 +48,7 @@ struct KLaunch {
     int64_t block[KMAXD];    // logical block shape of the launch
     int variant;             // tuning variant (0 = default)
     int32_t rop[KMAXP];      // reduce(f) operator per parameter (ROp: 0 +, 1 *, 2 min, 3 max)
+    const void *user;        // runtime-compiled kernels: their definition
 };
 
 typedef hipError_t (*KernelFn)(const KLaunch &);
@@ -62,6 +63,8 @@ hipError_t launch_kmeans_assign_f32(const KLaunch &);
 hipError_t launch_rowreduce_f32(const KLaunch &);
 hipError_t launch_kmeans_update_f32(const KLaunch &);
 hipError_t launch_kmeans_centres_f32(const KLaunch &);
+// Runtime-compiled user kernels (rtc.cpp).
+hipError_t launch_rtc(const KLaunch &);
 
 // k-means update: points per workgroup tile and the largest number of
 // workgroups (= partial slots) per task.  A task of p points gets

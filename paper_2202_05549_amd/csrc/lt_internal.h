@@ -138,6 +138,18 @@ struct KernelDef {
     // partial slots per task of a reduce parameter (nullptr = 1): a body that
     // folds floats over several workgroups writes one partial per workgroup
     int64_t (*slots)(const int64_t *lo, const int64_t *hi, const int64_t *iarg);
+    void *user = nullptr;   // the RtcKernel of a runtime-compiled user kernel
+};
+
+// A user kernel compiled at run time (csrc/rtc.cpp): its definition, the
+// owned strings the definition points to, and its source.
+struct RtcKernel {
+    KernelDef def{};
+    std::vector<std::string> names;
+    std::string source, function;
+    std::string source_key;           // source hash, function, parameter signature
+    bool is_const[MAXPARAM] = {false};
+    std::string last_error;           // compile/load/launch failure of the last dispatch
 };
 
 const KernelDef *find_builtin(const char *name);
@@ -427,6 +439,7 @@ struct lt_context {
     uint64_t next_launch_id = 1;
     std::vector<lt::Array *> arrays;
     std::vector<std::unique_ptr<lt_kernel>> kernels;
+    std::vector<std::unique_ptr<lt::RtcKernel>> rtc_kernels;
     std::unordered_map<std::string, std::shared_ptr<lt::Annotation>> annot_cache;
 
     // planner records (kept until lt_sync)
@@ -462,9 +475,12 @@ struct lt_context {
     struct ProfPending {
         const char *name;
         hipEvent_t a, b;
+        int stream;
     };
     std::vector<ProfPending> prof_pending;
     std::map<std::string, lt_kernel_prof> prof_acc;
+    hipEvent_t prof_base = nullptr;    // time origin of the spans (recorded at enable / reset)
+    std::vector<lt_span> prof_spans;   // every timed operation since, on the device clock
     std::vector<hipEvent_t> prof_pool;
     std::vector<void *> host_allocs;
 };
@@ -502,6 +518,10 @@ lt_status flush_group(Ctx *ctx);
 lt_status batch_flush(Ctx *ctx);
 lt_status batch_flush_noalloc(Ctx *ctx);
 void fold_drain_status(Ctx *ctx);
+lt_status rtc_define(Ctx *ctx, const char *source, const char *function, const lt_param *params, int32_t nparams,
+                     const char *annotation, lt_kernel **out);
+const char *rtc_last_error(const KernelDef *def);
+void rtc_counters(uint64_t *compiles, uint64_t *loads, double *compile_s);
 // Releases the pins of the queued tasks and empties the batch (it stays
 // open if it was).
 void batch_drop(Ctx *ctx);

@@ -325,6 +325,13 @@ lt_status copy_box(Ctx *ctx, int stream, char *dst, const int64_t *ds,
     }
     hipStream_t h = ctx->streams[stream].h;
     hipError_t r = hipSuccess;
+    // with profiling on, copies over the host link are timed like kernels
+    const char *pname = tk == 1 ? "copy_h2d" : tk == 2 ? "copy_d2h" : nullptr;
+    hipEvent_t pa = nullptr;
+    if (pname) {
+        lt_status st = prof_begin(ctx, stream, pname, &pa);
+        if (st) return st;
+    }
     if (n == 1) {
         r = hipMemcpyAsync(dst, src, e[0] * esz, kind, h);
     } else if (n == 2) {
@@ -335,7 +342,7 @@ lt_status copy_box(Ctx *ctx, int stream, char *dst, const int64_t *ds,
                                  s[1] * esz, e[2] * esz, e[1], kind, h);
     }
     if (r != hipSuccess) return hip_fail(ctx, r, "hipMemcpyAsync");
-    return LT_OK;
+    return pname ? prof_end(ctx, stream, pname, pa) : LT_OK;
 }
 
 // ------------------------------------------------------------------- arena
@@ -568,14 +575,26 @@ lt_status write_back(Ctx *ctx, Chunk *c, uint64_t *seq) {
     if (st) return st;
     const Array *arr = c->arr;
     const Box &part = arr->host_backed ? c->core : c->box;
-    if (c->host_owned && !ctx->dry && c->bytes >= ((int64_t)1 << 20) &&
+    hipEvent_t pa = nullptr;
+    const bool by_kernel = c->host_owned && !ctx->dry && c->bytes >= ((int64_t)1 << 20);
+    if (by_kernel) {
+        st = prof_begin(ctx, ctx->d2h, "copy_d2h", &pa);
+        if (st) return st;
+    }
+    if (by_kernel &&
         launch_copy_linear(ctx->streams[ctx->d2h].h, c->host_ptr, dev_ptr(ctx, c), c->bytes) == hipSuccess) {
         // a spill buffer (pinned by the runtime, so kernels can write it)
         // holds the whole box with the device layout: one linear copy, done
         // by a copy kernel
         ctx->stats.bytes_d2h += (uint64_t)c->bytes;
         ctx->stats.copies_d2h++;
+        st = prof_end(ctx, ctx->d2h, "copy_d2h", pa);
+        if (st) return st;
     } else {
+        if (pa) {
+            // the copy kernel could not take it: the timing goes to copy_box
+            ctx->prof_pool.push_back(pa);
+        }
         st = copy_sub(ctx, ctx->d2h, c->host_ptr, c->box.lo, c->host_stride, dev_ptr(ctx, c), c->box.lo,
                       c->dev_stride, part, arr->ndim, arr->esz, hipMemcpyDeviceToHost);
         if (st) return st;

@@ -50,3 +50,24 @@ def test_traffic_at_least_algorithmic():
     # dispatch and 2^22 per update dispatch (plus 1024 partial slots)
     assert b.TRAFFIC["k_kmeans"]["bytes_per_dispatch"] >= (1 << 26) * 68
     assert b.TRAFFIC["k_kmeans_update"]["bytes_per_dispatch"] >= (1 << 22) * 68 + 1024 * (64 * 16 * 8 + 64 * 4)
+
+
+def test_copy_overlap_measures_copy_time_under_kernels():
+    import numpy as np
+
+    b = _bench_module()
+    dt = [("name", "S32"), ("stream", np.int32), ("start_ms", np.float64), ("end_ms", np.float64)]
+    # H2D copies [0, 10] and [12, 20] (18 ms in flight), kernels [5, 15] and
+    # [14, 16] (merged: [5, 16]); D2H [14, 18]
+    sp = np.array([(b"copy_h2d", 4, 0.0, 10.0), (b"copy_h2d", 4, 12.0, 20.0), (b"k", 0, 5.0, 15.0),
+                   (b"k", 1, 14.0, 16.0), (b"copy_d2h", 5, 14.0, 18.0)], dtype=dt)
+    o = b.copy_overlap(sp)
+    assert o["kernel_busy_ms"] == 11.0
+    assert o["h2d"]["copies"] == 2 and o["h2d"]["busy_ms"] == 18.0
+    assert abs(o["h2d"]["overlap_frac"] - 9.0 / 18.0) < 1e-12   # [5, 10] and [12, 16]
+    assert abs(o["d2h"]["overlap_frac"] - 2.0 / 4.0) < 1e-12    # [14, 16]
+    # overlapping copies of one direction count once
+    sp2 = np.array([(b"copy_h2d", 4, 0.0, 4.0), (b"copy_h2d", 4, 2.0, 6.0), (b"k", 0, 0.0, 6.0)], dtype=dt)
+    o2 = b.copy_overlap(sp2)
+    assert o2["h2d"]["busy_ms"] == 6.0 and o2["h2d"]["overlap_frac"] == 1.0
+    assert o2["d2h"]["overlap_frac"] is None
