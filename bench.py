@@ -119,6 +119,16 @@ KMU_SOURCES = [("reduce.hip", "// ==============================================
                 "// ========================================================= k-means centres"),
                ("kernels.h", "// k-means update: points per workgroup tile", "// Runtime helpers.")]
 
+# the code of k_drain on the 1-D mix: the drain loop and its launcher, the
+# 1-D stencil and histogram bodies it runs, and the task record
+DRAIN_SOURCES = [("drain.hip", "#include <hip/hip_runtime.h>", "// Device scratch of the no-allocation batch issue"),
+                 ("bodies.h", "// -------------------------------------------------------------- stencil1d",
+                  "// ---------------------------------------------------------------- jacobi2d"),
+                 ("bodies.h", "// ---------------------------------------------------------------- hist256",
+                  "}  // namespace body"),
+                 ("kernels.h", "// ------------------------------------------------------------ batched path",
+                  "hipError_t launch_drain(")]
+
 TRAFFIC = {
     # k_jacobi2d_stack<4>, one 16384 x 16384 sweep per dispatch: FETCH_SIZE
     # 528,412 KiB x 2.000 (the 1 GiB copy reads 524,309 KiB) + WRITE_SIZE
@@ -140,6 +150,12 @@ TRAFFIC = {
     # partial slots of 64 x 16 float64 sums and 64 counts)
     "k_kmeans_update": {"sources": KMU_SOURCES, "digest": "d98381726987eb27",
                         "bytes_per_dispatch": 139300 * 1024 * 2.000 + 8448 * 1024},
+    # k_drain<27, 4>, one dispatch per step of the 8192-launch mix at
+    # superblock 2^24, 1024 workgroups (graph replay): FETCH_SIZE 27,025,249
+    # KiB x 2.000 + WRITE_SIZE 27,225,629 KiB x 1.000 = 83.23 GB, against
+    # 83.0 GB of algorithmic bytes
+    "k_drain": {"sources": DRAIN_SOURCES, "digest": "0a995e9484e40093",
+                "bytes_per_dispatch": 27025249 * 1024 * 2.000 + 27225629 * 1024},
 }
 
 
@@ -176,11 +192,16 @@ def copy_overlap(spans):
     """Copy/compute overlap from the library's device-clock spans: per
     direction, the time some copy of that direction is in flight (union of
     its spans), and the share of it during which some kernel also runs,
-    (copy time AND kernel time) / copy time."""
+    (copy time AND kernel time) / copy time; and the share of kernel time
+    during which some copy runs (for a link-bound pass, the compute hidden
+    under the copies)."""
     names = spans["name"]
     iv = np.stack([spans["start_ms"], spans["end_ms"]], axis=1) if len(spans) else np.zeros((0, 2))
-    kern = _union(iv[(names != b"copy_h2d") & (names != b"copy_d2h")])
-    out = {"kernel_busy_ms": round(float((kern[:, 1] - kern[:, 0]).sum()) if len(kern) else 0.0, 3)}
+    is_copy = (names == b"copy_h2d") | (names == b"copy_d2h")
+    kern = _union(iv[~is_copy])
+    kbusy = float((kern[:, 1] - kern[:, 0]).sum()) if len(kern) else 0.0
+    out = {"kernel_busy_ms": round(kbusy, 3),
+           "kernel_under_copy_frac": round(_meet(kern, _union(iv[is_copy])) / kbusy, 4) if kbusy > 0 else None}
     for d in ("h2d", "d2h"):
         u = _union(iv[names == ("copy_" + d).encode()])
         busy = float((u[:, 1] - u[:, 0]).sum()) if len(u) else 0.0
@@ -721,16 +742,24 @@ def bench_batch(args, L, torch):
             times.append(dt)
         return dt
 
-    log("autotuning superblock size, drain width, flush size and vector groups on the full mix")
-    best = autotune.tune("batch8192", {"sb": [1 << 18, 1 << 20, 1 << 22, 1 << 24], "wg": [1024, 2048],
-                                       "flush": [0, 4096], "vec": [2, 4]},
-                         lambda sb, wg, flush, vec: run("batched", sb, wg, flush, vec=vec), reps=1, cache=None,
-                         log=log)
-    log("tuned: %s" % best)
-    best_plain = autotune.tune("batch8192_plain", {"sb": [1 << 18, 1 << 20, 1 << 22, 1 << 24]},
-                               lambda sb: run("plain", sb), reps=1, cache=None, log=log)
-    log("tuned plain: %s" % best_plain)
-    for mode in ("plain", "batched", "graph"):
+    if args.tuned:
+        # fixed parameters instead of the sweep (counter runs of one configuration)
+        sb, wg, flush, vec = (int(v) for v in args.tuned.split(":"))
+        best = {"sb": sb, "wg": wg, "flush": flush, "vec": vec}
+        best_plain = {"sb": sb}
+        log("fixed parameters: %s" % best)
+    else:
+        log("autotuning superblock size, drain width, flush size and vector groups on the full mix")
+        best = autotune.tune("batch8192", {"sb": [1 << 18, 1 << 20, 1 << 22, 1 << 24], "wg": [1024, 2048],
+                                           "flush": [0, 4096], "vec": [2, 4]},
+                             lambda sb, wg, flush, vec: run("batched", sb, wg, flush, vec=vec), reps=1,
+                             cache=None, log=log)
+        log("tuned: %s" % best)
+        best_plain = autotune.tune("batch8192_plain", {"sb": [1 << 18, 1 << 20, 1 << 22, 1 << 24]},
+                                   lambda sb: run("plain", sb), reps=1, cache=None, log=log)
+        log("tuned plain: %s" % best_plain)
+    modes = ("batched", "graph") if args.executor == "drain" else ("plain", "batched", "graph")
+    for mode in modes:
         graph = None
         if mode == "graph":
             ctx.configure(drain_workgroups=best["wg"], batch_flush_tasks=0, drain_vectors=best["vec"])
@@ -756,6 +785,8 @@ def bench_batch(args, L, torch):
         outs = [arrs[i][0].read() for i in sample]
         if mode == "plain":
             sample_out["plain"] = outs
+        elif "plain" not in sample_out:
+            sample_out[mode] = None
         else:
             same = all(np.array_equal(a, b) for a, b in zip(outs, sample_out["plain"]))
             sample_out[mode] = same
@@ -788,13 +819,16 @@ def bench_batch(args, L, torch):
                  "hbm_frac": round(m["gbs"] / HBM_PEAK_GBS, 4),
                  "roofline": {"bound": "hbm", "achieved": round(m.get("kernel_gbs", float("nan")), 2),
                               "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                              "frac": round(m.get("kernel_gbs", float("nan")) / HBM_PEAK_GBS, 4), "traffic": None,
+                              "frac": round(m.get("kernel_gbs", float("nan")) / HBM_PEAK_GBS, 4),
+                              # counters were taken on one drain per step at superblock 2^24
+                              "traffic": (traffic_for("k_drain") if ex == "graph" and best["sb"] == 1 << 24
+                                          and best["wg"] == 1024 and best["vec"] == 4 else None),
                               "kernel": "k_drain", "kernel_ms_per_step": round(m.get("drain_ms", float("nan")), 3)},
-                 "plain": {k: round(v, 3) for k, v in res["plain"].items()},
+                 "plain": {k: round(v, 3) for k, v in res["plain"].items()} if "plain" in res else None,
                  "batched": {k: round(v, 3) for k, v in res["batched"].items()},
                  "graph": {k: round(v, 3) for k, v in res["graph"].items()},
-                 "batched_over_plain": round(res["batched"]["gbs"] / res["plain"]["gbs"], 3),
-                 "graph_over_plain": round(res["graph"]["gbs"] / res["plain"]["gbs"], 3),
+                 "batched_over_plain": round(res["batched"]["gbs"] / res["plain"]["gbs"], 3) if "plain" in res else None,
+                 "graph_over_plain": round(res["graph"]["gbs"] / res["plain"]["gbs"], 3) if "plain" in res else None,
                  "sample_check": {"launches": len(sample),
                                   "elements": int(ns[sample].sum()),
                                   "batched_equals_plain": sample_out["batched"],
@@ -972,6 +1006,8 @@ def bench_kmeans(args, L, torch):
         x.write(X)
         del X
         ctx.sync()
+        if args.kmu_variant:
+            ctx.tune("kmeans_update_f32", args.kmu_variant)
 
         def step():
             cen.write(cen0)
@@ -1150,7 +1186,7 @@ def bench_kmeans_ooc(args, L, torch):
 def bench_serve(args, L, torch):
     from paper_2202_05549_amd import serve
 
-    return serve.bench(args, L, torch, log)
+    return serve.bench(args, L, torch, log, overlap=copy_overlap)
 
 
 def main():
@@ -1169,11 +1205,20 @@ def main():
     ap.add_argument("--rows", type=int, default=0,
                     help="Jacobi tile variant (lt_kernel_tune: 8/16/32, 132/164/228, 302/304/308; 0 = default)")
     ap.add_argument("--executor", choices=["all", "grouped", "drain", "plain"], default="all",
-                    help="jacobi: executors to run (all = grouped, drain and plain)")
+                    help="jacobi: executors to run (all = grouped, drain and plain); batch: drain = the "
+                         "batched and graph legs only")
     ap.add_argument("--compute-streams", type=int, default=0,
                     help="gemm_ooc: compute streams of the context (0 = 1)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one 1 GiB float32 device copy first (the reference kernel for HBM counter scaling)")
+    ap.add_argument("--kmu-variant", type=int, default=0,
+                    help="kmeans: centre-update body (lt_kernel_tune: 2 = two features per lane)")
+    ap.add_argument("--d2h-kernel", type=int, default=-1,
+                    help="serve: write-backs into pinned homes through a copy kernel (1) or the copy engine (0); "
+                         "-1 = the copy kernel for --serve-full (pageable inputs keep the copy engines busy), "
+                         "the copy engine otherwise")
+    ap.add_argument("--tuned", default="",
+                    help="batch: fixed SB:WG:FLUSH:VEC instead of the autotuning sweep")
     ap.add_argument("--serve-full", action="store_true",
                     help="serving trace at the full size ranges (GEMM to 65536, k-means to 1e9 points)")
     args = ap.parse_args()

@@ -134,7 +134,14 @@ typedef struct lt_config {
                                        Changes traffic only, never results.   */
     int32_t sb_band;                /* LT_ORDER_BANDS: rows of superblocks per
                                        band, >= 0; 0 = 2                      */
-    int32_t reserved[1];
+    int32_t d2h_kernel;             /* write-backs into pinned home buffers of
+                                       host-backed arrays: 0 (default) with the
+                                       copy engine (hipMemcpy*Async), 1 with a
+                                       copy kernel over the host link (it takes
+                                       compute units, but does not queue behind
+                                       other copy-engine work).  Pageable homes
+                                       always use the copy engine.  Changes
+                                       speed only.                            */
     uint64_t host_budget_bytes;     /* cap on the pinned host memory of spill
                                        buffers (chunks of device-home arrays
                                        evicted from the device); beyond it the
@@ -145,6 +152,12 @@ typedef struct lt_config {
                                        $TMPDIR or /tmp.  The file is unlinked
                                        at creation and vanishes with the
                                        context.                                 */
+    int64_t drain_tile;             /* batch drain: elements of a 1-D stencil or
+                                       histogram task per ticket, a multiple of
+                                       4096 (0 = 65536).  Larger tiles take
+                                       fewer tickets; a task's tiles interleave
+                                       its 4096-element groups.  Changes speed
+                                       only, never results.                   */
 } lt_config;
 
 #define LT_ORDER_ROWMAJOR 0
@@ -486,10 +499,11 @@ lt_status lt_graph_destroy(lt_context *ctx, lt_graph *g);
 
 /* ------------------------------------------------------------------ serving
  * A request loop with continuous batching on one context.  Requests are
- * queued by lt_server_submit and admitted in arrival order as soon as an
- * active slot is free and their device footprint fits next to the admitted
- * ones (a request larger than the budget is admitted alone and runs out of
- * core through the memory manager).  An admitted request's launches are
+ * queued by lt_server_submit and admitted in arrival order (or, with a
+ * lookahead, cached datasets first) as soon as an active slot is free and
+ * their device footprint fits next to the admitted ones (a request larger
+ * than the budget is admitted alone and runs out of core through the memory
+ * manager).  An admitted request's launches are
  * issued at once, so the work of all admitted requests overlaps on the
  * device.  Inputs are host-backed arrays over the caller's buffers, cached
  * per (kind, dataset, size): a later request on the same dataset finds its
@@ -520,7 +534,15 @@ typedef struct lt_server_config {
     int64_t chunk_rows;        /* row chunk / superblock for Jacobi and
                                   k-means (0 = 512 rows / 2^20 points)        */
     int64_t gemm_tile;         /* GEMM superblock edge (0 = 4096)            */
-    int32_t reserved[4];
+    int32_t lookahead;         /* 0: admit in arrival order.  k > 0: when a
+                                  slot frees, the oldest of the first k queued
+                                  requests whose dataset is already cached
+                                  goes first (its inputs may still be in HBM),
+                                  else the oldest that fits; a request passed
+                                  over max_bypass times blocks admission
+                                  until it is admitted                       */
+    int32_t max_bypass;        /* with lookahead: 0 = 4 * lookahead          */
+    int32_t reserved[2];
 } lt_server_config;
 
 typedef struct lt_request {

@@ -51,9 +51,9 @@ class lt_config(C.Structure):
                 ("stage_threshold_bytes", C.c_uint64), ("device_arena", C.c_void_p),
                 ("arena_bytes", C.c_uint64), ("trace", C.c_int32), ("sb_order", C.c_int32),
                 ("drain_workgroups", C.c_int32), ("batch_flush_tasks", C.c_int32), ("drain_vectors", C.c_int32),
-                ("evict_policy", C.c_int32), ("sb_band", C.c_int32), ("reserved", C.c_int32 * 1),
+                ("evict_policy", C.c_int32), ("sb_band", C.c_int32), ("d2h_kernel", C.c_int32),
                 ("host_budget_bytes", C.c_uint64),
-                ("spill_dir", C.c_char_p)]
+                ("spill_dir", C.c_char_p), ("drain_tile", C.c_int64)]
 
 
 class lt_box(C.Structure):
@@ -117,7 +117,8 @@ class lt_kernel_prof(C.Structure):
 
 class lt_server_config(C.Structure):
     _fields_ = [("max_active", C.c_int32), ("keep_resident", C.c_int32), ("admit_bytes", C.c_uint64),
-                ("chunk_rows", C.c_int64), ("gemm_tile", C.c_int64), ("reserved", C.c_int32 * 4)]
+                ("chunk_rows", C.c_int64), ("gemm_tile", C.c_int64), ("lookahead", C.c_int32),
+                ("max_bypass", C.c_int32), ("reserved", C.c_int32 * 2)]
 
 
 class lt_request(C.Structure):
@@ -341,8 +342,8 @@ class Context:
 
     def configure(self, **cfg):
         """Change tunable fields (exec_mode, stage_threshold_bytes, sb_order,
-        sb_band, drain_workgroups, batch_flush_tasks, drain_vectors, evict_policy,
-        trace) of the live context."""
+        sb_band, drain_workgroups, batch_flush_tasks, drain_vectors, drain_tile,
+        evict_policy, trace) of the live context."""
         self._check_keys(cfg)
         for k, v in cfg.items():
             setattr(self.cfg, k, v)

@@ -29,7 +29,7 @@ static const KernelDef kBuiltins[] = {
      2, launch_gemm_f32, 8, -1},
     {"hist256_i32", "global i => read v[i], reduce(+) h[:]", 3,
      {{"n", P_INT, LT_I32, 0}, {"h", P_ARRAY, LT_I32, 1}, {"v", P_ARRAY, LT_I32, 1}}, 1,
-     launch_hist256_i32, 1, DK_HIST256},
+     launch_hist256_i32, 1, DK_HIST256, hist_slots, true},
     {"kmeans_assign_f32", "global i => read X[i, :], read Cen[:, :], write lab[i]", 6,
      {{"N", P_INT, LT_F32, 0},
       {"d", P_INT, LT_F32, 0},
@@ -49,7 +49,7 @@ static const KernelDef kBuiltins[] = {
       {"counts", P_ARRAY, LT_I32, 1},
       {"X", P_ARRAY, LT_F32, 2},
       {"lab", P_ARRAY, LT_I32, 1}},
-     1, launch_kmeans_update_f32, 1, -1, kmeans_update_slots},
+     1, launch_kmeans_update_f32, 1, -1, kmeans_update_slots, true},
     {"kmeans_centres_f32", "global [k, j] => read sums[k, j], read counts[k], readwrite Cen[k, j]", 5,
      {{"K", P_INT, LT_F32, 0},
       {"d", P_INT, LT_F32, 0},
@@ -483,6 +483,10 @@ lt_status lt_context_create(const lt_config *cfg_in, lt_context **out) {
         g_create_err = "drain_vectors must be 0, 2 or 4";
         return LT_ERR_INVALID;
     }
+    if (cfg.drain_tile < 0 || cfg.drain_tile % 4096 != 0) {
+        g_create_err = "drain_tile must be 0 or a positive multiple of 4096";
+        return LT_ERR_INVALID;
+    }
     if (cfg.evict_policy != LT_EVICT_NEXT_USE && cfg.evict_policy != LT_EVICT_LRU) {
         g_create_err = "evict_policy must be LT_EVICT_NEXT_USE or LT_EVICT_LRU";
         return LT_ERR_INVALID;
@@ -548,6 +552,8 @@ lt_status lt_context_configure(lt_context *ctx, const lt_config *cfg) {
         return set_err(ctx, LT_ERR_INVALID, "unknown exec_mode %d", cfg->exec_mode);
     if (cfg->drain_vectors != 0 && cfg->drain_vectors != 2 && cfg->drain_vectors != 4)
         return set_err(ctx, LT_ERR_INVALID, "drain_vectors must be 0, 2 or 4");
+    if (cfg->drain_tile < 0 || cfg->drain_tile % 4096 != 0)
+        return set_err(ctx, LT_ERR_INVALID, "drain_tile must be 0 or a positive multiple of 4096");
     if (cfg->evict_policy != LT_EVICT_NEXT_USE && cfg->evict_policy != LT_EVICT_LRU)
         return set_err(ctx, LT_ERR_INVALID, "evict_policy must be LT_EVICT_NEXT_USE or LT_EVICT_LRU");
     if (cfg->sb_order < LT_ORDER_ROWMAJOR || cfg->sb_order > LT_ORDER_BANDS || cfg->sb_band < 0)
@@ -562,6 +568,7 @@ lt_status lt_context_configure(lt_context *ctx, const lt_config *cfg) {
     ctx->cfg.drain_workgroups = cfg->drain_workgroups;
     ctx->cfg.batch_flush_tasks = cfg->batch_flush_tasks;
     ctx->cfg.drain_vectors = cfg->drain_vectors;
+    ctx->cfg.drain_tile = cfg->drain_tile;
     ctx->cfg.evict_policy = cfg->evict_policy;
     ctx->cfg.trace = cfg->trace;
     return LT_OK;
@@ -595,6 +602,15 @@ static lt_status create_common(lt_context *ctx, lt_dtype dtype, int32_t ndim, co
     }
     arr->host_backed = host_ptr != nullptr;
     arr->host_base = (char *)host_ptr;
+    if (host_ptr && !ctx->dry) {
+        // pinned memory that kernels reach at the same address (lt_host_alloc,
+        // hipHostMalloc) can take copy kernels; pageable memory cannot
+        hipPointerAttribute_t at;
+        if (hipPointerGetAttributes(&at, host_ptr) == hipSuccess)
+            arr->home_pinned = at.type == hipMemoryTypeHost && at.devicePointer == host_ptr;
+        else
+            (void)hipGetLastError();  // pageable: the query's error is not the caller's
+    }
     lt_status st = make_chunks(ctx, arr, dist);
     if (st) {
         for (Chunk *c : arr->chunks) delete c;

@@ -196,6 +196,41 @@ __device__ __forceinline__ void stencil_stream(int64_t xb, int64_t yb, int64_t n
     for (; g < s1; g += 1024) stencil_span(xb, yb, n, lo, hi, g);
 }
 
+// Outputs of the task [lo, hi) in the groups of G spans of 1024 that start at
+// g0, g0 + stride, g0 + 2 stride, ... (stride a multiple of G * 1024).  The
+// batch drain gives tile j of a task with T tiles the groups j, j + T, ...:
+// tiles handed out together then work on neighbouring groups, so the
+// workgroups in flight stream through one region of memory instead of T
+// separate ones.  Pipelined like stencil_stream; a ragged last group goes
+// span by span.
+template <int G>
+__device__ __forceinline__ void stencil_strided(int64_t xb, int64_t yb, int64_t n, int64_t lo, int64_t hi,
+                                                int64_t g0, int64_t stride) {
+    constexpr int64_t GS = (int64_t)G * 1024;
+    const int64_t end = hi < n ? hi : n;
+    const bool aligned = ((xb + lo * 4) & 15) == 0 && ((yb + lo * 4) & 15) == 0 && ((g0 - lo) & 3) == 0;
+    int64_t g = g0;
+    if (aligned && g + GS <= end) {
+        const LT_GLOBAL float *X = gp<const float>(xb);
+        LT_GLOBAL float *Y = gp<float>(yb);
+        const int lane = threadIdx.x & (WAVE - 1);
+        StGroup<G> cur;
+        st_load<G>(X, n, g, lane, cur);
+        for (;;) {
+            const int64_t gn = g + stride;
+            const bool more = gn + GS <= end;
+            StGroup<G> nxt;
+            if (more) st_load<G>(X, n, gn, lane, nxt);
+            st_store<G>(Y, g, lane, cur);
+            g = gn;
+            if (!more) break;
+            cur = nxt;
+        }
+    }
+    for (; g < end; g += stride)
+        for (int64_t s = g; s < g + GS && s < end; s += 1024) stencil_span(xb, yb, n, lo, hi, s);
+}
+
 // ---------------------------------------------------------------- jacobi2d
 // y[r][c] = 0.25*((x[r-1][c] + x[r+1][c]) + (x[r][c-1] + x[r][c+1])), zero
 // outside the n x m field.

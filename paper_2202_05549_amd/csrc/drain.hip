@@ -31,10 +31,9 @@ __device__ __forceinline__ void run_tile(const DTask &t, int64_t local, int *sh)
         }
         case DK_STENCIL1D: {
             if constexpr (!(KINDS & (1u << DK_STENCIL1D))) break;
-            const int64_t end = t.hi0 < t.n ? t.hi0 : t.n;
-            const int64_t s0 = t.lo0 + local * DSPAN;
-            if (s0 >= end) break;
-            stencil_stream<G>(t.x, t.y, t.n, t.lo0, t.hi0, s0, s0 + DSPAN < end ? s0 + DSPAN : end);
+            // tile `local` of ntiles: the groups local, local + ntiles, ...
+            constexpr int64_t GS = (int64_t)G * 1024;
+            stencil_strided<G>(t.x, t.y, t.n, t.lo0, t.hi0, t.lo0 + local * GS, (int64_t)t.ntiles * GS);
             break;
         }
         case DK_JACOBI2D: {
@@ -57,10 +56,10 @@ __device__ __forceinline__ void run_tile(const DTask &t, int64_t local, int *sh)
         }
         case DK_HIST256: {
             if constexpr (!(KINDS & (1u << DK_HIST256))) break;
+            // tile `local` of ntiles: the 4096-element chunks local,
+            // local + ntiles, ... (neighbouring tiles read neighbouring chunks)
             const int64_t end = t.hi0 < t.n ? t.hi0 : t.n;
-            const int64_t s0 = t.lo0 + local * DSPAN;
-            const int64_t s1 = s0 + DSPAN < end ? s0 + DSPAN : end;
-            hist_span(t.x, s0, s1, 4096, sh);
+            hist_span(t.x, t.lo0 + local * 4096, end, (int64_t)t.ntiles * 4096, sh);
             hist_flush(t.y, sh);
             break;
         }
@@ -100,8 +99,31 @@ __device__ __forceinline__ void drain_loop(const DTask *q, int ntasks, int32_t *
         __syncthreads();
         const int64_t tile = __builtin_amdgcn_readfirstlane(s_tile);
         if (tile >= total) break;
+        if (threadIdx.x < WAVE) {
+            // the task holding `tile`: the last one whose first tile is at
+            // most `tile`.  First tiles grow with the task index and a
+            // workgroup's tickets only grow, so the search starts at its
+            // previous task.  The first wave tests 64 candidates per step
+            // (one memory round trip): tasks cur + 1 .. cur + 64, galloping
+            // to strides of 64 and 4096 while every candidate is passed,
+            // then narrowing back to stride 1.  Passed candidates form a
+            // prefix, so their count is the step.
+            const int lane = threadIdx.x;
+            int stride = 1;
+            for (;;) {
+                const int64_t idx = (int64_t)cur + (int64_t)(lane + 1) * stride;
+                const bool passed = idx < ntasks && q[idx].tile_begin <= tile;
+                const int adv = __popcll(__ballot(passed));
+                cur += adv * stride;
+                if (adv < WAVE) {
+                    if (stride == 1) break;
+                    stride >>= 6;
+                } else if (stride < 4096) {
+                    stride <<= 6;
+                }
+            }
+        }
         if (threadIdx.x == 0) {
-            while (cur + 1 < ntasks && q[cur + 1].tile_begin <= tile) ++cur;
             const DTask &t = q[cur];
             int ok = 1;
             for (int d = 0; d < t.ndeps && ok; ++d) {

@@ -593,8 +593,11 @@ static lt_status batch_add_exec(Ctx *ctx, const KernelDef *def, TaskPlan &tp, Ta
         return set_err(ctx, LT_ERR_UNSUPPORTED, "%s cannot run inside a batch", def->name);
     }
     if (d.kind != DK_JACOBI2D) {
+        // the touch body walks DSPAN-element tiles; the stencil and
+        // histogram bodies take whatever count of interleaved tiles
+        const int64_t span = d.kind == DK_TOUCH || ctx->cfg.drain_tile <= 0 ? DSPAN : ctx->cfg.drain_tile;
         int64_t e = std::min(d.hi0, d.n) - d.lo0;
-        d.ntiles = e > 0 ? (int)((e + DSPAN - 1) / DSPAN) : 0;
+        d.ntiles = e > 0 ? (int)((e + span - 1) / span) : 0;
     }
     for (uint64_t dep : rec.deps) {
         lt_status st = batch_dep(ctx, d, dep);
@@ -1754,7 +1757,9 @@ lt_status launch(Ctx *ctx, lt_kernel *k, int nd, const int64_t *grid,
             a.op = pop[p];
         }
         seen.clear();
-        if (def->slots) tp.slots = std::max<int64_t>(1, def->slots(tp.sb.lo, tp.sb.hi, iparams));
+        // batched bodies fold into one partial per task
+        if (def->slots && !(ctx->batch.open && def->dkind >= 0))
+            tp.slots = std::max<int64_t>(1, def->slots(tp.sb.lo, tp.sb.hi, iparams));
         for (int p = 0; p < def->nparam; ++p) {
             ArgPlan &a = tp.arg[p];
             if (!a.used) continue;
@@ -1848,6 +1853,12 @@ lt_status launch(Ctx *ctx, lt_kernel *k, int nd, const int64_t *grid,
         int s = 0;
         st = stream_wait(ctx, s, mem);
         if (st) return st;
+        if (def->slots_written) {
+            // the body stores every element of its slots: no identity fill,
+            // only the memory's earlier users to wait for
+            P.ready.merge(mem);
+            continue;
+        }
         unsigned char idv[8];
         int esz;
         identity_bytes(arrs[P.param]->dtype, P.op, idv, &esz);

@@ -77,6 +77,18 @@ inline int64_t kmu_slots(int64_t points) {
     int64_t t = (points + KMU_TILE - 1) / KMU_TILE;
     return t < KMU_MAXSLOTS ? t : KMU_MAXSLOTS;
 }
+// hist256 outside batches: one workgroup and one partial slot per 64 Ki
+// elements of a task (at most 1024, at least one); each workgroup stores its
+// whole 256-bin histogram into its slot, so no two workgroups add into the
+// same words
+constexpr int64_t HIST_WG_SPAN = 65536;
+constexpr int64_t HIST_MAXSLOTS = 1024;
+inline int64_t hist_slots(const int64_t *lo, const int64_t *hi, const int64_t *iarg) {
+    const int64_t e = (hi[0] < iarg[0] ? hi[0] : iarg[0]) - lo[0];
+    if (e <= 0) return 1;
+    const int64_t b = (e + HIST_WG_SPAN - 1) / HIST_WG_SPAN;
+    return b < HIST_MAXSLOTS ? b : HIST_MAXSLOTS;
+}
 constexpr int KMU_MAXD = 32;
 constexpr int KMU_MAXK = 256;
 constexpr int KMU_MAXKD = 1536;   // K * d limit: four float64 copies stay under 64 KiB of LDS
@@ -102,6 +114,11 @@ hipError_t launch_copy_boxes(hipStream_t s, const CopyBoxEntry *table, int n, in
 // pointers may be device memory or pinned host memory (which kernels reach
 // over the host link).  Returns hipErrorInvalidValue for other shapes.
 hipError_t launch_copy_linear(hipStream_t s, void *dst, const void *src, int64_t bytes);
+
+// Copies `rows` rows of `width` bytes (source and destination pitches in
+// bytes) with a kernel; either side may be device or pinned host memory.
+hipError_t launch_copy_rows(hipStream_t s, void *dst, int64_t dpitch, const void *src, int64_t spitch,
+                            int64_t width, int64_t rows);
 
 // Sets `count` elements of size esz (1, 4 or 8 bytes) at dst to *value.
 hipError_t launch_fill(hipStream_t s, void *dst, int64_t count, int esz,

@@ -223,14 +223,28 @@ hipError_t launch_jacobi2d_f32(const KLaunch &L) {
 }
 
 // ================================================================ hist256
-// h[b] += #{i in task : v[i] == b}; h is the superblock's private partial.
-// Each wave keeps its own 256-bin LDS histogram (skewed data hammers few
-// bins), the workgroup sums them and adds to the partial with integer
-// atomics, which are exact and order-free.
+// Slot w of the superblock's partial = #{i in the workgroup's 64 Ki-element
+// chunks : v[i] == b} for every bin b.  Each wave counts into its own LDS
+// sub-histograms (skewed data hammers few bins); the workgroup sums them and
+// stores the whole slot, so no two workgroups add into the same words.  The
+// slots are folded afterwards (integers: exact in any order).
 struct HTask {
     int64_t lo, hi;
     int64_t h, v;
+    int64_t slot;     // element distance between slots
 };
+// Stores the sum of the sub-histograms as the 256 bins at hb (no other
+// workgroup writes them).
+__device__ __forceinline__ void hist_store(int64_t hb, const int *sh) {
+    __syncthreads();
+    LT_GLOBAL int32_t *H = gp<int32_t>(hb);
+    const int b = threadIdx.x;
+    int s = 0;
+#pragma unroll
+    for (int k = 0; k < HIST_COPIES; ++k) s += sh[k * HIST_STRIDE + b];
+    H[b] = s;
+}
+
 struct HArgs {
     int64_t n;
     int ntask;
@@ -246,9 +260,10 @@ __global__ __launch_bounds__(256) void k_hist256(HArgs a) {
     for (int i = threadIdx.x; i < HIST_WORDS; i += 256) sh[i] = 0;
     __syncthreads();
     const int64_t end = t.hi < a.n ? t.hi : a.n;
+    const int w = blockIdx.x - a.begin[ti];
     const int nblk = a.begin[ti + 1] - a.begin[ti];
-    hist_span(t.v, t.lo + (int64_t)(blockIdx.x - a.begin[ti]) * 4096, end, (int64_t)nblk * 4096, sh);
-    hist_flush(t.h, sh);
+    hist_span(t.v, t.lo + (int64_t)w * 4096, end, (int64_t)nblk * 4096, sh);
+    hist_store(t.h + (int64_t)w * t.slot * 4, sh);
 }
 
 hipError_t launch_hist256_i32(const KLaunch &L) {
@@ -261,11 +276,11 @@ hipError_t launch_hist256_i32(const KLaunch &L) {
         a.t[i].hi = L.tasks[i].hi[0];
         a.t[i].h = L.tasks[i].v[1].base;
         a.t[i].v = L.tasks[i].v[2].base;
-        int64_t e = std::min(a.t[i].hi, a.n) - a.t[i].lo;
-        // 64 Ki elements per workgroup: every workgroup flushes 256 atomics
-        // into the one partial, so fewer, longer workgroups contend less
-        // (measured 2.9 TB/s against 2.1 with 16 Ki and 128 Ki at 2^24)
-        int64_t blocks = e > 0 ? std::min<int64_t>((e + 65535) / 65536, 1024) : 0;
+        a.t[i].slot = L.tasks[i].slot[1];
+        // one workgroup per slot, as the planner sized the partial (every
+        // slot is stored whole, empty tasks included)
+        const int64_t blocks = hist_slots(L.tasks[i].lo, L.tasks[i].hi, L.iarg);
+        if (blocks > 1 && a.t[i].slot <= 0) return hipErrorInvalidValue;
         a.begin[i] = (int)nb;
         nb += blocks;
     }
@@ -407,6 +422,46 @@ hipError_t launch_copy_linear(hipStream_t s, void *dst, const void *src, int64_t
     const int64_t blocks = (words + 255) / 256;
     if (blocks > INT32_MAX) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_copy16, dim3((unsigned)blocks), dim3(256), 0, s, (int4 *)dst, (const int4 *)src, words);
+    return hipGetLastError();
+}
+
+// Rows of `width` bytes: row r from src + r * spitch to dst + r * dpitch.
+// Each row is cut into segments of at most 4096 T-sized words (16, 4 or 1
+// bytes, the widest that every address, pitch and the width allow);
+// workgroup b copies segments b, b + gridDim.x, ... of the rows x segments,
+// 16 words per lane at most.
+template <class T>
+__global__ __launch_bounds__(256) void k_copy_rows(char *dst, int64_t dpitch, const char *src, int64_t spitch,
+                                                   int64_t words, int64_t rows, int64_t segs) {
+    for (int64_t b = blockIdx.x; b < rows * segs; b += gridDim.x) {
+        const int64_t r = b / segs, w0 = (b - r * segs) * 4096;
+        const int64_t w1 = w0 + 4096 < words ? w0 + 4096 : words;
+        T *d = reinterpret_cast<T *>(dst + r * dpitch);
+        const T *s = reinterpret_cast<const T *>(src + r * spitch);
+        for (int64_t i = w0 + threadIdx.x; i < w1; i += 256) d[i] = s[i];
+    }
+}
+
+template <class T>
+static void copy_rows_as(hipStream_t s, char *d, int64_t dpitch, const char *c, int64_t spitch, int64_t width,
+                         int64_t rows) {
+    const int64_t words = width / (int64_t)sizeof(T);
+    const int64_t segs = (words + 4095) / 4096;
+    const int64_t blocks = std::min<int64_t>(rows * segs, 65536);
+    hipLaunchKernelGGL(k_copy_rows<T>, dim3((unsigned)blocks), dim3(256), 0, s, d, dpitch, c, spitch, words, rows,
+                       segs);
+}
+
+hipError_t launch_copy_rows(hipStream_t s, void *dst, int64_t dpitch, const void *src, int64_t spitch,
+                            int64_t width, int64_t rows) {
+    if (width <= 0 || rows <= 0) return hipSuccess;
+    const uintptr_t all = (uintptr_t)dst | (uintptr_t)src | (uintptr_t)width |
+                          (uintptr_t)(rows > 1 ? (dpitch | spitch) : 0);
+    char *d = static_cast<char *>(dst);
+    const char *c = static_cast<const char *>(src);
+    if ((all & 15) == 0) copy_rows_as<int4>(s, d, dpitch, c, spitch, width, rows);
+    else if ((all & 3) == 0) copy_rows_as<int>(s, d, dpitch, c, spitch, width, rows);
+    else copy_rows_as<char>(s, d, dpitch, c, spitch, width, rows);
     return hipGetLastError();
 }
 

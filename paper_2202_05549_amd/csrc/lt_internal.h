@@ -138,6 +138,9 @@ struct KernelDef {
     // partial slots per task of a reduce parameter (nullptr = 1): a body that
     // folds floats over several workgroups writes one partial per workgroup
     int64_t (*slots)(const int64_t *lo, const int64_t *hi, const int64_t *iarg);
+    // the body writes every element of every partial slot it is given
+    // (empty tasks included), so partials need no identity fill
+    bool slots_written = false;
     void *user = nullptr;   // the RtcKernel of a runtime-compiled user kernel
 };
 
@@ -252,6 +255,7 @@ struct lt_array {
     int64_t strides[lt::MAXD] = {1, 1, 1};
     bool host_backed = false;
     char *host_base = nullptr;
+    bool home_pinned = false;  // host_base is pinned memory kernels can address directly
     bool row_slab = false;   // every chunk spans full trailing axes
     bool has_halo = false;   // chunks store a halo around their core (LT_DIST_STENCIL)
     int64_t halo[lt::MAXD] = {0, 0, 0};
@@ -549,13 +553,16 @@ lt_status stream_wait(Ctx *ctx, int stream, const Fence &f);
 // Records an event at stream s's current end, so that a later wait for what
 // has been issued so far waits for exactly that and not for work issued after.
 lt_status mark_tail(Ctx *ctx, int s);
+// by_kernel: a copy kernel instead of the copy engine (both sides must be
+// reachable by kernels: device or pinned host memory)
 lt_status copy_box(Ctx *ctx, int stream, char *dst, const int64_t *ds,
                    const char *src, const int64_t *ss, const int64_t *ext,
-                   int nd, int esz, hipMemcpyKind kind);
+                   int nd, int esz, hipMemcpyKind kind, bool by_kernel = false);
 // copies the elements `sub` between two buffers holding boxes with origins
 // dlo / slo and element strides ds / ss
 lt_status copy_sub(Ctx *ctx, int stream, char *dst, const int64_t *dlo, const int64_t *ds, const char *src,
-                   const int64_t *slo, const int64_t *ss, const Box &sub, int nd, int esz, hipMemcpyKind kind);
+                   const int64_t *slo, const int64_t *ss, const Box &sub, int nd, int esz, hipMemcpyKind kind,
+                   bool by_kernel = false);
 // D2H of a dirty chunk to its host copy on the D2H stream (after its data is
 // ready): the core for host-backed arrays (the halo belongs to other
 // chunks), the whole stored box for spill buffers.  Returns the D2H seq.

@@ -275,7 +275,7 @@ lt_status wait_fence(Ctx *ctx, const Fence &f) {
 // contiguous on both sides are merged first.
 lt_status copy_box(Ctx *ctx, int stream, char *dst, const int64_t *ds,
                    const char *src, const int64_t *ss, const int64_t *ext,
-                   int nd, int esz, hipMemcpyKind kind) {
+                   int nd, int esz, hipMemcpyKind kind, bool by_kernel) {
     // axes from the innermost outwards; an outer axis is merged into the
     // current innermost group when both layouts are contiguous across them
     int64_t e[MAXD], d[MAXD], s[MAXD];
@@ -332,7 +332,16 @@ lt_status copy_box(Ctx *ctx, int stream, char *dst, const int64_t *ds,
         lt_status st = prof_begin(ctx, stream, pname, &pa);
         if (st) return st;
     }
-    if (n == 1) {
+    if (by_kernel) {
+        // rows of the innermost axis; a third axis loops over planes
+        const int64_t planes = n == 3 ? e[0] : 1;
+        for (int64_t i = 0; i < planes && r == hipSuccess; ++i) {
+            char *dp = dst + (n == 3 ? i * d[0] * esz : 0);
+            const char *sp = src + (n == 3 ? i * s[0] * esz : 0);
+            r = n == 1 ? launch_copy_rows(h, dp, 0, sp, 0, e[0] * esz, 1)
+                       : launch_copy_rows(h, dp, d[n - 2] * esz, sp, s[n - 2] * esz, e[n - 1] * esz, e[n - 2]);
+        }
+    } else if (n == 1) {
         r = hipMemcpyAsync(dst, src, e[0] * esz, kind, h);
     } else if (n == 2) {
         r = hipMemcpy2DAsync(dst, d[0] * esz, src, s[0] * esz, e[1] * esz, e[0], kind, h);
@@ -557,7 +566,8 @@ static void chunk_ext(const Chunk *c, int64_t *ext) {
 char *dev_ptr(Ctx *ctx, const Chunk *c) { return ctx->arena_base + c->dev_off; }
 
 lt_status copy_sub(Ctx *ctx, int stream, char *dst, const int64_t *dlo, const int64_t *ds, const char *src,
-                   const int64_t *slo, const int64_t *ss, const Box &sub, int nd, int esz, hipMemcpyKind kind) {
+                   const int64_t *slo, const int64_t *ss, const Box &sub, int nd, int esz, hipMemcpyKind kind,
+                   bool by_kernel) {
     int64_t doff = 0, soff = 0, ext[MAXD];
     for (int a = 0; a < MAXD; ++a) {
         const int64_t lo = a < nd ? sub.lo[a] : 0;
@@ -565,7 +575,7 @@ lt_status copy_sub(Ctx *ctx, int stream, char *dst, const int64_t *dlo, const in
         soff += (lo - (a < nd ? slo[a] : 0)) * ss[a];
         ext[a] = a < nd ? sub.hi[a] - sub.lo[a] : 1;
     }
-    return copy_box(ctx, stream, dst + doff * esz, ds, src + soff * esz, ss, ext, nd, esz, kind);
+    return copy_box(ctx, stream, dst + doff * esz, ds, src + soff * esz, ss, ext, nd, esz, kind, by_kernel);
 }
 
 lt_status write_back(Ctx *ctx, Chunk *c, uint64_t *seq) {
@@ -595,8 +605,10 @@ lt_status write_back(Ctx *ctx, Chunk *c, uint64_t *seq) {
             // the copy kernel could not take it: the timing goes to copy_box
             ctx->prof_pool.push_back(pa);
         }
+        // a pinned home buffer can take a copy kernel too (d2h_kernel = 1)
+        const bool k = arr->host_backed && arr->home_pinned && ctx->cfg.d2h_kernel && !ctx->dry;
         st = copy_sub(ctx, ctx->d2h, c->host_ptr, c->box.lo, c->host_stride, dev_ptr(ctx, c), c->box.lo,
-                      c->dev_stride, part, arr->ndim, arr->esz, hipMemcpyDeviceToHost);
+                      c->dev_stride, part, arr->ndim, arr->esz, hipMemcpyDeviceToHost, k);
         if (st) return st;
     }
     *seq = bump(ctx, ctx->d2h);

@@ -630,8 +630,10 @@ hipError_t launch_kmeans_update_f32(const KLaunch &L) {
         u.nslots = (int)kmu_slots(e);
         // a task with several slots needs the slot strides from the planner
         if (u.nslots > 1 && (u.sslot <= 0 || u.cslot <= 0)) return hipErrorInvalidValue;
+        // every slot gets its workgroup, empty tasks included: the partials
+        // are not filled beforehand, each slot is written whole
         a.begin[i] = (int)nb;
-        nb += e > 0 ? u.nslots : 0;
+        nb += u.nslots;
     }
     a.begin[L.ntask] = (int)nb;
     if (nb == 0) return hipSuccess;

@@ -5,7 +5,9 @@
 // do, and every request's result is the one it would get alone.  Admission
 // is by device footprint; inputs are cached host-backed arrays whose chunks
 // stay in HBM across requests until the memory manager spills them.
+#include <algorithm>
 #include <chrono>
+#include <cstddef>
 #include <cstring>
 #include <deque>
 #include <map>
@@ -34,6 +36,7 @@ struct SReq {
     std::vector<lt_array *> owned;
     SDataset *ds = nullptr;
     std::tuple<int, int, int64_t> key;
+    int bypassed = 0;        // times a later request was admitted first
 };
 
 double now_s() {
@@ -251,10 +254,34 @@ void progress(lt_server *s) {
     }
     const int64_t cap = s->cfg.admit_bytes > 0 ? (int64_t)s->cfg.admit_bytes
                                                : (int64_t)s->ctx->cfg.device_budget_bytes;
+    auto fits = [&](const SReq *q) { return s->active.empty() || s->admitted + q->footprint <= cap; };
+    const int look = s->cfg.lookahead > 0 ? s->cfg.lookahead : 0;
+    const int max_bypass = s->cfg.max_bypass > 0 ? s->cfg.max_bypass : 4 * look;
     while (!s->queue.empty() && (int)s->active.size() < s->cfg.max_active) {
-        SReq *q = s->queue.front();
-        if (!s->active.empty() && s->admitted + q->footprint > cap) break;
-        s->queue.pop_front();
+        size_t pick = 0;
+        if (look > 0 && s->queue.front()->bypassed < max_bypass) {
+            // the oldest queued request on a cached dataset, else the oldest
+            // that fits, among the first `look`
+            const size_t w = std::min(s->queue.size(), (size_t)look);
+            size_t first_fit = w;
+            pick = w;
+            for (size_t i = 0; i < w; ++i) {
+                const SReq *q = s->queue[i];
+                if (!fits(q)) continue;
+                if (first_fit == w) first_fit = i;
+                if (s->cache.count(std::make_tuple(q->r.kind, q->r.dataset, q->r.size))) {
+                    pick = i;
+                    break;
+                }
+            }
+            if (pick == w) pick = first_fit;
+            if (pick == w) break;
+        } else if (!fits(s->queue.front())) {
+            break;
+        }
+        SReq *q = s->queue[pick];
+        for (size_t i = 0; i < pick; ++i) s->queue[i]->bypassed++;
+        s->queue.erase(s->queue.begin() + (std::ptrdiff_t)pick);
         lt_status st = admit(s, q);
         if (st) {
             finish(s, q, st);

@@ -25,13 +25,16 @@ KINDS = {"jacobi": LT_REQ_JACOBI, "kmeans": LT_REQ_KMEANS, "gemm": LT_REQ_GEMM}
 
 
 class Server:
-    def __init__(self, ctx, max_active=8, keep_resident=True, admit_bytes=0, chunk_rows=0, gemm_tile=0):
+    def __init__(self, ctx, max_active=8, keep_resident=True, admit_bytes=0, chunk_rows=0, gemm_tile=0,
+                 lookahead=0, max_bypass=0):
         cfg = lt_server_config()
         cfg.max_active = max_active
         cfg.keep_resident = 1 if keep_resident else 0
         cfg.admit_bytes = admit_bytes
         cfg.chunk_rows = chunk_rows
         cfg.gemm_tile = gemm_tile
+        cfg.lookahead = lookahead
+        cfg.max_bypass = max_bypass
         self.ctx = ctx
         self.h = C.c_void_p()
         check(ctx.h, lt_server_create(ctx.h, C.byref(cfg), C.byref(self.h)))
@@ -238,7 +241,9 @@ def summarize(trace, done, start):
             "errors": int(sum(c["status"] != 0 for c in done.values()))}
 
 
-def bench(args, L, torch, log):
+def bench(args, L, torch, log, overlap=None):
+    """``overlap(spans)``, when given, summarizes the device-clock spans of
+    each mode (kernel and host-link copy busy time)."""
     import synthetic
 
     full = getattr(args, "serve_full", False)
@@ -256,17 +261,22 @@ def bench(args, L, torch, log):
     # two compute streams: with the H2D and D2H streams that makes four,
     # the number of hardware queues a process gets by default; more streams
     # would share queues and order unrelated work behind each other
+    d2h_kernel = getattr(args, "d2h_kernel", -1)
+    if d2h_kernel < 0:
+        d2h_kernel = 1 if full else 0
     ctx = L.Context(device_budget_bytes=budget, n_compute_streams=2, stage_threshold_bytes=8 << 30,
-                    sb_order=L.LT_ORDER_SERPENTINE)
+                    sb_order=L.LT_ORDER_SERPENTINE, d2h_kernel=d2h_kernel)
     slots = 16
     try:
         log("serving: generating %d datasets in pinned host memory" % len({(r["kind"], r["dataset"]) for r in trace}))
         # the full trace's datasets (about 130 GB) exceed what one process
         # can pin on the GPU machine (hipHostMalloc fails beyond about 64 GiB in
-        # total): the largest datasets then stay in pageable memory
+        # total): the largest inputs then stay in pageable memory.  Outputs
+        # are pinned first: a copy into pageable memory blocks the issuing
+        # thread until it is done
         host = HostBuffers(ctx, pin_bytes=(56 << 30) if full else None)
-        data = make_datasets(ctx, trace, host=host)
         outs = output_buffers(ctx, trace, host=host)
+        data = make_datasets(ctx, trace, host=host)
         host_gb = (host.pinned_bytes + host.pageable_bytes) / 1e9
         log("serving: %.1f GB of inputs and outputs (%.1f GB pinned, %.1f GB pageable)"
             % (host_gb, host.pinned_bytes / 1e9, host.pageable_bytes / 1e9))
@@ -281,10 +291,17 @@ def bench(args, L, torch, log):
         finally:
             srv.close()
         ctx.sync()
-        for mode, (act, keep) in (("continuous", (slots, True)), ("plain", (1, False))):
+        # continuous batching with cached datasets first among the first 64
+        # queued requests, the same in arrival order, and plain (one request
+        # at a time, in arrival order, inputs uploaded for every request)
+        for mode, (act, keep, look) in (("continuous", (slots, True, 64)), ("continuous_fcfs", (slots, True, 0)),
+                                        ("plain", (1, False, 0))):
             log("serving %s: %d requests, Poisson 200/s" % (mode, count))
-            srv = Server(ctx, max_active=act, keep_resident=keep, admit_bytes=budget)
+            srv = Server(ctx, max_active=act, keep_resident=keep, admit_bytes=budget, lookahead=look)
             ctx.reset_stats()
+            if overlap:
+                ctx.profile(True)
+                ctx.profile_reset()
             def progress(k, total):
                 if k % 16 == 0 or k == total:
                     log("%s: %d of %d requests done" % (mode, k, total))
@@ -298,6 +315,9 @@ def bench(args, L, torch, log):
             res[mode] = summarize(trace, done, start)
             res[mode].update({"h2d_gb": st["bytes_h2d"] / 1e9, "d2h_gb": st["bytes_d2h"] / 1e9,
                               "dispatches": st["dispatches"]})
+            if overlap:
+                res[mode]["device_time"] = overlap(ctx.profile_spans())
+                ctx.profile(False)
             log("%s: %s" % (mode, json.dumps(res[mode])))
     finally:
         ctx.close()
@@ -314,11 +334,17 @@ def bench(args, L, torch, log):
                                       ranges["kmeans_range"][0], ranges["kmeans_range"][1],
                                       ranges["gemm_range"][0], ranges["gemm_range"][1], pool, host_gb,
                                       host.pinned_bytes / 1e9, host.pageable_bytes / 1e9),
-                       "executor": "continuous batching, %d slots, resident datasets" % slots},
+                       "executor": "continuous batching, %d slots, resident datasets, cached datasets first "
+                                   "among the first 64 queued (at most 256 bypasses)" % slots,
+                       "write_backs": "copy kernel" if d2h_kernel else "copy engine"},
             "value": round(m["gbs"], 2), "unit": "GB/s", "ms_per_step": round(m["makespan_s"] * 1e3, 2),
             "dtype": "f32+i32", "p50_ms": round(m["p50_ms"], 2), "p99_ms": round(m["p99_ms"], 2),
             "req_per_s": round(m["req_per_s"], 3), "tflops": round(m["tflops"], 2),
             "plain": {k: (round(v, 3) if isinstance(v, float) else v) for k, v in res["plain"].items()},
+            "continuous_fcfs": {k: (round(v, 3) if isinstance(v, float) else v)
+                                for k, v in res["continuous_fcfs"].items()},
             "served_over_plain": round(res["plain"]["makespan_s"] / m["makespan_s"], 3),
-            "cache_hits": m["cache_hits"]}
+            "fcfs_over_plain": round(res["plain"]["makespan_s"] / res["continuous_fcfs"]["makespan_s"], 3),
+            "cache_hits": m["cache_hits"], "h2d_gb": round(m["h2d_gb"], 2), "d2h_gb": round(m["d2h_gb"], 2),
+            "device_time": m.get("device_time")}
     return line

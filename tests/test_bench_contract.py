@@ -66,6 +66,8 @@ def test_copy_overlap_measures_copy_time_under_kernels():
     assert o["h2d"]["copies"] == 2 and o["h2d"]["busy_ms"] == 18.0
     assert abs(o["h2d"]["overlap_frac"] - 9.0 / 18.0) < 1e-12   # [5, 10] and [12, 16]
     assert abs(o["d2h"]["overlap_frac"] - 2.0 / 4.0) < 1e-12    # [14, 16]
+    # kernels [5, 16] under copies [0, 10] U [12, 20]: [5, 10] and [12, 16]
+    assert abs(o["kernel_under_copy_frac"] - 9.0 / 11.0) < 1e-4   # rounded to 4 places
     # overlapping copies of one direction count once
     sp2 = np.array([(b"copy_h2d", 4, 0.0, 4.0), (b"copy_h2d", 4, 2.0, 6.0), (b"k", 0, 0.0, 6.0)], dtype=dt)
     o2 = b.copy_overlap(sp2)

@@ -23,11 +23,11 @@ def L():
     return L
 
 
-def _mix(L, count, hi_log2, sb, batched, seed=3, drain_wg=0):
+def _mix(L, count, hi_log2, sb, batched, seed=3, drain_wg=0, drain_tile=0):
     plan = synthetic.batch_plan(count, seed=seed, hi_log2=hi_log2)
     data = [synthetic.batch_data(k, n, i, seed=seed) for i, (k, n) in enumerate(plan)]
     outs = []
-    with L.Context(device_budget_bytes=4 << 30, drain_workgroups=drain_wg) as ctx:
+    with L.Context(device_budget_bytes=4 << 30, drain_workgroups=drain_wg, drain_tile=drain_tile) as ctx:
         arrs = []
         for (k, n), v in zip(plan, data):
             if k == 0:
@@ -62,6 +62,16 @@ def test_batched_mix_matches_oracle_and_plain(L, sb):
         ref = oracle.stencil1d(v) if k == 0 else oracle.hist256(v)
         assert np.array_equal(g, ref), (k, n)
         assert np.array_equal(g, p), (k, n)
+
+
+@pytest.mark.parametrize("tile", [4096, 12288, 1 << 18])
+def test_batched_mix_drain_tile_sizes(L, tile):
+    # tasks cut into interleaved tiles of other sizes: the same results
+    say("batch mix drain tile", tile)
+    plan, data, got = _mix(L, 48, 20.0, 1 << 20, batched=True, drain_tile=tile)
+    for (k, n), v, g in zip(plan, data, got):
+        ref = oracle.stencil1d(v) if k == 0 else oracle.hist256(v)
+        assert np.array_equal(g, ref), (k, n)
 
 
 def test_batched_mix_small_drain(L):

@@ -227,7 +227,8 @@ _C2 = {}
 
 # ---------------------------------------------------------------- hist256
 
-@pytest.mark.parametrize("n,chunk,sb", [(1_000_003, 1 << 16, 1 << 16), (777, 100, 64), (1 << 22, 1 << 20, 1 << 19)])
+@pytest.mark.parametrize("n,chunk,sb", [(1_000_003, 1 << 16, 1 << 16), (777, 100, 64), (1 << 22, 1 << 20, 1 << 19),
+                                        (1 << 26, 1 << 24, 1 << 26), (70 << 20, 0, 0)])
 def test_hist256_bit_exact_and_overwrites_target(L, n, chunk, sb):
     say("hist", n, chunk, sb)
     v = synthetic.zipf_values(n, np.random.default_rng(12))
@@ -581,3 +582,31 @@ def test_gemm_subnormal_products_kept(L):
     exact = np.float32(K * 2.0 ** -140)   # 2^-132, a subnormal, exactly representable
     assert exact != 0 and exact < np.finfo(np.float32).tiny
     assert np.all(got == exact)
+
+
+@pytest.mark.parametrize("pinned", [True, False])
+@pytest.mark.parametrize("engine", [0, 1])
+@pytest.mark.parametrize("shape,chunk", [((300, 517), (64, 128)), ((257, 1024), (64, 0)), ((33, 7), (5, 3))])
+def test_host_backed_write_back_paths(L, pinned, engine, shape, chunk):
+    # results written back into the home buffer through a copy kernel
+    # (pinned home, d2h_kernel 1: rows of any pitch and width, 16-, 4- and
+    # 1-byte words) or the copy engine, out of core so that write-backs
+    # happen during the launches and at the sync
+    n, m = shape
+    say("write-back paths", shape, chunk, pinned, engine)
+    x0 = synthetic.jacobi2d_input(n, m, seed=31)
+    tile = chunk[0] * (chunk[1] or m) * 4
+    with ctx_of(L, device_budget_bytes=16 * tile + (1 << 20), d2h_kernel=1 - engine) as ctx:
+        A = ctx.pinned((n, m)) if pinned else np.empty((n, m), np.float32)
+        B = ctx.pinned((n, m)) if pinned else np.empty((n, m), np.float32)
+        A[...] = x0
+        B[...] = np.nan
+        a = ctx.array_host(A, chunk=list(chunk))
+        b = ctx.array_host(B, chunk=list(chunk))
+        inp, out = a, b
+        for _ in range(3):
+            ctx.launch("jacobi2d_f32", [n, m], [1, 1], list(chunk), args=[n, m, out, inp])
+            inp, out = out, inp
+        ctx.sync()
+        got = np.array(B if inp is b else A)
+    assert np.array_equal(got, oracle.jacobi2d(x0, 3))

@@ -31,7 +31,7 @@ def _trace():
     return tr
 
 
-def _serve(L, trace, max_active, keep, budget=1 << 30, realtime=True, chunk_rows=0):
+def _serve(L, trace, max_active, keep, budget=1 << 30, realtime=True, chunk_rows=0, lookahead=0):
     from paper_2202_05549_amd import serve
 
     outs = {}
@@ -44,7 +44,8 @@ def _serve(L, trace, max_active, keep, budget=1 << 30, realtime=True, chunk_rows
             outs[r["id"]] = buf
             return buf
 
-        srv = serve.Server(ctx, max_active=max_active, keep_resident=keep, chunk_rows=chunk_rows, gemm_tile=256)
+        srv = serve.Server(ctx, max_active=max_active, keep_resident=keep, chunk_rows=chunk_rows, gemm_tile=256,
+                           lookahead=lookahead)
         try:
             done, _ = serve.replay(srv, trace, serve.submit_with(data, out_for), realtime=realtime)
         finally:
@@ -92,3 +93,28 @@ def test_serving_under_a_small_budget_spills(L):
     say("serve small budget")
     outs, host, done = _serve(L, trace, max_active=4, keep=True, budget=4 << 20, chunk_rows=4096)
     _check_oracle(trace, outs, host)
+
+
+def test_lookahead_admits_cached_datasets_first_with_the_same_results(L):
+    # one slot, everything queued behind a long first request (Jacobi 8192^2,
+    # 100 sweeps: milliseconds on the device, longer than submitting the
+    # rest): with a lookahead, a queued request on a dataset already cached
+    # goes before older ones on other datasets; results are the oracle's and
+    # those of the arrival-order run
+    blocker = {"id": 0, "t": 0.0, "kind": "jacobi", "dataset": 99, "size": 8192, "sweeps": 100}
+    trace = [blocker] + [dict(r, id=r["id"] + 1, t=0.0) for r in _trace()]
+    say("serve lookahead")
+    la, host, done = _serve(L, trace, max_active=1, keep=True, realtime=False, lookahead=8)
+    _check_oracle(trace[1:], la, host)
+    fcfs, _, done_f = _serve(L, trace, max_active=1, keep=True, realtime=False)
+    for r in trace:
+        assert np.array_equal(la[r["id"]], fcfs[r["id"]]), r
+    order = [i for i, _ in sorted(done.items(), key=lambda kv: kv[1]["t_admit"])]
+    order_f = [i for i, _ in sorted(done_f.items(), key=lambda kv: kv[1]["t_admit"])]
+    assert order_f == sorted(order_f)          # arrival order
+    assert order[0] == 0 and order != sorted(order)   # some request went ahead
+    assert sum(c["cache_hit"] for c in done.values()) >= sum(c["cache_hit"] for c in done_f.values())
+    # no request waited behind more than max_bypass (4 x 8) later ones
+    pos = {i: k for k, i in enumerate(order)}
+    for i in order:
+        assert sum(1 for j in order if j > i and pos[j] < pos[i]) <= 32

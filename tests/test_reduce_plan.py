@@ -37,16 +37,18 @@ def test_kmeans_update_plan(N, sb):
         # each combine waits for every superblock task
         for c in comb:
             assert set(ctx.deps(c.id)) >= {t.id for t in ex}
-        # partial bytes: slots x (K d float64 + K int32) per task; the fills
-        # of the two partial blocks appear in the trace with their sizes
+        # partial bytes: slots x (K d float64 + K int32) per task; the two
+        # partial blocks appear in the trace as allocations with no owner
+        # chunk, and are not filled (the body stores every slot whole)
         want = [0, 0]
         for t in ex:
             s = _kmu_slots(min(t.sb_hi[0], N) - t.sb_lo[0])
             want[0] += s * K * d * 8
             want[1] += s * K * 4
-        fills = [op for op in ctx.trace() if op.kind == 4]
-        got = sorted(int(f.bytes) for f in fills)
-        assert got == sorted((w + 255) // 256 * 256 for w in want)
+        tr = ctx.trace()
+        parts = sorted(int(op.bytes) for op in tr if op.kind == 6 and op.chunk == 0)
+        assert parts == sorted((w + 255) // 256 * 256 for w in want)
+        assert not [op for op in tr if op.kind == 4]
         ctx.sync()
 
 
@@ -80,3 +82,32 @@ def test_rowreduce_partials_per_column_superblock():
             r = [g for g in regs if g.arg == 2][0]
             assert (r.lo[0], r.hi[0]) == (t.sb_lo[0], min(t.sb_hi[0], n))
         ctx.sync()
+
+
+@pytest.mark.parametrize("n,sb", [(1_000_003, 1 << 20), (65536, 65536), (70000, 1 << 16), (5, 4)])
+def test_hist_slots_outside_batches_one_partial_inside(n, sb):
+    # outside a batch: one 256-bin slot per 64 Ki elements of a superblock
+    # (at most 1024), stored whole by the body, so no fill; inside a batch:
+    # one partial per superblock, cleared with the batch's counters
+    def slots(e):
+        return 1 if e <= 0 else min(1024, -(-e // 65536))
+
+    with dry() as ctx:
+        v = ctx.array([n], np.int32)
+        h = ctx.array([256], np.int32)
+        ctx.clear_trace()
+        lid = ctx.launch("hist256_i32", [n], [1], [sb], args=[n, h, v])
+        ex = [t for t in ctx.tasks(lid) if t.kind == L.LT_TASK_EXEC]
+        want = sum(slots(min(t.sb_hi[0], n) - t.sb_lo[0]) for t in ex) * 256 * 4
+        tr = ctx.trace()
+        parts = [int(op.bytes) for op in tr if op.kind == 6 and op.chunk == 0]
+        assert parts == [(want + 255) // 256 * 256]
+        assert not [op for op in tr if op.kind == 4]
+        ctx.sync()
+        ctx.clear_trace()
+        ctx.batch_begin()
+        ctx.launch("hist256_i32", [n], [1], [sb], args=[n, h, v])
+        ctx.batch_end()
+        ctx.sync()
+        st = ctx.stats()
+        assert st["dispatches"] >= 1
