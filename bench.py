@@ -121,6 +121,8 @@ KMU_SOURCES = [("reduce.hip", "// ==============================================
 
 # the code of k_drain on the 1-D mix: the drain loop and its launcher, the
 # 1-D stencil and histogram bodies it runs, and the task record
+# the drain tile size the k_drain counters were taken at (0: the per-body defaults)
+DRAIN_TRAFFIC_TILE = 0
 DRAIN_SOURCES = [("drain.hip", "#include <hip/hip_runtime.h>", "// Device scratch of the no-allocation batch issue"),
                  ("bodies.h", "// -------------------------------------------------------------- stencil1d",
                   "// ---------------------------------------------------------------- jacobi2d"),
@@ -151,11 +153,11 @@ TRAFFIC = {
     "k_kmeans_update": {"sources": KMU_SOURCES, "digest": "d98381726987eb27",
                         "bytes_per_dispatch": 139300 * 1024 * 2.000 + 8448 * 1024},
     # k_drain<27, 4>, one dispatch per step of the 8192-launch mix at
-    # superblock 2^24, 1024 workgroups (graph replay): FETCH_SIZE 27,025,249
-    # KiB x 2.000 + WRITE_SIZE 27,225,629 KiB x 1.000 = 83.23 GB, against
-    # 83.0 GB of algorithmic bytes
-    "k_drain": {"sources": DRAIN_SOURCES, "digest": "0a995e9484e40093",
-                "bytes_per_dispatch": 27025249 * 1024 * 2.000 + 27225629 * 1024},
+    # superblock 2^24, 1024 workgroups, per-body drain tiles (graph replay):
+    # FETCH_SIZE 27,213,872 KiB x 2.000 + WRITE_SIZE 27,245,512 KiB x 1.000 =
+    # 83.63 GB, against 83.02 GB of algorithmic bytes
+    "k_drain": {"sources": DRAIN_SOURCES, "digest": "8c90a005240dfe0c",
+                "bytes_per_dispatch": 27213872 * 1024 * 2.000 + 27245512 * 1024},
 }
 
 
@@ -274,11 +276,13 @@ def jacobi_run(L, torch, x0, executor, steps, warmup, rows=None):
 
         for _ in range(warmup):
             step()
-        # HIP events around every dispatch during the timed steps (grouped:
-        # one per sweep), so the summed kernel time can never exceed the
-        # wall; plain: per-task events would slow its host path, so its
+        # HIP events around each step's dispatches on their stream during
+        # the timed steps (grouped: the 100 sweeps between two events), so
+        # the kernel time per dispatch includes the gaps between dispatches
+        # and can never exceed the wall, and no event sits between two
+        # sweeps; plain: per-task events would slow its host path, so its
         # kernel time comes from a separate profiled step
-        ctx.profile(executor != "plain", every=1)
+        ctx.profile(executor != "plain", steps=executor == "grouped")
         ctx.profile_reset()
         ctx.reset_stats()
         torch.cuda.synchronize()
@@ -723,8 +727,8 @@ def bench_batch(args, L, torch):
                     | set(order[-6:].tolist()) | set(order[:2].tolist()))
     sample_out = {}
 
-    def run(mode, sb, wg=1024, flush=0, steps=None, times=None, graph=None, vec=0):
-        ctx.configure(drain_workgroups=wg, batch_flush_tasks=flush, drain_vectors=vec)
+    def run(mode, sb, wg=1024, flush=0, steps=None, times=None, graph=None, vec=0, tile=0):
+        ctx.configure(drain_workgroups=wg, batch_flush_tasks=flush, drain_vectors=vec, drain_tile=tile)
         sbs = np.full((len(plan), 1), sb, dtype=np.int64)
         args_t = L.Context.arg_table(len(plan), [ns, [a[0] for a in arrs], [a[1] for a in arrs]])
         s0 = time.perf_counter()
@@ -744,16 +748,16 @@ def bench_batch(args, L, torch):
 
     if args.tuned:
         # fixed parameters instead of the sweep (counter runs of one configuration)
-        sb, wg, flush, vec = (int(v) for v in args.tuned.split(":"))
-        best = {"sb": sb, "wg": wg, "flush": flush, "vec": vec}
+        sb, wg, flush, vec, tile = (int(v) for v in args.tuned.split(":"))
+        best = {"sb": sb, "wg": wg, "flush": flush, "vec": vec, "tile": tile}
         best_plain = {"sb": sb}
         log("fixed parameters: %s" % best)
     else:
-        log("autotuning superblock size, drain width, flush size and vector groups on the full mix")
-        best = autotune.tune("batch8192", {"sb": [1 << 18, 1 << 20, 1 << 22, 1 << 24], "wg": [1024, 2048],
-                                           "flush": [0, 4096], "vec": [2, 4]},
-                             lambda sb, wg, flush, vec: run("batched", sb, wg, flush, vec=vec), reps=1,
-                             cache=None, log=log)
+        log("autotuning superblock size, drain width, flush size, vector groups and tile size on the full mix")
+        best = autotune.tune("batch8192", {"sb": [1 << 20, 1 << 22, 1 << 24], "wg": [1024, 2048],
+                                           "flush": [0, 4096], "vec": [2, 4], "tile": [0, 16384, 32768]},
+                             lambda sb, wg, flush, vec, tile: run("batched", sb, wg, flush, vec=vec, tile=tile),
+                             reps=1, cache=None, log=log)
         log("tuned: %s" % best)
         best_plain = autotune.tune("batch8192_plain", {"sb": [1 << 18, 1 << 20, 1 << 22, 1 << 24]},
                                    lambda sb: run("plain", sb), reps=1, cache=None, log=log)
@@ -762,21 +766,23 @@ def bench_batch(args, L, torch):
     for mode in modes:
         graph = None
         if mode == "graph":
-            ctx.configure(drain_workgroups=best["wg"], batch_flush_tasks=0, drain_vectors=best["vec"])
+            ctx.configure(drain_workgroups=best["wg"], batch_flush_tasks=0, drain_vectors=best["vec"],
+                          drain_tile=best["tile"])
             ctx.graph_begin()
             ctx.launch_many(names, grids, [1], np.full((len(plan), 1), best["sb"], dtype=np.int64),
                             L.Context.arg_table(len(plan), [ns, [a[0] for a in arrs], [a[1] for a in arrs]]))
             graph = ctx.graph_end()
         sb = best_plain["sb"] if mode == "plain" else best["sb"]
         for _ in range(args.warmup):
-            run(mode, sb, best["wg"], best["flush"] if mode == "batched" else 0, graph=graph, vec=best["vec"])
+            run(mode, sb, best["wg"], best["flush"] if mode == "batched" else 0, graph=graph, vec=best["vec"],
+                tile=best["tile"])
         ctx.profile(mode != "plain")
         ctx.profile_reset()
         ctx.reset_stats()
         times = []
         for _ in range(args.steps):
             run(mode, sb, best["wg"], best["flush"] if mode == "batched" else 0, times=times, graph=graph,
-                vec=best["vec"])
+                vec=best["vec"], tile=best["tile"])
         prof = ctx.profile_get()
         stats = ctx.stats()
         ctx.profile(False)
@@ -813,7 +819,8 @@ def bench_batch(args, L, torch):
                       "executor": {"graph": "batch recorded as a HIP graph (persistent drain), replayed",
                                    "batched": "batched (persistent drain)"}[ex],
                       "superblock": best["sb"], "drain_workgroups": best["wg"], "batch_flush_tasks": best["flush"],
-                      "drain_vectors": best["vec"], "plain_superblock": best_plain["sb"]}, args.steps, args.warmup)
+                      "drain_vectors": best["vec"], "drain_tile": best["tile"], "plain_superblock": best_plain["sb"]},
+                     args.steps, args.warmup)
     line.update({"value": round(m["gbs"], 2), "unit": "GB/s", "ms_per_step": round(m["ms_per_step"], 3),
                  "dtype": "f32+i32", "p50_ms": round(m["p50_ms"], 3), "p99_ms": round(m["p99_ms"], 3),
                  "hbm_frac": round(m["gbs"] / HBM_PEAK_GBS, 4),
@@ -821,8 +828,9 @@ def bench_batch(args, L, torch):
                               "peak": HBM_PEAK_GBS, "unit": "GB/s",
                               "frac": round(m.get("kernel_gbs", float("nan")) / HBM_PEAK_GBS, 4),
                               # counters were taken on one drain per step at superblock 2^24
+                              # with 4-vector groups
                               "traffic": (traffic_for("k_drain") if ex == "graph" and best["sb"] == 1 << 24
-                                          and best["wg"] == 1024 and best["vec"] == 4 else None),
+                                          and best["tile"] == DRAIN_TRAFFIC_TILE and best["vec"] == 4 else None),
                               "kernel": "k_drain", "kernel_ms_per_step": round(m.get("drain_ms", float("nan")), 3)},
                  "plain": {k: round(v, 3) for k, v in res["plain"].items()} if "plain" in res else None,
                  "batched": {k: round(v, 3) for k, v in res["batched"].items()},

@@ -154,8 +154,8 @@ typedef struct lt_config {
                                        context.                                 */
     int64_t drain_tile;             /* batch drain: elements of a 1-D stencil or
                                        histogram task per ticket, a multiple of
-                                       4096 (0 = 65536).  Larger tiles take
-                                       fewer tickets; a task's tiles interleave
+                                       4096 (0 = 16384 for stencils, 65536 for
+                                       histograms).  A task's tiles interleave
                                        its 4096-element groups.  Changes speed
                                        only, never results.                   */
 } lt_config;
@@ -230,9 +230,12 @@ typedef struct lt_dist {
  *   Contents are undefined until written or filled.  dist NULL = one chunk.
  * lt_array_create_host: a host-backed array whose home is the caller's
  *   buffer host_ptr (row-major, shape[] elements).  host_ptr is BORROWED for
- *   the array's lifetime; it should be pinned (lt_host_alloc) for
- *   asynchronous copies.  The buffer holds the array's contents after
- *   lt_sync; chunks are loaded on demand and written back when evicted.
+ *   the array's lifetime.  Pinned buffers (lt_host_alloc) are copied
+ *   asynchronously; chunks of a pageable buffer are packed by host threads
+ *   into pinned bounce buffers and copied from there (the packing runs on the
+ *   calling thread's time), and write-backs into a pageable buffer wait for
+ *   their copy.  The buffer holds the array's contents after lt_sync; chunks
+ *   are loaded on demand and written back when evicted.
  * Errors: LT_ERR_INVALID (ndim not in 1..3, shape <= 0, dtype, dist),
  *         LT_ERR_OOM, LT_ERR_BUDGET (creation of an array whose single chunk
  *         exceeds the device budget is allowed; launching on it is not).
@@ -660,7 +663,12 @@ lt_status lt_trace_clear(lt_context *ctx);
  * "graph" (the whole replay).  Meant for measurement runs (the events add a
  * little overhead).  lt_profile_enable(ctx, k): 0 off, 1 every dispatch, k > 1
  * every k-th dispatch of each body (a sample with 1/k of the overhead; the
- * returned counts and totals cover the sampled dispatches).  Copies between
+ * returned counts and totals cover the sampled dispatches), -1 whole steps:
+ * each stream's dispatches between two lt_sync calls are timed as one
+ * interval, entered under the first body dispatched with the number of
+ * dispatches in it (two events per stream and step instead of two per
+ * dispatch; the average includes the gaps between the dispatches, and
+ * copies are not timed).  Copies between
  * host and device memory are timed the same way, as "copy_h2d" and
  * "copy_d2h" (copy-engine copies and copy kernels alike).
  *

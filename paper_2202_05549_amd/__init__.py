@@ -577,10 +577,11 @@ class Context:
         check(self.h, lt_trace_get(self.h, buf, n.value, C.byref(n)))
         return [buf[i] for i in range(n.value)]
 
-    def profile(self, on=True, every=1):
-        """Time dispatches with HIP events: all of them, or every ``every``-th
-        dispatch of each body."""
-        check(self.h, lt_profile_enable(self.h, int(every) if on else 0))
+    def profile(self, on=True, every=1, steps=False):
+        """Time dispatches with HIP events: all of them, every ``every``-th
+        dispatch of each body, or (``steps``) each stream's run of dispatches
+        between two syncs as one interval."""
+        check(self.h, lt_profile_enable(self.h, (-1 if steps else int(every)) if on else 0))
 
     def profile_reset(self):
         check(self.h, lt_profile_reset(self.h))

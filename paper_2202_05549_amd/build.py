@@ -20,7 +20,7 @@ OUT = os.path.join(HERE, "liblt.so")
 BUILD = os.path.join(HERE, "_build")
 ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 
-HOST_SRC = ["annot.cpp", "plan.cpp", "memory.cpp", "exec.cpp", "api.cpp", "serve.cpp", "rtc.cpp"]
+HOST_SRC = ["annot.cpp", "plan.cpp", "memory.cpp", "exec.cpp", "api.cpp", "serve.cpp", "rtc.cpp", "bounce.cpp"]
 HIP_SRC = ["kernels.hip", "gemm.hip", "drain.hip", "reduce.hip"]
 
 HOST_FLAGS = ["-O2", "-g", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",

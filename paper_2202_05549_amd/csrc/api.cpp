@@ -98,6 +98,8 @@ lt_status sync_all(Ctx *ctx) {
         }
     }
     if (!ctx->dry) {
+        lt_status ps = prof_close_steps(ctx);
+        if (ps && !st) st = ps;
         for (int s = 0; s < ctx->nstreams; ++s) {
             hipError_t r = hipStreamSynchronize(ctx->streams[s].h);
             if (r != hipSuccess && !st) st = hip_fail(ctx, r, "hipStreamSynchronize");
@@ -195,6 +197,7 @@ void ctx_release_all(Ctx *ctx) {
     (void)sync_all(ctx);
     drain_pin_pool(ctx);
     if (!ctx->dry) {
+        bounce_release(ctx);
         for (int s = 0; s < ctx->nstreams; ++s)
             if (ctx->streams[s].h) (void)hipStreamDestroy(ctx->streams[s].h);
         for (hipEvent_t e : ctx->event_pool) (void)hipEventDestroy(e);
@@ -931,7 +934,7 @@ static lt_status prof_mark_base(Ctx *ctx) {
 }
 
 lt_status lt_profile_enable(lt_context *ctx, int32_t on) {
-    if (!ctx || on < 0) return LT_ERR_INVALID;
+    if (!ctx || on < -1) return LT_ERR_INVALID;
     const bool was = ctx->prof != 0;
     ctx->prof = on;
     ctx->prof_seen.clear();

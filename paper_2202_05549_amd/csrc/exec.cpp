@@ -207,7 +207,7 @@ static hipEvent_t prof_event(Ctx *ctx) {
 
 lt_status prof_begin(Ctx *ctx, int s, const char *name, hipEvent_t *a) {
     *a = nullptr;
-    if (!ctx->prof || ctx->dry) return LT_OK;
+    if (ctx->prof <= 0 || ctx->dry) return LT_OK;  // off, or whole steps (dispatch)
     if (ctx->prof > 1 && ctx->prof_seen[name]++ % (uint64_t)ctx->prof != 0) return LT_OK;  // sampled
     *a = prof_event(ctx);
     hipError_t r = hipEventRecord(*a, ctx->streams[s].h);
@@ -220,7 +220,7 @@ lt_status prof_end(Ctx *ctx, int s, const char *name, hipEvent_t a) {
     hipEvent_t b = prof_event(ctx);
     hipError_t r = hipEventRecord(b, ctx->streams[s].h);
     if (r != hipSuccess) return hip_fail(ctx, r, "hipEventRecord(profile)");
-    ctx->prof_pending.push_back({name, a, b, s});
+    ctx->prof_pending.push_back({name, a, b, s, 1});
     return LT_OK;
 }
 
@@ -230,7 +230,7 @@ void prof_collect(Ctx *ctx) {
         if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
             lt_kernel_prof &k = ctx->prof_acc[p.name];
             snprintf(k.name, sizeof k.name, "%s", p.name);
-            k.dispatches++;
+            k.dispatches += p.count;
             k.total_ms += ms;
             if (ms > k.max_ms) k.max_ms = ms;
             float t0 = 0.f;
@@ -251,11 +251,38 @@ void prof_collect(Ctx *ctx) {
     ctx->prof_pending.clear();
 }
 
+lt_status prof_close_steps(Ctx *ctx) {
+    if (ctx->dry) return LT_OK;
+    for (int s = 0; s < ctx->nstreams; ++s) {
+        Stream &S = ctx->streams[s];
+        if (!S.step_a) continue;
+        hipEvent_t b = prof_event(ctx);
+        hipError_t r = hipEventRecord(b, S.h);
+        if (r != hipSuccess) return hip_fail(ctx, r, "hipEventRecord(profile)");
+        ctx->prof_pending.push_back({S.step_name, S.step_a, b, s, S.step_count});
+        S.step_a = nullptr;
+        S.step_count = 0;
+    }
+    return LT_OK;
+}
+
 static lt_status dispatch(Ctx *ctx, const KernelDef *def, KLaunch &kl, int s) {
     ctx->stats.dispatches++;
     trace_op(ctx, 0, s, kl.ntask ? 0 : ~0ull, 0, (uint64_t)kl.ntask, 0);
     if (ctx->dry) return LT_OK;
     kl.stream = ctx->streams[s].h;
+    if (ctx->prof < 0) {
+        // whole steps: one event before the stream's first dispatch since
+        // the last sync, one at the sync
+        Stream &S = ctx->streams[s];
+        if (!S.step_a) {
+            S.step_a = prof_event(ctx);
+            hipError_t r = hipEventRecord(S.step_a, S.h);
+            if (r != hipSuccess) return hip_fail(ctx, r, "hipEventRecord(profile)");
+            S.step_name = def->name;
+        }
+        S.step_count++;
+    }
     hipEvent_t pa;
     lt_status st = prof_begin(ctx, s, def->name, &pa);
     if (st) return st;
@@ -369,8 +396,13 @@ static lt_status stage_chunk(Ctx *ctx, Chunk *c, Mode m, const Box &region,
             if (st) return st;
             int64_t ext[MAXD];
             for (int a = 0; a < MAXD; ++a) ext[a] = c->box.hi[a] - c->box.lo[a];
-            st = copy_box(ctx, ctx->h2d, dev_ptr(ctx, c), c->dev_stride, c->host_ptr, c->host_stride, ext,
-                          nd, c->arr->esz, hipMemcpyHostToDevice);
+            if (c->arr->host_backed && !c->arr->home_pinned && !ctx->dry)
+                // a pageable home: packed into pinned bounce buffers first
+                st = bounce_h2d(ctx, ctx->h2d, dev_ptr(ctx, c), c->dev_stride, c->host_ptr, c->host_stride, ext,
+                                nd, c->arr->esz);
+            else
+                st = copy_box(ctx, ctx->h2d, dev_ptr(ctx, c), c->dev_stride, c->host_ptr, c->host_stride, ext,
+                              nd, c->arr->esz, hipMemcpyHostToDevice);
             if (st) return st;
             uint64_t p = bump(ctx, ctx->h2d);
             trace_op(ctx, 1, ctx->h2d, ~0ull, c->id, c->bytes, c->dev_off);
@@ -595,7 +627,13 @@ static lt_status batch_add_exec(Ctx *ctx, const KernelDef *def, TaskPlan &tp, Ta
     if (d.kind != DK_JACOBI2D) {
         // the touch body walks DSPAN-element tiles; the stencil and
         // histogram bodies take whatever count of interleaved tiles
-        const int64_t span = d.kind == DK_TOUCH || ctx->cfg.drain_tile <= 0 ? DSPAN : ctx->cfg.drain_tile;
+        // (defaults measured on the 8192-launch mix: stencil tasks stream
+        // fastest in tiles of 16 Ki elements, histogram tasks, which flush
+        // their sub-histograms once per tile, in tiles of 64 Ki)
+        const int64_t span = d.kind == DK_TOUCH              ? DSPAN
+                             : ctx->cfg.drain_tile > 0       ? ctx->cfg.drain_tile
+                             : d.kind == DK_HIST256          ? DSPAN
+                                                             : DTILE;
         int64_t e = std::min(d.hi0, d.n) - d.lo0;
         d.ntiles = e > 0 ? (int)((e + span - 1) / span) : 0;
     }

@@ -160,7 +160,8 @@ namespace lt {
 // tile finishes also bumps counters[signal] once.
 enum DKind { DK_TOUCH = 0, DK_STENCIL1D = 1, DK_JACOBI2D = 2, DK_HIST256 = 3, DK_SUM_PARTIALS = 4 };
 constexpr int DMAXDEP = 8;
-constexpr int64_t DSPAN = 65536;  // elements per tile of the 1-D bodies
+constexpr int64_t DSPAN = 65536;  // elements per tile of the touch body (and default of the histogram's)
+constexpr int64_t DTILE = 16384;  // default elements per tile of the stencil body
 constexpr int DJROWS = 128;       // rows per Jacobi tile (marched in groups of 8)
 
 struct DTask {

@@ -144,6 +144,14 @@ struct KernelDef {
     void *user = nullptr;   // the RtcKernel of a runtime-compiled user kernel
 };
 
+// H2D out of pageable home buffers (csrc/bounce.cpp): pinned bounce
+// buffers of BOUNCE_BYTES in a ring of BOUNCE_BUFS, packed by BOUNCE_THREADS
+// host threads (the caller included).
+constexpr int64_t BOUNCE_BYTES = (int64_t)64 << 20;
+constexpr int BOUNCE_BUFS = 4;
+constexpr int BOUNCE_THREADS = 8;
+struct BounceRing;
+
 // A user kernel compiled at run time (csrc/rtc.cpp): its definition, the
 // owned strings the definition points to, and its source.
 struct RtcKernel {
@@ -329,6 +337,11 @@ struct Stream {
     uint64_t done = 0;                 // operations known to have completed
     std::deque<Mark> marks;            // events recorded at given seqs
     uint64_t waited[MAXSTREAM] = {0};  // highest seq of other streams waited on
+    // step profiling (lt_profile_enable(ctx, -1)): the event before the
+    // stream's first dispatch since the last sync, its body and the count
+    hipEvent_t step_a = nullptr;
+    const char *step_name = nullptr;
+    uint64_t step_count = 0;
 };
 
 // ------------------------------------------------------------- the arena
@@ -472,6 +485,7 @@ struct lt_context {
     // (looked up at creation; null with scratch_err set if that failed)
     void *scratch = nullptr;
     hipError_t scratch_err = hipSuccess;
+    lt::BounceRing *bounce = nullptr;  // created at the first copy out of a pageable home
 
     // profiling: (kernel name, start, end) awaiting resolution
     int prof = 0;                      // 0 off; k: every k-th dispatch of each body is timed
@@ -480,6 +494,7 @@ struct lt_context {
         const char *name;
         hipEvent_t a, b;
         int stream;
+        uint64_t count;                // dispatches between a and b
     };
     std::vector<ProfPending> prof_pending;
     std::map<std::string, lt_kernel_prof> prof_acc;
@@ -522,6 +537,11 @@ lt_status flush_group(Ctx *ctx);
 lt_status batch_flush(Ctx *ctx);
 lt_status batch_flush_noalloc(Ctx *ctx);
 void fold_drain_status(Ctx *ctx);
+// Copies a box from pageable host memory to the device through the bounce
+// ring (same arguments as copy_box with kind H2D); bounce_release frees it.
+lt_status bounce_h2d(Ctx *ctx, int stream, char *dst, const int64_t *ds, const char *src, const int64_t *ss,
+                     const int64_t *ext, int nd, int esz);
+void bounce_release(Ctx *ctx);
 lt_status rtc_define(Ctx *ctx, const char *source, const char *function, const lt_param *params, int32_t nparams,
                      const char *annotation, lt_kernel **out);
 const char *rtc_last_error(const KernelDef *def);
@@ -536,6 +556,8 @@ lt_status flush_all(Ctx *ctx);
 lt_status prof_begin(Ctx *ctx, int s, const char *name, hipEvent_t *a);
 lt_status prof_end(Ctx *ctx, int s, const char *name, hipEvent_t a);
 void prof_collect(Ctx *ctx);
+// step profiling: closes every stream's open interval (before a sync)
+lt_status prof_close_steps(Ctx *ctx);
 lt_status wait_fence(Ctx *ctx, const Fence &f);
 bool fence_done(Ctx *ctx, const Fence &f);
 lt_status array_flush_async(Ctx *ctx, Array *arr, Fence *out);

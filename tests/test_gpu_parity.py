@@ -610,3 +610,26 @@ def test_host_backed_write_back_paths(L, pinned, engine, shape, chunk):
         ctx.sync()
         got = np.array(B if inp is b else A)
     assert np.array_equal(got, oracle.jacobi2d(x0, 3))
+
+
+@pytest.mark.parametrize("n,chunk", [(3_000_001, 1 << 19), (40_000_000, 1 << 25)])
+def test_stencil1d_pageable_home_out_of_core(L, n, chunk):
+    # a 1-D host-backed array over pageable memory, larger than the device
+    # budget: its chunks reach the device through the pinned bounce ring
+    # (pieces of up to 64 MiB of one row)
+    say("stencil pageable home", n, chunk)
+    x0 = synthetic.stencil1d_input(n, 7)
+    A = x0.copy()
+    B = np.full(n, np.nan, np.float32)
+    with ctx_of(L, device_budget_bytes=6 * chunk * 4 + (1 << 20)) as ctx:
+        a = ctx.array_host(A, chunk=[chunk])
+        b = ctx.array_host(B, chunk=[chunk])
+        inp, out = a, b
+        for _ in range(3):
+            ctx.launch("stencil1d_f32", [n], [256], [chunk], args=[n, out, inp])
+            inp, out = out, inp
+        ctx.sync()
+        st = ctx.stats()
+        got = np.array(B if inp is b else A)
+    assert st["bytes_h2d"] > 0
+    assert np.array_equal(got, oracle.stencil1d_iter(x0, 3))
