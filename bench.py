@@ -754,13 +754,16 @@ def bench_batch(args, L, torch):
         log("fixed parameters: %s" % best)
     else:
         log("autotuning superblock size, drain width, flush size, vector groups and tile size on the full mix")
+        # coordinate descent from the library defaults, two timings per
+        # point, and the three fastest points timed twice more
         best = autotune.tune("batch8192", {"sb": [1 << 20, 1 << 22, 1 << 24], "wg": [1024, 2048],
                                            "flush": [0, 4096], "vec": [2, 4], "tile": [0, 16384, 32768]},
                              lambda sb, wg, flush, vec, tile: run("batched", sb, wg, flush, vec=vec, tile=tile),
-                             reps=1, cache=None, log=log)
+                             reps=2, cache=None, log=log, strategy="descent", confirm=2,
+                             start={"sb": 1 << 24, "wg": 1024, "flush": 0, "vec": 4, "tile": 0})
         log("tuned: %s" % best)
         best_plain = autotune.tune("batch8192_plain", {"sb": [1 << 18, 1 << 20, 1 << 22, 1 << 24]},
-                                   lambda sb: run("plain", sb), reps=1, cache=None, log=log)
+                                   lambda sb: run("plain", sb), reps=2, cache=None, log=log)
         log("tuned plain: %s" % best_plain)
     modes = ("batched", "graph") if args.executor == "drain" else ("plain", "batched", "graph")
     for mode in modes:
