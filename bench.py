@@ -57,6 +57,17 @@ def pct(times, q):
     return float(np.percentile(np.asarray(times) * 1e3, q))
 
 
+def median_runs(fn, runs=5):
+    """Times ``runs`` calls of ``fn`` (after the caller's warm-up); returns
+    the median duration and all of them, in seconds."""
+    ts = []
+    for _ in range(runs):
+        t0 = time.perf_counter()
+        fn()
+        ts.append(time.perf_counter() - t0)
+    return float(np.median(ts)), ts
+
+
 def cpu_model():
     """Model name of this host's CPU (from /proc/cpuinfo), for the CPU
     baselines."""
@@ -147,11 +158,11 @@ TRAFFIC = {
     # 1.000, the 64 B of each point and its 4 B label
     "k_kmeans": {"sources": KMEANS_SOURCES, "digest": "9c654699cb5049b5",
                  "bytes_per_dispatch": 2097210 * 1024 * 2.000 + 262144 * 1024},
-    # k_kmeans_update_v<16, 4>, one dispatch per 2^22-point superblock:
-    # FETCH_SIZE 139,300 KiB x 2.000 + WRITE_SIZE 8,448 KiB x 1.000 (1024
+    # k_kmeans_update_c<16, 8>, one dispatch per 2^22-point superblock:
+    # FETCH_SIZE 139,327 KiB x 2.000 + WRITE_SIZE 4,224 KiB x 1.000 (512
     # partial slots of 64 x 16 float64 sums and 64 counts)
-    "k_kmeans_update": {"sources": KMU_SOURCES, "digest": "d98381726987eb27",
-                        "bytes_per_dispatch": 139300 * 1024 * 2.000 + 8448 * 1024},
+    "k_kmeans_update": {"sources": KMU_SOURCES, "digest": "fd9d3ed93481840f",
+                        "bytes_per_dispatch": 139327 * 1024 * 2.000 + 4224 * 1024},
     # k_drain<27, 4>, one dispatch per step of the 8192-launch mix at
     # superblock 2^24, 1024 workgroups, per-body drain tiles (graph replay):
     # FETCH_SIZE 27,213,872 KiB x 2.000 + WRITE_SIZE 27,245,512 KiB x 1.000 =
@@ -313,23 +324,23 @@ def jacobi_cpu_baseline(x0, budget_s=24.0):
 
     a = np.array(x0, copy=True)
     b = np.empty_like(a)
-    # the first sweep also pays the first touch of b: size the sample on the second
+    # warm-up: the first sweep also pays the first touch of b; the sample is
+    # sized on the second
     oracle.lib().or_jacobi2d_sweep_f32(N, N, a.ctypes.data, b.ctypes.data)
     t0 = time.perf_counter()
     oracle.lib().or_jacobi2d_sweep_f32(N, N, a.ctypes.data, b.ctypes.data)
     one = time.perf_counter() - t0
     # about budget_s of CPU work (the estimate from one sweep runs high, so 10-25 s
-    # in practice): whole steps of SWEEPS sweeps where they fit
-    # (up to 20), else the sweeps of one step that fit
-    sweeps = int(max(1, min(20 * SWEEPS, budget_s / max(one, 1e-3))))
-    if sweeps > SWEEPS:
-        sweeps -= sweeps % SWEEPS
-    t0 = time.perf_counter()
-    oracle.jacobi2d(a, sweeps, inplace=True)
-    dt = time.perf_counter() - t0
-    return {"value": round(sweeps * N * N * 8 / dt / 1e9, 3), "unit": "GB/s", "cores": oracle.num_threads(),
+    # in practice), as five runs of equal length: whole steps of SWEEPS sweeps
+    # per run where they fit (up to 4), else the sweeps that fit
+    per = int(max(1, min(4 * SWEEPS, budget_s / 5 / max(one, 1e-3))))
+    if per > SWEEPS:
+        per -= per % SWEEPS
+    med, ts = median_runs(lambda: oracle.jacobi2d(a, per, inplace=True))
+    return {"value": round(per * N * N * 8 / med / 1e9, 3), "unit": "GB/s", "cores": oracle.num_threads(),
             "cpu_model": cpu_model(), "kind": "oracle",
-            "sample": "%d sweeps of the 16384x16384 float32 field (%d per step), %.2f s" % (sweeps, SWEEPS, dt)}
+            "sample": "median of 5 runs of %d sweeps of the 16384x16384 float32 field (%d per step) after a "
+                      "warm-up sweep; runs %.2f-%.2f s" % (per, SWEEPS, min(ts), max(ts))}
 
 
 def bench_jacobi(args, L, torch):
@@ -663,20 +674,20 @@ def bench_gemm_ooc(args, L, torch):
     return line
 
 
-def gemm_cpu_baseline(A, B, n, rows=64):
-    """The oracle's float64-accumulated product timed on the first ``rows``
-    rows of C (a panel of A times all of B), extrapolated to the whole
-    product by FLOP count."""
+def gemm_cpu_baseline(A, B, n, rows=16):
+    """The oracle's float64-accumulated product timed on ``rows`` rows of C
+    (a panel of A times all of B): one warm-up panel, then the median of
+    five, extrapolated to the whole product by FLOP count."""
     import oracle
 
-    t0 = time.perf_counter()
     oracle.gemm(A[:rows], B)
-    dt = time.perf_counter() - t0
-    rate = 2.0 * rows * n * n / dt
+    med, ts = median_runs(lambda: oracle.gemm(A[rows:2 * rows], B))
+    rate = 2.0 * rows * n * n / med
     return {"value": round(rate / 1e12, 4), "unit": "TFLOP/s", "cores": oracle.num_threads(),
             "cpu_model": cpu_model(), "kind": "oracle",
-            "sample": "%d rows of C (A panel %d x %d times B %d x %d), %.2f s; extrapolated to the whole "
-                      "65536^3 product: %.0f s" % (rows, rows, n, n, n, dt, 2.0 * n ** 3 / rate)}
+            "sample": "median of 5 runs of %d rows of C (A panel %d x %d times B %d x %d) after a warm-up "
+                      "panel; runs %.2f-%.2f s; extrapolated to the whole 65536^3 product: %.0f s"
+                      % (rows, rows, n, n, n, min(ts), max(ts), 2.0 * n ** 3 / rate)}
 
 
 # ==================================================================== batch
@@ -853,24 +864,31 @@ def bench_batch(args, L, torch):
 
 def batch_cpu_baseline(plan, sample, budget_s=12.0):
     """The oracle's stencil and histogram over the inputs of a sample of the
-    mix's launches (the same seeded recipe), repeated to about budget_s of
-    CPU work; GB/s of algorithmic bytes."""
+    mix's launches (the same seeded recipe): one warm-up pass, then five runs
+    of repeated passes, about budget_s of CPU work in all; GB/s of
+    algorithmic bytes at the median run."""
     import oracle
     import synthetic
 
     data = [(plan[i][0], synthetic.batch_data(plan[i][0], plan[i][1], i, 3)) for i in sample]
     nbytes = sum(v.size * (8 if k == 0 else 4) + (0 if k == 0 else 1024) for k, v in data)
-    reps, dt = 0, 0.0
-    t0 = time.perf_counter()
-    while dt < budget_s and reps < 100:
+
+    def one_pass():
         for k, v in data:
             oracle.stencil1d(v) if k == 0 else oracle.hist256(v)
-        reps += 1
-        dt = time.perf_counter() - t0
-    return {"value": round(reps * nbytes / dt / 1e9, 3), "unit": "GB/s", "cores": oracle.num_threads(),
+    t0 = time.perf_counter()
+    one_pass()
+    one = time.perf_counter() - t0
+    reps = int(max(1, min(40, budget_s / 5 / max(one, 1e-3))))
+
+    def run():
+        for _ in range(reps):
+            one_pass()
+    med, ts = median_runs(run)
+    return {"value": round(reps * nbytes / med / 1e9, 3), "unit": "GB/s", "cores": oracle.num_threads(),
             "cpu_model": cpu_model(), "kind": "oracle",
-            "sample": "%d launches of the mix (%d elements) x %d repetitions, %.2f s" %
-                      (len(data), sum(v.size for _, v in data), reps, dt)}
+            "sample": "%d launches of the mix (%d elements): median of 5 runs of %d passes after a warm-up "
+                      "pass; runs %.2f-%.2f s" % (len(data), sum(v.size for _, v in data), reps, min(ts), max(ts))}
 
 
 # ==================================================================== serve
@@ -1073,15 +1091,16 @@ def bench_kmeans(args, L, torch):
     if not args.no_cpu:
         import oracle
 
-        ns = 1 << 21
+        # one round over 2^24 points takes about 1.3 s on the GPU machine's 16 cores
+        ns = 1 << 24
         Xs, mus, _ = synthetic.kmeans_blobs(ns, d, K, seed=4)
         c0 = (mus + np.random.default_rng(5).normal(0, 1.5, mus.shape)).astype(np.float32)
-        t0 = time.perf_counter()
         oracle.kmeans_lloyd(Xs, c0, 1)
-        dt = time.perf_counter() - t0
-        line["cpu_baseline"] = {"value": round(ns * 2 * (d * 4 + 4) / dt / 1e9, 3), "unit": "GB/s",
+        med, ts = median_runs(lambda: oracle.kmeans_lloyd(Xs, c0, 1))
+        line["cpu_baseline"] = {"value": round(ns * 2 * (d * 4 + 4) / med / 1e9, 3), "unit": "GB/s",
                                 "cores": oracle.num_threads(), "cpu_model": cpu_model(), "kind": "oracle",
-                                "sample": "one round of %d points (of %d x 5 per step), %.2f s" % (ns, N, dt)}
+                                "sample": "median of 5 runs of one round over %d points (of %d x 5 per step) "
+                                          "after a warm-up round; runs %.2f-%.2f s" % (ns, N, min(ts), max(ts))}
     return line
 
 
@@ -1223,13 +1242,12 @@ def main():
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one 1 GiB float32 device copy first (the reference kernel for HBM counter scaling)")
     ap.add_argument("--kmu-variant", type=int, default=0,
-                    help="kmeans: centre-update body (lt_kernel_tune: 2 = two features per lane)")
-    ap.add_argument("--d2h-kernel", type=int, default=-1,
-                    help="serve: write-backs into pinned homes through a copy kernel (1) or the copy engine (0); "
-                         "-1 = the copy kernel for --serve-full (pageable inputs keep the copy engines busy), "
-                         "the copy engine otherwise")
+                    help="kmeans: centre-update body (lt_kernel_tune): 0 = default (d 16/32: one feature per "
+                         "lane, two LDS copies per wave), 1 = four features per lane, 2 = two features per lane")
+    ap.add_argument("--d2h-kernel", type=int, default=0,
+                    help="serve: write-backs into pinned homes through a copy kernel (1) or the copy engine (0)")
     ap.add_argument("--tuned", default="",
-                    help="batch: fixed SB:WG:FLUSH:VEC instead of the autotuning sweep")
+                    help="batch: fixed SB:WG:FLUSH:VEC:TILE instead of the autotuning sweep")
     ap.add_argument("--serve-full", action="store_true",
                     help="serving trace at the full size ranges (GEMM to 65536, k-means to 1e9 points)")
     args = ap.parse_args()

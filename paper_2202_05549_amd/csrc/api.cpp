@@ -106,6 +106,9 @@ lt_status sync_all(Ctx *ctx) {
         }
         prof_collect(ctx);
         fold_drain_status(ctx);
+        // spill file transfers ran on the streams just drained
+        lt_status ds = disk_status(ctx);
+        if (ds && !st) st = ds;
         for (int32_t *gs : ctx->graph_status)
             if (*gs && ctx->sticky == LT_OK) {
                 ctx->sticky = LT_ERR_TIMEOUT;
@@ -287,6 +290,9 @@ lt_status array_write(Ctx *ctx, Array *arr, const void *src, bool device_src) {
             }
             st = ensure_host_copy(ctx, c);
             if (st) return st;
+            // a recycled spill buffer may still be read by a spill file write
+            st = wait_fence(ctx, c->host_ready);
+            if (st) return st;
             if (c->host_ptr != sp) {
                 st = copy_box(ctx, ctx->h2d, c->host_ptr, c->host_stride, sp, arr->strides, ext, nd, arr->esz,
                               hipMemcpyHostToHost);
@@ -342,6 +348,10 @@ lt_status array_read(Ctx *ctx, Array *arr, void *dst, bool device_dst) {
             int64_t off = 0;
             for (int a = 0; a < nd; ++a) off += c->box.lo[a] * arr->strides[a];
             if ((char *)dst + off * arr->esz == c->host_ptr) continue;  // the home buffer itself
+            // a read back from the spill file runs on the H2D stream: a
+            // device-bound copy waits for it on the stream, a host memcpy here
+            st = device_dst ? stream_wait(ctx, ctx->d2h, c->host_ready) : wait_fence(ctx, c->host_ready);
+            if (st) return st;
             // host -> host or host -> device through the copy helper on d2h
             st = copy_sub(ctx, ctx->d2h, (char *)dst, zero, arr->strides, c->host_ptr, c->box.lo, c->host_stride,
                           c->core, nd, arr->esz, device_dst ? hipMemcpyHostToDevice : hipMemcpyHostToHost);
@@ -349,6 +359,8 @@ lt_status array_read(Ctx *ctx, Array *arr, void *dst, bool device_dst) {
         }
         r = hipStreamSynchronize(ctx->streams[ctx->d2h].h);
         if (r != hipSuccess) return hip_fail(ctx, r, "hipStreamSynchronize");
+        st = disk_status(ctx);
+        if (st) return st;
     }
     if (ctx->sticky != LT_OK) {
         lt_status s = ctx->sticky;
@@ -372,6 +384,8 @@ lt_status array_fill(Ctx *ctx, Array *arr, const void *scalar) {
             hipError_t r = hipDeviceSynchronize();
             if (r != hipSuccess) return hip_fail(ctx, r, "hipDeviceSynchronize");
             st = ensure_host_copy(ctx, c);
+            if (st) return st;
+            st = wait_fence(ctx, c->host_ready);
             if (st) return st;
             std::vector<char> tmp((size_t)c->bytes);
             for (int64_t i = 0; i < c->elems; ++i) memcpy(tmp.data() + i * arr->esz, scalar, arr->esz);

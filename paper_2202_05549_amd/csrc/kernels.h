@@ -68,14 +68,18 @@ hipError_t launch_rtc(const KLaunch &);
 
 // k-means update: points per workgroup tile and the largest number of
 // workgroups (= partial slots) per task.  A task of p points gets
-// kmu_slots(p) workgroups; workgroup w takes tiles w, w + slots, ... in
+// kmu_slots(p, d) workgroups; workgroup w takes tiles w, w + slots, ... in
 // order and writes slot w, so the float folds never depend on scheduling.
+// The cap is about as many workgroups as fit on the chip at once: 1024 for
+// the bodies with one LDS copy per wave, 512 for d = 16 and 32, whose body
+// keeps two copies per wave (two workgroups per CU).
 constexpr int64_t KMU_TILE = 4096;
-constexpr int64_t KMU_MAXSLOTS = 1024;  // about as many workgroups as fit on the chip at once
-inline int64_t kmu_slots(int64_t points) {
+constexpr int64_t KMU_MAXSLOTS = 1024;
+inline int64_t kmu_slot_cap(int64_t d) { return d == 16 || d == 32 ? 512 : KMU_MAXSLOTS; }
+inline int64_t kmu_slots(int64_t points, int64_t d) {
     if (points <= 0) return 1;
-    int64_t t = (points + KMU_TILE - 1) / KMU_TILE;
-    return t < KMU_MAXSLOTS ? t : KMU_MAXSLOTS;
+    const int64_t t = (points + KMU_TILE - 1) / KMU_TILE, cap = kmu_slot_cap(d);
+    return t < cap ? t : cap;
 }
 // hist256 outside batches: one workgroup and one partial slot per 64 Ki
 // elements of a task (at most 1024, at least one); each workgroup stores its
@@ -95,7 +99,7 @@ constexpr int KMU_MAXKD = 1536;   // K * d limit: four float64 copies stay under
 // partial slots of a k-means update task over points [lo, min(hi, N))
 inline int64_t kmeans_update_slots(const int64_t *lo, const int64_t *hi, const int64_t *iarg) {
     const int64_t end = hi[0] < iarg[0] ? hi[0] : iarg[0];
-    return kmu_slots(end - lo[0]);
+    return kmu_slots(end - lo[0], iarg[1]);
 }
 
 // Runtime helpers.

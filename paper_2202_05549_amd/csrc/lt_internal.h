@@ -8,6 +8,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <cstdint>
 #include <cstring>
 #include <deque>
@@ -236,7 +237,8 @@ struct Chunk {
 
     Fence data_ready;   // the device copy holds valid data after this
     Fence last_access;  // every device-side use so far
-    Fence host_ready;   // host copy complete (after a write-back)
+    Fence host_ready;   // host copy complete (after a write-back or a read from the spill file)
+    Fence disk_ready;   // the spill file slot is written (the write is a host function on the D2H stream)
     uint64_t lru = 0;
     int pin = 0;
 
@@ -445,9 +447,19 @@ struct lt_context {
     int32_t cur_task = 0;         // index of the task being issued in it
     // disk tier: pinned spill memory in use, the spill file and its next free slot
     int64_t host_spill_bytes = 0;
-    std::multimap<int64_t, char *> pin_pool;  // recycled pinned spill buffers by size
+    // recycled pinned spill buffers by size, each free for a new owner once
+    // its fence has passed (a pending spill file write may still read it)
+    struct PooledPin {
+        char *p;
+        lt::Fence ready;
+    };
+    std::multimap<int64_t, PooledPin> pin_pool;
     int64_t pin_pooled = 0;
     int spill_fd = -1;
+    // first error of a spill file read or write, set by the host functions
+    // that run them: errno, and 1 for a read or 2 for a write
+    std::atomic<int> disk_errno{0};
+    std::atomic<int> disk_errop{0};
     int64_t disk_next = 0;
     std::string spill_dir;             // copy of cfg.spill_dir
 
@@ -604,6 +616,8 @@ lt_status ensure_host_copy(Ctx *ctx, Chunk *c);
 lt_status host_resident(Ctx *ctx, Chunk *c);
 // releases c's pinned spill buffer (and its disk slot stays reserved)
 void free_spill(Ctx *ctx, Chunk *c);
+// the first failed spill file read or write since the last call, as an error
+lt_status disk_status(Ctx *ctx);
 // Unpins every recycled spill buffer (context teardown).
 void drain_pin_pool(Ctx *ctx);
 char *dev_ptr(Ctx *ctx, const Chunk *c);

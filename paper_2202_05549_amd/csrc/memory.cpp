@@ -383,8 +383,12 @@ static void note_resident(Ctx *ctx) {
 // Spill buffers of device-home arrays live in pinned host memory up to
 // cfg.host_budget_bytes; beyond it the least recently used ones move to a
 // spill file (one slot per chunk) and come back on demand (Sec. 3.4: the
-// memory hierarchy continues below host memory).  Moving a buffer waits on
-// the host for every copy into or out of it.
+// memory hierarchy continues below host memory).  The file reads and writes
+// run as host functions on the copy streams (hipLaunchHostFunc), ordered
+// with the copies by the streams themselves: a write follows the copies
+// into or out of its buffer on the D2H stream, and a read precedes the H2D
+// copy of its chunk on the H2D stream.  The issuing thread never waits for
+// the disk.
 
 static lt_status open_spill_file(Ctx *ctx) {
     if (ctx->spill_fd >= 0 || ctx->dry) return LT_OK;
@@ -400,6 +404,57 @@ static lt_status open_spill_file(Ctx *ctx) {
     return LT_OK;
 }
 
+// One spill file transfer, run by the HIP runtime's host-function thread.
+struct DiskJob {
+    Ctx *ctx;
+    int fd;
+    char *p;
+    int64_t bytes, off;
+    bool write;
+};
+
+static void disk_io(void *arg) {
+    DiskJob *j = static_cast<DiskJob *>(arg);
+    int64_t done = 0;
+    while (done < j->bytes) {
+        const ssize_t r = j->write ? pwrite(j->fd, j->p + done, (size_t)(j->bytes - done), j->off + done)
+                                   : pread(j->fd, j->p + done, (size_t)(j->bytes - done), j->off + done);
+        if (r <= 0) {
+            int expected = 0;
+            // the first error wins; its operation is published after it
+            if (j->ctx->disk_errno.compare_exchange_strong(expected, r < 0 ? errno : EIO))
+                j->ctx->disk_errop.store(j->write ? 2 : 1);
+            break;
+        }
+        done += r;
+    }
+    delete j;
+}
+
+// Enqueues a transfer of `bytes` between p and the spill file at `off` on
+// stream s; *seq is the stream position after it.
+static lt_status enqueue_disk(Ctx *ctx, int s, char *p, int64_t bytes, int64_t off, bool write, uint64_t *seq) {
+    DiskJob *j = new DiskJob{ctx, ctx->spill_fd, p, bytes, off, write};
+    const hipError_t r = hipLaunchHostFunc(ctx->streams[s].h, disk_io, j);
+    if (r != hipSuccess) {
+        delete j;
+        return hip_fail(ctx, r, write ? "hipLaunchHostFunc(spill file write)" : "hipLaunchHostFunc(spill file read)");
+    }
+    *seq = bump(ctx, s);
+    return LT_OK;
+}
+
+lt_status disk_status(Ctx *ctx) {
+    const int e = ctx->disk_errno.load();
+    if (!e) return LT_OK;
+    int op = 0;
+    while (!(op = ctx->disk_errop.load())) {
+    }
+    ctx->disk_errop.store(0);
+    ctx->disk_errno.store(0);
+    return set_err(ctx, LT_ERR_OOM, "spill file %s: %s", op == 2 ? "write" : "read", strerror(e));
+}
+
 // Pinned spill buffers are recycled through a pool keyed by size: pinning
 // and unpinning host memory costs milliseconds per buffer (hipHostFree may
 // also wait for the device), while chunks of one array all have one size.
@@ -412,21 +467,24 @@ static void pin_release(Ctx *ctx, char *p) {
     else (void)hipHostFree(p);
 }
 
-static char *pool_take(Ctx *ctx, int64_t bytes) {
+static char *pool_take(Ctx *ctx, int64_t bytes, Fence *ready) {
     auto it = ctx->pin_pool.find(bytes);
     if (it == ctx->pin_pool.end()) return nullptr;
-    char *p = it->second;
+    char *p = it->second.p;
+    *ready = it->second.ready;
     ctx->pin_pool.erase(it);
     ctx->pin_pooled -= bytes;
     return p;
 }
 
-// Frees one pooled buffer (the largest); false when the pool is empty.
+// Frees one pooled buffer (the largest), after the transfers still using
+// it; false when the pool is empty.
 static bool pool_shrink(Ctx *ctx) {
     if (ctx->pin_pool.empty()) return false;
     auto it = std::prev(ctx->pin_pool.end());
+    (void)wait_fence(ctx, it->second.ready);
     ctx->pin_pooled -= it->first;
-    pin_release(ctx, it->second);
+    pin_release(ctx, it->second.p);
     ctx->pin_pool.erase(it);
     return true;
 }
@@ -436,13 +494,16 @@ void drain_pin_pool(Ctx *ctx) {
     }
 }
 
-void free_spill(Ctx *ctx, Chunk *c) {
+// Returns c's spill buffer to the pool (or frees it), free for a new owner
+// after `release`.
+static void release_spill(Ctx *ctx, Chunk *c, const Fence &release) {
     if (!c->host_owned || !c->host_ptr) return;
     const int64_t cap = (int64_t)ctx->cfg.host_budget_bytes;
     if (cap > 0 || ctx->pin_pooled + c->bytes <= PIN_POOL_CAP) {
-        ctx->pin_pool.emplace(c->bytes, c->host_ptr);
+        ctx->pin_pool.emplace(c->bytes, Ctx::PooledPin{c->host_ptr, release});
         ctx->pin_pooled += c->bytes;
     } else {
+        (void)wait_fence(ctx, release);
         pin_release(ctx, c->host_ptr);
     }
     c->host_ptr = nullptr;
@@ -450,55 +511,67 @@ void free_spill(Ctx *ctx, Chunk *c) {
     ctx->stats.host_spill_bytes = (uint64_t)ctx->host_spill_bytes;
 }
 
+void free_spill(Ctx *ctx, Chunk *c) {
+    // any copy into or out of the buffer, and a pending spill file write
+    Fence f = c->host_ready;
+    f.merge(c->last_access);
+    f.merge(c->disk_ready);
+    release_spill(ctx, c, f);
+}
+
 // Moves one spill buffer to the spill file (if it holds data the file does
-// not have yet) and frees it.
+// not have yet) and releases it.
 static lt_status demote(Ctx *ctx, Chunk *c) {
     Fence f = c->host_ready;
     f.merge(c->last_access);
-    lt_status st = wait_fence(ctx, f);
-    if (st) return st;
+    Fence release = f;
     if (c->host_valid && c->defined && !c->disk_valid) {
-        st = open_spill_file(ctx);
+        lt_status st = open_spill_file(ctx);
         if (st) return st;
         if (c->disk_off < 0) {
             c->disk_off = ctx->disk_next;
             ctx->disk_next += round_up(c->bytes, 4096);
         }
         if (!ctx->dry) {
-            int64_t done = 0;
-            while (done < c->bytes) {
-                ssize_t w = pwrite(ctx->spill_fd, c->host_ptr + done, (size_t)(c->bytes - done), c->disk_off + done);
-                if (w <= 0) return set_err(ctx, LT_ERR_OOM, "spill file write: %s", strerror(errno));
-                done += w;
-            }
+            // after the copies into and out of the buffer
+            st = stream_wait(ctx, ctx->d2h, f);
+            if (st) return st;
+            uint64_t seq;
+            st = enqueue_disk(ctx, ctx->d2h, c->host_ptr, c->bytes, c->disk_off, true, &seq);
+            if (st) return st;
+            c->disk_ready = Fence();
+            c->disk_ready.add(ctx->d2h, seq);
+            release = c->disk_ready;
         }
         c->disk_valid = true;
         ctx->stats.bytes_disk_write += (uint64_t)c->bytes;
         trace_op(ctx, 8, -1, ~0ull, c->id, (uint64_t)c->bytes, (uint64_t)c->disk_off);
     }
-    free_spill(ctx, c);
+    release_spill(ctx, c, release);
     return LT_OK;
 }
 
 // A pinned buffer of `need` bytes for chunk `keep`: from the pool when one of
-// that size is there, else newly pinned once the held and pooled buffers
-// leave room under the host budget.  Room is made by freeing pooled
-// buffers, then by moving the least recently used spill buffer to the disk
-// tier (its buffer returns to the pool and is taken here when it fits).
-static lt_status pinned_for(Ctx *ctx, int64_t need, const Chunk *keep, char **out) {
+// that size is there (free after *ready), else newly pinned once the held
+// and pooled buffers leave room under the host budget.  Room is made by
+// freeing pooled buffers, then by moving the least recently used spill
+// buffer to the disk tier (its buffer returns to the pool and is taken here
+// when it fits).
+static lt_status pinned_for(Ctx *ctx, int64_t need, const Chunk *keep, char **out, Fence *ready) {
     const int64_t cap = (int64_t)ctx->cfg.host_budget_bytes;
     if (cap > 0 && need > cap)
         return set_err(ctx, LT_ERR_BUDGET, "a %lld-byte spill buffer exceeds the host budget of %lld bytes",
                        (long long)need, (long long)cap);
+    *ready = Fence();
     for (;;) {
-        if (char *p = pool_take(ctx, need)) {
+        if (char *p = pool_take(ctx, need, ready)) {
             *out = p;
             return LT_OK;
         }
         if (cap <= 0 || ctx->host_spill_bytes + ctx->pin_pooled + need <= cap) break;
         if (pool_shrink(ctx)) continue;
-        // any other buffer may go: a host copy is only read right after it
-        // is made resident, and demote() waits for the copies using it
+        // any other buffer may go: its new owner's transfers wait for the
+        // copies and the spill file write using it
         Chunk *victim = nullptr;
         for (Array *arr : ctx->arrays)
             for (Chunk *c : arr->chunks)
@@ -526,12 +599,17 @@ lt_status host_resident(Ctx *ctx, Chunk *c) {
     lt_status st = ensure_host_copy(ctx, c);
     if (st) return st;
     if (!ctx->dry) {
-        int64_t done = 0;
-        while (done < c->bytes) {
-            ssize_t r = pread(ctx->spill_fd, c->host_ptr + done, (size_t)(c->bytes - done), c->disk_off + done);
-            if (r <= 0) return set_err(ctx, LT_ERR_OOM, "spill file read: %s", strerror(errno));
-            done += r;
-        }
+        // after the buffer's previous users and the slot's write; the H2D
+        // copy of the chunk follows on the same stream
+        Fence f = c->host_ready;
+        f.merge(c->disk_ready);
+        st = stream_wait(ctx, ctx->h2d, f);
+        if (st) return st;
+        uint64_t seq;
+        st = enqueue_disk(ctx, ctx->h2d, c->host_ptr, c->bytes, c->disk_off, false, &seq);
+        if (st) return st;
+        c->host_ready = Fence();
+        c->host_ready.add(ctx->h2d, seq);
     }
     ctx->stats.bytes_disk_read += (uint64_t)c->bytes;
     trace_op(ctx, 9, -1, ~0ull, c->id, (uint64_t)c->bytes, (uint64_t)c->disk_off);
@@ -549,10 +627,13 @@ lt_status ensure_host_copy(Ctx *ctx, Chunk *c) {
         return LT_OK;
     }
     char *p = nullptr;
-    lt_status st = pinned_for(ctx, c->bytes, c, &p);
+    Fence ready;
+    lt_status st = pinned_for(ctx, c->bytes, c, &p, &ready);
     if (st) return st;
     c->host_ptr = p;
     c->host_owned = true;
+    // writers into the buffer wait for its previous owner's transfers
+    c->host_ready = ready;
     ctx->host_spill_bytes += c->bytes;
     ctx->stats.host_spill_bytes = (uint64_t)ctx->host_spill_bytes;
     for (int a = 0; a < MAXD; ++a) c->host_stride[a] = c->dev_stride[a];
@@ -581,7 +662,11 @@ lt_status copy_sub(Ctx *ctx, int stream, char *dst, const int64_t *dlo, const in
 lt_status write_back(Ctx *ctx, Chunk *c, uint64_t *seq) {
     lt_status st = ensure_host_copy(ctx, c);
     if (st) return st;
-    st = stream_wait(ctx, ctx->d2h, c->data_ready);
+    // after the device copy is written, and after earlier transfers of the
+    // host buffer (a pooled buffer's previous owner included)
+    Fence f = c->data_ready;
+    f.merge(c->host_ready);
+    st = stream_wait(ctx, ctx->d2h, f);
     if (st) return st;
     const Array *arr = c->arr;
     const Box &part = arr->host_backed ? c->core : c->box;

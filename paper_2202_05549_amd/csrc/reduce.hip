@@ -599,6 +599,158 @@ __global__ __launch_bounds__(256) void k_kmeans_update_v(KUArgs a) {
     kmu_flush(lds, VD, K, t, w);
 }
 
+// d = VD in {16, 32} with dense rows: one feature per lane, P = 64 / VD
+// points per step (point q on lanes q VD .. q VD + VD - 1).  Each wave has
+// two LDS copies of the sums, interleaved by cluster: row k holds copy 0's
+// VD doubles and then copy 1's (double k 2VD + c VD + j), and point q of a
+// step adds into copy q % 2.  A row is 4 VD dwords, a multiple of 64, so
+// copy 0 of every cluster starts on one bank and copy 1 VD doubles further:
+// the two points that share an LDS half-instruction (32 lanes) fall on
+// disjoint banks whatever their clusters.  Only points q and q + 2 share a
+// copy; when their clusters agree, point q + 2 adds in a second round, so
+// each cell of a copy is a sequential sum in point order.  Counts are
+// integer adds in one copy per wave, exact in any order.
+// Loads one batch of U steps: lane (q, j) gets feature j of point
+// pb + u P + q and that point's raw label.  With FULL every point of the
+// batch is in range and the loads take immediate offsets from one scalar
+// base; otherwise points at or past p1 read point p1 - 1 instead.  Either
+// way every load is issued and none of the loaded values is inspected here,
+// so the wave does not wait for a batch until it adds it.
+template <int VD, int U, bool FULL>
+__device__ __forceinline__ void kmc_load(const KUReg &t, int64_t pb, int64_t p1, int lane, float *xv, int *kv) {
+    constexpr int P = 64 / VD;
+    const int q = lane / VD, j = lane % VD;
+    if constexpr (FULL) {
+        const LT_GLOBAL float *x = t.X + pb * VD + lane;
+        const LT_GLOBAL int32_t *lb = t.LB + pb + q;
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            xv[u] = __builtin_nontemporal_load(x + u * 64);
+            kv[u] = lb[u * P];
+        }
+    } else {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            int64_t p = pb + (int64_t)u * P + q;
+            p = p < p1 ? p : p1 - 1;
+            xv[u] = t.X[p * VD + j];
+            kv[u] = t.LB[p];
+        }
+    }
+}
+
+// Adds one loaded batch; nleft = points of the batch inside the range
+// (unchecked with FULL).  Point q + 2 of a step finds the cluster of point
+// q, its copy-mate, 32 lanes down with one lane swap of the two wave halves.
+// The batch's counts go in one integer LDS add after its U steps: lane
+// (q, j) with j < U counts point q of step j (integer adds need no order,
+// and the atomic keeps equal clusters in one instruction correct).
+template <int VD, int U, bool FULL>
+__device__ __forceinline__ void kmc_add(double *acc, int *cnt, const float *xv, const int *kv, int64_t nleft, int q,
+                                        int j, int K) {
+    constexpr int P = 64 / VD;
+    static_assert(U <= VD, "one count lane per step");
+    const int krow = 2 * VD;
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int k = kv[u];
+        const bool ok = (unsigned)k < (unsigned)K && (FULL || (int64_t)(u * P + q) < nleft);
+        bool late = false;
+        if constexpr (P == 4) {
+            // lanes 32..63 receive lanes 0..31 of k: the copy-mate's cluster
+            const int mate = __builtin_amdgcn_permlane32_swap(k, k, false, false)[0];
+            late = ok && q >= 2 && k == mate;
+        }
+        if (ok && !late) lds_add(acc + k * krow, (double)xv[u]);
+        if constexpr (P == 4) {
+            if (__builtin_amdgcn_ballot_w64(late)) {
+                asm volatile("" ::: "memory");
+                if (late) lds_add(acc + k * krow, (double)xv[u]);
+            }
+        }
+        asm volatile("" ::: "memory");
+    }
+    int kc = -1;
+#pragma unroll
+    for (int u = 0; u < U; ++u) kc = j == u ? kv[u] : kc;
+    if (j < U && (unsigned)kc < (unsigned)K && (FULL || (int64_t)(j * P + q) < nleft)) lds_add(&cnt[kc], 1);
+}
+
+// Points [p0, p1) of one wave: two register batches, A and B, alternate, so
+// the next batch is in flight while the current one is added.  With FULL,
+// p1 - p0 is a whole number of batch pairs (a whole quarter tile).
+template <int VD, int U, bool FULL>
+__device__ __forceinline__ void kmc_range(const KUReg &t, double *acc, int *cnt, int64_t p0, int64_t p1, int lane,
+                                          int K) {
+    constexpr int P = 64 / VD;
+    constexpr int64_t BATCH = (int64_t)U * P;
+    const int q = lane / VD, j = lane % VD;
+    float xa[U], xb[U];
+    int ka[U], kb[U];
+    kmc_load<VD, U, FULL>(t, p0, p1, lane, xa, ka);
+    for (int64_t pb = p0;; pb += 2 * BATCH) {
+        if (!FULL && pb + BATCH >= p1) {
+            kmc_add<VD, U, FULL>(acc, cnt, xa, ka, p1 - pb, q, j, K);
+            break;
+        }
+        kmc_load<VD, U, FULL>(t, pb + BATCH, p1, lane, xb, kb);
+        kmc_add<VD, U, FULL>(acc, cnt, xa, ka, p1 - pb, q, j, K);
+        if (pb + 2 * BATCH >= p1) {
+            kmc_add<VD, U, FULL>(acc, cnt, xb, kb, p1 - pb - BATCH, q, j, K);
+            break;
+        }
+        kmc_load<VD, U, FULL>(t, pb + 2 * BATCH, p1, lane, xa, ka);
+        kmc_add<VD, U, FULL>(acc, cnt, xb, kb, p1 - pb - BATCH, q, j, K);
+    }
+}
+
+template <int VD, int U>
+__global__ __launch_bounds__(256) void k_kmeans_update_c(KUArgs a) {
+    constexpr int P = 64 / VD;
+    static_assert(P == 2 || P == 4, "two or four points per step");
+    constexpr int64_t QUARTER = KMU_TILE / 4;
+    static_assert(QUARTER % (2 * U * P) == 0, "a quarter tile is a whole number of batch pairs");
+    extern __shared__ double lds[];
+    const int ti = find_task(a.begin, a.ntask, blockIdx.x);
+    const KUReg t = kmu_regs(a.t[ti]);
+    const int w = blockIdx.x - a.begin[ti];
+    const int K = a.K, KROW = 2 * VD, KD2 = K * KROW;
+    // the wave index is uniform: readfirstlane keeps the point ranges, and
+    // the branches on them, scalar
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+    int *cnt_all = reinterpret_cast<int *>(lds + 4 * KD2);
+    for (int i = threadIdx.x; i < 4 * KD2; i += 256) lds[i] = 0.0;
+    for (int i = threadIdx.x; i < 4 * K; i += 256) cnt_all[i] = 0;
+    __syncthreads();
+    const int q = lane / VD, j = lane % VD;
+    double *acc = lds + wave * KD2 + (q & 1) * VD + j;
+    int *cnt = cnt_all + wave * K;
+    for (int64_t tile = w; t.lo + tile * KMU_TILE < t.hi; tile += t.nslots) {
+        const int64_t p0 = t.lo + tile * KMU_TILE + wave * QUARTER;
+        const int64_t p1 = p0 + QUARTER < t.hi ? p0 + QUARTER : t.hi;
+        if (p1 - p0 == QUARTER) kmc_range<VD, U, true>(t, acc, cnt, p0, p1, lane, K);
+        else if (p0 < p1) kmc_range<VD, U, false>(t, acc, cnt, p0, p1, lane, K);
+    }
+    // the eight copies in wave order, copy 0 before copy 1, into slot w
+    __syncthreads();
+    LT_GLOBAL double *S = t.S + (int64_t)w * t.sslot;
+    for (int e = threadIdx.x; e < K * VD; e += 256) {
+        const int k = e / VD, jj = e % VD;
+        const int i = k * KROW + jj;
+        double s = lds[i];
+        s += lds[i + VD];
+#pragma unroll
+        for (int v = 1; v < 4; ++v) {
+            s += lds[v * KD2 + i];
+            s += lds[v * KD2 + i + VD];
+        }
+        S[k * t.ss0 + jj * t.ss1] = s;
+    }
+    LT_GLOBAL int32_t *Cn = t.C + (int64_t)w * t.cslot;
+    for (int k = threadIdx.x; k < K; k += 256)
+        Cn[k * t.cs0] = cnt_all[k] + cnt_all[K + k] + cnt_all[2 * K + k] + cnt_all[3 * K + k];
+}
+
 hipError_t launch_kmeans_update_f32(const KLaunch &L) {
     // parameters: N, d, K, sums, counts, X, lab
     KUArgs a;
@@ -627,7 +779,7 @@ hipError_t launch_kmeans_update_f32(const KLaunch &L) {
         u.xs = k.v[5].s[0];
         u.lab = k.v[6].base;
         const int64_t e = u.hi - u.lo;
-        u.nslots = (int)kmu_slots(e);
+        u.nslots = (int)kmu_slots(e, a.d);
         // a task with several slots needs the slot strides from the planner
         if (u.nslots > 1 && (u.sslot <= 0 || u.cslot <= 0)) return hipErrorInvalidValue;
         // every slot gets its workgroup, empty tasks included: the partials
@@ -644,11 +796,26 @@ hipError_t launch_kmeans_update_f32(const KLaunch &L) {
     bool vec = a.d == a.dp && a.d >= 4;  // d in {4, 8, 16, 32}
     for (int i = 0; i < L.ntask && vec; ++i)
         vec = a.t[i].xs == a.d && a.t[i].x % 16 == 0 && (a.t[i].lo * a.d * 4) % 16 == 0;
+    if (vec && a.d >= 16 && L.variant == 0) {
+        // d in {16, 32}: one feature per lane with two interleaved copies per
+        // wave: 4 x K x 2d float64 sums and K int32 counts per wave, at most
+        // 4 x 1536 x 2 x 8 + 4 x 96 x 4 bytes
+        const size_t lc = (size_t)4 * a.K * 2 * a.d * sizeof(double) + (size_t)4 * a.K * sizeof(int);
+        void (*f)(KUArgs) = a.d == 16 ? k_kmeans_update_c<16, 8> : k_kmeans_update_c<32, 8>;
+        if (lc > 65536) {
+            // more than 64 KiB of dynamic LDS (up to 160 KiB per workgroup on gfx950)
+            const hipError_t e = hipFuncSetAttribute((const void *)f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lc);
+            if (e != hipSuccess) return e;
+        }
+        hipLaunchKernelGGL(f, g, b, lc, L.stream, a);
+        return hipGetLastError();
+    }
     if (vec) {
         switch (a.d) {
-            // four features per lane; variant 2 takes two (d >= 8): fewer add
-            // rounds per point, but measured slower (3.24 against 3.45 TB/s at
-            // d = 16, K = 64), the LDS being bound by lanes, not instructions
+            // four features per lane (d in {4, 8}, and variant 1 for d in
+            // {16, 32}); variant 2 takes two (d >= 8): fewer add rounds per
+            // point, but measured slower (3.24 against 3.45 TB/s at d = 16,
+            // K = 64), the LDS being bound by lanes, not instructions
             case 4: hipLaunchKernelGGL((k_kmeans_update_v<4, 4>), g, b, lds, L.stream, a); break;
             case 8:
                 if (L.variant == 2) hipLaunchKernelGGL((k_kmeans_update_v<8, 2>), g, b, lds, L.stream, a);

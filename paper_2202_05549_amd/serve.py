@@ -261,9 +261,7 @@ def bench(args, L, torch, log, overlap=None):
     # two compute streams: with the H2D and D2H streams that makes four,
     # the number of hardware queues a process gets by default; more streams
     # would share queues and order unrelated work behind each other
-    d2h_kernel = getattr(args, "d2h_kernel", -1)
-    if d2h_kernel < 0:
-        d2h_kernel = 1 if full else 0
+    d2h_kernel = getattr(args, "d2h_kernel", 0)
     ctx = L.Context(device_budget_bytes=budget, n_compute_streams=2, stage_threshold_bytes=8 << 30,
                     sb_order=L.LT_ORDER_SERPENTINE, d2h_kernel=d2h_kernel)
     slots = 16

@@ -263,12 +263,13 @@ def test_kmeans_lloyd_five_rounds(L):
 
 @pytest.mark.parametrize("d", [8, 16, 32])
 def test_kmeans_update_lane_widths_bit_identical(L, d):
-    # two or four features per lane add the same values in the same order
+    # two or four features per lane (tuning variants 2 and 1) add the same
+    # values in the same order
     N, K, sb = 70001, 40 if d == 32 else 64, 16384
     say("kmeans update lane widths", d)
     X, _, z = synthetic.kmeans_blobs(N, d, K, seed=21)
     outs = []
-    for variant in (0, 2):
+    for variant in (1, 2):
         with ctx_of(L) as ctx:
             if variant:
                 ctx.tune("kmeans_update_f32", variant)
@@ -277,6 +278,31 @@ def test_kmeans_update_lane_widths_bit_identical(L, d):
     assert np.array_equal(outs[0][1], outs[1][1])
     rs, rc, ra = oracle.kmeans_update(X, z, K)
     assert np.array_equal(outs[0][1].astype(np.int64), rc)
+
+
+@pytest.mark.parametrize("variant", [0, 1])
+@pytest.mark.parametrize("N,d,K,sb", [(312345, 16, 64, 65536), (50001, 32, 48, 4096), (20000, 16, 96, 1 << 20),
+                                      (4093, 16, 7, 1000), (9000, 32, 2, 2500)])
+def test_kmeans_update_d16_d32_kernels(L, variant, N, d, K, sb):
+    # d = 16 and 32: the default body (one feature per lane, two interleaved
+    # LDS copies per wave) and variant 1 (four features per lane, one copy)
+    # sum in different fixed orders: both within the float64 bound of the
+    # oracle and bit-identical run to run.  Superblocks of 1000 and 2500
+    # points leave partial tiles (the clamped load path); K = 96 at d = 16
+    # and K = 48 at d = 32 need more than 64 KiB of LDS
+    say("kmeans update d16/d32 kernels", variant, N, d, K, sb)
+    X, _, z = synthetic.kmeans_blobs(N, d, K, seed=23)
+    lab = z.copy()
+    lab[::89] = -1
+    lab[7::113] = K + 1
+    with ctx_of(L) as ctx:
+        ctx.tune("kmeans_update_f32", variant)
+        sums, counts = _update(L, ctx, X, lab, K, sb)
+        sums2, counts2 = _update(L, ctx, X, lab, K, sb)
+    rs, rc, ra = oracle.kmeans_update(X, lab, K)
+    assert np.array_equal(counts.astype(np.int64), rc)
+    assert np.all(np.abs(sums - rs) <= 2 * N * 2.0 ** -53 * ra)
+    assert np.array_equal(sums.view(np.uint64), sums2.view(np.uint64)) and np.array_equal(counts, counts2)
 
 
 @pytest.mark.parametrize("N,d,K", [(1, 4, 1), (3, 16, 5), (7, 3, 64), (2, 32, 2)])

@@ -16,13 +16,17 @@ def dry(**kw):
     return L.Context(dry_run=1, **kw)
 
 
-def _kmu_slots(points, tile=4096, cap=1024):
+def _kmu_slots(points, d, tile=4096):
+    # one slot per 4096-point tile, at most 512 for d = 16 and 32 (two LDS
+    # copies per wave: two workgroups per CU), else 1024
+    cap = 512 if d in (16, 32) else 1024
     return max(1, min(cap, -(-points // tile)))
 
 
-@pytest.mark.parametrize("N,sb", [(300000, 65536), (777, 256), (20000, 1 << 20)])
-def test_kmeans_update_plan(N, sb):
-    d, K = 16, 64
+@pytest.mark.parametrize("N,sb,d", [(300000, 65536, 16), (777, 256, 16), (20000, 1 << 20, 16),
+                                    (3000000, 1 << 22, 16), (5000000, 1 << 23, 8)])
+def test_kmeans_update_plan(N, sb, d):
+    K = 64
     with dry() as ctx:
         x = ctx.array([N, d])
         lb = ctx.array([N], np.int32)
@@ -42,7 +46,7 @@ def test_kmeans_update_plan(N, sb):
         # chunk, and are not filled (the body stores every slot whole)
         want = [0, 0]
         for t in ex:
-            s = _kmu_slots(min(t.sb_hi[0], N) - t.sb_lo[0])
+            s = _kmu_slots(min(t.sb_hi[0], N) - t.sb_lo[0], d)
             want[0] += s * K * d * 8
             want[1] += s * K * 4
         tr = ctx.trace()
