@@ -401,7 +401,7 @@ def bench_stencil1d(args, L, torch):
     n, chunk = 1 << 20, 1 << 17
     x0 = synthetic.stencil1d_input(n, 0)
     res = {}
-    for ex in ("plain", "grouped", "drain"):
+    for ex in ("plain", "grouped", "drain", "graph"):
         arena = torch_arena(torch, 64 << 20)
         ctx = L.Context(device_budget_bytes=64 << 20, device_arena=arena.data_ptr(), arena_bytes=64 << 20,
                         exec_mode=0 if ex == "plain" else 1)
@@ -409,8 +409,19 @@ def bench_stencil1d(args, L, torch):
         y = ctx.array([n], chunk=[chunk])
         x.write(x0)
         ctx.sync()
+        graph = None
+        if ex == "graph":
+            # the launch recorded once as a HIP graph (a persistent drain
+            # over its 8 tasks) and replayed: no planning per step
+            ctx.graph_begin()
+            ctx.launch("stencil1d_f32", [n], [256], [chunk], args=[n, y, x])
+            graph = ctx.graph_end()
 
         def step():
+            if ex == "graph":
+                ctx.graph_launch(graph)
+                ctx.sync()
+                return
             if ex == "drain":
                 ctx.batch_begin()
             ctx.launch("stencil1d_f32", [n], [256], [chunk], args=[n, y, x])
@@ -433,16 +444,26 @@ def bench_stencil1d(args, L, torch):
             times.append(time.perf_counter() - s0)
         total = time.perf_counter() - t0
         prof = ctx.profile_get()
+        out = y.read()
+        if graph is not None:
+            ctx.graph_destroy(graph)
         ctx.close()
         del arena
-        kname = "drain" if ex == "drain" else "stencil1d_f32"
+        # every executor's output is the plain path's, bit for bit
+        if ex == "plain":
+            ref_out = out
+        elif not np.array_equal(out, ref_out):
+            raise RuntimeError("stencil1d %s output differs from the plain path's" % ex)
+        # a graph replay is timed as a whole (queue upload, counter clear,
+        # drain, status copy)
+        kname = {"plain": "stencil1d_f32", "grouped": "stencil1d_f32", "drain": "drain", "graph": "graph"}[ex]
         k = prof[kname]
-        per_dispatch = {"plain": chunk * 8, "grouped": n * 8, "drain": n * 8}[ex]
+        per_dispatch = {"plain": chunk * 8, "grouped": n * 8, "drain": n * 8, "graph": n * 8}[ex]
         avg_ms = k["total_ms"] / k["dispatches"]
         res[ex] = {"gbs": n * 8 / (total / steps) / 1e9, "us_per_launch": total / steps * 1e6,
                    "p50_us": pct(times, 50) * 1e3, "p99_us": pct(times, 99) * 1e3,
                    "kernel_gbs": per_dispatch / (avg_ms * 1e-3) / 1e9, "kernel_avg_us": avg_ms * 1e3,
-                   "dispatches_per_launch": {"plain": 8, "grouped": 1, "drain": 1}[ex], "steps": steps}
+                   "dispatches_per_launch": {"plain": 8, "grouped": 1, "drain": 1, "graph": 1}[ex], "steps": steps}
         log("%s: %s" % (ex, json.dumps(res[ex])))
     m = res["plain"]
     line = base_line({"workload": "stencil1d 2^20 f32 ~U(-1,1) seed 0, 8 chunks of 2^17, one launch per step, "
@@ -454,10 +475,11 @@ def bench_stencil1d(args, L, torch):
                               "unit": "GB/s", "frac": round(m["kernel_gbs"] / HBM_PEAK_GBS, 4), "traffic": None,
                               "kernel": "k_stencil1d", "kernel_avg_us": round(m["kernel_avg_us"], 3),
                               "note": "launch-latency bound: 1 MiB per dispatch, data cache-resident"}})
-    for ex in ("grouped", "drain"):
+    for ex in ("grouped", "drain", "graph"):
         r = res[ex]
         line[ex] = {"value": round(r["gbs"], 2), "p50_us": round(r["p50_us"], 2), "p99_us": round(r["p99_us"], 2),
                     "kernel_gbs": round(r["kernel_gbs"], 2)}
+    line["graph"]["note"] = "kernel_gbs times the whole replay (queue upload, counter clear, drain, status copy)"
     return line
 
 
@@ -1106,7 +1128,7 @@ def bench_kmeans(args, L, torch):
 
 def link_peak(torch, nbytes=1 << 30, reps=5):
     """Pinned host <-> device copy rates (GB/s) of 1 GiB copies through the
-    copy engines (torch's copy_, i.e. hipMemcpyAsync), measured here: the
+    HIP runtime (torch's copy_, i.e. hipMemcpyAsync), measured here: the
     host-link roofline of the out-of-core legs."""
     h = torch.empty(nbytes, dtype=torch.uint8, pin_memory=True)
     d = torch.empty(nbytes, dtype=torch.uint8, device="cuda:0")
@@ -1245,7 +1267,8 @@ def main():
                     help="kmeans: centre-update body (lt_kernel_tune): 0 = default (d 16/32: one feature per "
                          "lane, two LDS copies per wave), 1 = four features per lane, 2 = two features per lane")
     ap.add_argument("--d2h-kernel", type=int, default=0,
-                    help="serve: write-backs into pinned homes through a copy kernel (1) or the copy engine (0)")
+                    help="serve: write-backs into pinned homes through the library's row-copy kernel (1) or "
+                         "hipMemcpy*Async (0)")
     ap.add_argument("--tuned", default="",
                     help="batch: fixed SB:WG:FLUSH:VEC:TILE instead of the autotuning sweep")
     ap.add_argument("--serve-full", action="store_true",

@@ -135,12 +135,11 @@ typedef struct lt_config {
     int32_t sb_band;                /* LT_ORDER_BANDS: rows of superblocks per
                                        band, >= 0; 0 = 2                      */
     int32_t d2h_kernel;             /* write-backs into pinned home buffers of
-                                       host-backed arrays: 0 (default) with the
-                                       copy engine (hipMemcpy*Async), 1 with a
-                                       copy kernel over the host link (it takes
-                                       compute units, but does not queue behind
-                                       other copy-engine work).  Pageable homes
-                                       always use the copy engine.  Changes
+                                       host-backed arrays: 0 (default) with
+                                       hipMemcpy*Async, 1 with the library's
+                                       row-copy kernel over the host link.
+                                       Pageable homes always use
+                                       hipMemcpy*Async.  Changes
                                        speed only.                            */
     uint64_t host_budget_bytes;     /* cap on the pinned host memory of spill
                                        buffers (chunks of device-home arrays

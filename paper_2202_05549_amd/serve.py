@@ -334,7 +334,7 @@ def bench(args, L, torch, log, overlap=None):
                                       host.pinned_bytes / 1e9, host.pageable_bytes / 1e9),
                        "executor": "continuous batching, %d slots, resident datasets, cached datasets first "
                                    "among the first 64 queued (at most 256 bypasses)" % slots,
-                       "write_backs": "copy kernel" if d2h_kernel else "copy engine"},
+                       "write_backs": "row-copy kernel" if d2h_kernel else "hipMemcpyAsync"},
             "value": round(m["gbs"], 2), "unit": "GB/s", "ms_per_step": round(m["makespan_s"] * 1e3, 2),
             "dtype": "f32+i32", "p50_ms": round(m["p50_ms"], 2), "p99_ms": round(m["p99_ms"], 2),
             "req_per_s": round(m["req_per_s"], 3), "tflops": round(m["tflops"], 2),
