@@ -114,13 +114,15 @@ struct CopyBoxEntry {
 hipError_t launch_copy_boxes(hipStream_t s, const CopyBoxEntry *table, int n, int esz, int64_t max_elems);
 
 // Copies `bytes` bytes (a multiple of 16; both pointers 16-byte aligned)
-// with a kernel: one 16-byte word per thread, one pass per workgroup.  The
-// pointers may be device memory or pinned host memory (which kernels reach
-// over the host link).  Returns hipErrorInvalidValue for other shapes.
+// with a kernel of at most 64 workgroups, sized for the host link: 16-byte
+// words, four in flight per lane.  The pointers may be device memory or
+// pinned host memory (which kernels reach over the host link).  Returns
+// hipErrorInvalidValue for other shapes.
 hipError_t launch_copy_linear(hipStream_t s, void *dst, const void *src, int64_t bytes);
 
 // Copies `rows` rows of `width` bytes (source and destination pitches in
-// bytes) with a kernel; either side may be device or pinned host memory.
+// bytes) with a kernel of at most 64 workgroups, sized for the host link;
+// either side may be device or pinned host memory.
 hipError_t launch_copy_rows(hipStream_t s, void *dst, int64_t dpitch, const void *src, int64_t spitch,
                             int64_t width, int64_t rows);
 

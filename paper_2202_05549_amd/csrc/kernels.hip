@@ -410,17 +410,37 @@ hipError_t launch_copy_boxes(hipStream_t s, const CopyBoxEntry *table, int n, in
 }
 
 // ============================================================ linear copy
-__global__ __launch_bounds__(256) void k_copy16(int4 *dst, const int4 *src, int64_t words) {
-    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (i < words) dst[i] = src[i];
+// Copies over the host link (write-backs into pinned host memory) run on few
+// workgroups: the link, not the compute units, is the limit, and a narrow
+// grid leaves the CUs to the workload's kernels.  64 workgroups with four
+// 16-byte loads in flight per lane reach the link rate for device-to-host
+// copies (55 GB/s; 16 workgroups 53, 8 workgroups 47).
+constexpr int COPY_WG = 64;
+constexpr int COPY_U = 4;
+
+__global__ __launch_bounds__(256) void k_copy16(int4 *__restrict__ dst, const int4 *__restrict__ src,
+                                                int64_t words) {
+    const int64_t stride = (int64_t)gridDim.x * 256 * COPY_U;
+    for (int64_t base = (int64_t)blockIdx.x * 256 * COPY_U + threadIdx.x; base < words; base += stride) {
+        int4 v[COPY_U];
+#pragma unroll
+        for (int u = 0; u < COPY_U; ++u) {
+            const int64_t i = base + (int64_t)u * 256;
+            if (i < words) v[u] = src[i];
+        }
+#pragma unroll
+        for (int u = 0; u < COPY_U; ++u) {
+            const int64_t i = base + (int64_t)u * 256;
+            if (i < words) dst[i] = v[u];
+        }
+    }
 }
 
 hipError_t launch_copy_linear(hipStream_t s, void *dst, const void *src, int64_t bytes) {
     if (bytes <= 0) return hipSuccess;
     if ((bytes & 15) || ((uintptr_t)dst & 15) || ((uintptr_t)src & 15)) return hipErrorInvalidValue;
     const int64_t words = bytes / 16;
-    const int64_t blocks = (words + 255) / 256;
-    if (blocks > INT32_MAX) return hipErrorInvalidValue;
+    const int64_t blocks = std::min<int64_t>(COPY_WG, (words + 256 * COPY_U - 1) / (256 * COPY_U));
     hipLaunchKernelGGL(k_copy16, dim3((unsigned)blocks), dim3(256), 0, s, (int4 *)dst, (const int4 *)src, words);
     return hipGetLastError();
 }
@@ -429,16 +449,29 @@ hipError_t launch_copy_linear(hipStream_t s, void *dst, const void *src, int64_t
 // Each row is cut into segments of at most 4096 T-sized words (16, 4 or 1
 // bytes, the widest that every address, pitch and the width allow);
 // workgroup b copies segments b, b + gridDim.x, ... of the rows x segments,
-// 16 words per lane at most.
+// with COPY_U loads in flight per lane.
 template <class T>
-__global__ __launch_bounds__(256) void k_copy_rows(char *dst, int64_t dpitch, const char *src, int64_t spitch,
-                                                   int64_t words, int64_t rows, int64_t segs) {
+__global__ __launch_bounds__(256) void k_copy_rows(char *__restrict__ dst, int64_t dpitch,
+                                                   const char *__restrict__ src, int64_t spitch, int64_t words,
+                                                   int64_t rows, int64_t segs) {
     for (int64_t b = blockIdx.x; b < rows * segs; b += gridDim.x) {
         const int64_t r = b / segs, w0 = (b - r * segs) * 4096;
         const int64_t w1 = w0 + 4096 < words ? w0 + 4096 : words;
         T *d = reinterpret_cast<T *>(dst + r * dpitch);
         const T *s = reinterpret_cast<const T *>(src + r * spitch);
-        for (int64_t i = w0 + threadIdx.x; i < w1; i += 256) d[i] = s[i];
+        for (int64_t i0 = w0 + threadIdx.x; i0 < w1; i0 += 256 * COPY_U) {
+            T v[COPY_U];
+#pragma unroll
+            for (int u = 0; u < COPY_U; ++u) {
+                const int64_t i = i0 + (int64_t)u * 256;
+                if (i < w1) v[u] = s[i];
+            }
+#pragma unroll
+            for (int u = 0; u < COPY_U; ++u) {
+                const int64_t i = i0 + (int64_t)u * 256;
+                if (i < w1) d[i] = v[u];
+            }
+        }
     }
 }
 
@@ -447,7 +480,7 @@ static void copy_rows_as(hipStream_t s, char *d, int64_t dpitch, const char *c, 
                          int64_t rows) {
     const int64_t words = width / (int64_t)sizeof(T);
     const int64_t segs = (words + 4095) / 4096;
-    const int64_t blocks = std::min<int64_t>(rows * segs, 65536);
+    const int64_t blocks = std::min<int64_t>(rows * segs, COPY_WG);
     hipLaunchKernelGGL(k_copy_rows<T>, dim3((unsigned)blocks), dim3(256), 0, s, d, dpitch, c, spitch, words, rows,
                        segs);
 }
