@@ -161,7 +161,7 @@ TRAFFIC = {
     # k_kmeans_update_c<16, 8>, one dispatch per 2^22-point superblock:
     # FETCH_SIZE 139,327 KiB x 2.000 + WRITE_SIZE 4,224 KiB x 1.000 (512
     # partial slots of 64 x 16 float64 sums and 64 counts)
-    "k_kmeans_update": {"sources": KMU_SOURCES, "digest": "fd9d3ed93481840f",
+    "k_kmeans_update": {"sources": KMU_SOURCES, "digest": "a5bad5d31b3d229a",
                         "bytes_per_dispatch": 139327 * 1024 * 2.000 + 4224 * 1024},
     # k_drain<27, 4>, one dispatch per step of the 8192-launch mix at
     # superblock 2^24, 1024 workgroups, per-body drain tiles (graph replay):

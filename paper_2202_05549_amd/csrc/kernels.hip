@@ -223,8 +223,8 @@ hipError_t launch_jacobi2d_f32(const KLaunch &L) {
 }
 
 // ================================================================ hist256
-// Slot w of the superblock's partial = #{i in the workgroup's 64 Ki-element
-// chunks : v[i] == b} for every bin b.  Each wave counts into its own LDS
+// Slot w of the superblock's partial = #{i in the workgroup's 4096-element
+// groups (w, w + slots, ...) : v[i] == b} for every bin b.  Each wave counts into its own LDS
 // sub-histograms (skewed data hammers few bins); the workgroup sums them and
 // stores the whole slot, so no two workgroups add into the same words.  The
 // slots are folded afterwards (integers: exact in any order).

@@ -88,7 +88,7 @@ def test_rowreduce_partials_per_column_superblock():
         ctx.sync()
 
 
-@pytest.mark.parametrize("n,sb", [(1_000_003, 1 << 20), (65536, 65536), (70000, 1 << 16), (5, 4)])
+@pytest.mark.parametrize("n,sb", [(1_000_003, 1 << 20), (65536, 65536), (70000, 1 << 16), (5, 4), (40_000_000, 1 << 25)])
 def test_hist_slots_outside_batches_one_partial_inside(n, sb):
     # outside a batch: one 256-bin slot per 64 Ki elements of a superblock
     # (at most 1024), stored whole by the body, so no fill; inside a batch:
