@@ -125,7 +125,7 @@ GEMM_SOURCES = [("gemm.hip", "#include <hip/hip_runtime.h>", "}  // namespace lt
 # the code of k_kmeans (assignment): its section of kernels.hip
 KMEANS_SOURCES = [("kernels.hip", "// ========================================================== kmeans assign",
                    "// ============================================================== copy boxes")]
-# the code of k_kmeans_update_v: its section of reduce.hip and the slot rule
+# the code of the k-means update kernels: their section of reduce.hip and the slot rule
 KMU_SOURCES = [("reduce.hip", "// ======================================================== k-means update",
                 "// ========================================================= k-means centres"),
                ("kernels.h", "// k-means update: points per workgroup tile", "// Runtime helpers.")]
@@ -159,10 +159,10 @@ TRAFFIC = {
     "k_kmeans": {"sources": KMEANS_SOURCES, "digest": "9c654699cb5049b5",
                  "bytes_per_dispatch": 2097210 * 1024 * 2.000 + 262144 * 1024},
     # k_kmeans_update_c<16, 8>, one dispatch per 2^22-point superblock:
-    # FETCH_SIZE 139,327 KiB x 2.000 + WRITE_SIZE 4,224 KiB x 1.000 (512
+    # FETCH_SIZE 139,326 KiB x 2.000 + WRITE_SIZE 4,224 KiB x 1.000 (512
     # partial slots of 64 x 16 float64 sums and 64 counts)
-    "k_kmeans_update": {"sources": KMU_SOURCES, "digest": "a5bad5d31b3d229a",
-                        "bytes_per_dispatch": 139327 * 1024 * 2.000 + 4224 * 1024},
+    "k_kmeans_update": {"sources": KMU_SOURCES, "digest": "7435618759144446",
+                        "bytes_per_dispatch": 139326 * 1024 * 2.000 + 4224 * 1024},
     # k_drain<27, 4>, one dispatch per step of the 8192-launch mix at
     # superblock 2^24, 1024 workgroups, per-body drain tiles (graph replay):
     # FETCH_SIZE 27,213,872 KiB x 2.000 + WRITE_SIZE 27,245,512 KiB x 1.000 =

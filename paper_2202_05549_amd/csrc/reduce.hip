@@ -607,9 +607,11 @@ __global__ __launch_bounds__(256) void k_kmeans_update_v(KUArgs a) {
 // copy 0 of every cluster starts on one bank and copy 1 VD doubles further:
 // the two points that share an LDS half-instruction (32 lanes) fall on
 // disjoint banks whatever their clusters.  Only points q and q + 2 share a
-// copy; when their clusters agree, point q + 2 adds in a second round, so
-// each cell of a copy is a sequential sum in point order.  Counts are
-// integer adds in one copy per wave, exact in any order.
+// copy; when their clusters agree, the add of point q + 2 waits for the
+// end of its batch, so no two lanes of one instruction add into one cell
+// and the order of every cell's adds is fixed by the data alone.  Counts
+// are integer adds in one copy per wave, exact in any order.
+//
 // Loads one batch of U steps: lane (q, j) gets feature j of point
 // pb + u P + q and that point's raw label.  With FULL every point of the
 // batch is in range and the loads take immediate offsets from one scalar
@@ -642,34 +644,42 @@ __device__ __forceinline__ void kmc_load(const KUReg &t, int64_t pb, int64_t p1,
 // Adds one loaded batch; nleft = points of the batch inside the range
 // (unchecked with FULL).  Point q + 2 of a step finds the cluster of point
 // q, its copy-mate, 32 lanes down with one lane swap of the two wave halves.
-// The batch's counts go in one integer LDS add after its U steps: lane
-// (q, j) with j < U counts point q of step j (integer adds need no order,
-// and the atomic keeps equal clusters in one instruction correct).
+// A point whose copy-mate has its cluster is held back: the clashing adds of
+// the batch's U steps follow the others, step by step, so each cell's order
+// is fixed by the data alone.  The batch's counts go in one integer LDS add
+// after its U steps: lane (q, j) with j < U counts point q of step j
+// (integer adds need no order, and the atomic keeps equal clusters in one
+// instruction correct).
 template <int VD, int U, bool FULL>
 __device__ __forceinline__ void kmc_add(double *acc, int *cnt, const float *xv, const int *kv, int64_t nleft, int q,
                                         int j, int K) {
     constexpr int P = 64 / VD;
     static_assert(U <= VD, "one count lane per step");
     const int krow = 2 * VD;
+    bool late[U];
+    bool any_late = false;
 #pragma unroll
     for (int u = 0; u < U; ++u) {
         const int k = kv[u];
         const bool ok = (unsigned)k < (unsigned)K && (FULL || (int64_t)(u * P + q) < nleft);
-        bool late = false;
+        late[u] = false;
         if constexpr (P == 4) {
             // lanes 32..63 receive lanes 0..31 of k: the copy-mate's cluster
             const int mate = __builtin_amdgcn_permlane32_swap(k, k, false, false)[0];
-            late = ok && q >= 2 && k == mate;
+            late[u] = ok && q >= 2 && k == mate;
+            any_late |= late[u];
         }
-        if (ok && !late) lds_add(acc + k * krow, (double)xv[u]);
-        if constexpr (P == 4) {
-            if (__builtin_amdgcn_ballot_w64(late)) {
-                asm volatile("" ::: "memory");
-                if (late) lds_add(acc + k * krow, (double)xv[u]);
-            }
-        }
-        asm volatile("" ::: "memory");
+        if (ok && !late[u]) lds_add(acc + k * krow, (double)xv[u]);
     }
+    if constexpr (P == 4) {
+        if (__builtin_amdgcn_ballot_w64(any_late)) {
+            asm volatile("" ::: "memory");
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                if (late[u]) lds_add(acc + kv[u] * krow, (double)xv[u]);
+        }
+    }
+    asm volatile("" ::: "memory");
     int kc = -1;
 #pragma unroll
     for (int u = 0; u < U; ++u) kc = j == u ? kv[u] : kc;
@@ -714,6 +724,7 @@ __global__ __launch_bounds__(256) void k_kmeans_update_c(KUArgs a) {
     const int ti = find_task(a.begin, a.ntask, blockIdx.x);
     const KUReg t = kmu_regs(a.t[ti]);
     const int w = blockIdx.x - a.begin[ti];
+    // each wave: its two copies, K rows of 2 VD doubles
     const int K = a.K, KROW = 2 * VD, KD2 = K * KROW;
     // the wave index is uniform: readfirstlane keeps the point ranges, and
     // the branches on them, scalar
