@@ -335,15 +335,22 @@ __device__ __forceinline__ void jacobi_tile(const JView &t, int64_t n, int64_t m
             else
                 v[i] = make_float4(0.f, 0.f, 0.f, 0.f);
         }
+        // the columns beside the wave's end lanes, before any store
+        float el[RB], er[RB];
+#pragma unroll
+        for (int i = 0; i < RB; ++i) {
+            const LT_GLOBAL float *row = X + (r0 + i) * t.xs;
+            el[i] = active && lane == 0 && col - 1 >= 0 ? row[col - 1] : 0.f;
+            er[i] = active && (lane == WAVE - 1 || col + 4 >= cend) && col + 4 < m ? row[col + 4] : 0.f;
+        }
 #pragma unroll
         for (int i = 1; i <= RB; ++i) {
             const int64_t r = r0 - 1 + i;
             const float4 up = v[i - 1], mid = v[i], dn = v[i + 1];
             float left = __shfl_up(mid.w, 1);
             float right = __shfl_down(mid.x, 1);
-            const LT_GLOBAL float *row = X + r * t.xs;
-            if (active && lane == 0) left = (col - 1 >= 0) ? row[col - 1] : 0.f;
-            if (active && (lane == WAVE - 1 || col + 4 >= cend)) right = (col + 4 < m) ? row[col + 4] : 0.f;
+            if (lane == 0) left = el[i - 1];
+            if (lane == WAVE - 1 || col + 4 >= cend) right = er[i - 1];
             if (active) {
                 float4 o;
                 o.x = jpoint(up.x, dn.x, left, mid.y);
@@ -390,6 +397,15 @@ __device__ __forceinline__ void jacobi_stack(const JView &t, int64_t n, int64_t 
     v[RB + 1] = v[0];
     if (w == 0 && r0 >= 1) v[0] = ld4<float4>(X + (r0 - 1) * t.xs + col);
     if (w == NW - 1 && r0 + RB < n) v[RB + 1] = ld4<float4>(X + (r0 + RB) * t.xs + col);
+    // the neighbouring columns of the wave's end lanes, loaded with the rows
+    // (before any store, so no row waits for a load of its own)
+    float el[RB], er[RB];
+#pragma unroll
+    for (int i = 0; i < RB; ++i) {
+        const LT_GLOBAL float *row = X + (r0 + i) * t.xs;
+        el[i] = lane == 0 && col - 1 >= 0 ? row[col - 1] : 0.f;
+        er[i] = lane == WAVE - 1 && col + 4 < m ? row[col + 4] : 0.f;
+    }
     s_first[w][lane] = v[1];
     s_last[w][lane] = v[RB];
     __syncthreads();
@@ -401,9 +417,8 @@ __device__ __forceinline__ void jacobi_stack(const JView &t, int64_t n, int64_t 
         const float4 up = v[i - 1], mid = v[i], dn = v[i + 1];
         float left = __shfl_up(mid.w, 1);
         float right = __shfl_down(mid.x, 1);
-        const LT_GLOBAL float *row = X + r * t.xs;
-        if (lane == 0) left = (col - 1 >= 0) ? row[col - 1] : 0.f;
-        if (lane == WAVE - 1) right = (col + 4 < m) ? row[col + 4] : 0.f;
+        if (lane == 0) left = el[i - 1];
+        if (lane == WAVE - 1) right = er[i - 1];
         float4 o;
         o.x = jpoint(up.x, dn.x, left, mid.y);
         o.y = jpoint(up.y, dn.y, mid.x, mid.z);
@@ -417,7 +432,8 @@ __device__ __forceinline__ void jacobi_stack(const JView &t, int64_t n, int64_t 
 // of 8 rows: the two rows above a group are carried over in registers from
 // the group before, so each input row is loaded once per tile and only the
 // tile's first group reads a halo row above it (plus one below the last).
-// A group's 8 loads per lane are issued together before its arithmetic.
+// A group's 8 loads per lane, and the columns beside the wave's, are issued
+// together before its arithmetic.
 // Ragged tiles fall back to jacobi_tile per group.
 template <int NG>
 __device__ __forceinline__ void jacobi_march(const JView &t, int64_t n, int64_t m, int64_t tr0, int txi) {
@@ -440,7 +456,13 @@ __device__ __forceinline__ void jacobi_march(const JView &t, int64_t n, int64_t 
     auto load = [&](int64_t r) {
         return (active && r >= 0 && r < n) ? ld4<float4>(X + r * t.xs + col) : make_float4(0.f, 0.f, 0.f, 0.f);
     };
+    // the lanes at a wave's ends (and at the tile's last column) take the
+    // neighbouring columns from memory; they are loaded with the group's rows,
+    // before its stores, so no row waits for a load of its own
+    const bool need_l = active && lane == 0 && col - 1 >= 0;
+    const bool need_r = active && (lane == WAVE - 1 || col + 4 >= cend) && col + 4 < m;
     float4 v[RB + 2];
+    float el[RB], er[RB];
     v[0] = load(tr0 - 1);
     v[1] = load(tr0);
     for (int g = 0; g < NG; ++g) {
@@ -448,14 +470,19 @@ __device__ __forceinline__ void jacobi_march(const JView &t, int64_t n, int64_t 
 #pragma unroll
         for (int i = 0; i < RB; ++i) v[i + 2] = load(rb + 1 + i);
 #pragma unroll
+        for (int i = 0; i < RB; ++i) {
+            const LT_GLOBAL float *row = X + (rb + i) * t.xs;
+            el[i] = need_l ? row[col - 1] : 0.f;
+            er[i] = need_r ? row[col + 4] : 0.f;
+        }
+#pragma unroll
         for (int i = 1; i <= RB; ++i) {
             const int64_t r = rb - 1 + i;
             const float4 up = v[i - 1], mid = v[i], dn = v[i + 1];
             float left = __shfl_up(mid.w, 1);
             float right = __shfl_down(mid.x, 1);
-            const LT_GLOBAL float *row = X + r * t.xs;
-            if (active && lane == 0) left = (col - 1 >= 0) ? row[col - 1] : 0.f;
-            if (active && (lane == WAVE - 1 || col + 4 >= cend)) right = (col + 4 < m) ? row[col + 4] : 0.f;
+            if (lane == 0) left = el[i - 1];
+            if (lane == WAVE - 1 || col + 4 >= cend) right = er[i - 1];
             if (active) {
                 float4 o;
                 o.x = jpoint(up.x, dn.x, left, mid.y);

@@ -105,10 +105,12 @@ def test_batched_stencil_pingpong_dependencies(L, wg):
     assert np.array_equal(got, oracle.stencil1d_iter(x0, 12))
 
 
-@pytest.mark.parametrize("n,m,sb", [(1000, 1500, 64), (1000, 1024, 256), (777, 2048, 384), (300, 4096, 128)])
+@pytest.mark.parametrize("n,m,sb", [(1000, 1500, 64), (1000, 1024, 256), (777, 2048, 384), (300, 4096, 128),
+                                    (1000, 1500, 256)])
 def test_batched_jacobi_sweeps(L, n, m, sb):
     # superblocks smaller than a drain tile (ragged tiles), and larger ones
-    # whose full tiles take the marching path, with ragged last tasks
+    # whose full tiles take the marching path, with ragged last tasks; 1500
+    # columns end a marching tile inside its second wave
     say("batch jacobi", n, m, sb)
     x0 = synthetic.jacobi2d_input(n, m, seed=14)
     with L.Context(device_budget_bytes=1 << 30) as ctx:

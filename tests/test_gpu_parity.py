@@ -158,10 +158,12 @@ def test_jacobi_small_bit_exact(L, shape, chunk, sb, mode):
 
 @pytest.mark.parametrize("variant", [8, 16, 32, 132, 164, 228, 302, 304, 308])
 @pytest.mark.parametrize("shape,chunk,sb", [((1000, 2051), (96, 0), (96, 0)), ((777, 1024), (0, 0), (256, 0)),
-                                            ((300, 4096), (128, 0), (128, 1024)), ((513, 515), (0, 0), (0, 0))])
+                                            ((300, 4096), (128, 0), (128, 1024)), ((513, 515), (0, 0), (0, 0)),
+                                            ((600, 1500), (0, 0), (256, 0))])
 def test_jacobi_tile_variants_bit_exact(L, variant, shape, chunk, sb):
     # every tiling of the body (rows loaded at once, marched in groups of 8,
     # or stacked bands per wave) gives the same bits, on full and ragged tiles
+    # (1500 columns: a full-height tile whose columns end inside a wave)
     say("jacobi variant", variant, shape, chunk, sb)
     n, m = shape
     x0 = synthetic.jacobi2d_input(n, m, seed=11)
