@@ -154,11 +154,11 @@ TRAFFIC = {
     # copy reads 524,309 KiB) + WRITE_SIZE 68,518 KiB x 1.000
     "k_gemm": {"sources": GEMM_SOURCES, "digest": "09089ee7a4180e74",
                "bytes_per_dispatch": 4046964 * 1024 * 2.000 + 68518 * 1024},
-    # k_kmeans<16>, one dispatch per assignment launch of 2^26 points (d = 16,
-    # K = 64): FETCH_SIZE 2,097,210 KiB x 2.000 + WRITE_SIZE 262,144 KiB x
-    # 1.000, the 64 B of each point and its 4 B label
-    "k_kmeans": {"sources": KMEANS_SOURCES, "digest": "9c654699cb5049b5",
-                 "bytes_per_dispatch": 2097210 * 1024 * 2.000 + 262144 * 1024},
+    # k_kmeans_s<16, 1, 2>, one dispatch per assignment launch of 2^26 points
+    # (d = 16, K = 64): FETCH_SIZE 2,097,203 KiB x 2.000 + WRITE_SIZE 262,144
+    # KiB x 1.000, the 64 B of each point and its 4 B label
+    "k_kmeans": {"sources": KMEANS_SOURCES, "digest": "1a9b0a8c7ed47ba8",
+                 "bytes_per_dispatch": 2097203 * 1024 * 2.000 + 262144 * 1024},
     # k_kmeans_update_c<16, 8>, one dispatch per 2^22-point superblock:
     # FETCH_SIZE 139,326 KiB x 2.000 + WRITE_SIZE 4,224 KiB x 1.000 (512
     # partial slots of 64 x 16 float64 sums and 64 counts)
@@ -1060,6 +1060,8 @@ def bench_kmeans(args, L, torch):
         ctx.sync()
         if args.kmu_variant:
             ctx.tune("kmeans_update_f32", args.kmu_variant)
+        if args.kma_variant:
+            ctx.tune("kmeans_assign_f32", args.kma_variant)
 
         def step():
             cen.write(cen0)
@@ -1268,6 +1270,9 @@ def main():
                     help="gemm_ooc: compute streams of the context (0 = 1)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one 1 GiB float32 device copy first (the reference kernel for HBM counter scaling)")
+    ap.add_argument("--kma-variant", type=int, default=0,
+                    help="kmeans: assignment body (lt_kernel_tune, d = 16): 0 = default (centres in SGPRs), "
+                         "1 = centres broadcast from LDS, 2 = two points per lane")
     ap.add_argument("--kmu-variant", type=int, default=0,
                     help="kmeans: centre-update body (lt_kernel_tune): 0 = default (d 16/32: one feature per "
                          "lane, two LDS copies per wave), 1 = four features per lane, 2 = two features per lane")

@@ -347,6 +347,65 @@ __global__ __launch_bounds__(256) void k_kmeans(KArgs a) {
     *at<int32_t>(t.lab, p) = arg;
 }
 
+// The same with the centres read through scalar loads into SGPRs (every lane
+// of a wave needs the same centre value at the same time), not broadcast
+// from LDS: a 16-byte LDS broadcast fills 1 KiB of VGPRs for 8 VALU
+// instructions, and the four SIMDs of a CU share one LDS.  The centre loop
+// is unrolled UK times (2: the next centre's loads overlap this one's
+// arithmetic).  A lane takes PP points, 256 apart (a
+// workgroup covers 256 PP points): each centre load then serves PP points,
+// and their chains are independent.
+template <int D, int PP, int UK>
+__global__ __launch_bounds__(256) void k_kmeans_s(KArgs a) {
+    const int ti = find_task(a.begin, a.ntask, blockIdx.x);
+    const KTaskK &t = a.t[ti];
+    const int K = (int)a.K;
+    const int64_t end = t.hi < a.N ? t.hi : a.N;
+    const int64_t p0 = t.lo + (int64_t)(blockIdx.x - a.begin[ti]) * (256 * PP) + threadIdx.x;
+    if (p0 >= end) return;
+    float x[PP][D];
+#pragma unroll
+    for (int u = 0; u < PP; ++u) {
+        // a point past the end repeats the lane's first point (not stored)
+        const int64_t p = p0 + u * 256 < end ? p0 + u * 256 : p0;
+        const LT_GLOBAL float *X = gp<const float>(t.x) + p * t.xs;
+#pragma unroll
+        for (int j = 0; j < D; ++j) x[u][j] = X[j];
+    }
+    const LT_GLOBAL float *__restrict__ C = gp<const float>(t.c);
+    const int64_t cs = t.cs;
+    float best[PP];
+    int arg[PP];
+#pragma unroll
+    for (int u = 0; u < PP; ++u) {
+        best[u] = INFINITY;
+        arg[u] = 0;
+    }
+#pragma unroll UK
+    for (int k = 0; k < K; ++k) {
+        const LT_GLOBAL float *ck = C + k * cs;
+        float c[D];
+#pragma unroll
+        for (int j = 0; j < D; ++j) c[j] = ck[j];
+#pragma unroll
+        for (int u = 0; u < PP; ++u) {
+            float acc = 0.f;
+#pragma unroll
+            for (int j = 0; j < D; ++j) {
+                float df = x[u][j] - c[j];
+                acc = fmaf(df, df, acc);
+            }
+            if (acc < best[u]) {
+                best[u] = acc;
+                arg[u] = k;
+            }
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < PP; ++u)
+        if (p0 + u * 256 < end) *at<int32_t>(t.lab, p0 + u * 256) = arg[u];
+}
+
 hipError_t launch_kmeans_assign_f32(const KLaunch &L) {
     KArgs a;
     a.N = L.iarg[0];
@@ -354,6 +413,8 @@ hipError_t launch_kmeans_assign_f32(const KLaunch &L) {
     a.K = L.iarg[2];
     if (a.d < 1 || a.d > KM_MAXD || a.K < 1 || a.K > KM_MAXK) return hipErrorInvalidValue;
     a.ntask = L.ntask;
+    // points per lane: 2 for variant 2 at d = 16, else 1
+    const int pp = a.d == 16 && L.variant == 2 ? 2 : 1;
     int64_t nb = 0;
     for (int i = 0; i < L.ntask; ++i) {
         const KTask &k = L.tasks[i];
@@ -366,11 +427,18 @@ hipError_t launch_kmeans_assign_f32(const KLaunch &L) {
         a.t[i].cs = k.v[5].s[0];
         int64_t e = std::min(a.t[i].hi, a.N) - a.t[i].lo;
         a.begin[i] = (int)nb;
-        nb += e > 0 ? (e + 255) / 256 : 0;
+        nb += e > 0 ? (e + 256 * pp - 1) / (256 * pp) : 0;
     }
     a.begin[L.ntask] = (int)nb;
     if (nb == 0) return hipSuccess;
-    if (a.d == 16)
+    // d = 16: centres in SGPRs, the centre loop unrolled by 2 (default);
+    // variant 1 broadcasts them from LDS (the earlier body), variant 2 takes
+    // two points per lane
+    if (pp == 2)
+        hipLaunchKernelGGL((k_kmeans_s<16, 2, 1>), dim3(grid_of(nb)), dim3(256), 0, L.stream, a);
+    else if (a.d == 16 && L.variant != 1)
+        hipLaunchKernelGGL((k_kmeans_s<16, 1, 2>), dim3(grid_of(nb)), dim3(256), 0, L.stream, a);
+    else if (a.d == 16)
         hipLaunchKernelGGL(k_kmeans<16>, dim3(grid_of(nb)), dim3(256), 0, L.stream, a);
     else
         hipLaunchKernelGGL(k_kmeans<0>, dim3(grid_of(nb)), dim3(256), 0, L.stream, a);

@@ -284,11 +284,18 @@ def test_hist256_reductions_into_one_target_keep_program_order(L, batched, hchun
 
 # ----------------------------------------------------------------- k-means
 
-@pytest.mark.parametrize("N,d,K,chunk", [(100_003, 16, 64, 1 << 14), (5000, 3, 7, 999), (4096, 32, 256, 0)])
-def test_kmeans_assign_labels_bit_exact(L, N, d, K, chunk):
-    say("kmeans", N, d, K)
+@pytest.mark.parametrize("variant", [0, 1, 2])
+@pytest.mark.parametrize("N,d,K,chunk", [(100_003, 16, 64, 1 << 14), (5000, 3, 7, 999), (4096, 32, 256, 0),
+                                         (70_001, 16, 256, 1 << 14), (300, 16, 1, 0), (1000, 16, 5, 333)])
+def test_kmeans_assign_labels_bit_exact(L, variant, N, d, K, chunk):
+    # d = 16: the default body reads the centres through scalar loads,
+    # variant 1 broadcasts them from LDS, variant 2 takes two points per lane
+    # (superblocks of 333 points leave lanes whose second point is past the
+    # superblock)
+    say("kmeans", variant, N, d, K)
     X, mu, _ = synthetic.kmeans_blobs(N, d, K, seed=13)
     with ctx_of(L) as ctx:
+        ctx.tune("kmeans_assign_f32", variant)
         xa = ctx.array([N, d], chunk=[chunk, 0])
         ca = ctx.array([K, d])
         lab = ctx.array([N], np.int32, chunk=[chunk])
