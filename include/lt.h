@@ -386,15 +386,22 @@ lt_status lt_rtc_stats_get(lt_rtc_stats *out);
 
 /* Selects a tuning variant of a built-in body for later launches through
  * this handle (0 = default).  Variants change only the work mapping, never
- * the per-element arithmetic.  jacobi2d_f32 takes:
+ * the per-element arithmetic (but see kmeans_update_f32 below for the order
+ * of its float64 sums).  jacobi2d_f32 takes:
  *   8, 16 or 32: tiles of 1024 columns and that many rows, all loaded at once;
  *   132, 164 or 228: tiles of 1024 columns and 32, 64 or 128 rows, marched in
  *     groups of 8 (each input row loaded once per tile);
  *   302, 304 or 308: tiles of 256 columns and 4 bands of 2, 4 or 8 rows, one
  *     band per wave, the rows between bands exchanged on chip.
- * Unknown variants fall back to the default (304).  kmeans_update_f32 takes
- * 2 for two features per lane instead of four (d of 8, 16 or 32); the sums
- * are bit-identical either way. */
+ * Unknown variants fall back to the default (304).  kmeans_assign_f32 at
+ * d = 16 takes 1 to broadcast the centres from LDS instead of reading them
+ * through scalar loads, and 2 for two points per lane; the labels are
+ * identical.  kmeans_update_f32 takes 1 for four features per lane (d of 16
+ * or 32: the default there is one feature per lane with two LDS copies per
+ * wave) and 2 for two features per lane (d of 8, 16 or 32).  Its variants
+ * add each cell's points in different fixed orders: every variant gives the
+ * same bits on every run, each within the float64 rounding bound of the
+ * exact sums, but two variants may differ in the last bits. */
 lt_status lt_kernel_tune(lt_context *ctx, lt_kernel *k, int32_t variant);
 
 /* ------------------------------------------------------------------- launch */
