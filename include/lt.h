@@ -394,9 +394,9 @@ lt_status lt_rtc_stats_get(lt_rtc_stats *out);
  *   302, 304 or 308: tiles of 256 columns and 4 bands of 2, 4 or 8 rows, one
  *     band per wave, the rows between bands exchanged on chip.
  * Unknown variants fall back to the default (304).  kmeans_assign_f32 at
- * d = 16 takes 1 to broadcast the centres from LDS instead of reading them
- * through scalar loads, and 2 for two points per lane; the labels are
- * identical.  kmeans_update_f32 takes 1 for four features per lane (d of 16
+ * d of 4, 8, 16 or 32 takes 1 to broadcast the centres from LDS instead of
+ * reading them through scalar loads, and at d = 16 2 for two points per
+ * lane; the labels are identical.  kmeans_update_f32 takes 1 for four features per lane (d of 16
  * or 32: the default there is one feature per lane with two LDS copies per
  * wave) and 2 for two features per lane (d of 8, 16 or 32).  Its variants
  * add each cell's points in different fixed orders: every variant gives the

@@ -431,7 +431,7 @@ hipError_t launch_kmeans_assign_f32(const KLaunch &L) {
     }
     a.begin[L.ntask] = (int)nb;
     if (nb == 0) return hipSuccess;
-    // d = 16 and 32: centres in SGPRs, the centre loop unrolled by 2
+    // d = 4, 8, 16 and 32: centres in SGPRs, the centre loop unrolled by 2
     // (default); variant 1 broadcasts them from LDS (the earlier body); at
     // d = 16 variant 2 takes two points per lane
     if (pp == 2)
@@ -440,6 +440,10 @@ hipError_t launch_kmeans_assign_f32(const KLaunch &L) {
         hipLaunchKernelGGL((k_kmeans_s<16, 1, 2>), dim3(grid_of(nb)), dim3(256), 0, L.stream, a);
     else if (a.d == 32 && L.variant != 1)
         hipLaunchKernelGGL((k_kmeans_s<32, 1, 2>), dim3(grid_of(nb)), dim3(256), 0, L.stream, a);
+    else if (a.d == 8 && L.variant != 1)
+        hipLaunchKernelGGL((k_kmeans_s<8, 1, 2>), dim3(grid_of(nb)), dim3(256), 0, L.stream, a);
+    else if (a.d == 4 && L.variant != 1)
+        hipLaunchKernelGGL((k_kmeans_s<4, 1, 2>), dim3(grid_of(nb)), dim3(256), 0, L.stream, a);
     else if (a.d == 16)
         hipLaunchKernelGGL(k_kmeans<16>, dim3(grid_of(nb)), dim3(256), 0, L.stream, a);
     else

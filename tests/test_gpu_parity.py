@@ -287,9 +287,9 @@ def test_hist256_reductions_into_one_target_keep_program_order(L, batched, hchun
 @pytest.mark.parametrize("variant", [0, 1, 2])
 @pytest.mark.parametrize("N,d,K,chunk", [(100_003, 16, 64, 1 << 14), (5000, 3, 7, 999), (4096, 32, 256, 0),
                                          (70_001, 16, 256, 1 << 14), (300, 16, 1, 0), (1000, 16, 5, 333),
-                                         (20_001, 32, 48, 4096)])
+                                         (20_001, 32, 48, 4096), (9_999, 8, 33, 1000), (7_777, 4, 129, 0)])
 def test_kmeans_assign_labels_bit_exact(L, variant, N, d, K, chunk):
-    # d = 16 and 32: the default body reads the centres through scalar
+    # d = 4, 8, 16 and 32: the default body reads the centres through scalar
     # loads, variant 1 broadcasts them from LDS; at d = 16 variant 2 takes
     # two points per lane
     # (superblocks of 333 points leave lanes whose second point is past the
