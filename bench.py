@@ -157,7 +157,7 @@ TRAFFIC = {
     # k_kmeans_s<16, 1, 2>, one dispatch per assignment launch of 2^26 points
     # (d = 16, K = 64): FETCH_SIZE 2,097,203 KiB x 2.000 + WRITE_SIZE 262,144
     # KiB x 1.000, the 64 B of each point and its 4 B label
-    "k_kmeans": {"sources": KMEANS_SOURCES, "digest": "ae066ff5f9e159a3",
+    "k_kmeans": {"sources": KMEANS_SOURCES, "digest": "bf09ff7bc641c700",
                  "bytes_per_dispatch": 2097203 * 1024 * 2.000 + 262144 * 1024},
     # k_kmeans_update_c<16, 8>, one dispatch per 2^22-point superblock:
     # FETCH_SIZE 139,326 KiB x 2.000 + WRITE_SIZE 4,224 KiB x 1.000 (512

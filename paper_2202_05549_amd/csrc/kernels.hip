@@ -351,8 +351,8 @@ __global__ __launch_bounds__(256) void k_kmeans(KArgs a) {
 // of a wave needs the same centre value at the same time), not broadcast
 // from LDS: a 16-byte LDS broadcast fills 1 KiB of VGPRs for 8 VALU
 // instructions, and the four SIMDs of a CU share one LDS.  The centre loop
-// is unrolled UK times (2: the next centre's loads overlap this one's
-// arithmetic).  A lane takes PP points, 256 apart (a
+// is unrolled UK times (2: two centres' loads share one wait and their FMA
+// chains interleave).  A lane takes PP points, 256 apart (a
 // workgroup covers 256 PP points): each centre load then serves PP points,
 // and their chains are independent.
 template <int D, int PP, int UK>
