@@ -91,13 +91,30 @@ __global__ __launch_bounds__(256) void k_combine(CombineArgs a) {
         LT_GLOBAL T *tp = gp<T>(a.target.base) + g[0] * a.target.s[0] + g[1] * a.target.s[1] +
                 g[2] * a.target.s[2];
         T acc = a.accumulate ? *tp : identity<T>(a.op);
-        for (int p = 0; p < a.nparts; ++p) {
-            const CombinePart &q = a.parts[p];
-            bool in = true;
-            for (int x = 0; x < a.ndim; ++x)
-                if (g[x] < q.lo[x] || g[x] >= q.hi[x]) in = false;
-            if (!in) continue;
-            acc = rop<T>(a.op, acc, gp<const T>(a.part_base)[q.off + part_offset(q, a.ndim, g)]);
+        // parts in groups of 8: a group's loads are issued together, then
+        // folded in part order
+        for (int p0 = 0; p0 < a.nparts; p0 += 8) {
+            T v[8];
+            bool ok[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int p = p0 + u;
+                ok[u] = false;
+                v[u] = T(0);
+                if (p < a.nparts) {
+                    const CombinePart &q = a.parts[p];
+                    bool in = true;
+                    for (int x = 0; x < a.ndim; ++x)
+                        if (g[x] < q.lo[x] || g[x] >= q.hi[x]) in = false;
+                    if (in) {
+                        ok[u] = true;
+                        v[u] = gp<const T>(a.part_base)[q.off + part_offset(q, a.ndim, g)];
+                    }
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+                if (ok[u]) acc = rop<T>(a.op, acc, v[u]);
         }
         *tp = acc;
     }
