@@ -84,8 +84,10 @@ def _check_row(op, A, got, sb_cols):
 
 @pytest.mark.parametrize("op", ["+", "*", "min", "max"])
 @pytest.mark.parametrize("n,m,sb", [(300, 5000, (64, 2048)), (7, 70001, (8, 70016)), (1000, 37, (128, 64)),
-                                    (513, 4099, (512, 1024))])
+                                    (513, 4099, (512, 1024)), (50, 20000, (16, 1024))])
 def test_rowreduce_ops_against_oracle(L, op, n, m, sb):
+    # 20000 columns in superblocks of 1024: 20 partials per row, folded by
+    # the combine in groups of 8 (8 + 8 + 4)
     say("rowreduce", op, n, m, sb)
     A = _row_input(op, n, m, n + m)
     with ctx_of(L) as ctx:
