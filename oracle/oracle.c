@@ -222,7 +222,7 @@ void or_kmeans_assign_f32(int64_t N, int64_t dim, int64_t K, const float *X,
 }
 
 /* Float64 squared distance of point p to centre k: the exact-arithmetic scale
- * used to judge whether two labels are a near-tie.
+ * used to decide whether two labels are a near-tie.
  */
 double or_kmeans_dist_f64(int64_t dim, const float *x, const float *c)
 {
